@@ -1,0 +1,473 @@
+"""Pins of the FP64 CPU oracle against the paper and against mathematics.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (fixtures under tests/golden/), closed forms, library routines
+(numpy FFT, scipy expm / eigvalsh, scipy.constants), brute force over global
+slices, finite differences and invariants.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+import scipy.linalg as sla
+
+import oracle
+import synth
+from tests._systems import custom, lj_table
+
+POW2 = [1, 2, 4, 8, 16, 32]
+
+
+# ---------------------------------------------------------------- slice map
+
+def _nested_pairs(ni, nj):
+    """Paper's 2-body index sets of Eq. (mts-hamiltonian), 1-based."""
+    out = []
+    for a in range(1, nj + 1):
+        for g in range(1, ni // nj + 1):
+            out.append(((a - 1) * (ni // nj) + g, a))
+    return sorted(out)
+
+
+def _nested_triples(ni, nj, nk):
+    """Paper's 3-body index sets of Eq. (mts-hamiltonian), 1-based."""
+    out = []
+    for a in range(1, nk + 1):
+        for lam in range(1, nj // nk + 1):
+            for g in range(1, ni // nj + 1):
+                bj = (a - 1) * (nj // nk) + lam
+                bi = ((a - 1) * (nj // nk) + lam - 1) * (ni // nj) + g
+                out.append((bi, bj, a))
+    return sorted(out)
+
+
+def test_slice_map_matches_paper_example(golden_dir):
+    """Fig. 1(b)-(d) discussion: exact bead pairs for N_1=4 vs N_2=4,1,2."""
+    rows = [l.split() for l in open(os.path.join(golden_dir, "fig1_bead_pairs.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        n1, n2 = int(row[1]), int(row[2])
+        want = sorted(tuple(int(x) for x in p.split("-")) for p in row[3:])
+        got = sorted((oracle.slice_bead(s, n1, n1) + 1, oracle.slice_bead(s, n2, n1) + 1)
+                     for s in range(max(n1, n2)))
+        assert got == want, row[0]
+
+
+@pytest.mark.parametrize("ni", POW2)
+def test_slice_map_equals_nested_indices_two_body(ni):
+    for nj in [n for n in POW2 if n <= ni]:
+        got = sorted((oracle.slice_bead(s, ni, ni) + 1, oracle.slice_bead(s, nj, ni) + 1)
+                     for s in range(ni))
+        assert got == _nested_pairs(ni, nj)
+
+
+def test_slice_map_equals_nested_indices_three_body():
+    for ni in POW2:
+        for nj in [n for n in POW2 if n <= ni]:
+            for nk in [n for n in POW2 if n <= nj]:
+                got = sorted(tuple(oracle.slice_bead(s, n, ni) + 1 for n in (ni, nj, nk))
+                             for s in range(ni))
+                assert got == _nested_triples(ni, nj, nk), (ni, nj, nk)
+
+
+def test_bead_totals_tables(golden_dir):
+    """Table 1 and Table 2 'Particles' columns from the generated systems."""
+    rows = [l.split() for l in open(os.path.join(golden_dir, "table_bead_totals.txt"))
+            if l.strip() and not l.startswith("#")]
+    for kind, nw, nh, no, ne, total in rows:
+        nw, nh, no, ne, total = map(int, (nw, nh, no, ne, total))
+        assert synth.water_bead_total(nw, nh, no) + ne + (1 if ne else 0) == total
+    # the generated 90-water box at (32,4) has that many beads
+    s = synth.water_box(90, 14.0, 32, 4, seed=3)
+    assert s.total_beads == 6120
+
+
+# ---------------------------------------------------------------- constants
+
+def test_constants_against_codata():
+    c = oracle.constants()
+    amu_a2_fs2 = sc.atomic_mass * 1e-20 / 1e-30
+    assert c["kcal"] == pytest.approx(4184.0 / sc.N_A / amu_a2_fs2, rel=1e-12)
+    assert c["hbar"] == pytest.approx(sc.hbar / (sc.atomic_mass * 1e-20 / 1e-15), rel=1e-9)
+    assert c["kb"] == pytest.approx(sc.k / amu_a2_fs2, rel=1e-9)
+    ke = sc.e ** 2 / (4 * math.pi * sc.epsilon_0) * sc.N_A / 4184.0 * 1e10
+    assert c["ke"] == pytest.approx(ke, rel=1e-8)
+
+
+# ---------------------------------------------------------------- pair terms
+
+def test_lj_zero_crossing_and_minimum():
+    eps, sig = lj_table(0, 0, 0.3, 2.0)
+    for r, v_want, f_want in [(2.0, 0.0, None), (2.0 * 2 ** (1 / 6), -0.3, 0.0)]:
+        s = custom([1, 1], [[0, 0, 0], [r, 0, 0]], lj_type=[0, 0], eps=eps, sig=sig)
+        F, e = oracle.OracleSystem(s).forces(s.q)
+        assert e[1] == pytest.approx(v_want, abs=1e-12)
+        if f_want is not None:
+            assert abs(F).max() < 1e-12
+
+
+def test_coulomb_form_and_constant():
+    s = custom([1, 1], [[0, 0, 0], [0, 3.0, 0]], charge=[0.5, -0.7])
+    F, e = oracle.OracleSystem(s).forces(s.q)
+    ke = sc.e ** 2 / (4 * math.pi * sc.epsilon_0) * sc.N_A / 4184.0 * 1e10
+    assert e[2] == pytest.approx(ke * 0.5 * -0.7 / 3.0, rel=1e-8)
+    # attraction pulls particle 0 toward +y
+    assert F[0, 1] == pytest.approx(-ke * 0.5 * -0.7 / 9.0, rel=1e-8)
+    assert np.allclose(F[0], -F[1])
+
+
+def test_pseudopotential_at_zero_separation_and_limit():
+    ke = sc.e ** 2 / (4 * math.pi * sc.epsilon_0) * sc.N_A / 4184.0 * 1e10
+    s = custom([1, 1], [[1, 1, 1], [1, 1, 1]], charge=[-1.0, 3.0], ele=[1, 0],
+               pp_q=-1.0, pp_a=0.5)
+    F, e = oracle.OracleSystem(s).forces(s.q)
+    assert e[3] == pytest.approx(ke * -3.0 / 0.5, rel=1e-8)
+    assert abs(F).max() < 1e-12
+    # far from the core the softened form approaches Coulomb
+    s = custom([1, 1], [[0, 0, 0], [400.0, 0, 0]], charge=[-1.0, 3.0], ele=[1, 0],
+               pp_a=0.5)
+    _, e = oracle.OracleSystem(s).forces(s.q)
+    assert e[3] == pytest.approx(ke * -3.0 / 400.0, rel=1e-5)
+
+
+def test_shifted_force_vanishes_at_cutoff():
+    eps, sig = lj_table(0, 0, 0.3, 2.0)
+    rc = 5.0
+    for kw in (dict(lj_type=[0, 0], eps=eps, sig=sig), dict(charge=[1.0, -1.0]),
+               dict(charge=[-1.0, 1.0], ele=[1, 0])):
+        s = custom([1, 1], [[0, 0, 0], [rc * (1 - 1e-9), 0, 0]], rc=rc, box=100.0, **kw)
+        F, e = oracle.OracleSystem(s).forces(s.q)
+        assert abs(e[0]) < 1e-9 and abs(F).max() < 1e-6
+        s = custom([1, 1], [[0, 0, 0], [rc * (1 + 1e-9), 0, 0]], rc=rc, box=100.0, **kw)
+        F, e = oracle.OracleSystem(s).forces(s.q)
+        assert e[0] == 0.0 and abs(F).max() == 0.0
+
+
+def test_nearest_image_and_exclusion():
+    box = 10.0
+    a = custom([1, 1], [[0.5, 2, 2], [9.0, 2, 2]], charge=[1, -1], box=box, rc=4.0)
+    b = custom([1, 1], [[0.5, 2, 2], [-1.0, 2, 2]], charge=[1, -1], box=box, rc=4.0)
+    Fa, ea = oracle.OracleSystem(a).forces(a.q)
+    Fb, eb = oracle.OracleSystem(b).forces(b.q)
+    assert ea[2] == pytest.approx(eb[2], rel=1e-14) and ea[2] != 0.0
+    assert np.allclose(Fa, Fb, rtol=1e-14)
+    c = custom([1, 1], [[0.5, 2, 2], [1.5, 2, 2]], charge=[1, -1], mol=[7, 7], box=box, rc=4.0)
+    Fc, ec = oracle.OracleSystem(c).forces(c.q)
+    assert ec[2] == 0.0 and abs(Fc).max() == 0.0
+
+
+def test_bond_and_angle_closed_forms():
+    s = custom([1, 1], [[0, 0, 0], [1.13, 0, 0]], bonds=[(0, 1)], bond_k=400.0,
+               bond_r0=1.0, mol=[1, 1])
+    F, e = oracle.OracleSystem(s).forces(s.q)
+    assert e[4] == pytest.approx(0.5 * 400.0 * 0.13 ** 2, rel=1e-12)
+    assert F[0, 0] == pytest.approx(400.0 * 0.13, rel=1e-12)
+    t0 = math.radians(105.0)
+    s = custom([1, 1, 1], [[1, 0, 0], [0, 0, 0], [0, 2, 0]], angles=[(0, 1, 2)],
+               angle_k=60.0, angle_t0=t0, mol=[1, 1, 1])
+    F, e = oracle.OracleSystem(s).forces(s.q)
+    assert e[5] == pytest.approx(0.5 * 60.0 * (math.pi / 2 - t0) ** 2, rel=1e-12)
+    assert np.abs(F.sum(axis=0)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- V_mix
+
+@pytest.mark.parametrize("seed", range(8))
+def test_o2_equals_global_slice_brute_force(seed):
+    """Per-term N_max evaluation == average over N_G global slices."""
+    s = synth.tiny_random(seed)
+    o = oracle.OracleSystem(s)
+    F2, e2 = o.forces(s.q, "o2")
+    F1, e1 = o.forces(s.q, "o1")
+    scale = np.abs(F1).max()
+    assert np.abs(F2 - F1).max() <= 1e-12 * scale
+    assert np.abs(e2 - e1).max() <= 1e-12 * np.abs(e1).sum()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_forces_are_minus_gradient(seed):
+    s = synth.tiny_random(seed)
+    o = oracle.OracleSystem(s)
+    F, _ = o.forces(s.q)
+    h = 1e-5
+    fd = np.zeros_like(F)
+    for b in range(s.q.shape[0]):
+        for c in range(3):
+            qp = s.q.copy(); qp[b, c] += h
+            qm = s.q.copy(); qm[b, c] -= h
+            fd[b, c] = -(o.forces(qp)[1][0] - o.forces(qm)[1][0]) / (2 * h)
+    assert np.abs(fd - F).max() <= 1e-6 * max(1.0, np.abs(F).max())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_newton3_and_translation(seed):
+    s = synth.tiny_random(seed)
+    o = oracle.OracleSystem(s)
+    F, e = o.forces(s.q)
+    assert np.abs(F.sum(axis=0)).max() <= 1e-11 * np.abs(F).max()
+    F2, e2 = o.forces(s.q + np.array([0.37, -1.21, 2.9]))
+    assert np.abs(e2 - e).max() <= 1e-11 * np.abs(e).sum()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_collapsed_rings_reduce_to_classical(seed):
+    """Coincident beads: V_mix = V_classical, sum of bead forces = classical."""
+    s = synth.tiny_random(seed)
+    off = s.bead_offset
+    X = np.array([s.q[off[i]:off[i + 1]].mean(axis=0) for i in range(s.n_particles)])
+    s.q = np.repeat(X, s.n_beads, axis=0)
+    o = oracle.OracleSystem(s)
+    F, e = o.forces(s.q)
+    Fc, ec = o.classical(X)
+    assert np.abs(e - ec).max() <= 1e-12 * np.abs(ec).sum()
+    Fs = np.array([F[off[i]:off[i + 1]].sum(axis=0) for i in range(s.n_particles)])
+    assert np.abs(Fs - Fc).max() <= 1e-12 * np.abs(Fc).max()
+
+
+def test_equal_bead_counts_reduce_to_standard_pimd():
+    """All N_i = N: V_mix = (1/N) sum_a V(q_a), each bead force = F_cl/N."""
+    s = synth.tiny_random(5, bead_choices=(4,))
+    o = oracle.OracleSystem(s)
+    F, e = o.forces(s.q)
+    N = 4
+    ecl = np.zeros(6)
+    for a in range(N):
+        X = s.q[a::N]
+        Fa, ea = o.classical(X)
+        ecl += ea / N
+        assert np.abs(F[a::N] - Fa / N).max() <= 1e-12 * np.abs(Fa).max()
+    # the constant background counts once, not once per bead
+    assert np.abs(e - ecl).max() <= 1e-12 * np.abs(ecl).sum()
+
+
+def test_block_shift_invariance():
+    s = synth.tiny_random(11, bead_choices=(2, 4, 8))
+    o = oracle.OracleSystem(s)
+    F, e = o.forces(s.q)
+    nmin = int(s.n_beads.min())
+    off = s.bead_offset
+    q2 = s.q.copy()
+    perm = np.arange(s.total_beads)
+    for i, n in enumerate(s.n_beads):
+        sh = n // nmin
+        idx = off[i] + (np.arange(n) + sh) % n
+        q2[off[i]:off[i + 1]] = s.q[idx]
+        perm[off[i]:off[i + 1]] = idx
+    F2, e2 = o.forces(q2)
+    assert np.abs(e2 - e).max() <= 1e-12 * np.abs(e).sum()
+    assert np.abs(F2 - F[perm]).max() <= 1e-12 * np.abs(F).max()
+
+
+# ---------------------------------------------------------------- theta
+
+@pytest.mark.parametrize("seed", range(3))
+def test_theta_gradient_euler_and_fd(seed):
+    s = synth.solvated_electron(6, 8, 8.0, seed=seed, rc_pp=3.9, rc_aa=3.9,
+                                n_h=4, n_o=2, ion_excl=3.4)
+    th0 = np.array([s.pp_q, s.pp_a, s.lj_eps[0, 0], s.lj_sigma[0, 0],
+                    s.bond_k[0], s.angle_k[0]])
+    o = oracle.OracleSystem(s, theta=th0)
+    g = o.dvdtheta(s.q)
+    _, e = o.forces(s.q)
+    # V_pp, V_bond, V_angle are linear in q_e, k_b, k_theta
+    assert th0[0] * g[0] == pytest.approx(e[3], rel=1e-12)
+    assert th0[4] * g[4] == pytest.approx(e[4], rel=1e-12)
+    assert th0[5] * g[5] == pytest.approx(e[5], rel=1e-12)
+    for k in range(6):
+        h = 1e-6 * abs(th0[k])
+        tp = th0.copy(); tp[k] += h
+        tm = th0.copy(); tm[k] -= h
+        ep = oracle.OracleSystem(s, theta=tp).forces(s.q)[1][0]
+        em = oracle.OracleSystem(s, theta=tm).forces(s.q)[1][0]
+        fd = (ep - em) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), k
+
+
+def test_theta_gradient_water_only():
+    s = synth.water_box(8, 7.0, 4, 2, seed=1, rc=3.4)
+    o = oracle.OracleSystem(s)
+    g = o.dvdtheta(s.q)
+    _, e = o.forces(s.q)
+    assert g[0] == 0.0 and g[1] == 0.0
+    assert s.lj_eps[0, 0] * g[2] == pytest.approx(e[1], rel=1e-12)
+
+
+# ---------------------------------------------------------------- ring polymer
+
+def _cyclic_laplacian(N):
+    D = np.eye(N) - np.roll(np.eye(N), 1, axis=1)   # (D q)_a = q_a - q_{a+1}
+    return D.T @ D
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 64, 256])
+def test_nm_basis_orthonormal_and_diagonalises_springs(N):
+    Cm = oracle.nm_basis(N)
+    assert np.abs(Cm.T @ Cm - np.eye(N)).max() < 1e-13
+    L = _cyclic_laplacian(N)
+    lam = np.array([oracle.nm_lambda(N, k) for k in range(N)])
+    assert np.abs(Cm.T @ L @ Cm - np.diag(lam)).max() < 1e-12
+    assert np.allclose(np.sort(lam), np.linalg.eigvalsh(L), atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [2, 4, 16, 128])
+def test_nm_basis_against_fft(N):
+    rng = np.random.default_rng(N)
+    x = rng.normal(size=N)
+    xi = oracle.nm_basis(N).T @ x
+    f = np.fft.fft(x)
+    want = np.empty(N)
+    want[0] = f[0].real / math.sqrt(N)
+    for k in range(1, N):
+        if 2 * k < N:
+            want[k] = math.sqrt(2.0 / N) * f[k].real
+        elif 2 * k == N:
+            want[k] = f[k].real / math.sqrt(N)
+        else:
+            want[k] = -math.sqrt(2.0 / N) * f[k].imag
+    assert np.abs(xi - want).max() < 1e-12
+
+
+def _beta_hbar(T):
+    return sc.hbar / (sc.k * T) * 1e15   # fs
+
+
+def test_mode_frequencies_closed_form():
+    """m_f = m/N gives omega_k = 2 (N / beta hbar) sin(k pi / N)."""
+    for N in (4, 32, 1024):
+        s = custom([N], np.zeros((N, 3)), mass=[1.00794], temperature=300.0)
+        o = oracle.OracleSystem(s)
+        wp = N / _beta_hbar(300.0)
+        for k in (0, 1, N // 3, N // 2, N - 1):
+            assert o.omega(0, k) == pytest.approx(2 * wp * math.sin(k * math.pi / N),
+                                                  rel=1e-9, abs=1e-15)
+
+
+def test_free_propagation_equals_matrix_exponential():
+    """Exact NM propagation == expm of the bead-space linear flow."""
+    N, m = 8, 2.0
+    rng = np.random.default_rng(0)
+    q = rng.normal(scale=0.2, size=(N, 3))
+    p = rng.normal(scale=0.05, size=(N, 3))
+    s = custom([N], q, mass=[m], fict_mass=[m / N * 3.0], p=p)
+    o = oracle.OracleSystem(s)
+    t = 2.7
+    q1, p1 = o.free_propagate(q, p, t)
+    bh = _beta_hbar(300.0)
+    ksp = N * m / bh ** 2
+    mf = m / N * 3.0
+    A = np.zeros((2 * N, 2 * N))
+    A[:N, N:] = np.eye(N) / mf
+    A[N:, :N] = -ksp * _cyclic_laplacian(N)
+    U = sla.expm(A * t)
+    for c in range(3):
+        z = U @ np.concatenate([q[:, c], p[:, c]])
+        assert np.abs(z[:N] - q1[:, c]).max() < 1e-10
+        assert np.abs(z[N:] - p1[:, c]).max() < 1e-10
+
+
+def test_free_propagation_reversible_and_conservative():
+    s = synth.tiny_random(2, bead_choices=(1, 4, 16))
+    o = oracle.OracleSystem(s)
+    q1, p1 = o.free_propagate(s.q, s.p, 5.0)
+    q2, p2 = o.free_propagate(q1, -p1, 5.0)
+    assert np.abs(q2 - s.q).max() < 1e-12 and np.abs(-p2 - s.p).max() < 1e-12
+    kcal = oracle.constants()["kcal"]
+
+    def energy(q, p):
+        ke = sum((p[s.bead_offset[i]:s.bead_offset[i + 1]] ** 2).sum() / (2 * s.fict_mass[i])
+                 for i in range(s.n_particles)) / kcal
+        return ke + o.springs(q)[0]
+    assert energy(q1, p1) == pytest.approx(energy(s.q, s.p), rel=1e-12)
+
+
+def test_springs_gradient():
+    s = synth.tiny_random(3, bead_choices=(1, 2, 4, 8))
+    o = oracle.OracleSystem(s)
+    e, F = o.springs(s.q)
+    h = 1e-6
+    for b in range(0, s.total_beads, 3):
+        for c in range(3):
+            qp = s.q.copy(); qp[b, c] += h
+            qm = s.q.copy(); qm[b, c] -= h
+            fd = -(o.springs(qp)[0] - o.springs(qm)[0]) / (2 * h)
+            assert fd == pytest.approx(F[b, c], abs=1e-5 * max(1.0, abs(F).max()))
+
+
+@pytest.mark.parametrize("P,want", [(1, 0.1), (4, (1 + 2 / 1.32 + 1 / 1.64) / 10)])
+def test_harmonic_oscillator_x2_finite_p(P, want):
+    """<x^2>_P from the oracle's mode frequencies equals the Gaussian
+    path-integral covariance (linear algebra), in units hbar/(m omega)."""
+    T, m = 300.0, 1.00794
+    bh = _beta_hbar(T)
+    w = 10.0 / bh                 # beta hbar omega = 10
+    s = custom([P], np.zeros((P, 3)), mass=[m], temperature=T)
+    o = oracle.OracleSystem(s)
+    beta = o.beta
+    x2_modes = sum(1.0 / (beta * m * (w * w + o.omega(0, k) ** 2)) for k in range(P))
+    ksp = P * m / bh ** 2
+    A = (m * w * w / P) * np.eye(P) + ksp * _cyclic_laplacian(P)
+    x2_lin = np.trace(np.linalg.inv(beta * A)) / P
+    assert x2_modes == pytest.approx(x2_lin, rel=1e-12)
+    unit = oracle.constants()["hbar"] / (m * w)
+    assert x2_modes / unit == pytest.approx(want, rel=1e-9)
+
+
+def test_harmonic_oscillator_x2_converges_to_quantum():
+    T, m = 300.0, 1.00794
+    bh = _beta_hbar(T)
+    w = 10.0 / bh
+    P = 4096
+    s = custom([P], np.zeros((P, 3)), mass=[m], temperature=T)
+    o = oracle.OracleSystem(s)
+    x2 = sum(1.0 / (o.beta * m * (w * w + o.omega(0, k) ** 2)) for k in range(P))
+    unit = oracle.constants()["hbar"] / (m * w)
+    assert x2 / unit == pytest.approx(0.5 / math.tanh(5.0), rel=2e-5)
+
+
+# ---------------------------------------------------------------- integrator
+
+def test_step_without_interactions_is_free_propagation():
+    s = synth.tiny_random(4, bead_choices=(1, 2, 8))
+    s.charge[:] = 0.0
+    s.lj_eps[:] = 0.0
+    s.bonds = np.zeros((0, 2), np.int32)
+    s.angles = np.zeros((0, 3), np.int32)
+    s.background = False
+    o = oracle.OracleSystem(s)
+    q, p, F, _ = o.step(s.q, s.p, 3)
+    qf, pf = o.free_propagate(s.q, s.p, 3 * s.dt)
+    assert np.abs(q - qf).max() < 1e-12 and np.abs(p - pf).max() < 1e-12
+
+
+def _nve_fluct(dt, nsteps):
+    s = synth.water_box(8, 7.0, 4, 2, seed=2, rc=3.4, dt=dt)
+    o = oracle.OracleSystem(s)
+    _, p, _, elog = o.step(s.q, s.p, nsteps)
+    h = elog[:, oracle.E_NAMES.index("ham")]
+    return h.std(), abs(h[-1] - h[0]), p.sum(axis=0)
+
+
+def test_nve_energy_error_scales_as_dt_squared():
+    s1, _, ptot = _nve_fluct(0.2, 400)
+    s2, _, _ = _nve_fluct(0.1, 800)
+    ratio = s1 / s2
+    assert 3.0 < ratio < 5.5, ratio
+    assert np.abs(ptot).max() < 1e-9
+
+
+def test_observables_classical_limits():
+    s = synth.tiny_random(6, bead_choices=(1,))
+    o = oracle.OracleSystem(s)
+    F, v = o.forces(s.q)
+    e = o.observables(s.q, s.p, F, v)
+    kT = oracle.constants()["kb_kcal"] * s.temperature
+    n = s.n_particles
+    assert e[oracle.E_NAMES.index("spring")] == 0.0
+    assert e[oracle.E_NAMES.index("kcv")] == pytest.approx(1.5 * n * kT, rel=1e-14)
+    assert e[oracle.E_NAMES.index("kprim")] == pytest.approx(1.5 * n * kT, rel=1e-14)
+    kcal = oracle.constants()["kcal"]
+    ke = sum((s.p[i] ** 2).sum() / (2 * s.fict_mass[i]) for i in range(n)) / kcal
+    assert e[oracle.E_NAMES.index("kin")] == pytest.approx(ke, rel=1e-13)
