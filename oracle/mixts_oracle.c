@@ -325,6 +325,31 @@ void orc_forces_o2(const orc_sys *S, const double *q, double *F, double *eout)
     for (int k = 0; k <= E_ANGLE; ++k) eout[k] = e[k];
 }
 
+/* Counts the slice-pairs of orc_forces_o2 with at least one term inside its
+ * cutoff: out[0] atom-atom, out[1] electron-atom. */
+void orc_pair_evals(const orc_sys *S, const double *q, long *out)
+{
+    long na = 0, ne = 0;
+    double e[E_N];
+    for (int i = 0; i < S->n; ++i)
+        for (int j = i + 1; j < S->n; ++j) {
+            int ni = S->nb[i], nj = S->nb[j];
+            int nmax = ni > nj ? ni : nj;
+            for (int s = 0; s < nmax; ++s) {
+                long bi = S->off[i] + orc_slice_bead(s, ni, nmax);
+                long bj = S->off[j] + orc_slice_bead(s, nj, nmax);
+                double d[3], g;
+                min_image(S, q + 3 * bi, q + 3 * bj, d);
+                if (pair_term(S, i, j, d, 1.0, e, &g)) {
+                    if (S->ele[i] || S->ele[j]) ++ne;
+                    else ++na;
+                }
+            }
+        }
+    out[0] = na;
+    out[1] = ne;
+}
+
 /* ---------------- V_mix as an average over global slices (O1) ------------ */
 
 /* Classical potential and forces of one configuration X[n][3]. */
@@ -515,17 +540,20 @@ double orc_springs(const orc_sys *S, const double *q, double *Fsp)
 
 /* Orthonormal real basis C[j*N + k] (bead j, mode k) of the cyclic ring:
  * k = 0: 1/sqrt(N); 1 <= k < N/2: sqrt(2/N) cos(2 pi j k / N);
- * k = N/2: (-1)^j / sqrt(N); N/2 < k < N: sqrt(2/N) sin(2 pi j k / N). */
+ * k = N/2: (-1)^j / sqrt(N); N/2 < k < N: sqrt(2/N) sin(2 pi j k / N).
+ * The phase uses j k mod N (the functions have period N in j k), which keeps
+ * the argument below 2 pi and the basis accurate to rounding for large N. */
 void orc_nm_basis(int N, double *C)
 {
     for (int j = 0; j < N; ++j)
         for (int k = 0; k < N; ++k) {
             double v;
+            double ph = 2.0 * O_PI * (double)(((long)j * k) % N) / N;
             if (k == 0) v = 1.0 / sqrt((double)N);
-            else if (2 * k < N) v = sqrt(2.0 / N) * cos(2.0 * O_PI * j * k / N);
+            else if (2 * k < N) v = sqrt(2.0 / N) * cos(ph);
             else if (2 * k == N) v = ((j % 2) ? -1.0 : 1.0) / sqrt((double)N);
-            else v = sqrt(2.0 / N) * sin(2.0 * O_PI * j * k / N);
-            C[j * N + k] = v;
+            else v = sqrt(2.0 / N) * sin(ph);
+            C[(long)j * N + k] = v;
         }
 }
 
