@@ -1,0 +1,241 @@
+/*
+ * mixpi.h -- C-ABI of the MI355X (gfx950) mixed-time-slicing PIMD hot path.
+ *
+ * The library computes, on one GPU, the per-step work of mixTS path-integral
+ * molecular dynamics as defined in arXiv 2411.11988 ("MixPI"):
+ *   - bead forces of V_mix, Eq. (mts-hamiltonian): every pair, bond and angle
+ *     is evaluated on N_max slices of its participants, participant p at
+ *     bead floor(s * N_p / N_max) in slice s, each slice weighted 1/N_max;
+ *   - the free ring polymers of Eq. (mts-hamiltonian-b) in normal modes and
+ *     their exact propagation (Sec. "Evaluation");
+ *   - the split propagator half-kick / free ring polymer / half-kick
+ *     (Sec. "Evaluation", symmetric Liouvillian splitting);
+ *   - energies and kinetic estimators after each step (Sec. "Output and
+ *     Analysis").
+ *
+ * Conventions
+ *   Units: Angstrom, fs, amu, kcal/mol, elementary charge, K.  Forces are
+ *   kcal/mol/A; momenta amu*A/fs.
+ *
+ *   Bead counts must be powers of two (Sec. "Setup") and particles must be
+ *   listed in non-increasing bead count (ring-polymer molecules first,
+ *   Sec. "Setup").  A *group* is a maximal run of consecutive particles with
+ *   equal bead count and equal electron flag.
+ *
+ *   State layout ("library layout"): FP64, for each group g in order a block
+ *   [N_g][n_g][3] (bead-major: all particles of bead 0, then bead 1, ...),
+ *   groups concatenated; for a batch, systems concatenated in order.
+ *   mixpi_bead_index() gives the row of every (particle, bead).
+ *
+ *   Force field (readings of the paper's q-SPC/Fw water, cation-water LJ and
+ *   electron pseudopotential): LJ 4 eps ((s/r)^12 - (s/r)^6), Coulomb
+ *   k_e q_i q_j / r, and for electron-atom pairs only the softened Coulomb
+ *   k_e pp_q q_j / sqrt(r^2 + pp_a^2).  Every cut term is shifted as
+ *   V(r) - V(rc) - (r^2 - rc^2) V'(rc) / (2 rc) inside r^2 < rc^2.  Nearest
+ *   image in a rectangular box.  Pairs with equal mol_id are excluded; two
+ *   electrons do not interact.  Harmonic bonds k/2 (r - r0)^2 and harmonic
+ *   angles k/2 (theta - theta0)^2 (vertex in the middle).  With background
+ *   set, a neutralising uniform background adds -pi k_e rc_coul^2 Q^2 / (5 V)
+ *   to V_Coul (Q = net charge of the non-electron particles).
+ *
+ *   Pointers: "device" pointers are GPU global memory on the current HIP
+ *   device, allocated and owned by the caller; "host" pointers are read
+ *   during the call only.  The stream argument is a hipStream_t (NULL = the
+ *   legacy default stream); all work is enqueued asynchronously on it.
+ *
+ *   Errors: every function returns MIXPI_OK (0) or a negative MIXPI_E_*
+ *   code and never aborts; mixpi_last_error() returns a message for the last
+ *   failure on the calling thread.  Argument errors are detected before any
+ *   work is enqueued.
+ */
+#ifndef MIXPI_H
+#define MIXPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MIXPI_OK = 0,
+    MIXPI_E_INVALID = -1,      /* null pointer, bad size or parameter */
+    MIXPI_E_NOT_POW2 = -2,     /* a bead count is not a power of two */
+    MIXPI_E_ORDER = -3,        /* bead counts increase along the particle list */
+    MIXPI_E_HIP = -4,          /* a HIP runtime call failed */
+    MIXPI_E_NONFINITE = -5,    /* a non-finite energy appeared (checked steps) */
+    MIXPI_E_UNSUPPORTED = -6   /* valid request outside the supported range */
+};
+
+/* Energy slots (kcal/mol). mixpi_forces/mixpi_energy write the first
+ * MIXPI_NV; each mixpi_step log row has MIXPI_NE. */
+enum {
+    MIXPI_E_VMIX = 0,   /* V_mix = LJ + COUL + PP + BOND + ANGLE */
+    MIXPI_E_LJ,
+    MIXPI_E_COUL,
+    MIXPI_E_PP,
+    MIXPI_E_BOND,
+    MIXPI_E_ANGLE,
+    MIXPI_E_SPRING,     /* sum_i N_i m_i/(2 beta^2 hbar^2) sum_a |q_ia - q_i,a+1|^2 */
+    MIXPI_E_KIN,        /* sum p^2 / (2 m_f) */
+    MIXPI_E_KCV,        /* centroid virial: sum_i 3/(2 beta) - 1/2 sum (q - qbar).F */
+    MIXPI_E_KPRIM,      /* primitive: sum_i 3 N_i/(2 beta) - E_spring */
+    MIXPI_E_HAM,        /* conserved H = KIN + SPRING + VMIX */
+    MIXPI_NE
+};
+#define MIXPI_NV 6
+#define MIXPI_NTHETA 6   /* theta = (pp_q, pp_a, eps_00, sigma_00, k_bond0, k_angle0) */
+
+typedef enum {
+    MIXPI_FP64 = 0,        /* all pair arithmetic in FP64 */
+    MIXPI_FP32_ACC64 = 1   /* FP64 separations and sums, FP32 pair potentials */
+} mixpi_precision;
+
+/* flags */
+#define MIXPI_FLAG_CHECK_FINITE 1   /* mixpi_step syncs and reports non-finite H */
+
+typedef struct mixpi_system mixpi_system;   /* opaque, owned by the library */
+
+/* Host description of one system; every array is host memory, copied by
+ * mixpi_create.  Bead counts: non-increasing powers of two. */
+typedef struct {
+    int32_t n_particles;
+    const int32_t *n_beads;        /* [n] */
+    const double *mass;            /* [n] physical mass, amu (> 0) */
+    const double *fict_mass;       /* [n] fictitious bead mass m_f, amu (> 0) */
+    const double *charge;          /* [n] e */
+    const int32_t *lj_type;        /* [n] in [0, n_lj_types) or -1 (no LJ) */
+    const int32_t *mol_id;         /* [n] equal ids exclude nonbonded pairs */
+    const int32_t *is_electron;    /* [n] 0/1 */
+    int32_t n_lj_types;            /* <= 8 */
+    const double *lj_eps;          /* [n_lj_types^2] kcal/mol, symmetric */
+    const double *lj_sigma;        /* [n_lj_types^2] A */
+    int32_t n_bonds;
+    const int32_t *bonds;          /* [n_bonds][2] particle indices */
+    const int32_t *bond_type;      /* [n_bonds] */
+    int32_t n_bond_types;
+    const double *bond_k;          /* [n_bond_types] kcal/mol/A^2 */
+    const double *bond_r0;         /* [n_bond_types] A */
+    int32_t n_angles;
+    const int32_t *angles;         /* [n_angles][3] (end, vertex, end) */
+    const int32_t *angle_type;     /* [n_angles] */
+    int32_t n_angle_types;
+    const double *angle_k;         /* [n_angle_types] kcal/mol/rad^2 */
+    const double *angle_t0;        /* [n_angle_types] rad */
+    double pp_q;                   /* pseudopotential charge of an electron, e */
+    double pp_a;                   /* softening length, A (> 0) */
+    double rc_pp, rc_coul, rc_lj;  /* cutoffs, A (> 0) */
+    int32_t background;            /* 0/1 */
+    double box[3];                 /* rectangular periodic box, A */
+    double temperature;            /* K (> 0) */
+    double dt;                     /* fs */
+    int32_t precision;             /* mixpi_precision */
+    int32_t flags;                 /* MIXPI_FLAG_* */
+} mixpi_system_desc;
+
+/* Message of the last failure on this thread ("" if none). */
+const char *mixpi_last_error(void);
+
+/* Validates desc and builds a one-system handle on the current HIP device:
+ * constant tables (normal-mode bases, propagator coefficients), pair and
+ * bonded work lists.  Errors: MIXPI_E_INVALID, _NOT_POW2, _ORDER,
+ * _UNSUPPORTED (more than 8 LJ types, N > 4096), _HIP.  *out is NULL on
+ * failure. */
+int mixpi_create(const mixpi_system_desc *desc, mixpi_system **out);
+
+/* A batch of n independent systems sharing one handle: every entry point
+ * then processes all systems in the same launches.  Arrays in the library
+ * layout hold the systems back to back; per-system outputs are indexed by
+ * system.  All systems must share precision and flags. */
+int mixpi_batch_create(const mixpi_system_desc *const *descs, int32_t n,
+                       mixpi_system **out);
+
+int mixpi_destroy(mixpi_system *sys);
+
+/* Sizes: total beads (rows of every state array), particles, groups,
+ * systems.  Any pointer may be NULL. */
+int mixpi_sizes(const mixpi_system *sys, int64_t *n_bead_rows, int32_t *n_particles,
+                int32_t *n_groups, int32_t *n_systems);
+
+/* Host int64 [total beads]: for particle i (batch: systems in order) and
+ * bead a in particle-major order, the row of that bead in the library
+ * layout. */
+int mixpi_bead_index(const mixpi_system *sys, int64_t *rows_out);
+
+/* Bead forces F = -dV_mix/dq (Eq. mts-hamiltonian).
+ *   q     device double [rows][3], library layout (positions, unwrapped)
+ *   theta device double [n_systems][6] overriding (pp_q, pp_a, eps and
+ *         sigma of LJ type pair (0,0), k of bond type 0, k of angle type 0),
+ *         or NULL for the values given at create
+ *   f     device double [rows][3], overwritten (must not alias q)
+ *   e_out device double [n_systems][MIXPI_NV] or NULL
+ * FP64 precision: arithmetic in FP64.  FP32_ACC64: separations, forces and
+ * sums in FP64, pair potentials in FP32. */
+int mixpi_forces(mixpi_system *sys, const double *q, const double *theta,
+                 double *f, double *e_out, void *stream);
+
+/* V_mix only: e_out device double [n_systems][MIXPI_NV]. */
+int mixpi_energy(mixpi_system *sys, const double *q, const double *theta,
+                 double *e_out, void *stream);
+
+/* Adjoint of E = V_mix(q; theta) (recomputes every term; no per-pair
+ * storage).  grad_e: device double [n_systems] (dL/dE) or NULL for 1.
+ * dq: device double [rows][3] = grad_e * dE/dq (= -grad_e F).  dtheta:
+ * device double [n_systems][6] = grad_e * dE/dtheta.  Either output may be
+ * NULL. */
+int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta,
+                         const double *grad_e, double *dq, double *dtheta,
+                         void *stream);
+
+/* Ring-polymer normal-mode transform of each particle's beads, per Cartesian
+ * component, in the orthonormal real basis C (bead j, mode k) of the cyclic
+ * ring: k = 0: 1/sqrt(N); 0 < k < N/2: sqrt(2/N) cos(2 pi j k / N);
+ * k = N/2: (-1)^j/sqrt(N); N/2 < k < N: sqrt(2/N) sin(2 pi j k / N).
+ * dir = +1: out = C^T in (bead -> mode); dir = -1: out = C in (mode -> bead).
+ * in/out: device double [rows][3], library layout (mode k of a group in the
+ * place of bead k); must not alias. */
+int mixpi_nm_transform(mixpi_system *sys, int32_t dir, const double *in, double *out,
+                       void *stream);
+
+/* nsteps of the split propagator (Sec. "Evaluation"):
+ *   p += dt/2 F;  free ring polymers evolved exactly for dt in normal modes;
+ *   F = F_mix(q);  p += dt/2 F;  energies -> elog.
+ * q, p, f: device double [rows][3], updated in place; on entry f must hold
+ * F_mix(q) (from mixpi_forces).  elog: device double
+ * [nsteps][n_systems][MIXPI_NE] or NULL.  Allocates nothing; repeated calls
+ * with the same pointers and nsteps replay a cached HIP graph. */
+int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+               double *elog, void *stream);
+
+/* Candidate slice-pairs of one force evaluation: every unordered,
+ * non-excluded particle pair times N_max of the pair, summed over systems
+ * (from the work lists; no device work). */
+int mixpi_pair_candidates(const mixpi_system *sys, int64_t *candidates);
+
+/* Slice-pair evaluations with at least one term inside its cutoff, counted
+ * on the device by every force evaluation since the last reset (forces,
+ * energy, adjoint and each step).  evals: host int64 [2] = (atom-atom
+ * pairs, electron-atom pairs).  Waits for the stream.  reset != 0 zeroes
+ * the counters after reading. */
+int mixpi_pair_evals(mixpi_system *sys, int64_t *evals, int32_t reset, void *stream);
+
+/* Builds and caches the HIP graph that mixpi_step would use for these
+ * arguments, without launching it (moves graph construction out of a
+ * latency-critical or timed region).  Same argument rules as mixpi_step. */
+int mixpi_step_prepare(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+                       double *elog);
+
+/* Measurement aid: launches one kernel of the step `reps` times on `stream`
+ * between two HIP events and returns the mean duration in microseconds.
+ * which: 0 = pair sweep, 1 = bonded sweep, 2 = free ring polymer (normal
+ * modes), 3 = half-kick/energy epilogue.  q, p: device double [rows][3]
+ * (read only; copied to library scratch, so no caller buffer changes).
+ * Waits for the stream. */
+int mixpi_kernel_time(mixpi_system *sys, int32_t which, int32_t reps, const double *q,
+                      const double *p, double *avg_us, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIXPI_H */

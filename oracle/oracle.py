@@ -74,6 +74,7 @@ def lib():
             getattr(_lib, name).argtypes = [P, P, P, P]
             getattr(_lib, name).restype = None
         _lib.orc_dvdtheta.argtypes = [P, P, P]
+        _lib.orc_pair_evals.argtypes = [P, P, P]
         _lib.orc_springs.argtypes = [P, P, P]
         _lib.orc_springs.restype = C.c_double
         _lib.orc_nm_basis.argtypes = [C.c_int, P]
@@ -173,6 +174,13 @@ class OracleSystem:
         e = np.zeros(N_POT)
         lib().orc_classical(self.ptr, _p(X), _p(F), _p(e))
         return F, e
+
+    def pair_evals(self, q):
+        """(atom-atom, electron-atom) slice-pairs inside a cutoff."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        out = np.zeros(2, dtype=np.int64)
+        lib().orc_pair_evals(self.ptr, _p(q), _p(out))
+        return int(out[0]), int(out[1])
 
     def dvdtheta(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)

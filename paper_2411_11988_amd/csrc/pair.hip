@@ -1,0 +1,277 @@
+// Slice-mapped nonbonded pair sweep of V_mix (arXiv 2411.11988,
+// Eq. mts-hamiltonian): every unordered, non-excluded pair of particles is
+// evaluated on N_max = max(N_i, N_j) slices, particle p at bead
+// floor(s * N_p / N_max) in slice s, weight 1/N_max.
+//
+// Work decomposition.  Particles come in groups of equal bead count, and
+// the state of group g is a [N_g][n_g][3] block.  For a group pair (a, b)
+// with N_b = N_a >> shift, slice-pairs that meet bead b of group b are
+// exactly the rows [b << shift, (b + 1) << shift) of group a -- a contiguous
+// run of n_a << shift beads.  One work item is a 64 x 64 tile of that
+// rectangle (or of the upper triangle for a group with itself): one wave,
+// one lane per i-bead, the 64 j-beads staged in LDS.  Lane l visits j-bead
+// (l + t) mod 64 at step t, so the 64 lanes always touch 64 distinct
+// j-beads and the Newton-3 reaction goes to a per-j LDS accumulator with a
+// return-less LDS atomic add; i-forces stay in registers.  Every tile ends
+// with FP64 global atomics of its 64 + 64 bead forces.
+//
+// Precision: separations and the nearest-image shift are FP64 (positions
+// sit up to a box length from the origin); the pair potential is evaluated
+// in R (double, or float for the FP32 form); forces and energies are summed
+// in FP64.
+#include "mixpi_internal.h"
+
+namespace mixpi {
+
+template <typename R> __device__ __forceinline__ R rsqrt_r(R x);
+template <> __device__ __forceinline__ double rsqrt_r<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <typename R> __device__ __forceinline__ R rcp_r(R x);
+template <> __device__ __forceinline__ double rcp_r<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename R, bool THETA>
+__global__ __launch_bounds__(64) void k_pair(PairLaunch a)
+{
+    const PairItem it = a.items[blockIdx.x];
+    const PairBlock bk = a.blocks[it.block];
+    const SysDev &S = a.sys[bk.sys];
+    const double *th = a.theta ? a.theta + 6 * bk.sys : S.theta0;
+    const int lane = threadIdx.x;
+
+    __shared__ double sx[kPairTile], sy[kPairTile], sz[kPairTile], sq[kPairTile];
+    __shared__ int st[kPairTile], sm[kPairTile];
+    __shared__ double fjx[kPairTile], fjy[kPairTile], fjz[kPairTile];
+    __shared__ R t_e4[kLjTab], t_s2[kLjTab], t_c0[kLjTab], t_c1[kLjTab];
+
+    const int nt1 = S.nt1;
+    const double rc_lj = S.rc_lj, rc_c = S.rc_c;
+    if (bk.kind == PK_ATOM) {
+        for (int tp = lane; tp < nt1 * nt1; tp += 64) {
+            double eps = tp == 0 ? th[2] : a.lj_eps[S.lj_off + tp];
+            double sig = tp == 0 ? th[3] : a.lj_sig[S.lj_off + tp];
+            double s2 = sig * sig;
+            double c6 = s2 / (rc_lj * rc_lj);
+            c6 = c6 * c6 * c6;
+            double c12 = c6 * c6;
+            t_e4[tp] = (R)(4.0 * eps);
+            t_s2[tp] = (R)s2;
+            t_c0[tp] = (R)(4.0 * eps * (c12 - c6));
+            t_c1[tp] = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+        }
+    }
+
+    // j tile: bead b of group b, particles j0 .. j0 + jn
+    const int jn = min(kPairTile, bk.nb - it.j0);
+    long long rowj = 0;
+    if (lane < jn) {
+        const int j = it.j0 + lane;
+        rowj = bk.rowb + (long long)it.b * bk.nb + j;
+        const int pj = bk.pb0 + j;
+        sx[lane] = a.q[3 * rowj];
+        sy[lane] = a.q[3 * rowj + 1];
+        sz[lane] = a.q[3 * rowj + 2];
+        sq[lane] = a.charge[pj];
+        st[lane] = a.ljt[pj];
+        sm[lane] = a.mol[pj];
+    }
+    fjx[lane] = 0.0;
+    fjy[lane] = 0.0;
+    fjz[lane] = 0.0;
+
+    // i bead
+    const long long li = (long long)bk.na << bk.shift;
+    const long long idx = (long long)it.i0 + lane;
+    const bool vi = idx < li;
+    const long long rowi = bk.rowa + ((long long)it.b << bk.shift) * bk.na + idx;
+    double xi = 0, yi = 0, zi = 0, qi = 0;
+    int ti = 0, mi = 0x7fffffff;
+    if (vi) {
+        const int pi = bk.pa0 + (int)(idx % bk.na);
+        xi = a.q[3 * rowi];
+        yi = a.q[3 * rowi + 1];
+        zi = a.q[3 * rowi + 2];
+        qi = a.charge[pi];
+        ti = a.ljt[pi];
+        mi = a.mol[pi];
+    }
+    __syncthreads();
+
+    const double Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
+    const double iLx = S.ibox[0], iLy = S.ibox[1], iLz = S.ibox[2];
+    double fxi = 0, fyi = 0, fzi = 0;
+    double e0 = 0, e1 = 0;            // atom: LJ, Coulomb; electron: pp
+    double g0 = 0, g1 = 0;            // theta partials (pp: q_e, a; atom: eps, sigma)
+    int cnt = 0;
+    // the triangle of a group with itself: j-bead index must exceed i's
+    const long long jmin = bk.same ? idx - it.j0 : -1;
+
+    if (bk.kind == PK_ATOM) {
+        const double rc2_lj = rc_lj * rc_lj, rc2_c = rc_c * rc_c;
+        const double rc2max = fmax(rc2_lj, rc2_c);
+        const R rl2 = (R)rc2_lj, rcc2 = (R)rc2_c;
+        const R irc = (R)(1.0 / rc_c);
+        const R irc3 = (R)(1.0 / (rc_c * rc_c * rc_c));
+        const double kqi = kCoulombKcal * qi;
+        const int trow = ti * nt1;
+        const R th_eps = (R)th[2], th_sig = (R)th[3];
+        for (int t = 0; t < kPairTile; ++t) {
+            const int jj = (lane + t) & (kPairTile - 1);
+            double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
+            dx -= Lx * rint(dx * iLx);
+            dy -= Ly * rint(dy * iLy);
+            dz -= Lz * rint(dz * iLz);
+            const double r2d = dx * dx + dy * dy + dz * dz;
+            const bool ok = vi && jj < jn && jj > jmin && mi != sm[jj] && r2d < rc2max;
+            if (ok) {
+                const R r2 = (R)r2d;
+                const int tp = trow + st[jj];
+                const R e4 = t_e4[tp];
+                const R ir2 = rcp_r<R>(r2);
+                const R s2 = t_s2[tp] * ir2;
+                const R s6 = s2 * s2 * s2;
+                const R s12 = s6 * s6;
+                const bool in_lj = r2d < rc2_lj && e4 != (R)0;
+                const R c1l = t_c1[tp];
+                const R vlj = e4 * (s12 - s6) - t_c0[tp] - (R)0.5 * (r2 - rl2) * c1l;
+                const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
+                const R K = (R)(kqi * sq[jj]);
+                const bool in_c = r2d < rc2_c && K != (R)0;
+                const R ir = rsqrt_r<R>(r2);
+                const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
+                const R gc = K * (ir * ir * ir - irc3);
+                R g = (R)0;
+                if (in_lj) { e0 += (double)vlj; g += glj; }
+                if (in_c) { e1 += (double)vc; g += gc; }
+                cnt += (in_lj || in_c) ? 1 : 0;
+                if (THETA && tp == 0 && in_lj) {
+                    // d/d eps and d/d sigma of the (0,0) LJ term
+                    const R c6 = t_s2[0] / rl2;
+                    const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
+                    g0 += (double)(vlj / th_eps);
+                    const R fs = (R)4 * th_eps / th_sig;
+                    g1 += (double)(fs * ((R)12 * s12 - (R)6 * s6) - fs * ((R)12 * c12c - (R)6 * c6c) -
+                                   (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2);
+                }
+                const double gd = (double)g;
+                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+                fxi += fx;
+                fyi += fy;
+                fzi += fz;
+                atomicAdd(&fjx[jj], -fx);
+                atomicAdd(&fjy[jj], -fy);
+                atomicAdd(&fjz[jj], -fz);
+            }
+        }
+    } else {
+        // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom
+        const double rc = S.rc_pp, rc2 = rc * rc;
+        const double pa = th[1], a2 = pa * pa, pq = th[0];
+        const double u_c = rc2 + a2;
+        const R phic = (R)(1.0 / sqrt(u_c));
+        const R psic = (R)(-1.0 / (u_c * sqrt(u_c)));
+        const R chic = (R)(1.0 / (u_c * u_c * sqrt(u_c)));
+        const R ra2 = (R)a2, rrc2 = (R)rc2, rpa = (R)pa;
+        const bool e_is_i = bk.kind == PK_E_ATOM;
+        for (int t = 0; t < kPairTile; ++t) {
+            const int jj = (lane + t) & (kPairTile - 1);
+            double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
+            dx -= Lx * rint(dx * iLx);
+            dy -= Ly * rint(dy * iLy);
+            dz -= Lz * rint(dz * iLz);
+            const double r2d = dx * dx + dy * dy + dz * dz;
+            const bool ok = vi && jj < jn && jj > jmin && mi != sm[jj] && r2d < rc2;
+            if (ok) {
+                const R r2 = (R)r2d;
+                const R kq = (R)(kCoulombKcal * (e_is_i ? sq[jj] : qi));
+                const R ir = rsqrt_r<R>(r2 + ra2);
+                const R ir3 = ir * ir * ir;
+                const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
+                const R gq = kq * (ir3 + psic);
+                e0 += pq * (double)vq;
+                cnt += 1;
+                if (THETA) {
+                    g0 += (double)vq;
+                    g1 += pq * (double)(kq * (-rpa * ir3 - rpa * psic -
+                                              (R)1.5 * rpa * (r2 - rrc2) * chic));
+                }
+                const double gd = pq * (double)gq;
+                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+                fxi += fx;
+                fyi += fy;
+                fzi += fz;
+                atomicAdd(&fjx[jj], -fx);
+                atomicAdd(&fjy[jj], -fy);
+                atomicAdd(&fjz[jj], -fz);
+            }
+        }
+    }
+    __syncthreads();
+
+    const double w = bk.w;
+    if (vi) {
+        unsafeAtomicAdd(&a.f[3 * rowi], w * fxi);
+        unsafeAtomicAdd(&a.f[3 * rowi + 1], w * fyi);
+        unsafeAtomicAdd(&a.f[3 * rowi + 2], w * fzi);
+    }
+    if (lane < jn) {
+        unsafeAtomicAdd(&a.f[3 * rowj], w * fjx[lane]);
+        unsafeAtomicAdd(&a.f[3 * rowj + 1], w * fjy[lane]);
+        unsafeAtomicAdd(&a.f[3 * rowj + 2], w * fjz[lane]);
+    }
+    e0 = wave_sum(e0);
+    e1 = wave_sum(e1);
+    cnt = wave_sum_i(cnt);
+    if (THETA) {
+        g0 = wave_sum(g0);
+        g1 = wave_sum(g1);
+    }
+    if (lane == 0) {
+        double *acc = acc_row(a.eacc, bk.sys, blockIdx.x);
+        if (bk.kind == PK_ATOM) {
+            unsafeAtomicAdd(&acc[A_LJ], w * e0);
+            unsafeAtomicAdd(&acc[A_COUL], w * e1);
+            if (THETA) {
+                unsafeAtomicAdd(&acc[A_TH2], w * g0);
+                unsafeAtomicAdd(&acc[A_TH3], w * g1);
+            }
+        } else {
+            unsafeAtomicAdd(&acc[A_PP], w * e0);
+            if (THETA) {
+                unsafeAtomicAdd(&acc[A_TH0], w * g0);
+                unsafeAtomicAdd(&acc[A_TH1], w * g1);
+            }
+        }
+        if (cnt)
+            atomicAdd(&a.npairs[(bk.kind == PK_ATOM ? 0 : kAccCopies) + blockIdx.x % kAccCopies],
+                      (unsigned long long)cnt);
+    }
+}
+
+void launch_pair(const PairLaunch &a, int precision, bool with_theta, hipStream_t st)
+{
+    if (a.n_items <= 0) return;
+    dim3 grid(a.n_items), block(kPairTile);
+    if (precision == 0) {
+        if (with_theta) hipLaunchKernelGGL((k_pair<double, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_pair<double, false>), grid, block, 0, st, a);
+    } else {
+        if (with_theta) hipLaunchKernelGGL((k_pair<float, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_pair<float, false>), grid, block, 0, st, a);
+    }
+}
+
+}  // namespace mixpi

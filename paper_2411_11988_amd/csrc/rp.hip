@@ -1,0 +1,266 @@
+// Free ring polymers in normal modes (arXiv 2411.11988, Sec. "Evaluation":
+// the free ring-polymer part of the split propagator is integrated exactly
+// in the ring-polymer normal modes; Eq. mts-hamiltonian-b gives each
+// particle its own bead count N_i and spring constant N_i m_i/(beta hbar)^2).
+//
+// One launch processes every group of every system:
+//   * groups with N <= 64: "dense" items.  A workgroup holds 256/N columns
+//     (particle x Cartesian component) of the [N][n][3] block in LDS with the
+//     orthonormal basis C and C^T; thread (column, mode) forms the mode,
+//     propagates it, and thread (column, bead) transforms back.  Global
+//     loads and stores run column-fastest (coalesced).
+//   * groups with N > 64 (a many-bead electron): one workgroup per column,
+//     a radix-2 FP64 FFT in LDS.  q and p are packed as one complex signal
+//     q + i p; the real basis C follows from the FFT of a real signal
+//     (mode 0 and N/2 from the real parts, cos mode m from Re Z_m, sin mode
+//     N - m from Im Z_m, scaled by sqrt(2/N)), so the result equals the dense
+//     transform up to rounding with O(N log N) work instead of O(N^2).
+//
+// OP_STEP fuses: first half-kick p += dt/2 F on load, forward transform,
+// exact propagation of every mode with tabulated coefficients
+// (xi, pi) <- (a xi + b pi, c xi + d pi), spring energy sum_k k lambda_k/2
+// xi_k^2 and centroids of the new positions from mode 0, backward transform,
+// store of q and p, and zeroing of F for the force accumulation that follows.
+#include "mixpi_internal.h"
+
+namespace mixpi {
+
+__device__ __forceinline__ double bsum256(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+__device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, double *red)
+{
+    const int N = it.N, n = it.n;
+    const int CB = 256 / N;
+    const int tid = threadIdx.x;
+    double *sC = smem;              // C[j*N + k]
+    double *sCT = sC + N * N;       // C^T[k*N + j]
+    double *s0 = sCT + N * N;       // [N][CB]
+    double *s1 = s0 + 256;
+    double *s2 = s1 + 256;
+    double *s3 = s2 + 256;
+    const double *Cg = a.basis + it.basis_off;
+    for (int i = tid; i < 2 * N * N; i += 256) sC[i] = Cg[i];
+
+    const double hk = a.sys[it.sys].hkick;
+    {   // stage: column fastest
+        const int r = tid / CB, cl = tid % CB;
+        double v0 = 0.0, v1 = 0.0;
+        if (cl < it.ncols) {
+            const long long g = (it.row + (long long)r * n) * 3 + it.c0 + cl;
+            v0 = a.in_q[g];
+            if (a.op == OP_STEP) v1 = a.p[g] + hk * a.f[g];
+        }
+        if (a.op == OP_BWD) s2[r * CB + cl] = v0;
+        else { s0[r * CB + cl] = v0; s1[r * CB + cl] = v1; }
+    }
+    __syncthreads();
+
+    const int cl = tid % CB, k = tid / CB;
+    const bool valid = cl < it.ncols;
+    const int c = it.c0 + cl;
+    double esp = 0.0;
+    if (a.op != OP_BWD) {
+        double xi = 0.0, pi = 0.0;
+        for (int j = 0; j < N; ++j) {
+            const double cjk = sC[j * N + k];
+            xi += cjk * s0[j * CB + cl];
+            pi += cjk * s1[j * CB + cl];
+        }
+        if (a.op == OP_FWD) {
+            if (valid) a.out_q[(it.row + (long long)k * n) * 3 + c] = xi;
+            return;
+        }
+        if (valid) {
+            const int i = c / 3, d = c - 3 * i;
+            const double *pr = a.prop + 5 * (it.row + (long long)k * n + i);
+            const double x2 = pr[0] * xi + pr[1] * pi;
+            const double p2 = pr[2] * xi + pr[3] * pi;
+            xi = x2;
+            pi = p2;
+            esp = pr[4] * x2 * x2;
+            if (k == 0) a.cent[3LL * (it.p0 + i) + d] = x2 / sqrt((double)N);
+        }
+        s2[k * CB + cl] = xi;
+        s3[k * CB + cl] = pi;
+        __syncthreads();
+    }
+    // backward: thread (column, bead j = k)
+    const int j = k;
+    double qn = 0.0, pn = 0.0;
+    for (int m = 0; m < N; ++m) {
+        const double cjm = sCT[m * N + j];
+        qn += cjm * s2[m * CB + cl];
+        if (a.op == OP_STEP) pn += cjm * s3[m * CB + cl];
+    }
+    if (valid) {
+        const long long g = (it.row + (long long)j * n) * 3 + c;
+        a.out_q[g] = qn;
+        if (a.op == OP_STEP) {
+            a.p[g] = pn;
+            a.f[g] = 0.0;
+        }
+    }
+    if (a.op == OP_STEP) {
+        const double s = bsum256(esp, red);
+        if (tid == 0 && s != 0.0)
+            unsafeAtomicAdd(&acc_row(a.eacc, it.sys, blockIdx.x)[A_SPRING], s);
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 x, double2 y)
+{
+    return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+
+// In-place radix-2 decimation-in-time FFT (exp(-2 pi i jk/N)) of a
+// bit-reversed-order input held in LDS.
+__device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
+{
+    for (int s = 1; s <= L; ++s) {
+        const int half = 1 << (s - 1);
+        __syncthreads();
+        for (int b = threadIdx.x; b < N / 2; b += blockDim.x) {
+            const int grp = b >> (s - 1), pos = b & (half - 1);
+            const int i0 = (grp << s) + pos, i1 = i0 + half;
+            const double2 w = tw[pos << (L - s)];
+            const double2 u = z[i0];
+            const double2 v = cmul(z[i1], w);
+            z[i0] = make_double2(u.x + v.x, u.y + v.y);
+            z[i1] = make_double2(u.x - v.x, u.y - v.y);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int brev(int j, int L) { return (int)(__brev((unsigned)j) >> (32 - L)); }
+
+__device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *red)
+{
+    const int N = it.N, L = it.logN, n = it.n;
+    const int col = it.c0, i = col / 3, d = col - 3 * i;
+    const double2 *tw = a.twiddle + it.tw_off;
+    const int tid = threadIdx.x;
+    const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
+    const double hk = a.sys[it.sys].hkick;
+    auto gaddr = [&](int j) { return (it.row + (long long)j * n) * 3 + col; };
+
+    if (a.op == OP_BWD) {
+        // modes -> Hermitian spectrum Z; load conj(Z) in bit-reversed order
+        for (int m = tid; m <= N / 2; m += blockDim.x) {
+            if (m == 0 || 2 * m == N) {
+                z[brev(m, L)] = make_double2(rN * a.in_q[gaddr(m)], 0.0);
+            } else {
+                const double x1 = a.in_q[gaddr(m)], x2 = a.in_q[gaddr(N - m)];
+                // Z_m = sqrt(N/2) (xi_m + i xi_{N-m}), Z_{N-m} = conj(Z_m)
+                z[brev(m, L)] = make_double2(rN2 * x1, -rN2 * x2);       // conj(Z_m)
+                z[brev(N - m, L)] = make_double2(rN2 * x1, rN2 * x2);    // conj(Z_{N-m})
+            }
+        }
+        fft_stages(z, tw, N, L);
+        for (int j = tid; j < N; j += blockDim.x) a.out_q[gaddr(j)] = z[j].x / N;
+        return;
+    }
+
+    for (int j = tid; j < N; j += blockDim.x) {
+        const long long g = gaddr(j);
+        const double re = a.in_q[g];
+        const double im = a.op == OP_STEP ? a.p[g] + hk * a.f[g] : 0.0;
+        z[brev(j, L)] = make_double2(re, im);
+    }
+    fft_stages(z, tw, N, L);
+
+    if (a.op == OP_FWD) {
+        for (int m = tid; m <= N / 2; m += blockDim.x) {
+            const double2 Z = z[m];
+            if (m == 0 || 2 * m == N) {
+                a.out_q[gaddr(m)] = Z.x / rN;
+            } else {
+                a.out_q[gaddr(m)] = r2N * Z.x;
+                a.out_q[gaddr(N - m)] = r2N * Z.y;
+            }
+        }
+        return;
+    }
+
+    // OP_STEP: unpack q and p modes, propagate, repack z = Zq' + i Zp'
+    double esp = 0.0;
+    const double *prop = a.prop;
+    auto prow = [&](int k) { return prop + 5 * (it.row + (long long)k * n + i); };
+    for (int m = tid; m <= N / 2; m += blockDim.x) {
+        const double2 Zm = z[m];
+        const double2 Zc = make_double2(z[(N - m) & (N - 1)].x, -z[(N - m) & (N - 1)].y);
+        const double Qr = 0.5 * (Zm.x + Zc.x), Qi = 0.5 * (Zm.y + Zc.y);
+        const double Dr = Zm.x - Zc.x, Di = Zm.y - Zc.y;
+        const double Pr = 0.5 * Di, Pi = -0.5 * Dr;        // (Zm - Zc) / (2i)
+        if (m == 0 || 2 * m == N) {
+            const double *pr = prow(m);
+            const double x = Qr / rN, y = Pr / rN;
+            const double x2 = pr[0] * x + pr[1] * y, y2 = pr[2] * x + pr[3] * y;
+            esp += pr[4] * x2 * x2;
+            if (m == 0) a.cent[3LL * (it.p0 + i) + d] = x2 / rN;
+            z[m] = make_double2(rN * x2, rN * y2);
+        } else {
+            const double *p1 = prow(m), *p2 = prow(N - m);
+            const double x1 = r2N * Qr, x2 = r2N * Qi;
+            const double y1 = r2N * Pr, y2 = r2N * Pi;
+            const double x1n = p1[0] * x1 + p1[1] * y1, y1n = p1[2] * x1 + p1[3] * y1;
+            const double x2n = p2[0] * x2 + p2[1] * y2, y2n = p2[2] * x2 + p2[3] * y2;
+            esp += p1[4] * x1n * x1n + p2[4] * x2n * x2n;
+            // Zq' = sqrt(N/2) (x1 + i x2), Zp' = sqrt(N/2) (y1 + i y2); z = Zq' + i Zp'
+            z[m] = make_double2(rN2 * (x1n - y2n), rN2 * (x2n + y1n));
+            z[N - m] = make_double2(rN2 * (x1n + y2n), rN2 * (y1n - x2n));
+        }
+    }
+    __syncthreads();
+    // inverse transform as conj(FFT(conj(z))) / N: conjugate and bit-reverse
+    for (int j = tid; j < N; j += blockDim.x) {
+        const int r = brev(j, L);
+        if (j < r) {
+            const double2 u = z[j], v = z[r];
+            z[j] = make_double2(v.x, -v.y);
+            z[r] = make_double2(u.x, -u.y);
+        } else if (j == r) {
+            z[j].y = -z[j].y;
+        }
+    }
+    fft_stages(z, tw, N, L);
+    const double iN = 1.0 / N;
+    for (int j = tid; j < N; j += blockDim.x) {
+        const long long g = gaddr(j);
+        a.out_q[g] = z[j].x * iN;
+        a.p[g] = -z[j].y * iN;
+        a.f[g] = 0.0;
+    }
+    const double s = bsum256(esp, red);
+    if (tid == 0 && s != 0.0) unsafeAtomicAdd(&acc_row(a.eacc, it.sys, blockIdx.x)[A_SPRING], s);
+}
+
+__global__ __launch_bounds__(256) void k_rp(RpLaunch a)
+{
+    extern __shared__ __align__(16) double smem[];
+    __shared__ double red[4];
+    const RpItem it = a.items[blockIdx.x];
+    if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);
+    else rp_fft(a, it, reinterpret_cast<double2 *>(smem), red);
+}
+
+const void *rp_kernel_symbol() { return (const void *)k_rp; }
+
+void launch_rp(const RpLaunch &a, hipStream_t st)
+{
+    if (a.n_items <= 0) return;
+    hipLaunchKernelGGL(k_rp, dim3(a.n_items), dim3(256), a.lds_bytes, st, a);
+}
+
+}  // namespace mixpi

@@ -1,0 +1,142 @@
+"""GPU parity of the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Tolerances (per evaluation on identical inputs):
+  FP64 form: bead forces within 1e-12 x RMS(F), energies 1e-12 relative.
+  FP32 form: bead forces within 1e-5 x RMS(F), energies 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import dev, energy_err, force_err, from_rows, host, layout_rows, to_rows
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL_F = {FP64: 1e-12, FP32: 1e-5}
+TOL_E = {FP64: 1e-12, FP32: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def mp():
+    from paper_2411_11988_amd import mixpi
+    mixpi.load()
+    return mixpi
+
+
+def _systems():
+    out = [("tiny%d" % k, synth.tiny_random(k)) for k in range(4)]
+    out.append(("tiny-wide", synth.tiny_random(9, n_particles=90, box=14.0,
+                                                 bead_choices=(1, 2, 4, 8, 16))))
+    out.append(("c1", synth.config_c1()))
+    out.append(("water-h8-o2", synth.water_box(40, 11.0, 8, 2, seed=4, rc=5.4)))
+    out.append(("e256-water", synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4,
+                                                      rc_aa=6.0, n_h=2, n_o=1)))
+    return out
+
+
+SYSTEMS = _systems()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("name,s", SYSTEMS, ids=[n for n, _ in SYSTEMS])
+def test_forces_match_oracle(mp, name, s, prec):
+    print(f"[forces] {name} prec={prec}", flush=True)
+    sysm = mp.System(s, precision=prec)
+    rows = layout_rows(s)
+    assert np.array_equal(sysm.bead_index, rows)
+    q = dev(to_rows(s, s.q, rows))
+    f, e = sysm.forces(q)
+    F = from_rows(s, host(f), rows)
+    Fo, eo = oracle.OracleSystem(s).forces(s.q)
+    assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
+    assert energy_err(host(e)[0], eo) <= TOL_E[prec], (host(e)[0], eo)
+
+
+@pytest.mark.parametrize("name,s", SYSTEMS[4:], ids=[n for n, _ in SYSTEMS[4:]])
+def test_energy_matches_forces_call(mp, name, s):
+    sysm = mp.System(s)
+    q = dev(to_rows(s, s.q))
+    _, e1 = sysm.forces(q)
+    e2 = sysm.energy(q)
+    assert np.allclose(host(e1), host(e2), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096])
+def test_nm_transform_matches_oracle(mp, N):
+    print(f"[nm] N={N}", flush=True)
+    rng = np.random.default_rng(N)
+    n = 3 if N > 64 else 37
+    s = synth.tiny_random(1, n_particles=n, bead_choices=(N,), with_electron=False)
+    s.q = rng.normal(size=s.q.shape)
+    sysm = mp.System(s)
+    o = oracle.OracleSystem(s)
+    rows = layout_rows(s)
+    x = dev(to_rows(s, s.q, rows))
+    fwd = from_rows(s, host(sysm.nm_transform(x, +1)), rows)
+    want = o.nm_transform(s.q, +1)
+    assert np.abs(fwd - want).max() <= 1e-12 * np.abs(want).max()
+    bwd = from_rows(s, host(sysm.nm_transform(x, -1)), rows)
+    want = o.nm_transform(s.q, -1)
+    assert np.abs(bwd - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def _step_compare(mp, s, prec, nsteps, tol_q, tol_p, tol_e):
+    sysm = mp.System(s, precision=prec)
+    o = oracle.OracleSystem(s)
+    rows = layout_rows(s)
+    Fo0, _ = o.forces(s.q)
+    q = dev(to_rows(s, s.q, rows))
+    p = dev(to_rows(s, s.p, rows))
+    f = dev(to_rows(s, Fo0, rows))
+    import torch
+    elog = torch.zeros((nsteps, 1, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+    sysm.step(nsteps, q, p, f, elog)
+    qo, po, Fo, elo = o.step(s.q, s.p, nsteps, F=Fo0)
+    qg, pg = from_rows(s, host(q), rows), from_rows(s, host(p), rows)
+    el = host(elog)[:, 0, :]
+    dq = np.abs(qg - qo).max()
+    dp = np.abs(pg - po).max() / np.abs(po).max()
+    de = max(energy_err(el[k], elo[k]) for k in range(nsteps))
+    assert dq <= tol_q, dq
+    assert dp <= tol_p, dp
+    assert de <= tol_e, (de, el[-1], elo[-1])
+    return sysm, q, p, f
+
+
+@pytest.mark.parametrize("name,s", [SYSTEMS[0], SYSTEMS[5], SYSTEMS[6], SYSTEMS[7]],
+                         ids=["tiny0", "c1", "water-h8-o2", "e256-water"])
+def test_one_step_fp64(mp, name, s):
+    print(f"[step64] {name}", flush=True)
+    _step_compare(mp, s, FP64, 1, 1e-12, 1e-11, 1e-11)
+
+
+def test_c1_twenty_steps_fp64(mp):
+    print("[step64] c1 x20", flush=True)
+    _step_compare(mp, synth.config_c1(), FP64, 20, 1e-10, 1e-9, 1e-9)
+
+
+@pytest.mark.parametrize("name,s", [SYSTEMS[5], SYSTEMS[6]], ids=["c1", "water-h8-o2"])
+def test_one_step_fp32(mp, name, s):
+    print(f"[step32] {name}", flush=True)
+    _step_compare(mp, s, FP32, 1, 1e-12, 1e-6, 1e-5)
+
+
+def test_pair_counts(mp):
+    s = synth.config_c1()
+    sysm = mp.System(s)
+    n = s.n_particles
+    cand = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if s.mol_id[i] == s.mol_id[j] or (s.is_electron[i] and s.is_electron[j]):
+                continue
+            cand += max(s.n_beads[i], s.n_beads[j])
+    assert sysm.pair_candidates() == cand
+    sysm.pair_evals(reset=True)
+    q = dev(to_rows(s, s.q))
+    sysm.forces(q)
+    ev = sysm.pair_evals()
+    assert ev == oracle.OracleSystem(s).pair_evals(s.q)
+    assert 0 < ev[0] + ev[1] <= cand and ev[1] > 0
