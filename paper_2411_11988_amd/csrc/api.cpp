@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -76,32 +77,46 @@ struct mixpi_system {
     int n_sys = 0;
     int precision = 0, flags = 0;
     long long rows = 0;
-    int n_part = 0;
-    int n_groups = 0;
+    int n_part = 0, n_groups = 0;
     long long candidates = 0;
     std::vector<long long> bead_index;
+    int pair_tj = 64;
 
     SysDev *d_sys = nullptr;
-    double *d_lj_eps = nullptr, *d_lj_sig = nullptr;
-    double *d_charge = nullptr, *d_fm = nullptr;
-    int *d_ljt = nullptr, *d_mol = nullptr, *d_part_sys = nullptr, *d_row_part = nullptr;
+    double *d_lj_eps = nullptr, *d_lj_sig = nullptr, *d_charge = nullptr;
+    int *d_ljt = nullptr, *d_mol = nullptr, *d_row_sys = nullptr;
+    double *d_row_fm = nullptr, *d_row_hk = nullptr;
+    // pair sweep: items on fast groups first, then items touching FFT groups
     PairBlock *d_blocks = nullptr;
     PairItem *d_items = nullptr;
-    int n_items = 0;
-    BondTerm *d_bonds = nullptr;
-    int n_bonds = 0;
-    AngleTerm *d_angles = nullptr;
-    int n_angles = 0;
+    int n_items = 0, n_items_fast = 0;
+    // bonded sweep: terms and system-pure blocks of 256 (fast blocks first)
+    BondedTerm *d_bterms = nullptr;
+    BlockRange *d_bblocks = nullptr;
+    int n_bblocks = 0, n_bblocks_fast = 0;
     double *d_bond_k = nullptr, *d_bond_r0 = nullptr, *d_angle_k = nullptr, *d_angle_t0 = nullptr;
+    // normal modes: dense items first, then FFT items
     RpItem *d_rp = nullptr;
-    int n_rp = 0;
+    int n_rp = 0, n_rp_fast = 0;
     unsigned rp_lds = 0;
     double *d_basis = nullptr;
     double2 *d_tw = nullptr;
     double *d_prop = nullptr;
-    double *d_eacc = nullptr;
+    // partial forces and their per-row gather lists
+    long long *d_row_ptr = nullptr;
+    int *d_slot = nullptr;
+    double *d_part = nullptr;
+    long long n_slots = 0, part_bonded = 0;
+    // epilogue blocks (4 rows of one system)
+    BlockRange *d_fblocks = nullptr;
+    int n_fblocks = 0;
+    // energy slots (two buffers, alternating by step): pair items | bonded
+    // blocks | normal-mode items | epilogue blocks; per-system slot lists for
+    // the force-only range and for the whole step
+    double *d_eslot = nullptr;
+    int *d_order_f = nullptr, *d_sysptr_f = nullptr, *d_order_a = nullptr, *d_sysptr_a = nullptr;
+    int n_eslots = 0, e_bonded = 0, e_rp = 0, e_fin = 0;
     unsigned long long *d_npairs = nullptr;
-    unsigned *d_ticket = nullptr;
     int *d_nonfinite = nullptr;
     double *d_cent = nullptr;
     double *d_scratch = nullptr;
@@ -118,11 +133,13 @@ void release(mixpi_system *s)
         (void)hipGraphExecDestroy(g.exec);
         (void)hipGraphDestroy(g.graph);
     }
-    void *ptrs[] = {s->d_sys, s->d_lj_eps, s->d_lj_sig, s->d_charge, s->d_fm, s->d_ljt,
-                    s->d_mol, s->d_part_sys, s->d_row_part, s->d_blocks, s->d_items,
-                    s->d_bonds, s->d_angles, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
-                    s->d_angle_t0, s->d_rp, s->d_basis, s->d_tw, s->d_prop, s->d_eacc,
-                    s->d_npairs, s->d_ticket, s->d_nonfinite, s->d_cent, s->d_scratch};
+    void *ptrs[] = {s->d_sys, s->d_lj_eps, s->d_lj_sig, s->d_charge, s->d_ljt, s->d_mol,
+                    s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items,
+                    s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
+                    s->d_angle_t0, s->d_rp, s->d_basis, s->d_tw, s->d_prop, s->d_row_ptr,
+                    s->d_slot, s->d_part, s->d_fblocks, s->d_eslot, s->d_order_f,
+                    s->d_sysptr_f, s->d_order_a, s->d_sysptr_a,
+                    s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -210,17 +227,18 @@ int validate(const mixpi_system_desc *d, int idx)
 // Host tables being assembled for all systems of a handle.
 struct Build {
     std::vector<SysDev> sys;
-    std::vector<double> lj_eps, lj_sig, charge, fm, bond_k, bond_r0, angle_k, angle_t0;
-    std::vector<int> ljt, mol, part_sys, row_part;
+    std::vector<double> lj_eps, lj_sig, charge, bond_k, bond_r0, angle_k, angle_t0;
+    std::vector<int> ljt, mol, row_part, row_sys;
+    std::vector<double> row_fm, row_hk;
     std::vector<PairBlock> blocks;
-    std::vector<PairItem> items;
-    std::vector<BondTerm> bonds;
-    std::vector<AngleTerm> angles;
+    std::vector<char> block_slow;              // block touches an FFT group
+    std::vector<BondedTerm> bterms, bterms_slow;
     std::vector<RpItem> rp_fft, rp_dense;
     std::vector<double> basis, prop;
     std::vector<double2> tw;
     std::map<int, int> basis_off, tw_off;
     std::vector<long long> bead_index;
+    std::vector<std::pair<long long, long long>> sys_rows;   // [begin, end) per system
     long long rows = 0;
     long long candidates = 0;
     int n_part = 0, n_groups = 0;
@@ -300,10 +318,8 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
     }
     for (int i = 0; i < n; ++i) {
         B.charge.push_back(d->charge[i]);
-        B.fm.push_back(d->fict_mass[i]);
         B.ljt.push_back(d->lj_type[i] < 0 ? nt : d->lj_type[i]);
         B.mol.push_back(d->mol_id[i]);
-        B.part_sys.push_back(s);
     }
 
     // groups: maximal runs of equal bead count and electron flag
@@ -329,18 +345,22 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         }
     }
     std::vector<long long> rows_of(beads);
-    B.row_part.resize(row - 0, -1);
+    B.row_part.resize(row, -1);
+    B.row_sys.resize(row, s);
+    B.row_fm.resize(row, 0.0);
+    B.row_hk.resize(row, S.hkick);
     for (const Group &g : groups)
         for (int a = 0; a < g.N; ++a)
             for (int i = 0; i < g.n; ++i) {
                 const long long r = g.row + (long long)a * g.n + i;
                 rows_of[part_first[g.p0 + i] + a] = r;
                 B.row_part[r] = p_base + g.p0 + i;
+                B.row_fm[r] = d->fict_mass[g.p0 + i];
             }
     B.bead_index.insert(B.bead_index.end(), rows_of.begin(), rows_of.end());
     auto bead_row = [&](int i, int a) { return rows_of[part_first[i] + a]; };
 
-    // nonbonded pair blocks and 64 x 64 tiles
+    // nonbonded pair blocks (tiles are cut later, once the tile width is known)
     for (size_t ga = 0; ga < groups.size(); ++ga)
         for (size_t gb = ga; gb < groups.size(); ++gb) {
             const Group &A = groups[ga], &Bg = groups[gb];
@@ -357,15 +377,9 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
             pb.rowa = A.row;
             pb.rowb = Bg.row;
             pb.w = 1.0 / A.N;
-            const int bi = (int)B.blocks.size();
+            pb.nbeads_b = Bg.N;
+            B.block_slow.push_back(A.N > kDenseMaxN || Bg.N > kDenseMaxN);
             B.blocks.push_back(pb);
-            const long long li = (long long)A.n << pb.shift;
-            for (int b = 0; b < Bg.N; ++b)
-                for (long long i0 = 0; i0 < li; i0 += kPairTile)
-                    for (int j0 = 0; j0 < Bg.n; j0 += kPairTile) {
-                        if (pb.same && j0 < i0) continue;
-                        B.items.push_back(PairItem{bi, b, (int)i0, j0});
-                    }
             const long long pairs = pb.same ? (long long)A.n * (A.n - 1) / 2 : (long long)A.n * Bg.n;
             B.candidates += pairs * A.N;
         }
@@ -382,24 +396,40 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         }
     }
 
-    // bonded terms: one entry per (term, slice), beads resolved here
+    // bonded terms: one entry per (term, slice), beads resolved here;
+    // terms whose slices reach an FFT group go to the "slow" list
     for (int b = 0; b < d->n_bonds; ++b) {
         const int i = d->bonds[2 * b], j = d->bonds[2 * b + 1];
         const int Ni = d->n_beads[i], Nj = d->n_beads[j], Nm = std::max(Ni, Nj);
-        for (int sl = 0; sl < Nm; ++sl)
-            B.bonds.push_back(BondTerm{(int)bead_row(i, (int)((long long)sl * Ni / Nm)),
-                                       (int)bead_row(j, (int)((long long)sl * Nj / Nm)),
-                                       S.bond_off + d->bond_type[b], s, 1.0 / Nm});
+        auto &dst = Nm > kDenseMaxN ? B.bterms_slow : B.bterms;
+        for (int sl = 0; sl < Nm; ++sl) {
+            BondedTerm t{};
+            t.r[0] = (int)bead_row(i, (int)((long long)sl * Ni / Nm));
+            t.r[1] = (int)bead_row(j, (int)((long long)sl * Nj / Nm));
+            t.r[2] = t.r[1];
+            t.type = S.bond_off + d->bond_type[b];
+            t.kind = 0;
+            t.sys = s;
+            t.w = 1.0 / Nm;
+            dst.push_back(t);
+        }
     }
     for (int a = 0; a < d->n_angles; ++a) {
         const int i = d->angles[3 * a], v = d->angles[3 * a + 1], j = d->angles[3 * a + 2];
         const int Ni = d->n_beads[i], Nv = d->n_beads[v], Nj = d->n_beads[j];
         const int Nm = std::max(Ni, std::max(Nv, Nj));
-        for (int sl = 0; sl < Nm; ++sl)
-            B.angles.push_back(AngleTerm{(int)bead_row(i, (int)((long long)sl * Ni / Nm)),
-                                         (int)bead_row(v, (int)((long long)sl * Nv / Nm)),
-                                         (int)bead_row(j, (int)((long long)sl * Nj / Nm)),
-                                         S.angle_off + d->angle_type[a], s, 0, 1.0 / Nm});
+        auto &dst = Nm > kDenseMaxN ? B.bterms_slow : B.bterms;
+        for (int sl = 0; sl < Nm; ++sl) {
+            BondedTerm t{};
+            t.r[0] = (int)bead_row(i, (int)((long long)sl * Ni / Nm));
+            t.r[1] = (int)bead_row(v, (int)((long long)sl * Nv / Nm));
+            t.r[2] = (int)bead_row(j, (int)((long long)sl * Nj / Nm));
+            t.type = S.angle_off + d->angle_type[a];
+            t.kind = 1;
+            t.sys = s;
+            t.w = 1.0 / Nm;
+            dst.push_back(t);
+        }
     }
 
     // normal modes: propagator coefficients per (mode row, particle)
@@ -475,11 +505,105 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 it.tw_off = B.tw_off[N];
                 B.rp_fft.push_back(it);
             }
-            B.rp_lds = std::max(B.rp_lds, (unsigned)(N * sizeof(double2)));
+            B.rp_lds = std::max(B.rp_lds, (unsigned)(3 * N / 2 * sizeof(double2)));
         }
     }
+    B.sys_rows.push_back({row_base, row});
     B.rows = row;
     B.n_part += n;
+}
+
+// Cuts the pair blocks with block_slow == slow into 64 x tj tiles: for each
+// j-bead b, i-tiles of 64 beads of the contiguous i-run times j-tiles of tj
+// particles (upper triangle only for a group with itself).
+std::vector<PairItem> pair_items(const std::vector<PairBlock> &blocks,
+                                 const std::vector<char> &block_slow, bool slow, int tj)
+{
+    std::vector<PairItem> items;
+    for (size_t bi = 0; bi < blocks.size(); ++bi) {
+        if ((bool)block_slow[bi] != slow) continue;
+        const PairBlock &pb = blocks[bi];
+        const long long li = (long long)pb.na << pb.shift;
+        for (int b = 0; b < pb.nbeads_b; ++b)
+            for (long long i0 = 0; i0 < li; i0 += 64)
+                for (int j0 = 0; j0 < pb.nb; j0 += tj) {
+                    if (pb.same && j0 < i0) continue;
+                    items.push_back(PairItem{(int)bi, b, (int)i0, j0});
+                }
+    }
+    return items;
+}
+
+// Tile width of the pair sweep: 64-wide j-tiles unless that leaves the
+// chip with fewer than about two waves per SIMD (1024 SIMDs), then 32.
+int choose_tj(const std::vector<PairBlock> &blocks, const std::vector<char> &block_slow)
+{
+    const size_t n64 = pair_items(blocks, block_slow, false, 64).size() +
+                       pair_items(blocks, block_slow, true, 64).size();
+    return n64 < 2048 ? 32 : 64;
+}
+
+// Workgroup ranges over a list sorted by system: chunks of at most `per`
+// entries that never span two systems.
+std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin, int end, int per)
+{
+    std::vector<BlockRange> out;
+    int i = begin;
+    while (i < end) {
+        int j = i;
+        while (j < end && j - i < per && sys_of[j] == sys_of[i]) ++j;
+        out.push_back(BlockRange{sys_of[i], i, j - i, 0});
+        i = j;
+    }
+    return out;
+}
+
+// Partial-force slots and the per-row gather lists.  Slot numbering: pair
+// item k owns slots k*(64+tj) + [0, 64) for its i-beads and + 64 + [0, tj)
+// for its j-beads; bonded term t owns part_bonded + 3t + (0, 1, 2) for its
+// beads r[0], r[1] (and r[2] of an angle).  Rows list their slots in this
+// order, so every gather sums in a fixed order.
+struct Gather {
+    std::vector<long long> row_ptr;
+    std::vector<int> slot;
+    long long n_slots = 0;
+};
+
+Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
+                    const std::vector<PairItem> &items, int tj,
+                    const std::vector<BondedTerm> &terms, long long part_bonded)
+{
+    Gather G;
+    std::vector<long long> cnt(rows + 1, 0);
+    auto visit = [&](auto &&emit) {
+        for (size_t k = 0; k < items.size(); ++k) {
+            const PairItem &it = items[k];
+            const PairBlock &pb = blocks[it.block];
+            const long long li = (long long)pb.na << pb.shift;
+            const long long base = (long long)k * (64 + tj);
+            for (int l = 0; l < 64; ++l) {
+                const long long idx = (long long)it.i0 + l;
+                if (idx < li) emit(pb.rowa + ((long long)it.b << pb.shift) * pb.na + idx, base + l);
+            }
+            const int jn = std::min(tj, pb.nb - it.j0);
+            for (int l = 0; l < jn; ++l)
+                emit(pb.rowb + (long long)it.b * pb.nb + it.j0 + l, base + 64 + l);
+        }
+        for (size_t t = 0; t < terms.size(); ++t) {
+            const long long b = part_bonded + 3 * (long long)t;
+            emit(terms[t].r[0], b);
+            emit(terms[t].r[1], b + 1);
+            if (terms[t].kind == 1) emit(terms[t].r[2], b + 2);
+        }
+        return part_bonded + 3 * (long long)terms.size();
+    };
+    G.n_slots = visit([&](long long row, long long) { ++cnt[row + 1]; });
+    for (long long r = 0; r < rows; ++r) cnt[r + 1] += cnt[r];
+    G.row_ptr = cnt;
+    G.slot.resize(cnt[rows]);
+    std::vector<long long> fill(cnt.begin(), cnt.end() - 1);
+    visit([&](long long row, long long sl) { G.slot[fill[row]++] = (int)sl; });
+    return G;
 }
 
 int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system **out)
@@ -487,6 +611,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     if (!out) return fail(MIXPI_E_INVALID, "out is null");
     *out = nullptr;
     if (!descs || n_sys < 1) return fail(MIXPI_E_INVALID, "need at least one system");
+    if (n_sys > kMaxSystems)
+        return fail(MIXPI_E_UNSUPPORTED, "at most %d systems per handle", kMaxSystems);
     for (int s = 0; s < n_sys; ++s) {
         int rc = validate(descs[s], s);
         if (rc) return rc;
@@ -499,10 +625,6 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         return fail(MIXPI_E_UNSUPPORTED, "too many beads (%lld)", B.rows);
 
     mixpi_system *S = new mixpi_system();
-    int rc = MIXPI_OK;
-    auto T = [&](int r) {
-        if (r && !rc) rc = r;
-    };
     if (hipGetDevice(&S->device) != hipSuccess) {
         delete S;
         return fail(MIXPI_E_HIP, "hipGetDevice failed (no GPU?)");
@@ -515,27 +637,98 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->n_groups = B.n_groups;
     S->candidates = B.candidates;
     S->bead_index = B.bead_index;
-    S->n_items = (int)B.items.size();
-    S->n_bonds = (int)B.bonds.size();
-    S->n_angles = (int)B.angles.size();
-    std::vector<RpItem> rp = B.rp_fft;
-    rp.insert(rp.end(), B.rp_dense.begin(), B.rp_dense.end());
+
+    // pair items: fast groups first, then items touching an FFT group
+    S->pair_tj = choose_tj(B.blocks, B.block_slow);
+    if (const char *env = getenv("MIXPI_PAIR_TJ")) {
+        const int v = atoi(env);
+        if (v == 32 || v == 64) S->pair_tj = v;
+    }
+    std::vector<PairItem> items = pair_items(B.blocks, B.block_slow, false, S->pair_tj);
+    S->n_items_fast = (int)items.size();
+    {
+        auto slow = pair_items(B.blocks, B.block_slow, true, S->pair_tj);
+        items.insert(items.end(), slow.begin(), slow.end());
+    }
+    S->n_items = (int)items.size();
+
+    // bonded terms and their system-pure blocks
+    std::vector<BondedTerm> terms = B.bterms;
+    const int n_terms_fast = (int)terms.size();
+    terms.insert(terms.end(), B.bterms_slow.begin(), B.bterms_slow.end());
+    std::vector<int> term_sys(terms.size());
+    for (size_t t = 0; t < terms.size(); ++t) term_sys[t] = terms[t].sys;
+    std::vector<BlockRange> bblocks = system_blocks(term_sys, 0, n_terms_fast, 64);
+    S->n_bblocks_fast = (int)bblocks.size();
+    {
+        auto slow = system_blocks(term_sys, n_terms_fast, (int)terms.size(), 64);
+        bblocks.insert(bblocks.end(), slow.begin(), slow.end());
+    }
+    S->n_bblocks = (int)bblocks.size();
+
+    // normal-mode items: dense first, then FFT
+    std::vector<RpItem> rp = B.rp_dense;
+    S->n_rp_fast = (int)rp.size();
+    rp.insert(rp.end(), B.rp_fft.begin(), B.rp_fft.end());
     S->n_rp = (int)rp.size();
     S->rp_lds = B.rp_lds;
 
+    // epilogue blocks: 4 rows of one system
+    std::vector<BlockRange> fblocks;
+    for (int s = 0; s < n_sys; ++s)
+        for (long long r = B.sys_rows[s].first; r < B.sys_rows[s].second; r += 4)
+            fblocks.push_back(BlockRange{s, (int)r, (int)std::min<long long>(4, B.sys_rows[s].second - r), 0});
+    S->n_fblocks = (int)fblocks.size();
+
+    // partial-force slots
+    S->part_bonded = (long long)S->n_items * (64 + S->pair_tj);
+    Gather G = build_gather(B.rows, B.blocks, items, S->pair_tj, terms, S->part_bonded);
+    if (G.n_slots > (1LL << 31) - 1) {
+        delete S;
+        return fail(MIXPI_E_UNSUPPORTED, "too many partial-force slots (%lld)", G.n_slots);
+    }
+    S->n_slots = G.n_slots;
+
+    // energy slots and their systems
+    S->e_bonded = S->n_items;
+    S->e_rp = S->e_bonded + S->n_bblocks;
+    S->e_fin = S->e_rp + S->n_rp;
+    S->n_eslots = S->e_fin + S->n_fblocks;
+    std::vector<int> eslot_sys(S->n_eslots);
+    for (int k = 0; k < S->n_items; ++k) eslot_sys[k] = B.blocks[items[k].block].sys;
+    for (int b = 0; b < S->n_bblocks; ++b) eslot_sys[S->e_bonded + b] = bblocks[b].sys;
+    for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
+    for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
+    // per-system slot lists (stable order) for the reducer
+    auto group_by_system = [&](int n, std::vector<int> &order, std::vector<int> &ptr) {
+        ptr.assign(n_sys + 1, 0);
+        for (int k = 0; k < n; ++k) ++ptr[eslot_sys[k] + 1];
+        for (int x = 0; x < n_sys; ++x) ptr[x + 1] += ptr[x];
+        order.resize(n);
+        std::vector<int> fillp(ptr.begin(), ptr.end() - 1);
+        for (int k = 0; k < n; ++k) order[fillp[eslot_sys[k]]++] = k;
+    };
+    std::vector<int> order_f, sysptr_f, order_a, sysptr_a;
+    group_by_system(S->e_rp, order_f, sysptr_f);
+    group_by_system(S->n_eslots, order_a, sysptr_a);
+
+    int rc = MIXPI_OK;
+    auto T = [&](int r) {
+        if (r && !rc) rc = r;
+    };
     T(upload(&S->d_sys, B.sys));
     T(upload(&S->d_lj_eps, B.lj_eps));
     T(upload(&S->d_lj_sig, B.lj_sig));
     T(upload(&S->d_charge, B.charge));
-    T(upload(&S->d_fm, B.fm));
     T(upload(&S->d_ljt, B.ljt));
     T(upload(&S->d_mol, B.mol));
-    T(upload(&S->d_part_sys, B.part_sys));
-    T(upload(&S->d_row_part, B.row_part));
+    T(upload(&S->d_row_sys, B.row_sys));
+    T(upload(&S->d_row_fm, B.row_fm));
+    T(upload(&S->d_row_hk, B.row_hk));
     T(upload(&S->d_blocks, B.blocks));
-    T(upload(&S->d_items, B.items));
-    T(upload(&S->d_bonds, B.bonds));
-    T(upload(&S->d_angles, B.angles));
+    T(upload(&S->d_items, items));
+    T(upload(&S->d_bterms, terms));
+    T(upload(&S->d_bblocks, bblocks));
     T(upload(&S->d_bond_k, B.bond_k));
     T(upload(&S->d_bond_r0, B.bond_r0));
     T(upload(&S->d_angle_k, B.angle_k));
@@ -544,11 +737,18 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_basis, B.basis));
     T(upload(&S->d_tw, B.tw));
     T(upload(&S->d_prop, B.prop));
-    T(upload(&S->d_eacc, std::vector<double>((size_t)n_sys * kAccCopies * A_N, 0.0)));
-    T(upload(&S->d_npairs, std::vector<unsigned long long>(2 * kAccCopies, 0ull)));
-    T(upload(&S->d_ticket, std::vector<unsigned>(1, 0u)));
+    T(upload(&S->d_row_ptr, G.row_ptr));
+    T(upload(&S->d_slot, G.slot));
+    T(upload(&S->d_part, std::vector<double>((size_t)3 * std::max<long long>(G.n_slots, 1), 0.0)));
+    T(upload(&S->d_fblocks, fblocks));
+    T(upload(&S->d_eslot, std::vector<double>((size_t)2 * A_N * std::max(S->n_eslots, 1), 0.0)));
+    T(upload(&S->d_order_f, order_f));
+    T(upload(&S->d_sysptr_f, sysptr_f));
+    T(upload(&S->d_order_a, order_a));
+    T(upload(&S->d_sysptr_a, sysptr_a));
+    T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
-    T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.n_part, 0.0)));
+    T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
     T(upload(&S->d_scratch, std::vector<double>((size_t)9 * B.rows, 0.0)));
     if (!rc) {
         hipError_t e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
@@ -575,11 +775,19 @@ int check_sys(const mixpi_system *s)
     return MIXPI_OK;
 }
 
-PairLaunch pair_args(mixpi_system *s, const double *q, double *f, const double *theta)
+enum Part { ALL = 0, FAST = 1, SLOW = 2 };
+
+double *eslot_buf(mixpi_system *s, int buf) { return s->d_eslot + (long long)buf * s->n_eslots * A_N; }
+
+PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int buf = 0,
+                     Part part = ALL)
 {
     PairLaunch a{};
-    a.items = s->d_items;
-    a.n_items = s->n_items;
+    const int lo = part == SLOW ? s->n_items_fast : 0;
+    const int hi = part == FAST ? s->n_items_fast : s->n_items;
+    a.items = s->d_items + lo;
+    a.n_items = hi - lo;
+    a.tj = s->pair_tj;
     a.blocks = s->d_blocks;
     a.sys = s->d_sys;
     a.lj_eps = s->d_lj_eps;
@@ -588,39 +796,62 @@ PairLaunch pair_args(mixpi_system *s, const double *q, double *f, const double *
     a.ljt = s->d_ljt;
     a.mol = s->d_mol;
     a.q = q;
-    a.f = f;
+    a.part = s->d_part;
+    a.item0 = lo;
     a.theta = theta;
-    a.eacc = s->d_eacc;
-    a.npairs = s->d_npairs;
+    a.eslot = eslot_buf(s, buf);
     return a;
 }
 
-BondedLaunch bonded_args(mixpi_system *s, const double *q, double *f, const double *theta)
+BondedLaunch bonded_args(mixpi_system *s, const double *q, const double *theta, int buf = 0,
+                         Part part = ALL)
 {
     BondedLaunch b{};
-    b.bonds = s->d_bonds;
-    b.n_bonds = s->n_bonds;
-    b.angles = s->d_angles;
-    b.n_angles = s->n_angles;
+    const int lo = part == SLOW ? s->n_bblocks_fast : 0;
+    const int hi = part == FAST ? s->n_bblocks_fast : s->n_bblocks;
+    b.terms = s->d_bterms;
+    b.blocks = s->d_bblocks + lo;
+    b.n_blocks = hi - lo;
     b.sys = s->d_sys;
     b.bond_k = s->d_bond_k;
     b.bond_r0 = s->d_bond_r0;
     b.angle_k = s->d_angle_k;
     b.angle_t0 = s->d_angle_t0;
     b.q = q;
-    b.f = f;
+    b.part = s->d_part;
+    b.part_base = s->part_bonded;
     b.theta = theta;
-    b.eacc = s->d_eacc;
+    b.eslot = eslot_buf(s, buf) + (long long)(s->e_bonded + lo) * A_N;
     return b;
 }
 
-// Enqueues F(q) (zeroed first) and the potential accumulators.
+GatherArgs gather_args(mixpi_system *s)
+{
+    return GatherArgs{s->d_row_ptr, s->d_slot, s->d_part};
+}
+
+// Reducer over buffer buf: the force-only slots (pair + bonded) or the
+// slots of a whole step.
+ReduceLaunch reduce_args(mixpi_system *s, int buf, bool whole_step)
+{
+    ReduceLaunch r{};
+    r.eslot = eslot_buf(s, buf);
+    r.order = whole_step ? s->d_order_a : s->d_order_f;
+    r.sys_ptr = whole_step ? s->d_sysptr_a : s->d_sysptr_f;
+    r.sys = s->d_sys;
+    r.n_sys = s->n_sys;
+    r.npairs = s->d_npairs;
+    r.nonfinite = s->d_nonfinite;
+    return r;
+}
+
+// Enqueues F(q): pair and bonded partials, then the per-row gather into f.
+// The energy slots of the pair and bonded ranges are left for a reducer.
 void enqueue_forces(mixpi_system *s, const double *q, const double *theta, double *f,
                     bool with_theta, hipStream_t st)
 {
-    launch_fill(f, 3 * s->rows, 0.0, st);
-    launch_pair(pair_args(s, q, f, theta), s->precision, with_theta, st);
-    launch_bonded(bonded_args(s, q, f, theta), with_theta, st);
+    launch_pair(pair_args(s, q, theta), bonded_args(s, q, theta), s->precision, with_theta, st);
+    launch_gather(gather_args(s), s->rows, f, st);
 }
 
 int last_launch_error()
@@ -630,55 +861,64 @@ int last_launch_error()
     return MIXPI_OK;
 }
 
-RpLaunch rp_step_args(mixpi_system *s, double *q, double *p, double *f)
+RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double *p, double *f,
+                 int buf = 0, Part part = ALL)
 {
     RpLaunch r{};
-    r.items = s->d_rp;
-    r.n_items = s->n_rp;
+    const int lo = part == SLOW ? s->n_rp_fast : 0;
+    const int hi = part == FAST ? s->n_rp_fast : s->n_rp;
+    r.items = s->d_rp + lo;
+    r.n_items = hi - lo;
     r.sys = s->d_sys;
     r.basis = s->d_basis;
     r.twiddle = s->d_tw;
     r.prop = s->d_prop;
-    r.op = OP_STEP;
-    r.in_q = q;
-    r.out_q = q;
+    r.op = op;
+    r.in_q = in;
+    r.out_q = out;
     r.p = p;
     r.f = f;
     r.cent = s->d_cent;
-    r.eacc = s->d_eacc;
+    r.eslot = eslot_buf(s, buf) + (long long)(s->e_rp + lo) * A_N;
     r.lds_bytes = s->rp_lds;
     return r;
 }
 
-FinishLaunch finish_args(mixpi_system *s, double *q, double *p, double *f, double *elog_row)
+FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f, int buf = 0)
 {
     FinishLaunch fl{};
-    fl.n3 = 3 * s->rows;
-    fl.row_part = s->d_row_part;
-    fl.part_sys = s->d_part_sys;
-    fl.fm = s->d_fm;
-    fl.sys = s->d_sys;
-    fl.n_sys = s->n_sys;
+    fl.blocks = s->d_fblocks;
+    fl.n_blocks = s->n_fblocks;
+    fl.gather = gather_args(s);
+    fl.row_fm = s->d_row_fm;
+    fl.row_hk = s->d_row_hk;
     fl.p = p;
     fl.f = f;
     fl.q = q;
     fl.cent = s->d_cent;
-    fl.eacc = s->d_eacc;
-    fl.elog = elog_row;
-    fl.ticket = s->d_ticket;
-    fl.nonfinite = s->d_nonfinite;
+    fl.eslot = eslot_buf(s, buf) + (long long)s->e_fin * A_N;
     return fl;
 }
 
-// One step: free ring polymers (with the first half-kick and F := 0), pair
-// and bonded forces, second half-kick with the energy-log row.
-void enqueue_step(mixpi_system *s, double *q, double *p, double *f, double *elog_row,
+// Step k of a sequence: free ring polymers (with the first half-kick; one
+// extra workgroup reduces the energies of step k-1 into its log row), pair
+// and bonded partial forces, epilogue (gather F, second half-kick, kinetic
+// sums).  Steps alternate between the two energy-slot buffers so that the
+// reducer of step k-1 never meets the writers of step k.
+void enqueue_step(mixpi_system *s, int k, double *q, double *p, double *f, double *elog_prev,
                   hipStream_t st)
 {
-    launch_rp(rp_step_args(s, q, p, f), st);
-    launch_pair(pair_args(s, q, f, nullptr), s->precision, false, st);
-    launch_bonded(bonded_args(s, q, f, nullptr), false, st);
-    launch_finish(finish_args(s, q, p, f, elog_row), st);
+    const int buf = k & 1;
+    RpLaunch r = rp_args(s, OP_STEP, q, q, p, f, buf);
+    if (k > 0) {
+        r.with_reduce = 1;
+        r.reduce = reduce_args(s, buf ^ 1, true);
+        r.reduce.elog = elog_prev;
+    }
+    launch_rp(r, st);
+    launch_pair(pair_args(s, q, nullptr, buf), bonded_args(s, q, nullptr, buf), s->precision,
+                false, st);
+    launch_finish(finish_args(s, q, p, f, buf), st);
 }
 
 // Finds or captures the graph of nsteps steps for these pointers.
@@ -703,10 +943,15 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
         sys->graphs.erase(sys->graphs.begin());
     }
     GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr};
+    auto row = [&](int k) { return elog ? elog + (size_t)k * sys->n_sys * MIXPI_NE : nullptr; };
     HIP_TRY(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < nsteps; ++k)
-        enqueue_step(sys, q, p, f, elog ? elog + (size_t)k * sys->n_sys * MIXPI_NE : nullptr,
-                     sys->cap_stream);
+        enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream);
+    {
+        ReduceLaunch r = reduce_args(sys, (nsteps - 1) & 1, true);
+        r.elog = row(nsteps - 1);
+        launch_reduce(r, sys->cap_stream);
+    }
     HIP_TRY(hipStreamEndCapture(sys->cap_stream, &g.graph));
     hipError_t e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -772,7 +1017,9 @@ int mixpi_forces(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     enqueue_forces(sys, q, theta, f, false, st);
-    launch_write_energy(sys->d_sys, sys->n_sys, sys->d_eacc, e_out, st);
+    ReduceLaunch r = reduce_args(sys, 0, false);
+    r.e_out = e_out;
+    launch_reduce(r, st);
     return last_launch_error();
 }
 
@@ -783,8 +1030,10 @@ int mixpi_energy(mixpi_system *sys, const double *q, const double *theta, double
     if (!q || !e_out) return fail(MIXPI_E_INVALID, "q and e_out must be non-null");
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
-    enqueue_forces(sys, q, theta, sys->d_scratch, false, st);
-    launch_write_energy(sys->d_sys, sys->n_sys, sys->d_eacc, e_out, st);
+    launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, false, st);
+    ReduceLaunch r = reduce_args(sys, 0, false);
+    r.e_out = e_out;
+    launch_reduce(r, st);
     return last_launch_error();
 }
 
@@ -796,10 +1045,15 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
     if ((const void *)q == (const void *)dq) return fail(MIXPI_E_INVALID, "dq must not alias q");
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
-    double *target = dq ? dq : sys->d_scratch;
-    enqueue_forces(sys, q, theta, target, true, st);
-    launch_adjoint_finish(sys->d_sys, sys->n_sys, sys->rows, sys->d_row_part, sys->d_part_sys,
-                          grad_e, dq, sys->d_eacc, dtheta, st);
+    launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, true, st);
+    if (dq) {
+        launch_gather(gather_args(sys), sys->rows, dq, st);
+        launch_scale_rows(sys->rows, sys->d_row_sys, grad_e, dq, st);
+    }
+    ReduceLaunch r = reduce_args(sys, 0, false);
+    r.dtheta = dtheta;
+    r.grad_e = grad_e;
+    launch_reduce(r, st);
     return last_launch_error();
 }
 
@@ -811,18 +1065,8 @@ int mixpi_nm_transform(mixpi_system *sys, int32_t dir, const double *in, double 
     if (!in || !out) return fail(MIXPI_E_INVALID, "in and out must be non-null");
     if ((const void *)in == (const void *)out) return fail(MIXPI_E_INVALID, "out must not alias in");
     HIP_TRY(hipSetDevice(sys->device));
-    RpLaunch r{};
-    r.items = sys->d_rp;
-    r.n_items = sys->n_rp;
-    r.sys = sys->d_sys;
-    r.basis = sys->d_basis;
-    r.twiddle = sys->d_tw;
-    r.prop = sys->d_prop;
-    r.op = dir > 0 ? OP_FWD : OP_BWD;
-    r.in_q = in;
-    r.out_q = out;
-    r.lds_bytes = sys->rp_lds;
-    launch_rp(r, (hipStream_t)stream);
+    launch_rp(rp_args(sys, dir > 0 ? OP_FWD : OP_BWD, in, out, nullptr, nullptr),
+              (hipStream_t)stream);
     return last_launch_error();
 }
 
@@ -872,10 +1116,15 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t which, int32_t reps, const doub
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
     for (int r = 0; r < reps; ++r) {
-        if (which == 0) launch_pair(pair_args(sys, sq, sf, nullptr), sys->precision, false, st);
-        else if (which == 1) launch_bonded(bonded_args(sys, sq, sf, nullptr), false, st);
-        else if (which == 2) launch_rp(rp_step_args(sys, sq, sp, sf), st);
-        else launch_finish(finish_args(sys, sq, sp, sf, nullptr), st);
+        if (which <= 1) {
+            PairLaunch pa = pair_args(sys, sq, nullptr);
+            BondedLaunch ba = bonded_args(sys, sq, nullptr);
+            if (which == 0) ba.n_blocks = 0;
+            else pa.n_items = 0;
+            launch_pair(pa, ba, sys->precision, false, st);
+        }
+        else if (which == 2) launch_rp(rp_args(sys, OP_STEP, sq, sq, sp, sf), st);
+        else launch_finish(finish_args(sys, sq, sp, sf), st);
     }
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
@@ -884,9 +1133,6 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t which, int32_t reps, const doub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_us = 1000.0 * ms / reps;
-    // leave the accumulators and counters as they were before the call
-    launch_write_energy(sys->d_sys, sys->n_sys, sys->d_eacc, nullptr, st);
-    HIP_TRY(hipStreamSynchronize(st));
     return last_launch_error();
 }
 
@@ -903,14 +1149,12 @@ int mixpi_pair_evals(mixpi_system *sys, int64_t *evals, int32_t reset, void *str
     if (int rc = check_sys(sys)) return rc;
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
-    unsigned long long h[2 * kAccCopies];
+    unsigned long long h[2];
     HIP_TRY(hipMemcpyAsync(h, sys->d_npairs, sizeof h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    unsigned long long tot[2] = {0, 0};
-    for (int c = 0; c < 2 * kAccCopies; ++c) tot[c / kAccCopies] += h[c];
     if (evals) {
-        evals[0] = (int64_t)tot[0];
-        evals[1] = (int64_t)tot[1];
+        evals[0] = (int64_t)h[0];
+        evals[1] = (int64_t)h[1];
     }
     if (reset) {
         HIP_TRY(hipMemsetAsync(sys->d_npairs, 0, sizeof h, st));

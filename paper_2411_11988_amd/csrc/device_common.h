@@ -1,0 +1,187 @@
+// Device helpers shared by the kernels: wave/workgroup sums, the bonded
+// sweep of one workgroup and the energy reducer.
+#pragma once
+
+#include "mixpi.h"
+#include "mixpi_internal.h"
+
+namespace mixpi {
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over the workgroup (blockDim.x a multiple of 64), valid in
+// thread 0.  red: LDS scratch of blockDim.x / 64 doubles.
+__device__ __forceinline__ double bsum(double v, double *red)
+{
+    v = wsum(v);
+    if (blockDim.x == 64) return v;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+__device__ __forceinline__ void min_img(double &x, double L, double iL) { x -= L * rint(x * iL); }
+
+// Bonds and angles of V_mix (Eq. mts-hamiltonian, 2- and 3-body terms) for
+// the terms of one workgroup (a system-pure range of at most blockDim.x
+// terms): one thread per (term, slice); the slice's beads were resolved on
+// the host, so a thread sees plain bead rows and the weight 1/N_max.  FP64
+// throughout: bonded terms are stiff and cheap.  Forces go to the term's own
+// partial-force slots (summed later by the per-row gather); the energy sums
+// go to the workgroup's energy slot `e`.
+template <bool THETA>
+__device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double *e, double *red)
+{
+    const SysDev &S = a.sys[br.sys];
+    const double *th = a.theta ? a.theta + 6 * br.sys : S.theta0;
+    const int t = br.begin + threadIdx.x;
+    double eb = 0, ea = 0, gb = 0, ga = 0;
+    if ((int)threadIdx.x < br.count) {
+        const BondedTerm bt = a.terms[t];
+        double *slot = a.part + 3 * (a.part_base + 3LL * t);
+        if (bt.kind == 0) {
+            const bool t0 = bt.type == S.bond_off;
+            const double k = t0 ? th[4] : a.bond_k[bt.type];
+            const double r0 = a.bond_r0[bt.type];
+            double d[3];
+            for (int c = 0; c < 3; ++c) {
+                d[c] = a.q[3LL * bt.r[0] + c] - a.q[3LL * bt.r[1] + c];
+                min_img(d[c], S.box[c], S.ibox[c]);
+            }
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double dr = r - r0;
+            eb = bt.w * 0.5 * k * dr * dr;
+            if (THETA && t0) gb = bt.w * 0.5 * dr * dr;
+            const double g = -bt.w * k * dr / r;
+            for (int c = 0; c < 3; ++c) {
+                slot[c] = g * d[c];
+                slot[3 + c] = -g * d[c];
+            }
+        } else {
+            const bool t0 = bt.type == S.angle_off;
+            const double k = t0 ? th[5] : a.angle_k[bt.type];
+            const double th0 = a.angle_t0[bt.type];
+            double r1[3], r2[3];
+            for (int c = 0; c < 3; ++c) {
+                r1[c] = a.q[3LL * bt.r[0] + c] - a.q[3LL * bt.r[1] + c];
+                r2[c] = a.q[3LL * bt.r[2] + c] - a.q[3LL * bt.r[1] + c];
+                min_img(r1[c], S.box[c], S.ibox[c]);
+                min_img(r2[c], S.box[c], S.ibox[c]);
+            }
+            const double l1 = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+            const double l2 = sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+            double c = (r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2]) / (l1 * l2);
+            c = fmin(1.0, fmax(-1.0, c));
+            const double dth = acos(c) - th0;
+            ea = bt.w * 0.5 * k * dth * dth;
+            if (THETA && t0) ga = bt.w * 0.5 * dth * dth;
+            const double s = sqrt(1.0 - c * c);
+            const double pref = bt.w * k * dth / s;
+            const double i12 = 1.0 / (l1 * l2), i11 = 1.0 / (l1 * l1), i22 = 1.0 / (l2 * l2);
+            for (int x = 0; x < 3; ++x) {
+                const double fa = pref * (r2[x] * i12 - c * r1[x] * i11);
+                const double fb = pref * (r1[x] * i12 - c * r2[x] * i22);
+                slot[x] = fa;              // end a
+                slot[3 + x] = -(fa + fb);  // vertex
+                slot[6 + x] = fb;          // end b
+            }
+        }
+    }
+    eb = bsum(eb, red);
+    ea = bsum(ea, red);
+    if (THETA) {
+        gb = bsum(gb, red);
+        ga = bsum(ga, red);
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+        e[A_BOND] = eb;
+        e[A_ANGLE] = ea;
+        e[A_TH4] = gb;
+        e[A_TH5] = ga;
+    }
+}
+
+// Energies of system s from its summed slot row r: writes the requested
+// outputs and adds its pair-evaluation counts (exact integers in FP64).
+__device__ inline void energy_outputs(const ReduceLaunch &a, int s, const double *r)
+{
+    const SysDev &S = a.sys[s];
+    double e[MIXPI_NE];
+    e[MIXPI_E_LJ] = r[A_LJ];
+    e[MIXPI_E_COUL] = r[A_COUL] + S.bg_energy;
+    e[MIXPI_E_PP] = r[A_PP];
+    e[MIXPI_E_BOND] = r[A_BOND];
+    e[MIXPI_E_ANGLE] = r[A_ANGLE];
+    e[MIXPI_E_VMIX] = e[1] + e[2] + e[3] + e[4] + e[5];
+    e[MIXPI_E_SPRING] = r[A_SPRING];
+    e[MIXPI_E_KIN] = r[A_KIN] / kKcal;
+    e[MIXPI_E_KCV] = S.cv_const - 0.5 * r[A_VIR];
+    e[MIXPI_E_KPRIM] = S.prim_const - r[A_SPRING];
+    e[MIXPI_E_HAM] = e[MIXPI_E_KIN] + e[MIXPI_E_SPRING] + e[MIXPI_E_VMIX];
+    if (a.e_out)
+        for (int k = 0; k < MIXPI_NV; ++k) a.e_out[(long long)s * MIXPI_NV + k] = e[k];
+    if (a.elog) {
+        for (int k = 0; k < MIXPI_NE; ++k) a.elog[(long long)s * MIXPI_NE + k] = e[k];
+        if (a.nonfinite && !isfinite(e[MIXPI_E_HAM])) atomicOr(a.nonfinite, 1);
+    }
+    if (a.dtheta) {
+        const double g = a.grad_e ? a.grad_e[s] : 1.0;
+        for (int k = 0; k < 6; ++k) a.dtheta[(long long)s * 6 + k] = g * r[A_TH0 + k];
+    }
+    if (a.npairs) {
+        if (r[A_CNT_AA] > 0.0) atomicAdd(&a.npairs[0], (unsigned long long)r[A_CNT_AA]);
+        if (r[A_CNT_EA] > 0.0) atomicAdd(&a.npairs[1], (unsigned long long)r[A_CNT_EA]);
+    }
+}
+
+// The energy reducer for one workgroup: the slots of each system (listed
+// by order[sys_ptr[s] .. sys_ptr[s+1])) are summed by whole waves, lanes
+// striding over the slots; with fewer systems than waves a system's list is
+// split among several waves and their sums meet in LDS (acc: >= 16 * A_N
+// doubles).
+__device__ inline void reduce_energies(const ReduceLaunch &a, double *acc)
+{
+    const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int S = a.n_sys >= W ? 1 : W / a.n_sys;
+    if (S > 1) {
+        for (int x = threadIdx.x; x < a.n_sys * A_N; x += blockDim.x) acc[x] = 0.0;
+        __syncthreads();
+    }
+    for (int u = w; u < a.n_sys * S; u += W) {
+        const int s = u / S, part = u - s * S;
+        const int b = a.sys_ptr[s], len = a.sys_ptr[s + 1] - b;
+        const int lo = b + (int)((long long)len * part / S);
+        const int hi = b + (int)((long long)len * (part + 1) / S);
+        double v[A_N];
+#pragma unroll
+        for (int k = 0; k < A_N; ++k) v[k] = 0.0;
+        for (int i = lo + lane; i < hi; i += 64) {
+            const double *e = a.eslot + (long long)a.order[i] * A_N;
+#pragma unroll
+            for (int k = 0; k < A_N; ++k) v[k] += e[k];
+        }
+#pragma unroll
+        for (int k = 0; k < A_N; ++k) v[k] = wsum(v[k]);
+        if (lane == 0) {
+            if (S == 1) energy_outputs(a, s, v);
+            else
+                for (int k = 0; k < A_N; ++k) atomicAdd(&acc[s * A_N + k], v[k]);
+        }
+    }
+    if (S > 1) {
+        __syncthreads();
+        for (int s = threadIdx.x; s < a.n_sys; s += blockDim.x) energy_outputs(a, s, acc + s * A_N);
+    }
+}
+
+}  // namespace mixpi

@@ -1,114 +1,100 @@
-// Bonded sweep, half-kick/estimator epilogue and small bookkeeping kernels.
+// Force gather, half-kick/estimator epilogue, energy reducer and small
+// bookkeeping kernels.
 #include "mixpi.h"
 #include "mixpi_internal.h"
+#include "device_common.h"
 
 namespace mixpi {
 
-__device__ __forceinline__ double wsum(double v)
+// ---------------------------------------------------------------------------
+// F[row] = sum over the row's partial-force slots, in the fixed CSR order
+// (so forces are reproducible bit for bit).  One wave per row: lane l takes
+// slots l, l + 64, ...; the wave then reduces the three components.
+struct Vec3 {
+    double x, y, z;
+};
+__device__ __forceinline__ Vec3 gather_row(const GatherArgs &g, long long row)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const int lane = threadIdx.x & 63;
+    double x = 0.0, y = 0.0, z = 0.0;
+    const long long e = g.row_ptr[row + 1];
+    for (long long k = g.row_ptr[row] + lane; k < e; k += 64) {
+        const double *p = g.part + 3LL * g.slot[k];
+        x += p[0];
+        y += p[1];
+        z += p[2];
+    }
+    return Vec3{wsum(x), wsum(y), wsum(z)};
 }
 
-// Adds v to slot of the accumulator row of `sys`: one atomic per wave when
-// every lane of the wave belongs to the same system (work lists are sorted
-// by system), one per lane otherwise.
-__device__ __forceinline__ void acc_add(double *eacc, int sys, int slot, double v)
+__global__ __launch_bounds__(256) void k_gather(GatherArgs g, long long rows, double *f)
 {
-    const int s0 = __shfl(sys, 0, 64);
-    const bool uniform = __all(sys == s0);
-    if (uniform) {
-        v = wsum(v);
-        if ((threadIdx.x & 63) == 0 && s0 >= 0 && v != 0.0)
-            unsafeAtomicAdd(&acc_row(eacc, s0, blockIdx.x)[slot], v);
-    } else if (sys >= 0 && v != 0.0) {
-        unsafeAtomicAdd(&acc_row(eacc, sys, blockIdx.x)[slot], v);
+    const long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= rows) return;   // whole waves leave together
+    const Vec3 v = gather_row(g, row);
+    if ((threadIdx.x & 63) == 0) {
+        f[3 * row] = v.x;
+        f[3 * row + 1] = v.y;
+        f[3 * row + 2] = v.z;
     }
 }
 
-__device__ __forceinline__ void min_img(double &x, double L, double iL) { x -= L * rint(x * iL); }
-
-// Bonds and angles of V_mix (Eq. mts-hamiltonian, 2- and 3-body terms): one
-// thread per (term, slice); the slice's beads were resolved on the host, so
-// a thread sees plain bead rows and the weight 1/N_max.  FP64 throughout:
-// bonded terms are stiff and cheap.
-template <bool THETA>
-__global__ __launch_bounds__(256) void k_bonded(BondedLaunch a)
+void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int sys = -1;
-    double eb = 0, ea = 0, gb = 0, ga = 0;
-    if (t < a.n_bonds) {
-        const BondTerm b = a.bonds[t];
-        sys = b.sys;
-        const SysDev &S = a.sys[sys];
-        const double *th = a.theta ? a.theta + 6 * sys : S.theta0;
-        const bool t0 = b.type == S.bond_off;
-        const double k = t0 ? th[4] : a.bond_k[b.type];
-        const double r0 = a.bond_r0[b.type];
-        double d[3];
-        for (int c = 0; c < 3; ++c) {
-            d[c] = a.q[3LL * b.ra + c] - a.q[3LL * b.rb + c];
-            min_img(d[c], S.box[c], S.ibox[c]);
-        }
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double dr = r - r0;
-        eb = b.w * 0.5 * k * dr * dr;
-        if (THETA && t0) gb = b.w * 0.5 * dr * dr;
-        const double g = -b.w * k * dr / r;
-        for (int c = 0; c < 3; ++c) {
-            unsafeAtomicAdd(&a.f[3LL * b.ra + c], g * d[c]);
-            unsafeAtomicAdd(&a.f[3LL * b.rb + c], -g * d[c]);
-        }
-    } else if (t < (long long)a.n_bonds + a.n_angles) {
-        const AngleTerm an = a.angles[t - a.n_bonds];
-        sys = an.sys;
-        const SysDev &S = a.sys[sys];
-        const double *th = a.theta ? a.theta + 6 * sys : S.theta0;
-        const bool t0 = an.type == S.angle_off;
-        const double k = t0 ? th[5] : a.angle_k[an.type];
-        const double th0 = a.angle_t0[an.type];
-        double r1[3], r2[3];
-        for (int c = 0; c < 3; ++c) {
-            r1[c] = a.q[3LL * an.ra + c] - a.q[3LL * an.rv + c];
-            r2[c] = a.q[3LL * an.rb + c] - a.q[3LL * an.rv + c];
-            min_img(r1[c], S.box[c], S.ibox[c]);
-            min_img(r2[c], S.box[c], S.ibox[c]);
-        }
-        const double l1 = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
-        const double l2 = sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
-        double c = (r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2]) / (l1 * l2);
-        c = fmin(1.0, fmax(-1.0, c));
-        const double dth = acos(c) - th0;
-        ea = an.w * 0.5 * k * dth * dth;
-        if (THETA && t0) ga = an.w * 0.5 * dth * dth;
-        const double s = sqrt(1.0 - c * c);
-        const double pref = an.w * k * dth / s;
-        const double i12 = 1.0 / (l1 * l2), i11 = 1.0 / (l1 * l1), i22 = 1.0 / (l2 * l2);
-        for (int x = 0; x < 3; ++x) {
-            const double fa = pref * (r2[x] * i12 - c * r1[x] * i11);
-            const double fb = pref * (r1[x] * i12 - c * r2[x] * i22);
-            unsafeAtomicAdd(&a.f[3LL * an.ra + x], fa);
-            unsafeAtomicAdd(&a.f[3LL * an.rb + x], fb);
-            unsafeAtomicAdd(&a.f[3LL * an.rv + x], -(fa + fb));
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, g, rows, f);
+}
+
+// ---------------------------------------------------------------------------
+// Second half-kick and per-step energies.  One wave per bead row (a
+// workgroup covers up to 4 rows of one system): F gathered from its partial
+// slots and stored, p += dt/2 F, then the kinetic energy p^2/(2 m_f) and the
+// centroid-virial term (q - qbar) . F summed into the workgroup's slot.
+__global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
+{
+    __shared__ double red[4];
+    const BlockRange br = a.blocks[blockIdx.x];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double ke = 0.0, vir = 0.0;
+    if (w < br.count) {
+        const long long row = (long long)br.begin + w;
+        const Vec3 fv = gather_row(a.gather, row);
+        if (lane < 3) {
+            const long long x = 3 * row + lane;
+            const double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
+            a.f[x] = fx;
+            const double pv = a.p[x] + a.row_hk[row] * fx;
+            a.p[x] = pv;
+            ke = pv * pv / (2.0 * a.row_fm[row]);
+            vir = (a.q[x] - a.cent[x]) * fx;
         }
     }
-    acc_add(a.eacc, sys, A_BOND, eb);
-    acc_add(a.eacc, sys, A_ANGLE, ea);
-    if (THETA) {
-        acc_add(a.eacc, sys, A_TH4, gb);
-        acc_add(a.eacc, sys, A_TH5, ga);
+    ke = bsum(ke, red);
+    vir = bsum(vir, red);
+    if (threadIdx.x == 0) {
+        double *e = a.eslot + (long long)blockIdx.x * A_N;
+        for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+        e[A_KIN] = ke;
+        e[A_VIR] = vir;
     }
 }
 
-void launch_bonded(const BondedLaunch &a, bool with_theta, hipStream_t st)
+void launch_finish(const FinishLaunch &a, hipStream_t st)
 {
-    const long long n = (long long)a.n_bonds + a.n_angles;
-    if (n <= 0) return;
-    dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    if (with_theta) hipLaunchKernelGGL((k_bonded<true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_bonded<false>), grid, block, 0, st, a);
+    if (a.n_blocks <= 0) return;
+    hipLaunchKernelGGL(k_finish, dim3(a.n_blocks), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_reduce(ReduceLaunch a)
+{
+    __shared__ double acc[16 * A_N];
+    reduce_energies(a, acc);
+}
+
+void launch_reduce(const ReduceLaunch &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,145 +114,23 @@ void launch_fill(double *x, long long n, double v, hipStream_t st)
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, x, n, v);
 }
 
-// Sums the accumulator copies of system s, slot k, and clears them.
-__device__ __forceinline__ double take(double *eacc, int s, int k)
-{
-    double v = 0.0;
-    for (int c = 0; c < kAccCopies; ++c) {
-        double *p = eacc + ((long long)s * kAccCopies + c) * A_N + k;
-        v += *p;
-        *p = 0.0;
-    }
-    return v;
-}
-
-__global__ void k_write_energy(const SysDev *sys, int n_sys, double *eacc, double *e_out)
-{
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
-        double e[MIXPI_NV];
-        e[MIXPI_E_LJ] = take(eacc, s, A_LJ);
-        e[MIXPI_E_COUL] = take(eacc, s, A_COUL) + sys[s].bg_energy;
-        e[MIXPI_E_PP] = take(eacc, s, A_PP);
-        e[MIXPI_E_BOND] = take(eacc, s, A_BOND);
-        e[MIXPI_E_ANGLE] = take(eacc, s, A_ANGLE);
-        e[MIXPI_E_VMIX] = e[1] + e[2] + e[3] + e[4] + e[5];
-        for (int k = A_SPRING; k < A_N; ++k) take(eacc, s, k);
-        if (e_out)
-            for (int k = 0; k < MIXPI_NV; ++k) e_out[(long long)s * MIXPI_NV + k] = e[k];
-    }
-}
-
-void launch_write_energy(const SysDev *sys, int n_sys, double *eacc, double *e_out,
-                         hipStream_t st)
-{
-    hipLaunchKernelGGL(k_write_energy, dim3((n_sys + 63) / 64), dim3(64), 0, st, sys, n_sys,
-                       eacc, e_out);
-}
-
-// dq <- -grad_e[sys] * dq (dq holds F on entry); dtheta <- grad_e * dV/dtheta.
-__global__ void k_adjoint_scale(long long rows, const int *row_part, const int *part_sys,
-                                const double *grad_e, double *dq)
+// dq <- -grad_e[sys] * dq (dq holds F on entry).
+__global__ void k_scale_rows(long long rows, const int *row_sys, const double *grad_e,
+                             double *dq)
 {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= 3 * rows) return;
-    const int s = part_sys[row_part[x / 3]];
+    const int s = row_sys[x / 3];
     const double g = grad_e ? grad_e[s] : 1.0;
     dq[x] = -g * dq[x];
 }
 
-__global__ void k_adjoint_theta(int n_sys, double *eacc, const double *grad_e, double *dtheta)
+void launch_scale_rows(long long rows, const int *row_sys, const double *grad_e, double *dq,
+                       hipStream_t st)
 {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
-        const double g = grad_e ? grad_e[s] : 1.0;
-        for (int k = 0; k < 6; ++k) {
-            const double v = take(eacc, s, A_TH0 + k);
-            if (dtheta) dtheta[(long long)s * 6 + k] = g * v;
-        }
-        for (int k = 0; k < A_TH0; ++k) take(eacc, s, k);
-        for (int k = A_TH5 + 1; k < A_N; ++k) take(eacc, s, k);
-    }
-}
-
-void launch_adjoint_finish(const SysDev *sys, int n_sys, long long rows, const int *row_part,
-                           const int *part_sys, const double *grad_e, double *dq,
-                           double *eacc, double *dtheta, hipStream_t st)
-{
-    (void)sys;
-    if (dq && rows > 0)
-        hipLaunchKernelGGL(k_adjoint_scale, dim3((unsigned)((3 * rows + 255) / 256)), dim3(256),
-                           0, st, rows, row_part, part_sys, grad_e, dq);
-    hipLaunchKernelGGL(k_adjoint_theta, dim3((n_sys + 63) / 64), dim3(64), 0, st, n_sys, eacc,
-                       grad_e, dtheta);
-}
-
-// ---------------------------------------------------------------------------
-// Second half-kick and per-step energies.  One thread per bead component:
-// p += dt/2 F, then the kinetic energy p^2/(2 m_f) and the centroid-virial
-// term (q - qbar) . F are summed per system.  The last workgroup to finish
-// (ticket) turns the accumulators into the energy-log row and clears them.
-__global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
-{
-    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int sys = -1;
-    double ke = 0.0, vir = 0.0;
-    if (x < a.n3) {
-        const long long row = x / 3;
-        const int d = (int)(x - 3 * row);
-        const int part = a.row_part[row];
-        sys = a.part_sys[part];
-        const double pv = a.p[x] + a.sys[sys].hkick * a.f[x];
-        a.p[x] = pv;
-        ke = pv * pv / (2.0 * a.fm[part]);
-        vir = (a.q[x] - a.cent[3LL * part + d]) * a.f[x];
-    }
-    acc_add(a.eacc, sys, A_KIN, ke);
-    acc_add(a.eacc, sys, A_VIR, vir);
-
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned tk = atomicAdd(a.ticket, 1u);
-        last = tk == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int s = threadIdx.x; s < a.n_sys; s += blockDim.x) {
-        const SysDev &S = a.sys[s];
-        double v[A_N];
-        for (int k = 0; k < A_N; ++k) {
-            double sum = 0.0;
-            for (int c = 0; c < kAccCopies; ++c) {
-                double *pp = a.eacc + ((long long)s * kAccCopies + c) * A_N + k;
-                unsigned long long old = atomicExch((unsigned long long *)pp, 0ull);
-                sum += __longlong_as_double((long long)old);
-            }
-            v[k] = sum;
-        }
-        double e[MIXPI_NE];
-        e[MIXPI_E_LJ] = v[A_LJ];
-        e[MIXPI_E_COUL] = v[A_COUL] + S.bg_energy;
-        e[MIXPI_E_PP] = v[A_PP];
-        e[MIXPI_E_BOND] = v[A_BOND];
-        e[MIXPI_E_ANGLE] = v[A_ANGLE];
-        e[MIXPI_E_VMIX] = e[1] + e[2] + e[3] + e[4] + e[5];
-        e[MIXPI_E_SPRING] = v[A_SPRING];
-        e[MIXPI_E_KIN] = v[A_KIN] / kKcal;
-        e[MIXPI_E_KCV] = S.cv_const - 0.5 * v[A_VIR];
-        e[MIXPI_E_KPRIM] = S.prim_const - v[A_SPRING];
-        e[MIXPI_E_HAM] = e[MIXPI_E_KIN] + e[MIXPI_E_SPRING] + e[MIXPI_E_VMIX];
-        if (!isfinite(e[MIXPI_E_HAM])) atomicOr(a.nonfinite, 1);
-        if (a.elog)
-            for (int k = 0; k < MIXPI_NE; ++k) a.elog[(long long)s * MIXPI_NE + k] = e[k];
-    }
-    if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
-}
-
-void launch_finish(const FinishLaunch &a, hipStream_t st)
-{
-    const long long blocks = (a.n3 + 255) / 256;
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, st, a);
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((3 * rows + 255) / 256)), dim3(256), 0, st,
+                       rows, row_sys, grad_e, dq);
 }
 
 }  // namespace mixpi

@@ -25,21 +25,16 @@ constexpr int kMaxLjTypes = 8;           // user types; one extra null type
 constexpr int kLjTab = (kMaxLjTypes + 1) * (kMaxLjTypes + 1);
 constexpr int kMaxBeads = 4096;
 constexpr int kDenseMaxN = 64;           // normal modes by dense basis up to N
-constexpr int kPairTile = 64;            // i and j tile of the pair kernel
 
-// per-system accumulator slots (device, FP64).  Each system owns
-// kAccCopies copies of the slot row; a workgroup adds into copy
-// blockIdx.x % kAccCopies so same-address atomics are spread out, and the
-// reader sums the copies.
+// Energy partials.  Every writer (pair tile, bonded block, normal-mode
+// item, epilogue block) owns one slot of A_N doubles and stores its sums
+// there; a one-block reducer adds the slots of each system in a fixed order
+// and writes the energies.  No atomics on shared addresses.
 enum {
     A_LJ = 0, A_COUL, A_PP, A_BOND, A_ANGLE, A_SPRING, A_KIN, A_VIR,
-    A_TH0, A_TH1, A_TH2, A_TH3, A_TH4, A_TH5, A_N = 16
+    A_TH0, A_TH1, A_TH2, A_TH3, A_TH4, A_TH5, A_CNT_AA, A_CNT_EA, A_N = 16
 };
-constexpr int kAccCopies = 16;
-__host__ __device__ inline double *acc_row(double *eacc, int sys, unsigned blk)
-{
-    return eacc + ((long long)sys * kAccCopies + (blk % kAccCopies)) * A_N;
-}
+constexpr int kMaxSystems = 1024;   // the reducer keeps one A_N row per system in LDS
 
 struct SysDev {
     double box[3], ibox[3];
@@ -66,19 +61,25 @@ struct PairBlock {
     int pa0, pb0;         // first global particle of a, b
     long long rowa, rowb; // first bead row of groups a, b
     double w;             // 1 / N_a
+    int nbeads_b;         // N_b
+    int pad;
 };
 struct PairItem {
     int block, b, i0, j0;
 };
 
-struct BondTerm {
-    int ra, rb, type, sys;
+// One slice of a bonded term: kind 0 = bond (r[0], r[1]), kind 1 = angle
+// (end r[0], vertex r[1], end r[2]); w = 1 / N_max.  Owns partial-force
+// slots 3t, 3t+1, 3t+2 of the bonded range.
+struct BondedTerm {
+    int r[3];
+    int type, kind, sys;
     double w;
 };
-struct AngleTerm {
-    int ra, rv, rb, type;
-    int sys, pad;
-    double w;
+
+// A workgroup's share of a list, never spanning two systems.
+struct BlockRange {
+    int sys, begin, count, pad;
 };
 
 // free ring-polymer / normal-mode work item
@@ -98,33 +99,52 @@ struct RpItem {
 struct PairLaunch {
     const PairItem *items;
     int n_items;
+    int tj;                  // j-tile width (32 or 64)
     const PairBlock *blocks;
     const SysDev *sys;
     const double *lj_eps, *lj_sig;
     const double *charge;
     const int *ljt, *mol;
     const double *q;
-    double *f;
+    double *part;            // partial-force slots [n_slots][3]
+    int item0;               // global index of items[0] (slot base = index * (64 + tj))
     const double *theta;
-    double *eacc;
-    unsigned long long *npairs;
+    double *eslot;           // energy slot of global item k: eslot + k * A_N
+    int n_bblocks;           // bonded workgroups run after the pair tiles
 };
-void launch_pair(const PairLaunch &a, int precision, bool with_theta, hipStream_t st);
 
 struct BondedLaunch {
-    const BondTerm *bonds;
-    int n_bonds;
-    const AngleTerm *angles;
-    int n_angles;
+    const BondedTerm *terms;
+    const BlockRange *blocks; // one per workgroup (256 terms, one system)
+    int n_blocks;
     const SysDev *sys;
     const double *bond_k, *bond_r0, *angle_k, *angle_t0;
     const double *q;
-    double *f;
+    double *part;            // partial-force slots; term t owns part_base + 3t .. +2
+    long long part_base;
     const double *theta;
-    double *eacc;
+    double *eslot;           // energy slot of this launch's block b: eslot + b * A_N
 };
-void launch_bonded(const BondedLaunch &a, bool with_theta, hipStream_t st);
+// One launch: the pair tiles, then the bonded workgroups (64 terms each).
+void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
+                 hipStream_t st);
 
+// Sums the energy slots listed per system and writes either e_out
+// [n_sys][NV] or an energy-log row [n_sys][NE]; adds the pair-evaluation
+// counts to npairs[2]; with dtheta, writes grad_e * dV/dtheta [n_sys][6].
+struct ReduceLaunch {
+    const double *eslot;
+    const int *order;          // slot indices grouped by system
+    const int *sys_ptr;        // [n_sys + 1] ranges of order per system
+    const SysDev *sys;
+    int n_sys;
+    double *e_out;             // [n_sys][NV] or null
+    double *elog;              // [n_sys][NE] or null
+    double *dtheta;            // [n_sys][6] or null
+    const double *grad_e;      // [n_sys] or null (= 1)
+    unsigned long long *npairs;
+    int *nonfinite;
+};
 struct RpLaunch {
     const RpItem *items;
     int n_items;
@@ -136,36 +156,41 @@ struct RpLaunch {
     const double *in_q;      // OP_STEP: q (in/out via out_q); FWD/BWD: input
     double *out_q;
     double *p;               // OP_STEP only
-    double *f;               // OP_STEP only: read (kick) then zeroed
-    double *cent;            // OP_STEP only: [particles][3]
-    double *eacc;            // OP_STEP only
+    double *f;               // OP_STEP only: read (first half-kick)
+    double *cent;            // OP_STEP only: [rows][3] centroid of each bead's ring
+    double *eslot;           // OP_STEP only: energy slot of item b: eslot + b * A_N
     unsigned lds_bytes;      // dynamic LDS: max over the items
+    int with_reduce;         // one extra workgroup runs `reduce`
+    ReduceLaunch reduce;
 };
 void launch_rp(const RpLaunch &a, hipStream_t st);
 const void *rp_kernel_symbol();
 
+// Gathers F[row] = sum of its partial-force slots, in the fixed CSR order.
+struct GatherArgs {
+    const long long *row_ptr;  // [rows + 1]
+    const int *slot;           // [nnz] slot indices
+    const double *part;        // [n_slots][3]
+};
+
 struct FinishLaunch {
-    long long n3;            // 3 * rows
-    const int *row_part;     // [rows] global particle
-    const int *part_sys;     // [particles]
-    const double *fm;        // [particles]
-    const SysDev *sys;
-    int n_sys;
+    const BlockRange *blocks;  // one per workgroup: 4 bead rows of one system
+    int n_blocks;
+    GatherArgs gather;
+    const double *row_fm;      // [rows] fictitious mass of the bead row
+    const double *row_hk;      // [rows] dt/2 in momentum units of its system
     double *p;
-    const double *f, *q, *cent;
-    double *eacc;
-    double *elog;            // row for this step, [n_sys][NE], or null
-    unsigned *ticket;
-    int *nonfinite;
+    double *f;                 // written: gathered forces
+    const double *q, *cent;
+    double *eslot;             // energy slot of block b: eslot + b * A_N
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);
 
+void launch_reduce(const ReduceLaunch &a, hipStream_t st);
+
 void launch_fill(double *x, long long n, double v, hipStream_t st);
-void launch_write_energy(const SysDev *sys, int n_sys, double *eacc, double *e_out,
-                         hipStream_t st);
-void launch_adjoint_finish(const SysDev *sys, int n_sys, long long rows,
-                           const int *row_part, const int *part_sys,
-                           const double *grad_e, double *dq, double *eacc,
-                           double *dtheta, hipStream_t st);
+void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);
+void launch_scale_rows(long long rows, const int *row_sys, const double *grad_e, double *dq,
+                       hipStream_t st);
 
 }  // namespace mixpi

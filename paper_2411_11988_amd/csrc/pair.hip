@@ -5,20 +5,23 @@
 //
 // Work decomposition.  Particles come in groups of equal bead count, and
 // the state of group g is a [N_g][n_g][3] block.  For a group pair (a, b)
-// with N_b = N_a >> shift, slice-pairs that meet bead b of group b are
+// with N_b = N_a >> shift, the slice-pairs that meet bead b of group b are
 // exactly the rows [b << shift, (b + 1) << shift) of group a -- a contiguous
-// run of n_a << shift beads.  One work item is a 64 x 64 tile of that
+// run of n_a << shift beads.  One work item is a 64 x TJ tile of that
 // rectangle (or of the upper triangle for a group with itself): one wave,
-// one lane per i-bead, the 64 j-beads staged in LDS.  Lane l visits j-bead
-// (l + t) mod 64 at step t, so the 64 lanes always touch 64 distinct
-// j-beads and the Newton-3 reaction goes to a per-j LDS accumulator with a
-// return-less LDS atomic add; i-forces stay in registers.  Every tile ends
-// with FP64 global atomics of its 64 + 64 bead forces.
+// one lane per i-bead, the TJ j-beads staged in LDS.  Lane l visits j-slot
+// (l + t) mod TJ at step t, so the lanes spread over distinct j-beads and
+// the Newton-3 reaction goes to a per-j LDS accumulator with a return-less
+// LDS atomic add; i-forces stay in registers.  The loop body has no
+// branches: cutoff, exclusion and padding are select masks, so consecutive
+// steps overlap.  Each tile stores its i- and j-partial forces into slots of
+// its own; a per-row gather in a fixed order sums them (no global atomics).
 //
 // Precision: separations and the nearest-image shift are FP64 (positions
 // sit up to a box length from the origin); the pair potential is evaluated
 // in R (double, or float for the FP32 form); forces and energies are summed
 // in FP64.
+#include "device_common.h"
 #include "mixpi_internal.h"
 
 namespace mixpi {
@@ -30,12 +33,6 @@ template <typename R> __device__ __forceinline__ R rcp_r(R x);
 template <> __device__ __forceinline__ double rcp_r<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 __device__ __forceinline__ int wave_sum_i(int v)
 {
 #pragma unroll
@@ -43,18 +40,25 @@ __device__ __forceinline__ int wave_sum_i(int v)
     return v;
 }
 
-template <typename R, bool THETA>
-__global__ __launch_bounds__(64) void k_pair(PairLaunch a)
+template <typename R, bool THETA, int TJ>
+__global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
 {
+    if ((int)blockIdx.x >= a.n_items) {
+        // bonded workgroups of the same launch (64 terms each)
+        const int bb = blockIdx.x - a.n_items;
+        bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, nullptr);
+        return;
+    }
     const PairItem it = a.items[blockIdx.x];
     const PairBlock bk = a.blocks[it.block];
     const SysDev &S = a.sys[bk.sys];
     const double *th = a.theta ? a.theta + 6 * bk.sys : S.theta0;
     const int lane = threadIdx.x;
 
-    __shared__ double sx[kPairTile], sy[kPairTile], sz[kPairTile], sq[kPairTile];
-    __shared__ int st[kPairTile], sm[kPairTile];
-    __shared__ double fjx[kPairTile], fjy[kPairTile], fjz[kPairTile];
+    __shared__ double sx[TJ], sy[TJ], sz[TJ];
+    __shared__ R sq[TJ];
+    __shared__ int st[TJ], sm[TJ];
+    __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
     __shared__ R t_e4[kLjTab], t_s2[kLjTab], t_c0[kLjTab], t_c1[kLjTab];
 
     const int nt1 = S.nt1;
@@ -74,23 +78,32 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a)
         }
     }
 
-    // j tile: bead b of group b, particles j0 .. j0 + jn
-    const int jn = min(kPairTile, bk.nb - it.j0);
-    long long rowj = 0;
-    if (lane < jn) {
-        const int j = it.j0 + lane;
-        rowj = bk.rowb + (long long)it.b * bk.nb + j;
-        const int pj = bk.pb0 + j;
-        sx[lane] = a.q[3 * rowj];
-        sy[lane] = a.q[3 * rowj + 1];
-        sz[lane] = a.q[3 * rowj + 2];
-        sq[lane] = a.charge[pj];
-        st[lane] = a.ljt[pj];
-        sm[lane] = a.mol[pj];
+    // j tile: bead b of group b, particles j0 .. j0 + jn; padding slots get
+    // harmless values and are masked out
+    const int jn = min(TJ, bk.nb - it.j0);
+    if (lane < TJ) {
+        if (lane < jn) {
+            const int j = it.j0 + lane;
+            const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
+            const int pj = bk.pb0 + j;
+            sx[lane] = a.q[3 * rowj];
+            sy[lane] = a.q[3 * rowj + 1];
+            sz[lane] = a.q[3 * rowj + 2];
+            sq[lane] = (R)a.charge[pj];
+            st[lane] = a.ljt[pj];
+            sm[lane] = a.mol[pj];
+        } else {
+            sx[lane] = 0.0;
+            sy[lane] = 0.0;
+            sz[lane] = 0.0;
+            sq[lane] = (R)0;
+            st[lane] = 0;
+            sm[lane] = -1;
+        }
+        fjx[lane] = 0.0;
+        fjy[lane] = 0.0;
+        fjz[lane] = 0.0;
     }
-    fjx[lane] = 0.0;
-    fjy[lane] = 0.0;
-    fjz[lane] = 0.0;
 
     // i bead
     const long long li = (long long)bk.na << bk.shift;
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a)
     const bool vi = idx < li;
     const long long rowi = bk.rowa + ((long long)it.b << bk.shift) * bk.na + idx;
     double xi = 0, yi = 0, zi = 0, qi = 0;
-    int ti = 0, mi = 0x7fffffff;
+    int ti = 0, mi = -2;
     if (vi) {
         const int pi = bk.pa0 + (int)(idx % bk.na);
         xi = a.q[3 * rowi];
@@ -116,8 +129,9 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a)
     double e0 = 0, e1 = 0;            // atom: LJ, Coulomb; electron: pp
     double g0 = 0, g1 = 0;            // theta partials (pp: q_e, a; atom: eps, sigma)
     int cnt = 0;
-    // the triangle of a group with itself: j-bead index must exceed i's
-    const long long jmin = bk.same ? idx - it.j0 : -1;
+    // slots that may interact: real j, and for a group with itself j > i
+    const int jlo = bk.same ? (int)max(-1LL, min((long long)TJ, idx - it.j0)) : -1;
+    const int jhi = vi ? jn : 0;
 
     if (bk.kind == PK_ATOM) {
         const double rc2_lj = rc_lj * rc_lj, rc2_c = rc_c * rc_c;
@@ -125,56 +139,58 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a)
         const R rl2 = (R)rc2_lj, rcc2 = (R)rc2_c;
         const R irc = (R)(1.0 / rc_c);
         const R irc3 = (R)(1.0 / (rc_c * rc_c * rc_c));
-        const double kqi = kCoulombKcal * qi;
+        const R kqi = (R)(kCoulombKcal * qi);
         const int trow = ti * nt1;
         const R th_eps = (R)th[2], th_sig = (R)th[3];
-        for (int t = 0; t < kPairTile; ++t) {
-            const int jj = (lane + t) & (kPairTile - 1);
+#pragma unroll 4
+        for (int t = 0; t < TJ; ++t) {
+            const int jj = (lane + t) & (TJ - 1);
             double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
+            const R qj = sq[jj];
+            const int tp = trow + st[jj];
+            const int mj = sm[jj];
             dx -= Lx * rint(dx * iLx);
             dy -= Ly * rint(dy * iLy);
             dz -= Lz * rint(dz * iLz);
             const double r2d = dx * dx + dy * dy + dz * dz;
-            const bool ok = vi && jj < jn && jj > jmin && mi != sm[jj] && r2d < rc2max;
-            if (ok) {
-                const R r2 = (R)r2d;
-                const int tp = trow + st[jj];
-                const R e4 = t_e4[tp];
-                const R ir2 = rcp_r<R>(r2);
-                const R s2 = t_s2[tp] * ir2;
-                const R s6 = s2 * s2 * s2;
-                const R s12 = s6 * s6;
-                const bool in_lj = r2d < rc2_lj && e4 != (R)0;
-                const R c1l = t_c1[tp];
-                const R vlj = e4 * (s12 - s6) - t_c0[tp] - (R)0.5 * (r2 - rl2) * c1l;
-                const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
-                const R K = (R)(kqi * sq[jj]);
-                const bool in_c = r2d < rc2_c && K != (R)0;
-                const R ir = rsqrt_r<R>(r2);
-                const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
-                const R gc = K * (ir * ir * ir - irc3);
-                R g = (R)0;
-                if (in_lj) { e0 += (double)vlj; g += glj; }
-                if (in_c) { e1 += (double)vc; g += gc; }
-                cnt += (in_lj || in_c) ? 1 : 0;
-                if (THETA && tp == 0 && in_lj) {
-                    // d/d eps and d/d sigma of the (0,0) LJ term
-                    const R c6 = t_s2[0] / rl2;
-                    const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
-                    g0 += (double)(vlj / th_eps);
-                    const R fs = (R)4 * th_eps / th_sig;
-                    g1 += (double)(fs * ((R)12 * s12 - (R)6 * s6) - fs * ((R)12 * c12c - (R)6 * c6c) -
-                                   (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2);
-                }
-                const double gd = (double)g;
-                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
-                fxi += fx;
-                fyi += fy;
-                fzi += fz;
-                atomicAdd(&fjx[jj], -fx);
-                atomicAdd(&fjy[jj], -fy);
-                atomicAdd(&fjz[jj], -fz);
+            const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
+            const R r2 = ok ? (R)r2d : (R)1;
+            const R e4 = t_e4[tp], c1l = t_c1[tp];
+            const R ir2 = rcp_r<R>(r2);
+            const R s2 = t_s2[tp] * ir2;
+            const R s6 = s2 * s2 * s2;
+            const R s12 = s6 * s6;
+            const bool in_lj = ok && r2d < rc2_lj && e4 != (R)0;
+            const R vlj = e4 * (s12 - s6) - t_c0[tp] - (R)0.5 * (r2 - rl2) * c1l;
+            const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
+            const R K = kqi * qj;
+            const bool in_c = ok && r2d < rc2_c && K != (R)0;
+            const R ir = rsqrt_r<R>(r2);
+            const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
+            const R gc = K * (ir * ir * ir - irc3);
+            const R g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
+            e0 += in_lj ? (double)vlj : 0.0;
+            e1 += in_c ? (double)vc : 0.0;
+            cnt += (in_lj || in_c) ? 1 : 0;
+            if (THETA) {
+                // d/d eps and d/d sigma of the (0,0) LJ term
+                const bool on = in_lj && tp == 0;
+                const R c6 = t_s2[0] / rl2;
+                const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
+                const R fs = (R)4 * th_eps / th_sig;
+                const R dsg = fs * ((R)12 * s12 - (R)6 * s6) - fs * ((R)12 * c12c - (R)6 * c6c) -
+                              (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2;
+                g0 += on ? (double)(vlj / th_eps) : 0.0;
+                g1 += on ? (double)dsg : 0.0;
             }
+            const double gd = (double)g;
+            const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+            fxi += fx;
+            fyi += fy;
+            fzi += fz;
+            atomicAdd(&fjx[jj], -fx);
+            atomicAdd(&fjy[jj], -fy);
+            atomicAdd(&fjz[jj], -fz);
         }
     } else {
         // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom
@@ -184,94 +200,107 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a)
         const R phic = (R)(1.0 / sqrt(u_c));
         const R psic = (R)(-1.0 / (u_c * sqrt(u_c)));
         const R chic = (R)(1.0 / (u_c * u_c * sqrt(u_c)));
-        const R ra2 = (R)a2, rrc2 = (R)rc2, rpa = (R)pa;
+        const R ra2 = (R)a2, rrc2 = (R)rc2, rpa = (R)pa, rpq = (R)pq;
         const bool e_is_i = bk.kind == PK_E_ATOM;
-        for (int t = 0; t < kPairTile; ++t) {
-            const int jj = (lane + t) & (kPairTile - 1);
+        const R kqi = (R)(kCoulombKcal * qi);
+        const R kc = (R)kCoulombKcal;
+#pragma unroll 4
+        for (int t = 0; t < TJ; ++t) {
+            const int jj = (lane + t) & (TJ - 1);
             double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
+            const R qj = sq[jj];
+            const int mj = sm[jj];
             dx -= Lx * rint(dx * iLx);
             dy -= Ly * rint(dy * iLy);
             dz -= Lz * rint(dz * iLz);
             const double r2d = dx * dx + dy * dy + dz * dz;
-            const bool ok = vi && jj < jn && jj > jmin && mi != sm[jj] && r2d < rc2;
-            if (ok) {
-                const R r2 = (R)r2d;
-                const R kq = (R)(kCoulombKcal * (e_is_i ? sq[jj] : qi));
-                const R ir = rsqrt_r<R>(r2 + ra2);
-                const R ir3 = ir * ir * ir;
-                const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
-                const R gq = kq * (ir3 + psic);
-                e0 += pq * (double)vq;
-                cnt += 1;
-                if (THETA) {
-                    g0 += (double)vq;
-                    g1 += pq * (double)(kq * (-rpa * ir3 - rpa * psic -
-                                              (R)1.5 * rpa * (r2 - rrc2) * chic));
-                }
-                const double gd = pq * (double)gq;
-                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
-                fxi += fx;
-                fyi += fy;
-                fzi += fz;
-                atomicAdd(&fjx[jj], -fx);
-                atomicAdd(&fjy[jj], -fy);
-                atomicAdd(&fjz[jj], -fz);
+            const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2;
+            const R r2 = (R)r2d;
+            const R kq = e_is_i ? kc * qj : kqi;
+            const R ir = rsqrt_r<R>(r2 + ra2);
+            const R ir3 = ir * ir * ir;
+            const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
+            const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
+            e0 += ok ? (double)(rpq * vq) : 0.0;
+            cnt += ok ? 1 : 0;
+            if (THETA) {
+                g0 += ok ? (double)vq : 0.0;
+                g1 += ok ? (double)(rpq * kq * (-rpa * ir3 - rpa * psic -
+                                                (R)1.5 * rpa * (r2 - rrc2) * chic))
+                         : 0.0;
             }
+            const double gd = (double)gq;
+            const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+            fxi += fx;
+            fyi += fy;
+            fzi += fz;
+            atomicAdd(&fjx[jj], -fx);
+            atomicAdd(&fjy[jj], -fy);
+            atomicAdd(&fjz[jj], -fz);
         }
     }
     __syncthreads();
 
+    // partial forces of this tile go to its own slots (64 i-slots, then TJ
+    // j-slots); the per-row gather sums them, so no two workgroups write the
+    // same address
     const double w = bk.w;
+    double *slot = a.part + 3 * ((long long)(a.item0 + blockIdx.x) * (64 + TJ));
     if (vi) {
-        unsafeAtomicAdd(&a.f[3 * rowi], w * fxi);
-        unsafeAtomicAdd(&a.f[3 * rowi + 1], w * fyi);
-        unsafeAtomicAdd(&a.f[3 * rowi + 2], w * fzi);
+        slot[3 * lane] = w * fxi;
+        slot[3 * lane + 1] = w * fyi;
+        slot[3 * lane + 2] = w * fzi;
     }
     if (lane < jn) {
-        unsafeAtomicAdd(&a.f[3 * rowj], w * fjx[lane]);
-        unsafeAtomicAdd(&a.f[3 * rowj + 1], w * fjy[lane]);
-        unsafeAtomicAdd(&a.f[3 * rowj + 2], w * fjz[lane]);
+        slot[3 * (64 + lane)] = w * fjx[lane];
+        slot[3 * (64 + lane) + 1] = w * fjy[lane];
+        slot[3 * (64 + lane) + 2] = w * fjz[lane];
     }
-    e0 = wave_sum(e0);
-    e1 = wave_sum(e1);
+    e0 = wsum(e0);
+    e1 = wsum(e1);
     cnt = wave_sum_i(cnt);
     if (THETA) {
-        g0 = wave_sum(g0);
-        g1 = wave_sum(g1);
+        g0 = wsum(g0);
+        g1 = wsum(g1);
     }
     if (lane == 0) {
-        double *acc = acc_row(a.eacc, bk.sys, blockIdx.x);
+        double *e = a.eslot + (long long)(a.item0 + blockIdx.x) * A_N;
+        for (int k = 0; k < A_N; ++k) e[k] = 0.0;
         if (bk.kind == PK_ATOM) {
-            unsafeAtomicAdd(&acc[A_LJ], w * e0);
-            unsafeAtomicAdd(&acc[A_COUL], w * e1);
-            if (THETA) {
-                unsafeAtomicAdd(&acc[A_TH2], w * g0);
-                unsafeAtomicAdd(&acc[A_TH3], w * g1);
-            }
+            e[A_LJ] = w * e0;
+            e[A_COUL] = w * e1;
+            e[A_TH2] = w * g0;
+            e[A_TH3] = w * g1;
+            e[A_CNT_AA] = (double)cnt;
         } else {
-            unsafeAtomicAdd(&acc[A_PP], w * e0);
-            if (THETA) {
-                unsafeAtomicAdd(&acc[A_TH0], w * g0);
-                unsafeAtomicAdd(&acc[A_TH1], w * g1);
-            }
+            e[A_PP] = w * e0;
+            e[A_TH0] = w * g0;
+            e[A_TH1] = w * g1;
+            e[A_CNT_EA] = (double)cnt;
         }
-        if (cnt)
-            atomicAdd(&a.npairs[(bk.kind == PK_ATOM ? 0 : kAccCopies) + blockIdx.x % kAccCopies],
-                      (unsigned long long)cnt);
     }
 }
 
-void launch_pair(const PairLaunch &a, int precision, bool with_theta, hipStream_t st)
+template <int TJ>
+void launch_pair_tj(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
+                    hipStream_t st)
 {
-    if (a.n_items <= 0) return;
-    dim3 grid(a.n_items), block(kPairTile);
+    dim3 grid(a.n_items + b.n_blocks), block(64);
     if (precision == 0) {
-        if (with_theta) hipLaunchKernelGGL((k_pair<double, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_pair<double, false>), grid, block, 0, st, a);
+        if (with_theta) hipLaunchKernelGGL((k_pair<double, true, TJ>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<double, false, TJ>), grid, block, 0, st, a, b);
     } else {
-        if (with_theta) hipLaunchKernelGGL((k_pair<float, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_pair<float, false>), grid, block, 0, st, a);
+        if (with_theta) hipLaunchKernelGGL((k_pair<float, true, TJ>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<float, false, TJ>), grid, block, 0, st, a, b);
     }
+}
+
+void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
+                 hipStream_t st)
+{
+    if (a.n_items + b.n_blocks <= 0) return;
+    if (a.tj == 32) launch_pair_tj<32>(a, b, precision, with_theta, st);
+    else launch_pair_tj<64>(a, b, precision, with_theta, st);
 }
 
 }  // namespace mixpi

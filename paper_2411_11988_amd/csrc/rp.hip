@@ -19,8 +19,10 @@
 // OP_STEP fuses: first half-kick p += dt/2 F on load, forward transform,
 // exact propagation of every mode with tabulated coefficients
 // (xi, pi) <- (a xi + b pi, c xi + d pi), spring energy sum_k k lambda_k/2
-// xi_k^2 and centroids of the new positions from mode 0, backward transform,
-// store of q and p, and zeroing of F for the force accumulation that follows.
+// xi_k^2 and the centroid of the new positions (mode 0 / sqrt N, stored for
+// every bead row), backward transform, store of q and p, and zeroing of F for
+// the force accumulation that follows.
+#include "device_common.h"
 #include "mixpi_internal.h"
 
 namespace mixpi {
@@ -82,14 +84,13 @@ __device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, doub
             return;
         }
         if (valid) {
-            const int i = c / 3, d = c - 3 * i;
+            const int i = c / 3;
             const double *pr = a.prop + 5 * (it.row + (long long)k * n + i);
             const double x2 = pr[0] * xi + pr[1] * pi;
             const double p2 = pr[2] * xi + pr[3] * pi;
             xi = x2;
             pi = p2;
             esp = pr[4] * x2 * x2;
-            if (k == 0) a.cent[3LL * (it.p0 + i) + d] = x2 / sqrt((double)N);
         }
         s2[k * CB + cl] = xi;
         s3[k * CB + cl] = pi;
@@ -108,13 +109,16 @@ __device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, doub
         a.out_q[g] = qn;
         if (a.op == OP_STEP) {
             a.p[g] = pn;
-            a.f[g] = 0.0;
+            a.cent[g] = s2[cl] / sqrt((double)N);   // propagated mode 0 / sqrt(N)
         }
     }
     if (a.op == OP_STEP) {
         const double s = bsum256(esp, red);
-        if (tid == 0 && s != 0.0)
-            unsafeAtomicAdd(&acc_row(a.eacc, it.sys, blockIdx.x)[A_SPRING], s);
+        if (tid == 0) {
+            double *e = a.eslot + (long long)blockIdx.x * A_N;
+            for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+            e[A_SPRING] = s;
+        }
     }
 }
 
@@ -123,21 +127,42 @@ __device__ __forceinline__ double2 cmul(double2 x, double2 y)
     return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
 }
 
-// In-place radix-2 decimation-in-time FFT (exp(-2 pi i jk/N)) of a
-// bit-reversed-order input held in LDS.
+// In-place decimation-in-time FFT (exp(-2 pi i jk/N)) of a bit-reversed
+// input held in LDS.  Radix-2 stages are fused in pairs (one radix-4 pass:
+// each thread loads 4 points, applies stages s and s+1, stores 4 points),
+// which halves the LDS round trips and barriers; an odd log2 N starts with
+// one plain radix-2 stage.
 __device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
 {
-    for (int s = 1; s <= L; ++s) {
-        const int half = 1 << (s - 1);
+    int s = 1;
+    if (L & 1) {
         __syncthreads();
         for (int b = threadIdx.x; b < N / 2; b += blockDim.x) {
-            const int grp = b >> (s - 1), pos = b & (half - 1);
-            const int i0 = (grp << s) + pos, i1 = i0 + half;
-            const double2 w = tw[pos << (L - s)];
-            const double2 u = z[i0];
-            const double2 v = cmul(z[i1], w);
-            z[i0] = make_double2(u.x + v.x, u.y + v.y);
-            z[i1] = make_double2(u.x - v.x, u.y - v.y);
+            const double2 u = z[2 * b], v = z[2 * b + 1];
+            z[2 * b] = make_double2(u.x + v.x, u.y + v.y);
+            z[2 * b + 1] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        s = 2;
+    }
+    for (; s < L; s += 2) {
+        const int h = 1 << (s - 1);
+        __syncthreads();
+        for (int b = threadIdx.x; b < N / 4; b += blockDim.x) {
+            const int pos = b & (h - 1);
+            const int i0 = ((b >> (s - 1)) << (s + 1)) + pos;
+            const int i1 = i0 + h, i2 = i0 + 2 * h, i3 = i0 + 3 * h;
+            const double2 w1 = tw[pos << (L - s)];
+            const double2 w2 = tw[pos << (L - s - 1)];
+            const double2 w3 = tw[(pos + h) << (L - s - 1)];
+            const double2 a0 = z[i0], a1 = cmul(z[i1], w1), a2 = z[i2], a3 = cmul(z[i3], w1);
+            const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
+            const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
+            const double2 c2 = cmul(make_double2(a2.x + a3.x, a2.y + a3.y), w2);
+            const double2 c3 = cmul(make_double2(a2.x - a3.x, a2.y - a3.y), w3);
+            z[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
+            z[i2] = make_double2(b0.x - c2.x, b0.y - c2.y);
+            z[i1] = make_double2(b1.x + c3.x, b1.y + c3.y);
+            z[i3] = make_double2(b1.x - c3.x, b1.y - c3.y);
         }
     }
     __syncthreads();
@@ -149,7 +174,9 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 {
     const int N = it.N, L = it.logN, n = it.n;
     const int col = it.c0, i = col / 3, d = col - 3 * i;
-    const double2 *tw = a.twiddle + it.tw_off;
+    // twiddles staged in LDS behind the signal (read every stage)
+    double2 *tw = z + N;
+    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
     const int tid = threadIdx.x;
     const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
     const double hk = a.sys[it.sys].hkick;
@@ -172,6 +199,16 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
         return;
     }
 
+    // modes m and N - m share lambda_m, hence one coefficient set; the
+    // first two sets of this thread are fetched before the transform
+    const double *prop = a.prop;
+    auto prow = [&](int k) { return prop + 5 * (it.row + (long long)k * n + i); };
+    double pre[2][5];
+    if (a.op == OP_STEP)
+        for (int r = 0; r < 2; ++r) {
+            const int m = tid + r * (int)blockDim.x;
+            for (int c = 0; c < 5; ++c) pre[r][c] = m <= N / 2 ? prow(m)[c] : 0.0;
+        }
     for (int j = tid; j < N; j += blockDim.x) {
         const long long g = gaddr(j);
         const double re = a.in_q[g];
@@ -195,28 +232,27 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 
     // OP_STEP: unpack q and p modes, propagate, repack z = Zq' + i Zp'
     double esp = 0.0;
-    const double *prop = a.prop;
-    auto prow = [&](int k) { return prop + 5 * (it.row + (long long)k * n + i); };
-    for (int m = tid; m <= N / 2; m += blockDim.x) {
+    __shared__ double cent_s;
+    for (int m = tid, r = 0; m <= N / 2; m += blockDim.x, ++r) {
+        double pc[5];
+        for (int c = 0; c < 5; ++c) pc[c] = r < 2 ? pre[r][c] : prow(m)[c];
         const double2 Zm = z[m];
         const double2 Zc = make_double2(z[(N - m) & (N - 1)].x, -z[(N - m) & (N - 1)].y);
         const double Qr = 0.5 * (Zm.x + Zc.x), Qi = 0.5 * (Zm.y + Zc.y);
         const double Dr = Zm.x - Zc.x, Di = Zm.y - Zc.y;
         const double Pr = 0.5 * Di, Pi = -0.5 * Dr;        // (Zm - Zc) / (2i)
         if (m == 0 || 2 * m == N) {
-            const double *pr = prow(m);
             const double x = Qr / rN, y = Pr / rN;
-            const double x2 = pr[0] * x + pr[1] * y, y2 = pr[2] * x + pr[3] * y;
-            esp += pr[4] * x2 * x2;
-            if (m == 0) a.cent[3LL * (it.p0 + i) + d] = x2 / rN;
+            const double x2 = pc[0] * x + pc[1] * y, y2 = pc[2] * x + pc[3] * y;
+            esp += pc[4] * x2 * x2;
+            if (m == 0) cent_s = x2 / rN;
             z[m] = make_double2(rN * x2, rN * y2);
         } else {
-            const double *p1 = prow(m), *p2 = prow(N - m);
             const double x1 = r2N * Qr, x2 = r2N * Qi;
             const double y1 = r2N * Pr, y2 = r2N * Pi;
-            const double x1n = p1[0] * x1 + p1[1] * y1, y1n = p1[2] * x1 + p1[3] * y1;
-            const double x2n = p2[0] * x2 + p2[1] * y2, y2n = p2[2] * x2 + p2[3] * y2;
-            esp += p1[4] * x1n * x1n + p2[4] * x2n * x2n;
+            const double x1n = pc[0] * x1 + pc[1] * y1, y1n = pc[2] * x1 + pc[3] * y1;
+            const double x2n = pc[0] * x2 + pc[1] * y2, y2n = pc[2] * x2 + pc[3] * y2;
+            esp += pc[4] * (x1n * x1n + x2n * x2n);
             // Zq' = sqrt(N/2) (x1 + i x2), Zp' = sqrt(N/2) (y1 + i y2); z = Zq' + i Zp'
             z[m] = make_double2(rN2 * (x1n - y2n), rN2 * (x2n + y1n));
             z[N - m] = make_double2(rN2 * (x1n + y2n), rN2 * (y1n - x2n));
@@ -236,20 +272,31 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
     }
     fft_stages(z, tw, N, L);
     const double iN = 1.0 / N;
+    const double cq = cent_s;
     for (int j = tid; j < N; j += blockDim.x) {
         const long long g = gaddr(j);
         a.out_q[g] = z[j].x * iN;
         a.p[g] = -z[j].y * iN;
-        a.f[g] = 0.0;
+        a.cent[g] = cq;
     }
     const double s = bsum256(esp, red);
-    if (tid == 0 && s != 0.0) unsafeAtomicAdd(&acc_row(a.eacc, it.sys, blockIdx.x)[A_SPRING], s);
+    if (tid == 0) {
+        double *e = a.eslot + (long long)blockIdx.x * A_N;
+        for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+        e[A_SPRING] = s;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
 {
     extern __shared__ __align__(16) double smem[];
     __shared__ double red[4];
+    if ((int)blockIdx.x >= a.n_items) {
+        // the extra workgroup: energy reducer of the previous step
+        __shared__ double racc[16 * A_N];
+        reduce_energies(a.reduce, racc);
+        return;
+    }
     const RpItem it = a.items[blockIdx.x];
     if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);
     else rp_fft(a, it, reinterpret_cast<double2 *>(smem), red);
@@ -259,8 +306,9 @@ const void *rp_kernel_symbol() { return (const void *)k_rp; }
 
 void launch_rp(const RpLaunch &a, hipStream_t st)
 {
-    if (a.n_items <= 0) return;
-    hipLaunchKernelGGL(k_rp, dim3(a.n_items), dim3(256), a.lds_bytes, st, a);
+    const int grid = a.n_items + (a.with_reduce ? 1 : 0);
+    if (grid <= 0) return;
+    hipLaunchKernelGGL(k_rp, dim3(grid), dim3(256), a.lds_bytes, st, a);
 }
 
 }  // namespace mixpi

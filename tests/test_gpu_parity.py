@@ -123,6 +123,37 @@ def test_one_step_fp32(mp, name, s):
     _step_compare(mp, s, FP32, 1, 1e-12, 1e-6, 1e-5)
 
 
+FULL = [("c2-water256-h32-o4", synth.config_c2), ("c3-e1024-ion-512w", synth.config_c3)]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("name,make", FULL, ids=[n for n, _ in FULL])
+def test_full_size_forces(mp, name, make, prec):
+    """The benchmark systems at full size, every bead compared."""
+    print(f"[full forces] {name} prec={prec}", flush=True)
+    s = make()
+    sysm = mp.System(s, precision=prec)
+    rows = layout_rows(s)
+    q = dev(to_rows(s, s.q, rows))
+    f, e = sysm.forces(q)
+    F = from_rows(s, host(f), rows)
+    Fo, eo = oracle.OracleSystem(s).forces(s.q)
+    assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
+    assert energy_err(host(e)[0], eo) <= TOL_E[prec], (host(e)[0], eo)
+
+
+@pytest.mark.parametrize("name,make", FULL, ids=[n for n, _ in FULL])
+def test_full_size_step_fp64(mp, name, make):
+    print(f"[full step64] {name}", flush=True)
+    _step_compare(mp, make(), FP64, 2, 1e-12, 1e-11, 1e-11)
+
+
+def test_e256_ten_steps_fp64(mp):
+    """Many-bead ring (FFT normal modes, forked step graph) over 10 steps."""
+    print("[step64] e256 x10", flush=True)
+    _step_compare(mp, SYSTEMS[7][1], FP64, 10, 1e-10, 1e-9, 1e-9)
+
+
 def test_pair_counts(mp):
     s = synth.config_c1()
     sysm = mp.System(s)
