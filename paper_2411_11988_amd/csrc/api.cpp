@@ -114,8 +114,11 @@ struct mixpi_system {
     // blocks | normal-mode items | epilogue blocks; per-system slot lists for
     // the force-only range and for the whole step
     double *d_eslot = nullptr;
-    int *d_order_f = nullptr, *d_sysptr_f = nullptr, *d_order_a = nullptr, *d_sysptr_a = nullptr;
+    int *d_order_f = nullptr, *d_osys_f = nullptr, *d_order_a = nullptr, *d_osys_a = nullptr;
     int n_eslots = 0, e_bonded = 0, e_rp = 0, e_fin = 0;
+    int nwg_f = 1, nwg_a = 1;         // reducer workgroups for each list
+    double *d_sums = nullptr;         // [n_sys][A_N] reducer sums (zero at rest)
+    unsigned *d_ticket = nullptr;     // reducer ticket (zero at rest)
     unsigned long long *d_npairs = nullptr;
     int *d_nonfinite = nullptr;
     double *d_cent = nullptr;
@@ -138,7 +141,7 @@ void release(mixpi_system *s)
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
                     s->d_angle_t0, s->d_rp, s->d_basis, s->d_tw, s->d_prop, s->d_row_ptr,
                     s->d_slot, s->d_part, s->d_fblocks, s->d_eslot, s->d_order_f,
-                    s->d_sysptr_f, s->d_order_a, s->d_sysptr_a,
+                    s->d_osys_f, s->d_order_a, s->d_osys_a, s->d_sums, s->d_ticket,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -488,8 +491,11 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         } else {
             if (!B.tw_off.count(N)) {
                 B.tw_off[N] = (int)B.tw.size();
-                for (int m = 0; m < N / 2; ++m)
-                    B.tw.push_back(make_double2(std::cos(2.0 * kPi * m / N), -std::sin(2.0 * kPi * m / N)));
+                // stage-major: stage s (span 2^s) holds exp(-2 pi i pos / 2^s), pos < 2^(s-1)
+                for (int span = 2; span <= N; span *= 2)
+                    for (int pos = 0; pos < span / 2; ++pos)
+                        B.tw.push_back(make_double2(std::cos(2.0 * kPi * pos / span),
+                                                    -std::sin(2.0 * kPi * pos / span)));
             }
             for (int c = 0; c < 3 * g.n; ++c) {
                 RpItem it{};
@@ -505,7 +511,7 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 it.tw_off = B.tw_off[N];
                 B.rp_fft.push_back(it);
             }
-            B.rp_lds = std::max(B.rp_lds, (unsigned)(3 * N / 2 * sizeof(double2)));
+            B.rp_lds = std::max(B.rp_lds, (unsigned)((2 * N - 1) * sizeof(double2)));
         }
     }
     B.sys_rows.push_back({row_base, row});
@@ -556,6 +562,24 @@ std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin,
         i = j;
     }
     return out;
+}
+
+// Reducer workgroups for a slot list grouped by system: about one slot per
+// thread, at most 32 workgroups, and no workgroup's share spanning more
+// systems than its LDS rows hold.
+int reducer_workgroups(const std::vector<int> &osys)
+{
+    const long long n = (long long)osys.size();
+    int w = (int)std::min<long long>(32, std::max<long long>(1, (n + 255) / 256));
+    for (;;) {
+        bool ok = true;
+        for (int g = 0; g < w && ok; ++g) {
+            const long long lo = n * g / w, hi = n * (g + 1) / w;
+            if (lo < hi && osys[hi - 1] - osys[lo] + 1 > kReduceSysPerWg) ok = false;
+        }
+        if (ok || w >= n) return w;
+        w = (int)std::min<long long>(n, 2LL * w);
+    }
 }
 
 // Partial-force slots and the per-row gather lists.  Slot numbering: pair
@@ -671,7 +695,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->n_rp_fast = (int)rp.size();
     rp.insert(rp.end(), B.rp_fft.begin(), B.rp_fft.end());
     S->n_rp = (int)rp.size();
-    S->rp_lds = B.rp_lds;
+    S->rp_lds = std::max<unsigned>(B.rp_lds, kReduceSysPerWg * A_N * sizeof(double));
 
     // epilogue blocks: 4 rows of one system
     std::vector<BlockRange> fblocks;
@@ -700,17 +724,21 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
     // per-system slot lists (stable order) for the reducer
-    auto group_by_system = [&](int n, std::vector<int> &order, std::vector<int> &ptr) {
-        ptr.assign(n_sys + 1, 0);
+    auto group_by_system = [&](int n, std::vector<int> &order, std::vector<int> &osys) {
+        std::vector<int> ptr(n_sys + 1, 0);
         for (int k = 0; k < n; ++k) ++ptr[eslot_sys[k] + 1];
         for (int x = 0; x < n_sys; ++x) ptr[x + 1] += ptr[x];
         order.resize(n);
+        osys.resize(n);
         std::vector<int> fillp(ptr.begin(), ptr.end() - 1);
         for (int k = 0; k < n; ++k) order[fillp[eslot_sys[k]]++] = k;
+        for (int k = 0; k < n; ++k) osys[k] = eslot_sys[order[k]];
     };
-    std::vector<int> order_f, sysptr_f, order_a, sysptr_a;
-    group_by_system(S->e_rp, order_f, sysptr_f);
-    group_by_system(S->n_eslots, order_a, sysptr_a);
+    std::vector<int> order_f, osys_f, order_a, osys_a;
+    group_by_system(S->e_rp, order_f, osys_f);
+    group_by_system(S->n_eslots, order_a, osys_a);
+    S->nwg_f = reducer_workgroups(osys_f);
+    S->nwg_a = reducer_workgroups(osys_a);
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -743,9 +771,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_fblocks, fblocks));
     T(upload(&S->d_eslot, std::vector<double>((size_t)2 * A_N * std::max(S->n_eslots, 1), 0.0)));
     T(upload(&S->d_order_f, order_f));
-    T(upload(&S->d_sysptr_f, sysptr_f));
+    T(upload(&S->d_osys_f, osys_f));
     T(upload(&S->d_order_a, order_a));
-    T(upload(&S->d_sysptr_a, sysptr_a));
+    T(upload(&S->d_osys_a, osys_a));
+    T(upload(&S->d_sums, std::vector<double>((size_t)A_N * n_sys, 0.0)));
+    T(upload(&S->d_ticket, std::vector<unsigned>(1, 0u)));
     T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
     T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
@@ -837,7 +867,11 @@ ReduceLaunch reduce_args(mixpi_system *s, int buf, bool whole_step)
     ReduceLaunch r{};
     r.eslot = eslot_buf(s, buf);
     r.order = whole_step ? s->d_order_a : s->d_order_f;
-    r.sys_ptr = whole_step ? s->d_sysptr_a : s->d_sysptr_f;
+    r.order_sys = whole_step ? s->d_osys_a : s->d_osys_f;
+    r.n = whole_step ? s->n_eslots : s->e_rp;
+    r.n_wg = whole_step ? s->nwg_a : s->nwg_f;
+    r.sums = s->d_sums;
+    r.ticket = s->d_ticket;
     r.sys = s->d_sys;
     r.n_sys = s->n_sys;
     r.npairs = s->d_npairs;

@@ -144,44 +144,77 @@ __device__ inline void energy_outputs(const ReduceLaunch &a, int s, const double
     }
 }
 
-// The energy reducer for one workgroup: the slots of each system (listed
-// by order[sys_ptr[s] .. sys_ptr[s+1])) are summed by whole waves, lanes
-// striding over the slots; with fewer systems than waves a system's list is
-// split among several waves and their sums meet in LDS (acc: >= 16 * A_N
-// doubles).
-__device__ inline void reduce_energies(const ReduceLaunch &a, double *acc)
+// One reducer workgroup (256 threads) of a ReduceLaunch.  Thread t sums a
+// contiguous piece of the workgroup's share of the slot list into 16
+// registers, flushing into the LDS row of a system when the system changes
+// (rarely: the list is grouped by system).  The workgroup then adds its
+// per-system rows to the global sums; the last workgroup (ticket) turns the
+// sums into the outputs and clears them.  lds: >= kReduceSysPerWg * A_N.
+__device__ inline void reduce_part(const ReduceLaunch &a, int wg, double *lds)
 {
-    const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int S = a.n_sys >= W ? 1 : W / a.n_sys;
-    if (S > 1) {
-        for (int x = threadIdx.x; x < a.n_sys * A_N; x += blockDim.x) acc[x] = 0.0;
-        __syncthreads();
-    }
-    for (int u = w; u < a.n_sys * S; u += W) {
-        const int s = u / S, part = u - s * S;
-        const int b = a.sys_ptr[s], len = a.sys_ptr[s + 1] - b;
-        const int lo = b + (int)((long long)len * part / S);
-        const int hi = b + (int)((long long)len * (part + 1) / S);
-        double v[A_N];
+    __shared__ int s_lo_sh;
+    __shared__ bool last;
+    const int T = blockDim.x;
+    const int lo = (int)((long long)a.n * wg / a.n_wg);
+    const int hi = (int)((long long)a.n * (wg + 1) / a.n_wg);
+    const int s_lo = lo < hi ? a.order_sys[lo] : 0;
+    const int s_hi = lo < hi ? a.order_sys[hi - 1] : -1;
+    const int ns = s_hi - s_lo + 1;
+    if (threadIdx.x == 0) s_lo_sh = s_lo;
+    for (int x = threadIdx.x; x < kReduceSysPerWg * A_N; x += T) lds[x] = 0.0;
+    __syncthreads();
+    const int chunk = (hi - lo + T - 1) / T;
+    const int b = lo + (int)threadIdx.x * chunk, e = min(hi, b + chunk);
+    double v[A_N];
 #pragma unroll
-        for (int k = 0; k < A_N; ++k) v[k] = 0.0;
-        for (int i = lo + lane; i < hi; i += 64) {
-            const double *e = a.eslot + (long long)a.order[i] * A_N;
+    for (int k = 0; k < A_N; ++k) v[k] = 0.0;
+    int cur = b < e ? a.order_sys[b] : -1;
+#pragma unroll 2
+    for (int i = b; i < e; ++i) {
+        const int si = a.order_sys[i];
+        if (si != cur) {
+            for (int k = 0; k < A_N; ++k)
+                if (v[k] != 0.0) atomicAdd(&lds[(cur - s_lo) * A_N + k], v[k]);
 #pragma unroll
-            for (int k = 0; k < A_N; ++k) v[k] += e[k];
+            for (int k = 0; k < A_N; ++k) v[k] = 0.0;
+            cur = si;
         }
+        const double *p = a.eslot + (long long)a.order[i] * A_N;
+#pragma unroll
+        for (int k = 0; k < A_N; ++k) v[k] += p[k];
+    }
+    // final flush: one LDS atomic per wave when the wave shares a system
+    const int c0 = __shfl(cur, 0, 64);
+    if (__all(cur == c0)) {
 #pragma unroll
         for (int k = 0; k < A_N; ++k) v[k] = wsum(v[k]);
-        if (lane == 0) {
-            if (S == 1) energy_outputs(a, s, v);
-            else
-                for (int k = 0; k < A_N; ++k) atomicAdd(&acc[s * A_N + k], v[k]);
+        if ((threadIdx.x & 63) == 0 && c0 >= 0)
+            for (int k = 0; k < A_N; ++k)
+                if (v[k] != 0.0) atomicAdd(&lds[(c0 - s_lo) * A_N + k], v[k]);
+    } else if (cur >= 0) {
+        for (int k = 0; k < A_N; ++k)
+            if (v[k] != 0.0) atomicAdd(&lds[(cur - s_lo) * A_N + k], v[k]);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < ns * A_N; x += T)
+        if (lds[x] != 0.0) unsafeAtomicAdd(&a.sums[(long long)s_lo_sh * A_N + x], lds[x]);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == (unsigned)(a.n_wg - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int s0 = 0; s0 < a.n_sys; s0 += kReduceSysPerWg) {
+        const int m = min(kReduceSysPerWg, a.n_sys - s0);
+        for (int x = threadIdx.x; x < m * A_N; x += T) {
+            unsigned long long *pp = (unsigned long long *)(a.sums + (long long)s0 * A_N + x);
+            lds[x] = __longlong_as_double((long long)atomicExch(pp, 0ull));
         }
-    }
-    if (S > 1) {
         __syncthreads();
-        for (int s = threadIdx.x; s < a.n_sys; s += blockDim.x) energy_outputs(a, s, acc + s * A_N);
+        for (int s = threadIdx.x; s < m; s += T) energy_outputs(a, s0 + s, lds + s * A_N);
+        __syncthreads();
     }
+    if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
 }
 
 }  // namespace mixpi

@@ -86,15 +86,15 @@ void launch_finish(const FinishLaunch &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_reduce(ReduceLaunch a)
+__global__ __launch_bounds__(256) void k_reduce(ReduceLaunch a)
 {
-    __shared__ double acc[16 * A_N];
-    reduce_energies(a, acc);
+    __shared__ double acc[kReduceSysPerWg * A_N];
+    reduce_part(a, blockIdx.x, acc);
 }
 
 void launch_reduce(const ReduceLaunch &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_reduce, dim3(a.n_wg), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,13 +28,13 @@ constexpr int kDenseMaxN = 64;           // normal modes by dense basis up to N
 
 // Energy partials.  Every writer (pair tile, bonded block, normal-mode
 // item, epilogue block) owns one slot of A_N doubles and stores its sums
-// there; a one-block reducer adds the slots of each system in a fixed order
-// and writes the energies.  No atomics on shared addresses.
+// there; a reducer adds the slots of each system and writes the energies.
+// Only the reducer's few per-system sums are shared addresses.
 enum {
     A_LJ = 0, A_COUL, A_PP, A_BOND, A_ANGLE, A_SPRING, A_KIN, A_VIR,
     A_TH0, A_TH1, A_TH2, A_TH3, A_TH4, A_TH5, A_CNT_AA, A_CNT_EA, A_N = 16
 };
-constexpr int kMaxSystems = 1024;   // the reducer keeps one A_N row per system in LDS
+constexpr int kMaxSystems = 1024;   // systems per batched handle
 
 struct SysDev {
     double box[3], ibox[3];
@@ -92,7 +92,7 @@ struct RpItem {
     long long row;        // first bead row of the group
     int c0, ncols;        // dense: column range (particle*3 + dim); fft: column c0
     int basis_off;        // offset (doubles) of the dense basis of size N
-    int tw_off;           // offset (complex) of the twiddle table of size N
+    int tw_off;           // offset (complex) of the stage-major twiddle table of N
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -132,12 +132,19 @@ void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool
 // Sums the energy slots listed per system and writes either e_out
 // [n_sys][NV] or an energy-log row [n_sys][NE]; adds the pair-evaluation
 // counts to npairs[2]; with dtheta, writes grad_e * dV/dtheta [n_sys][6].
+// n_wg workgroups each sum a contiguous share of the list into the global
+// per-system sums; the last one to finish (ticket) writes the outputs and
+// clears the sums and the ticket.
 struct ReduceLaunch {
     const double *eslot;
     const int *order;          // slot indices grouped by system
-    const int *sys_ptr;        // [n_sys + 1] ranges of order per system
+    const int *order_sys;      // system of each entry of order (non-decreasing)
+    int n;                     // entries of order
+    int n_wg;                  // reducer workgroups
     const SysDev *sys;
     int n_sys;
+    double *sums;              // [n_sys][A_N], zero between reductions
+    unsigned *ticket;          // zero between reductions
     double *e_out;             // [n_sys][NV] or null
     double *elog;              // [n_sys][NE] or null
     double *dtheta;            // [n_sys][6] or null
@@ -145,12 +152,14 @@ struct ReduceLaunch {
     unsigned long long *npairs;
     int *nonfinite;
 };
+constexpr int kReduceSysPerWg = 64;   // systems one reducer workgroup may span
+
 struct RpLaunch {
     const RpItem *items;
     int n_items;
     const SysDev *sys;
     const double *basis;     // dense bases C[j*N+k] then C^T, per N
-    const double2 *twiddle;  // exp(-2 pi i m / N), m < N/2, per N
+    const double2 *twiddle;  // per N, stage-major exp(-2 pi i pos / 2^s), N - 1 entries
     const double *prop;      // [rows][5] a, b, c, d, spring coefficient
     int op;
     const double *in_q;      // OP_STEP: q (in/out via out_q); FWD/BWD: input
@@ -160,7 +169,7 @@ struct RpLaunch {
     double *cent;            // OP_STEP only: [rows][3] centroid of each bead's ring
     double *eslot;           // OP_STEP only: energy slot of item b: eslot + b * A_N
     unsigned lds_bytes;      // dynamic LDS: max over the items
-    int with_reduce;         // one extra workgroup runs `reduce`
+    int with_reduce;         // reduce.n_wg extra workgroups run `reduce`
     ReduceLaunch reduce;
 };
 void launch_rp(const RpLaunch &a, hipStream_t st);

@@ -131,7 +131,9 @@ __device__ __forceinline__ double2 cmul(double2 x, double2 y)
 // input held in LDS.  Radix-2 stages are fused in pairs (one radix-4 pass:
 // each thread loads 4 points, applies stages s and s+1, stores 4 points),
 // which halves the LDS round trips and barriers; an odd log2 N starts with
-// one plain radix-2 stage.
+// one plain radix-2 stage.  Twiddles are stage-major (stage s at offset
+// 2^(s-1) - 1, entries exp(-2 pi i pos / 2^s)), so the lanes of a pass read
+// consecutive entries.
 __device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
 {
     int s = 1;
@@ -151,9 +153,9 @@ __device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
             const int pos = b & (h - 1);
             const int i0 = ((b >> (s - 1)) << (s + 1)) + pos;
             const int i1 = i0 + h, i2 = i0 + 2 * h, i3 = i0 + 3 * h;
-            const double2 w1 = tw[pos << (L - s)];
-            const double2 w2 = tw[pos << (L - s - 1)];
-            const double2 w3 = tw[(pos + h) << (L - s - 1)];
+            const double2 w1 = tw[h - 1 + pos];            // stage s: exp(-2 pi i pos / 2h)
+            const double2 w2 = tw[2 * h - 1 + pos];        // stage s+1: exp(-2 pi i pos / 4h)
+            const double2 w3 = tw[2 * h - 1 + pos + h];
             const double2 a0 = z[i0], a1 = cmul(z[i1], w1), a2 = z[i2], a3 = cmul(z[i3], w1);
             const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
             const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
@@ -174,9 +176,9 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 {
     const int N = it.N, L = it.logN, n = it.n;
     const int col = it.c0, i = col / 3, d = col - 3 * i;
-    // twiddles staged in LDS behind the signal (read every stage)
+    // stage-major twiddles (N - 1 entries) staged in LDS behind the signal
     double2 *tw = z + N;
-    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
+    for (int m = threadIdx.x; m < N - 1; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
     const int tid = threadIdx.x;
     const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
     const double hk = a.sys[it.sys].hkick;
@@ -292,9 +294,9 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
     extern __shared__ __align__(16) double smem[];
     __shared__ double red[4];
     if ((int)blockIdx.x >= a.n_items) {
-        // the extra workgroup: energy reducer of the previous step
-        __shared__ double racc[16 * A_N];
-        reduce_energies(a.reduce, racc);
+        // the extra workgroups: energy reducer of the previous step
+        // (the dynamic LDS holds at least kReduceSysPerWg * A_N doubles)
+        reduce_part(a.reduce, blockIdx.x - a.n_items, smem);
         return;
     }
     const RpItem it = a.items[blockIdx.x];
@@ -306,7 +308,7 @@ const void *rp_kernel_symbol() { return (const void *)k_rp; }
 
 void launch_rp(const RpLaunch &a, hipStream_t st)
 {
-    const int grid = a.n_items + (a.with_reduce ? 1 : 0);
+    const int grid = a.n_items + (a.with_reduce ? a.reduce.n_wg : 0);
     if (grid <= 0) return;
     hipLaunchKernelGGL(k_rp, dim3(grid), dim3(256), a.lds_bytes, st, a);
 }
