@@ -23,16 +23,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# algorithmic FLOPs per slice-pair of the pair sweep (op counts of the
-# kernel's arithmetic; FMA = 2, add/mul/compare/rint/rsqrt/rcp = 1):
-#   every candidate: separation, nearest image, r^2 and cutoff test
-#   an in-cutoff atom-atom pair adds LJ + Coulomb + force/energy sums
-#   an in-cutoff electron-atom pair adds the pseudopotential + sums
+# Algorithmic FLOPs of the force launch (op counts of the kernel's arithmetic;
+# FMA = 2, add/mul/compare/rint/rsqrt/rcp/sqrt/acos = 1):
+#   every candidate slice-pair: separation, nearest image, r^2, cutoff test
+#   an in-cutoff atom-atom slice-pair adds LJ + Coulomb + force/energy sums
+#   an in-cutoff electron-atom slice-pair adds the pseudopotential + sums
+#   a bond / angle slice (bonded workgroups of the same launch)
 FLOP_CANDIDATE = 21
-FLOP_ATOM_IN = 38
-FLOP_PP_IN = 22
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
-HBM_PEAK_GBS = 8000.0
+FLOP_ATOM_IN = 42
+FLOP_PP_IN = 25
+FLOP_BOND = 35
+FLOP_ANGLE = 100
+# ALU ceiling of the launch: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
+# The library is built without packed FP32, so FP32 and FP64 issue at the
+# same rate; the 157.3 TFLOP/s FP32 figure needs packed FP32.
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+# HBM traffic of one force launch on the default workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
+# on a plain 256 MiB device copy; valid only while the kernel source is the
+# one it was measured on (sha256 over KERNEL_SOURCES).
+KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/csrc/device_common.h",
+                  "paper_2411_11988_amd/csrc/mixpi_internal.h")
+TRAFFIC = {"workload": "c3", "sha256": None, "bytes": None}
+
+
+def _kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _workload(name):
@@ -43,23 +66,35 @@ def _workload(name):
         return synth.config_c2(), "water256 N_H=32 N_O=4 (19.7 A)"
     if name == "c1":
         return synth.config_c1(), "e64-ion-32w (10 A)"
+    if name == "c5":
+        print("[bench] generating the 64-system batch", file=sys.stderr, flush=True)
+        return (synth.config_c5(),
+                "batch64 e-/ion/water (P in 256..2048, 128..1024 H2O per system)")
     raise SystemExit(f"unknown workload {name}")
 
 
+def _as_list(s):
+    return list(s) if isinstance(s, (list, tuple)) else [s]
+
+
 def _run(s, precision, steps, warmup, mixpi, torch):
+    import numpy as np
+    systems = _as_list(s)
     sysm = mixpi.System(s, precision=precision)
     idx = sysm.bead_index
-    import numpy as np
+    n_sys = len(systems)
 
     def dev(x):
         out = np.empty_like(x)
         out[idx] = x
         return torch.from_numpy(out).cuda()
 
-    q, p = dev(s.q), dev(s.p)
+    q = dev(np.concatenate([x.q for x in systems]))
+    p = dev(np.concatenate([x.p for x in systems]))
     f, _ = sysm.forces(q)
-    elog_w = torch.zeros((max(warmup, 1), 1, mixpi.MIXPI_NE), dtype=torch.float64, device="cuda")
-    elog = torch.zeros((steps, 1, mixpi.MIXPI_NE), dtype=torch.float64, device="cuda")
+    elog_w = torch.zeros((max(warmup, 1), n_sys, mixpi.MIXPI_NE), dtype=torch.float64,
+                         device="cuda")
+    elog = torch.zeros((steps, n_sys, mixpi.MIXPI_NE), dtype=torch.float64, device="cuda")
     if warmup > 0:
         sysm.step(warmup, q, p, f, elog_w)
     sysm.step_prepare(steps, q, p, f, elog)
@@ -75,15 +110,52 @@ def _run(s, precision, steps, warmup, mixpi, torch):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     ev_atom, ev_pp = sysm.pair_evals(reset=True)
-    el = elog.cpu().numpy()[:, 0, :]
-    ham = el[:, mixpi.E_NAMES.index("ham")]
+    el = elog.cpu().numpy()
+    ham = el[:, :, mixpi.E_NAMES.index("ham")]
+    drift = ham[-1] - ham[0]
     return dict(sysm=sysm, q=q, p=p, f=f, ms=ms, ev=(ev_atom, ev_pp), elog=el,
-                drift=float(ham[-1] - ham[0]), hstd=float(ham.std()))
+                drift=float(drift[np.argmax(np.abs(drift))]), hstd=float(ham.std(axis=0).max()))
+
+
+def _bonded_slices(s):
+    """Bond and angle slices: each term is evaluated on N_max slices."""
+    n_bond = n_angle = 0
+    for x in _as_list(s):
+        nb = x.n_beads
+        n_bond += int(sum(max(nb[i], nb[j]) for i, j in x.bonds))
+        n_angle += int(sum(max(nb[i], nb[j], nb[k]) for i, j, k in x.angles))
+    return n_bond, n_angle
+
+
+def _cpu_baseline_batch(systems, target_s=15.0):
+    """The FP64 CPU oracle stepping the batch's systems one after another
+    (one step each, in order) until about target_s seconds have passed."""
+    import oracle
+    evals = 0
+    spent = 0.0
+    done = 0
+    for s in systems:
+        o = oracle.OracleSystem(s)
+        F, _ = o.forces(s.q)
+        ev = sum(o.pair_evals(s.q))
+        t = time.perf_counter()
+        o.step(s.q, s.p, 1, F=F)
+        spent += time.perf_counter() - t
+        evals += ev
+        done += 1
+        if spent > target_s:
+            break
+    return dict(value=evals / spent, unit="pair-evals/s", cores=oracle.num_threads(),
+                kind="oracle", steps_per_s=done / spent,
+                sample=f"one FP64 oracle step of each of the first {done} of "
+                       f"{len(systems)} systems (forces of the start state untimed)")
 
 
 def _cpu_baseline(s, target_s=15.0):
     """The FP64 CPU oracle stepping the same system on the host cores."""
     import oracle
+    if isinstance(s, (list, tuple)):
+        return _cpu_baseline_batch(s, target_s)
     o = oracle.OracleSystem(s)
     F, _ = o.forces(s.q)
     t = time.perf_counter()
@@ -105,10 +177,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--kernel-sha", action="store_true",
+                    help="print the sha256 of the force-kernel sources and exit")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (a known-size "
+                         "kernel that calibrates hardware byte counters)")
     args = ap.parse_args()
+    if args.kernel_sha:
+        print(_kernel_sha())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -130,15 +210,17 @@ def main():
     value = (r32["ev"][0] + r32["ev"][1]) / (r32["ms"] * 1e-3)
     steps_per_s = args.steps / (r32["ms"] * 1e-3)
 
-    # dominant kernel (pair sweep) timed with HIP events on the same stream
-    print("[bench] kernel timing", file=sys.stderr, flush=True)
+    # each launch of the step timed with HIP events around it, inside eager
+    # steps on the step's stream (same inputs and cache state as the graph)
+    print("[bench] per-launch timing", file=sys.stderr, flush=True)
     reps = 200
-    k_us = {name: sysm.kernel_time(k, reps, r32["q"], r32["p"])
-            for name, k in (("pair", 0), ("bonded", 1), ("free_rp", 2), ("finish", 3))}
+    k_us = sysm.kernel_time(reps, r32["q"], r32["p"], r32["f"])
     cand = sysm.pair_candidates()
     ev_atom, ev_pp = (x / args.steps for x in r32["ev"])
-    flops = cand * FLOP_CANDIDATE + ev_atom * FLOP_ATOM_IN + ev_pp * FLOP_PP_IN
-    achieved = flops / (k_us["pair"] * 1e-6) / 1e12
+    n_bond, n_angle = _bonded_slices(s)
+    flops = (cand * FLOP_CANDIDATE + ev_atom * FLOP_ATOM_IN + ev_pp * FLOP_PP_IN
+             + n_bond * FLOP_BOND + n_angle * FLOP_ANGLE)
+    achieved = flops / (k_us["force"] * 1e-6) / 1e12
 
     out = {
         "metric": "pair-force evals/s + PIMD steps/s, 1024-bead e-/512 H2O, FP32 vs FP64",
@@ -155,13 +237,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "beads": int(sysm.rows), "particles": int(sysm.n_particles),
                    "candidate_slice_pairs": int(cand), "in_cutoff_slice_pairs": ev_step,
-                   "dt_fs": s.dt, "precision": "fp32 pair potentials, fp64 state and sums"},
+                   "systems": len(_as_list(s)), "dt_fs": _as_list(s)[0].dt,
+                   "precision": "fp32 pair potentials, fp64 state and sums"},
         "steps_per_s": steps_per_s,
         "kernel_us": k_us,
         "energy_drift_kcal": r32["drift"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "k_pair"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": (TRAFFIC["bytes"] if args.workload == TRAFFIC["workload"]
+                                 and TRAFFIC["sha256"] == _kernel_sha() else None),
+                     "kernel": "k_pair<float,false,32>",
+                     "flop_per_launch": flops, "launch_us": k_us["force"]},
     }
     if not args.no_fp64:
         print("[bench] FP64 form", file=sys.stderr, flush=True)
@@ -169,10 +255,18 @@ def main():
         out["fp64"] = {"value": (r64["ev"][0] + r64["ev"][1]) / (r64["ms"] * 1e-3),
                        "steps_per_s": args.steps / (r64["ms"] * 1e-3),
                        "ms_per_step": r64["ms"] / args.steps,
-                       "pair_us": r64["sysm"].kernel_time(0, reps, r64["q"], r64["p"])}
+                       "kernel_us": r64["sysm"].kernel_time(reps, r64["q"], r64["p"], r64["f"])}
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = _cpu_baseline(s)
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * n * 8
     print(json.dumps(out), flush=True)
 
 

@@ -225,14 +225,20 @@ int mixpi_pair_evals(mixpi_system *sys, int64_t *evals, int32_t reset, void *str
 int mixpi_step_prepare(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
                        double *elog);
 
-/* Measurement aid: launches one kernel of the step `reps` times on `stream`
- * between two HIP events and returns the mean duration in microseconds.
- * which: 0 = pair sweep, 1 = bonded sweep, 2 = free ring polymer (normal
- * modes), 3 = half-kick/energy epilogue.  q, p: device double [rows][3]
- * (read only; copied to library scratch, so no caller buffer changes).
- * Waits for the stream. */
-int mixpi_kernel_time(mixpi_system *sys, int32_t which, int32_t reps, const double *q,
-                      const double *p, double *avg_us, void *stream);
+/* Measurement aid: runs `reps` steps (1..1000) eagerly on library copies of
+ * q, p, f (the caller's buffers are not changed) with a HIP event before and
+ * after each of a step's three launches, and returns their mean durations in
+ * microseconds: avg_us[0] = force launch (pair sweep + bonded workgroups),
+ * avg_us[1] = free ring-polymer launch (normal modes + the energy reducer of
+ * the previous step), avg_us[2] = half-kick/energy epilogue.  The events
+ * are timing-only (no system-scope fence), and the steps are enqueued in
+ * chunks of 16 behind a bounded delay kernel (2 ms) that holds the stream
+ * meanwhile, so each chunk's launches run back to back with the same inputs
+ * and cache state as in mixpi_step.
+ * q, p, f: device double [rows][3]; avg_us: host double[3].  Waits for the
+ * stream. */
+int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const double *p,
+                      const double *f, double *avg_us, void *stream);
 
 #ifdef __cplusplus
 }

@@ -96,8 +96,15 @@ struct mixpi_system {
     int n_bblocks = 0, n_bblocks_fast = 0;
     double *d_bond_k = nullptr, *d_bond_r0 = nullptr, *d_angle_k = nullptr, *d_angle_t0 = nullptr;
     // normal modes: dense items first, then FFT items
-    RpItem *d_rp = nullptr;
-    int n_rp = 0, n_rp_fast = 0;
+    RpItem *d_rp = nullptr;       // items of the step
+    RpItem *d_rp_nm = nullptr;    // items of the normal-mode transforms
+    int n_rp = 0, n_rp_fast = 0, n_rp_nm = 0;
+    double *d_circ = nullptr;
+    // circulant rings' stage rows: q and p + dt/2 F of each of their bead rows
+    double *d_stage = nullptr;
+    int *d_row_stage = nullptr;
+    long long *d_stage_rows = nullptr;
+    int n_stage = 0;
     unsigned rp_lds = 0;
     double *d_basis = nullptr;
     double2 *d_tw = nullptr;
@@ -114,11 +121,11 @@ struct mixpi_system {
     // blocks | normal-mode items | epilogue blocks; per-system slot lists for
     // the force-only range and for the whole step
     double *d_eslot = nullptr;
-    int *d_order_f = nullptr, *d_osys_f = nullptr, *d_order_a = nullptr, *d_osys_a = nullptr;
+    // reducer plans: the force-only slots [0, e_rp) and the whole step
+    int *d_red_f = nullptr, *d_red_a = nullptr;   // packed wg_sys | sys_run | begin | len
+    int red_f_off[4] = {0, 0, 0, 0}, red_a_off[4] = {0, 0, 0, 0};
     int n_eslots = 0, e_bonded = 0, e_rp = 0, e_fin = 0;
     int nwg_f = 1, nwg_a = 1;         // reducer workgroups for each list
-    double *d_sums = nullptr;         // [n_sys][A_N] reducer sums (zero at rest)
-    unsigned *d_ticket = nullptr;     // reducer ticket (zero at rest)
     unsigned long long *d_npairs = nullptr;
     int *d_nonfinite = nullptr;
     double *d_cent = nullptr;
@@ -139,9 +146,10 @@ void release(mixpi_system *s)
     void *ptrs[] = {s->d_sys, s->d_lj_eps, s->d_lj_sig, s->d_charge, s->d_ljt, s->d_mol,
                     s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
-                    s->d_angle_t0, s->d_rp, s->d_basis, s->d_tw, s->d_prop, s->d_row_ptr,
-                    s->d_slot, s->d_part, s->d_fblocks, s->d_eslot, s->d_order_f,
-                    s->d_osys_f, s->d_order_a, s->d_osys_a, s->d_sums, s->d_ticket,
+                    s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
+                    s->d_row_stage, s->d_stage_rows, s->d_basis, s->d_tw,
+                    s->d_prop, s->d_row_ptr,
+                    s->d_slot, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -237,7 +245,8 @@ struct Build {
     std::vector<char> block_slow;              // block touches an FFT group
     std::vector<BondedTerm> bterms, bterms_slow;
     std::vector<RpItem> rp_fft, rp_dense;
-    std::vector<double> basis, prop;
+    std::vector<RpItem> rings;                 // one per big ring column group (circulant candidates)
+    std::vector<double> basis, prop, circ;
     std::vector<double2> tw;
     std::map<int, int> basis_off, tw_off;
     std::vector<long long> bead_index;
@@ -497,6 +506,19 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                         B.tw.push_back(make_double2(std::cos(2.0 * kPi * pos / span),
                                                     -std::sin(2.0 * kPi * pos / span)));
             }
+            {
+                // a candidate for the bead-space (circulant) step
+                RpItem rg{};
+                rg.kind = RP_CIRC;
+                rg.sys = s;
+                rg.N = N;
+                rg.logN = ilog2(N);
+                rg.n = g.n;
+                rg.p0 = p_base + g.p0;
+                rg.row = g.row;
+                rg.tw_off = B.tw_off[N];
+                B.rings.push_back(rg);
+            }
             for (int c = 0; c < 3 * g.n; ++c) {
                 RpItem it{};
                 it.kind = RP_FFT;
@@ -517,6 +539,75 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
     B.sys_rows.push_back({row_base, row});
     B.rows = row;
     B.n_part += n;
+}
+
+// Rings propagated in bead space (circulant items): the cheapest first,
+// while the total multiply-adds stay within a budget of about two waves of
+// items over the chip, where they beat one FFT workgroup per column in
+// latency.  A ring needs N <= kCircMaxN.
+std::vector<char> choose_circulant(const std::vector<RpItem> &rings)
+{
+    std::vector<char> use(rings.size(), 0);
+    if (const char *env = getenv("MIXPI_RING_CIRC"))
+        if (atoi(env) == 0) return use;
+    std::vector<size_t> order(rings.size());
+    for (size_t r = 0; r < rings.size(); ++r) order[r] = r;
+    auto cost = [&](size_t r) { return 12.0 * rings[r].n * (double)rings[r].N * rings[r].N; };
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) < cost(y); });
+    const double budget = 32.0 * 1024 * 1024;
+    double used = 0.0;
+    for (size_t r : order) {
+        if (rings[r].N > kCircMaxN) continue;
+        if (used + cost(r) > budget) break;
+        used += cost(r);
+        use[r] = 1;
+    }
+    return use;
+}
+
+// Circulant rows a_d, b_d, c_d (d = 0 .. N-1) of every particle of ring
+// group rg, from the per-mode propagation coefficients: row_d =
+// (1/N) sum_k f_k cos(2 pi k d / N), f = (cos w dt, sin(w dt)/(m w),
+// -m w sin(w dt)); then the items of kCircOut outputs per column.
+void add_circulant(Build &B, const RpItem &rg, int stage0, std::vector<RpItem> &items)
+{
+    const int N = rg.N, n = rg.n;
+    std::vector<double> cs(N);
+    for (int m = 0; m < N; ++m) cs[m] = std::cos(2.0 * kPi * m / N);
+    for (int i = 0; i < n; ++i) {
+        const int off = (int)B.circ.size();
+        B.circ.resize(B.circ.size() + 3 * (size_t)N, 0.0);
+        double *A = &B.circ[off], *Bq = A + N, *Cq = Bq + N;
+        for (int d = 0; d < N; ++d) {
+            double sa = 0.0, sb = 0.0, sc = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const double *pr = &B.prop[5 * (size_t)(rg.row + (long long)k * n + i)];
+                const double c = cs[(int)(((long long)k * d) % N)];
+                sa += pr[0] * c;
+                sb += pr[1] * c;
+                sc += pr[2] * c;
+            }
+            A[d] = sa / N;
+            Bq[d] = sb / N;
+            Cq[d] = sc / N;
+        }
+        // spring weight k/2 per squared bead step, from mode 1's entry
+        // k lambda_1 / 2 of the propagation table
+        const double s1 = std::sin(kPi / N);
+        const double wsp = B.prop[5 * (size_t)(rg.row + (long long)n + i) + 4] / (4.0 * s1 * s1);
+        for (int dim = 0; dim < 3; ++dim)
+            for (int o0 = 0; o0 < N; o0 += kCircOut) {
+                RpItem it = rg;
+                it.c0 = 3 * i + dim;
+                it.ncols = 1;
+                it.o0 = o0;
+                it.circ_off = off;
+                it.stage0 = stage0;
+                it.wsp = wsp;
+                items.push_back(it);
+            }
+    }
+    B.rp_lds = std::max(B.rp_lds, (unsigned)((5 * (N + 32) + 2 * 32 * kCircOut) * sizeof(double)));
 }
 
 // Cuts the pair blocks with block_slow == slow into 64 x tj tiles: for each
@@ -564,22 +655,57 @@ std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin,
     return out;
 }
 
-// Reducer workgroups for a slot list grouped by system: about one slot per
-// thread, at most 32 workgroups, and no workgroup's share spanning more
-// systems than its LDS rows hold.
-int reducer_workgroups(const std::vector<int> &osys)
+// Reducer plan for the slots [0, n): each system's slots as maximal
+// contiguous runs (in slot order), and whole systems dealt to at most 32
+// workgroups in order, balanced by slot count.  Packed as
+// wg_sys[n_wg + 1] | sys_run[n_sys + 1] | run_begin[runs] | run_len[runs];
+// off[] receives the four offsets.  Returns n_wg.
+int reducer_plan(const std::vector<int> &eslot_sys, int n, int n_sys, std::vector<int> &out,
+                 int off[4])
 {
-    const long long n = (long long)osys.size();
-    int w = (int)std::min<long long>(32, std::max<long long>(1, (n + 255) / 256));
-    for (;;) {
-        bool ok = true;
-        for (int g = 0; g < w && ok; ++g) {
-            const long long lo = n * g / w, hi = n * (g + 1) / w;
-            if (lo < hi && osys[hi - 1] - osys[lo] + 1 > kReduceSysPerWg) ok = false;
-        }
-        if (ok || w >= n) return w;
-        w = (int)std::min<long long>(n, 2LL * w);
+    std::vector<std::vector<std::pair<int, int>>> runs(n_sys);
+    for (int k = 0; k < n;) {
+        int e = k;
+        while (e < n && eslot_sys[e] == eslot_sys[k]) ++e;
+        runs[eslot_sys[k]].push_back({k, e - k});
+        k = e;
     }
+    std::vector<long long> cnt(n_sys, 0);
+    for (int x = 0; x < n_sys; ++x)
+        for (auto &r : runs[x]) cnt[x] += r.second;
+    const int n_wg = std::max(1, std::min(n_sys, 32));
+    std::vector<int> wg_sys(n_wg + 1, n_sys);
+    wg_sys[0] = 0;
+    long long done = 0;
+    int w = 1, x = 0;
+    for (; x < n_sys && w < n_wg; ++x) {
+        done += cnt[x];
+        // close workgroup w-1 once it holds its share, leaving a system for
+        // each remaining workgroup
+        if (done * n_wg >= (long long)w * std::max<long long>(n, 1) || n_sys - (x + 1) <= n_wg - w)
+            wg_sys[w++] = x + 1;
+    }
+    for (; w <= n_wg; ++w) wg_sys[w] = n_sys;
+    std::vector<int> sys_run(n_sys + 1, 0), rb, rl;
+    for (int y = 0; y < n_sys; ++y) {
+        sys_run[y] = (int)rb.size();
+        for (auto &r : runs[y]) {
+            rb.push_back(r.first);
+            rl.push_back(r.second);
+        }
+    }
+    sys_run[n_sys] = (int)rb.size();
+    out.clear();
+    off[0] = 0;
+    out.insert(out.end(), wg_sys.begin(), wg_sys.end());
+    off[1] = (int)out.size();
+    out.insert(out.end(), sys_run.begin(), sys_run.end());
+    off[2] = (int)out.size();
+    out.insert(out.end(), rb.begin(), rb.end());
+    off[3] = (int)out.size();
+    out.insert(out.end(), rl.begin(), rl.end());
+    if (out.empty()) out.push_back(0);
+    return n_wg;
 }
 
 // Partial-force slots and the per-row gather lists.  Slot numbering: pair
@@ -690,12 +816,38 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     }
     S->n_bblocks = (int)bblocks.size();
 
-    // normal-mode items: dense first, then FFT
+    std::vector<int> row_stage;
+    std::vector<long long> stage_rows;
+    // normal-mode items.  Transforms: dense, then FFT.  Step: dense, FFT of
+    // the rings not chosen for the bead-space step, circulant items.
+    std::vector<RpItem> rp_nm = B.rp_dense;
+    rp_nm.insert(rp_nm.end(), B.rp_fft.begin(), B.rp_fft.end());
+    S->n_rp_nm = (int)rp_nm.size();
     std::vector<RpItem> rp = B.rp_dense;
     S->n_rp_fast = (int)rp.size();
-    rp.insert(rp.end(), B.rp_fft.begin(), B.rp_fft.end());
+    {
+        std::vector<char> circ_ring = choose_circulant(B.rings);
+        std::vector<RpItem> circ_items;
+        row_stage.assign((size_t)B.rows, -1);
+        for (size_t r = 0; r < B.rings.size(); ++r) {
+            const RpItem &rg = B.rings[r];
+            if (!circ_ring[r]) {
+                for (const RpItem &it : B.rp_fft)
+                    if (it.row == rg.row) rp.push_back(it);
+                continue;
+            }
+            const int stage0 = (int)stage_rows.size();
+            for (long long x = 0; x < (long long)rg.N * rg.n; ++x) {
+                row_stage[rg.row + x] = stage0 + (int)x;
+                stage_rows.push_back(rg.row + x);
+            }
+            add_circulant(B, rg, stage0, circ_items);
+        }
+        rp.insert(rp.end(), circ_items.begin(), circ_items.end());
+        S->n_stage = (int)stage_rows.size();
+    }
     S->n_rp = (int)rp.size();
-    S->rp_lds = std::max<unsigned>(B.rp_lds, kReduceSysPerWg * A_N * sizeof(double));
+    S->rp_lds = std::max<unsigned>(B.rp_lds, (kReduceThreads + A_N) * sizeof(double));
 
     // epilogue blocks: 4 rows of one system
     std::vector<BlockRange> fblocks;
@@ -724,21 +876,9 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
     // per-system slot lists (stable order) for the reducer
-    auto group_by_system = [&](int n, std::vector<int> &order, std::vector<int> &osys) {
-        std::vector<int> ptr(n_sys + 1, 0);
-        for (int k = 0; k < n; ++k) ++ptr[eslot_sys[k] + 1];
-        for (int x = 0; x < n_sys; ++x) ptr[x + 1] += ptr[x];
-        order.resize(n);
-        osys.resize(n);
-        std::vector<int> fillp(ptr.begin(), ptr.end() - 1);
-        for (int k = 0; k < n; ++k) order[fillp[eslot_sys[k]]++] = k;
-        for (int k = 0; k < n; ++k) osys[k] = eslot_sys[order[k]];
-    };
-    std::vector<int> order_f, osys_f, order_a, osys_a;
-    group_by_system(S->e_rp, order_f, osys_f);
-    group_by_system(S->n_eslots, order_a, osys_a);
-    S->nwg_f = reducer_workgroups(osys_f);
-    S->nwg_a = reducer_workgroups(osys_a);
+    std::vector<int> red_f, red_a;
+    S->nwg_f = reducer_plan(eslot_sys, S->e_rp, n_sys, red_f, S->red_f_off);
+    S->nwg_a = reducer_plan(eslot_sys, S->n_eslots, n_sys, red_a, S->red_a_off);
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -762,6 +902,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_angle_k, B.angle_k));
     T(upload(&S->d_angle_t0, B.angle_t0));
     T(upload(&S->d_rp, rp));
+    T(upload(&S->d_rp_nm, rp_nm));
+    T(upload(&S->d_circ, B.circ.empty() ? std::vector<double>(1, 0.0) : B.circ));
+    T(upload(&S->d_row_stage, row_stage));
+    T(upload(&S->d_stage_rows, stage_rows.empty() ? std::vector<long long>(1, 0) : stage_rows));
+    T(upload(&S->d_stage, std::vector<double>((size_t)6 * std::max<size_t>(stage_rows.size(), 1), 0.0)));
     T(upload(&S->d_basis, B.basis));
     T(upload(&S->d_tw, B.tw));
     T(upload(&S->d_prop, B.prop));
@@ -770,16 +915,12 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_part, std::vector<double>((size_t)3 * std::max<long long>(G.n_slots, 1), 0.0)));
     T(upload(&S->d_fblocks, fblocks));
     T(upload(&S->d_eslot, std::vector<double>((size_t)2 * A_N * std::max(S->n_eslots, 1), 0.0)));
-    T(upload(&S->d_order_f, order_f));
-    T(upload(&S->d_osys_f, osys_f));
-    T(upload(&S->d_order_a, order_a));
-    T(upload(&S->d_osys_a, osys_a));
-    T(upload(&S->d_sums, std::vector<double>((size_t)A_N * n_sys, 0.0)));
-    T(upload(&S->d_ticket, std::vector<unsigned>(1, 0u)));
+    T(upload(&S->d_red_f, red_f));
+    T(upload(&S->d_red_a, red_a));
     T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
     T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
-    T(upload(&S->d_scratch, std::vector<double>((size_t)9 * B.rows, 0.0)));
+    T(upload(&S->d_scratch, std::vector<double>((size_t)9 * B.rows + MIXPI_NE * n_sys, 0.0)));
     if (!rc) {
         hipError_t e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) rc = fail(MIXPI_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
@@ -866,12 +1007,13 @@ ReduceLaunch reduce_args(mixpi_system *s, int buf, bool whole_step)
 {
     ReduceLaunch r{};
     r.eslot = eslot_buf(s, buf);
-    r.order = whole_step ? s->d_order_a : s->d_order_f;
-    r.order_sys = whole_step ? s->d_osys_a : s->d_osys_f;
-    r.n = whole_step ? s->n_eslots : s->e_rp;
+    const int *plan = whole_step ? s->d_red_a : s->d_red_f;
+    const int *off = whole_step ? s->red_a_off : s->red_f_off;
+    r.wg_sys = plan + off[0];
+    r.sys_run = plan + off[1];
+    r.run_begin = plan + off[2];
+    r.run_len = plan + off[3];
     r.n_wg = whole_step ? s->nwg_a : s->nwg_f;
-    r.sums = s->d_sums;
-    r.ticket = s->d_ticket;
     r.sys = s->d_sys;
     r.n_sys = s->n_sys;
     r.npairs = s->d_npairs;
@@ -901,8 +1043,15 @@ RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double 
     RpLaunch r{};
     const int lo = part == SLOW ? s->n_rp_fast : 0;
     const int hi = part == FAST ? s->n_rp_fast : s->n_rp;
-    r.items = s->d_rp + lo;
-    r.n_items = hi - lo;
+    if (op == OP_STEP) {
+        r.items = s->d_rp + lo;
+        r.n_items = hi - lo;
+    } else {
+        r.items = s->d_rp_nm;
+        r.n_items = s->n_rp_nm;
+    }
+    r.circ = s->d_circ;
+    r.stage = s->d_stage;
     r.sys = s->d_sys;
     r.basis = s->d_basis;
     r.twiddle = s->d_tw;
@@ -931,7 +1080,24 @@ FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f,
     fl.q = q;
     fl.cent = s->d_cent;
     fl.eslot = eslot_buf(s, buf) + (long long)s->e_fin * A_N;
+    fl.row_stage = s->d_row_stage;
+    fl.stage = s->d_stage;
     return fl;
+}
+
+// Fills the stage rows of the circulant rings from (q, p, f) before a
+// sequence of steps (later steps get them from the epilogue).
+StageLaunch stage_args(mixpi_system *s, const double *q, const double *p, const double *f)
+{
+    StageLaunch a{};
+    a.rows = s->d_stage_rows;
+    a.n = s->n_stage;
+    a.q = q;
+    a.p = p;
+    a.f = f;
+    a.row_hk = s->d_row_hk;
+    a.stage = s->d_stage;
+    return a;
 }
 
 // Step k of a sequence: free ring polymers (with the first half-kick; one
@@ -979,6 +1145,7 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
     GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr};
     auto row = [&](int k) { return elog ? elog + (size_t)k * sys->n_sys * MIXPI_NE : nullptr; };
     HIP_TRY(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeRelaxed));
+    launch_stage(stage_args(sys, q, p, f), sys->cap_stream);
     for (int k = 0; k < nsteps; ++k)
         enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream);
     {
@@ -1132,41 +1299,77 @@ int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *
     return MIXPI_OK;
 }
 
-int mixpi_kernel_time(mixpi_system *sys, int32_t which, int32_t reps, const double *q,
-                      const double *p, double *avg_us, void *stream)
+int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const double *p,
+                      const double *f, double *avg_us, void *stream)
 {
     if (int rc = check_sys(sys)) return rc;
-    if (which < 0 || which > 3) return fail(MIXPI_E_INVALID, "which must be 0..3");
-    if (reps < 1 || !q || !p || !avg_us) return fail(MIXPI_E_INVALID, "bad arguments");
+    if (reps < 1 || reps > 1000 || !q || !p || !f || !avg_us)
+        return fail(MIXPI_E_INVALID, "bad arguments (reps must be in [1, 1000])");
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes = sizeof(double) * 3 * sys->rows;
     double *sq = sys->d_scratch, *sp = sq + 3 * sys->rows, *sf = sp + 3 * sys->rows;
+    double *selog = sf + 3 * sys->rows;
     HIP_TRY(hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(sp, p, bytes, hipMemcpyDeviceToDevice, st));
-    enqueue_forces(sys, sq, nullptr, sf, false, st);
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) {
-        if (which <= 1) {
-            PairLaunch pa = pair_args(sys, sq, nullptr);
-            BondedLaunch ba = bonded_args(sys, sq, nullptr);
-            if (which == 0) ba.n_blocks = 0;
-            else pa.n_items = 0;
-            launch_pair(pa, ba, sys->precision, false, st);
+    HIP_TRY(hipMemcpyAsync(sf, f, bytes, hipMemcpyDeviceToDevice, st));
+    launch_stage(stage_args(sys, sq, sp, sf), st);
+    // four timing-only events per step (no system-scope fence, so recording
+    // them does not write back or invalidate caches between the launches)
+    std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
+    int rc = MIXPI_OK;
+    for (auto &e : ev) {
+        hipError_t h = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+        if (h != hipSuccess) {
+            rc = fail(MIXPI_E_HIP, "hipEventCreate: %s", hipGetErrorString(h));
+            break;
         }
-        else if (which == 2) launch_rp(rp_args(sys, OP_STEP, sq, sq, sp, sf), st);
-        else launch_finish(finish_args(sys, sq, sp, sf), st);
     }
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *avg_us = 1000.0 * ms / reps;
+    // chunks of 16 steps, each behind a bounded delay kernel (2 ms) that
+    // holds the stream while the host enqueues the chunk, so the chunk's
+    // launches run back to back and fit the hardware queue
+    const int chunk = 16;
+    for (int r0 = 0; r0 < reps && !rc; r0 += chunk) {
+        launch_delay(200000LL, st);
+        for (int r = r0; r < std::min(reps, r0 + chunk) && !rc; ++r) {
+            const int buf = (r + 1) & 1;
+            RpLaunch ra = rp_args(sys, OP_STEP, sq, sq, sp, sf, buf);
+            ra.with_reduce = 1;
+            ra.reduce = reduce_args(sys, buf ^ 1, true);
+            ra.reduce.elog = selog;
+            ra.reduce.npairs = nullptr;
+            ra.reduce.nonfinite = nullptr;
+            (void)hipEventRecord(ev[4 * r], st);
+            launch_rp(ra, st);
+            (void)hipEventRecord(ev[4 * r + 1], st);
+            launch_pair(pair_args(sys, sq, nullptr, buf), bonded_args(sys, sq, nullptr, buf),
+                        sys->precision, false, st);
+            (void)hipEventRecord(ev[4 * r + 2], st);
+            launch_finish(finish_args(sys, sq, sp, sf, buf), st);
+            if (hipEventRecord(ev[4 * r + 3], st) != hipSuccess)
+                rc = fail(MIXPI_E_HIP, "hipEventRecord failed");
+        }
+    }
+    if (!rc) {
+        hipError_t h = hipStreamSynchronize(st);
+        if (h != hipSuccess) rc = fail(MIXPI_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(h));
+    }
+    if (!rc) {
+        double sum[3] = {0, 0, 0};
+        for (int r = 0; r < reps; ++r)
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ev[4 * r + k], ev[4 * r + k + 1]);
+                sum[k] += ms;
+            }
+        // [0] force launch, [1] free ring polymer, [2] epilogue
+        avg_us[0] = 1000.0 * sum[1] / reps;
+        avg_us[1] = 1000.0 * sum[0] / reps;
+        avg_us[2] = 1000.0 * sum[2] / reps;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) return rc;
     return last_launch_error();
 }
 

@@ -144,77 +144,34 @@ __device__ inline void energy_outputs(const ReduceLaunch &a, int s, const double
     }
 }
 
-// One reducer workgroup (256 threads) of a ReduceLaunch.  Thread t sums a
-// contiguous piece of the workgroup's share of the slot list into 16
-// registers, flushing into the LDS row of a system when the system changes
-// (rarely: the list is grouped by system).  The workgroup then adds its
-// per-system rows to the global sums; the last workgroup (ticket) turns the
-// sums into the outputs and clears them.  lds: >= kReduceSysPerWg * A_N.
+// One reducer workgroup (kReduceThreads threads) of a ReduceLaunch: for
+// each of its systems, thread t sums component t % A_N of the system's slots
+// (the runs start on slot boundaries and A_N divides the block size), then
+// the A_N-strided partials are added in LDS and thread 0 writes the outputs.
+// lds: >= kReduceThreads + A_N doubles.
 __device__ inline void reduce_part(const ReduceLaunch &a, int wg, double *lds)
 {
-    __shared__ int s_lo_sh;
-    __shared__ bool last;
-    const int T = blockDim.x;
-    const int lo = (int)((long long)a.n * wg / a.n_wg);
-    const int hi = (int)((long long)a.n * (wg + 1) / a.n_wg);
-    const int s_lo = lo < hi ? a.order_sys[lo] : 0;
-    const int s_hi = lo < hi ? a.order_sys[hi - 1] : -1;
-    const int ns = s_hi - s_lo + 1;
-    if (threadIdx.x == 0) s_lo_sh = s_lo;
-    for (int x = threadIdx.x; x < kReduceSysPerWg * A_N; x += T) lds[x] = 0.0;
-    __syncthreads();
-    const int chunk = (hi - lo + T - 1) / T;
-    const int b = lo + (int)threadIdx.x * chunk, e = min(hi, b + chunk);
-    double v[A_N];
-#pragma unroll
-    for (int k = 0; k < A_N; ++k) v[k] = 0.0;
-    int cur = b < e ? a.order_sys[b] : -1;
-#pragma unroll 2
-    for (int i = b; i < e; ++i) {
-        const int si = a.order_sys[i];
-        if (si != cur) {
-            for (int k = 0; k < A_N; ++k)
-                if (v[k] != 0.0) atomicAdd(&lds[(cur - s_lo) * A_N + k], v[k]);
-#pragma unroll
-            for (int k = 0; k < A_N; ++k) v[k] = 0.0;
-            cur = si;
+    const int T = kReduceThreads;
+    const int t = threadIdx.x;
+    for (int s = a.wg_sys[wg]; s < a.wg_sys[wg + 1]; ++s) {
+        double acc = 0.0;
+        for (int r = a.sys_run[s]; r < a.sys_run[s + 1]; ++r) {
+            const double *base = a.eslot + (long long)a.run_begin[r] * A_N;
+            const int n = a.run_len[r] * A_N;
+#pragma unroll 8
+            for (int k = t; k < n; k += T) acc += base[k];
         }
-        const double *p = a.eslot + (long long)a.order[i] * A_N;
-#pragma unroll
-        for (int k = 0; k < A_N; ++k) v[k] += p[k];
-    }
-    // final flush: one LDS atomic per wave when the wave shares a system
-    const int c0 = __shfl(cur, 0, 64);
-    if (__all(cur == c0)) {
-#pragma unroll
-        for (int k = 0; k < A_N; ++k) v[k] = wsum(v[k]);
-        if ((threadIdx.x & 63) == 0 && c0 >= 0)
-            for (int k = 0; k < A_N; ++k)
-                if (v[k] != 0.0) atomicAdd(&lds[(c0 - s_lo) * A_N + k], v[k]);
-    } else if (cur >= 0) {
-        for (int k = 0; k < A_N; ++k)
-            if (v[k] != 0.0) atomicAdd(&lds[(cur - s_lo) * A_N + k], v[k]);
-    }
-    __syncthreads();
-    for (int x = threadIdx.x; x < ns * A_N; x += T)
-        if (lds[x] != 0.0) unsafeAtomicAdd(&a.sums[(long long)s_lo_sh * A_N + x], lds[x]);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == (unsigned)(a.n_wg - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int s0 = 0; s0 < a.n_sys; s0 += kReduceSysPerWg) {
-        const int m = min(kReduceSysPerWg, a.n_sys - s0);
-        for (int x = threadIdx.x; x < m * A_N; x += T) {
-            unsigned long long *pp = (unsigned long long *)(a.sums + (long long)s0 * A_N + x);
-            lds[x] = __longlong_as_double((long long)atomicExch(pp, 0ull));
+        lds[t] = acc;
+        __syncthreads();
+        if (t < A_N) {
+            double v = 0.0;
+            for (int x = t; x < T; x += A_N) v += lds[x];
+            lds[T + t] = v;
         }
         __syncthreads();
-        for (int s = threadIdx.x; s < m; s += T) energy_outputs(a, s0 + s, lds + s * A_N);
+        if (t == 0) energy_outputs(a, s, lds + T);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
 }
 
 }  // namespace mixpi

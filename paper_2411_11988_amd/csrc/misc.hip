@@ -63,8 +63,14 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
             const long long x = 3 * row + lane;
             const double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
             a.f[x] = fx;
-            const double pv = a.p[x] + a.row_hk[row] * fx;
+            const double hk = a.row_hk[row];
+            const double pv = a.p[x] + hk * fx;
             a.p[x] = pv;
+            const int st = a.row_stage[row];
+            if (st >= 0) {
+                a.stage[6LL * st + lane] = a.q[x];
+                a.stage[6LL * st + 3 + lane] = pv + hk * fx;
+            }
             ke = pv * pv / (2.0 * a.row_fm[row]);
             vir = (a.q[x] - a.cent[x]) * fx;
         }
@@ -86,15 +92,33 @@ void launch_finish(const FinishLaunch &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce(ReduceLaunch a)
+__global__ __launch_bounds__(256) void k_stage(StageLaunch a)
 {
-    __shared__ double acc[kReduceSysPerWg * A_N];
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= 3LL * a.n) return;
+    const long long s = x / 3;
+    const int c = (int)(x - 3 * s);
+    const long long g = 3 * a.rows[s] + c;
+    a.stage[6 * s + c] = a.q[g];
+    a.stage[6 * s + 3 + c] = a.p[g] + a.row_hk[a.rows[s]] * a.f[g];
+}
+
+void launch_stage(const StageLaunch &a, hipStream_t st)
+{
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)((3LL * a.n + 255) / 256)), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceLaunch a)
+{
+    __shared__ double acc[kReduceThreads + A_N];
     reduce_part(a, blockIdx.x, acc);
 }
 
 void launch_reduce(const ReduceLaunch &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(a.n_wg), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reduce, dim3(a.n_wg), dim3(kReduceThreads), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -112,6 +136,18 @@ void launch_fill(double *x, long long n, double v, hipStream_t st)
     long long blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, x, n, v);
+}
+
+// Holds the stream for `ticks` of the 100 MHz wall clock (bounded wait).
+__global__ void k_delay(long long ticks)
+{
+    const long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(16);
+}
+
+void launch_delay(long long ticks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_delay, dim3(1), dim3(1), 0, st, ticks);
 }
 
 // dq <- -grad_e[sys] * dq (dq holds F on entry).

@@ -83,7 +83,9 @@ struct BlockRange {
 };
 
 // free ring-polymer / normal-mode work item
-enum { RP_DENSE = 0, RP_FFT = 1 };
+enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
+constexpr int kCircOut = 32;       // bead outputs per circulant item
+constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
 enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2 };
 struct RpItem {
     int kind, sys, N, logN;
@@ -93,6 +95,10 @@ struct RpItem {
     int c0, ncols;        // dense: column range (particle*3 + dim); fft: column c0
     int basis_off;        // offset (doubles) of the dense basis of size N
     int tw_off;           // offset (complex) of the stage-major twiddle table of N
+    int o0;               // circulant: first bead output of the item
+    int circ_off;         // circulant: offset (doubles) of the particle's a, b, c rows
+    int stage0;           // circulant: stage row of the group's first bead row
+    double wsp;           // circulant: spring energy per squared bead step, kcal/mol/A^2
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -128,23 +134,24 @@ struct BondedLaunch {
 // One launch: the pair tiles, then the bonded workgroups (64 terms each).
 void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
                  hipStream_t st);
+// The bonded workgroups alone.
+void launch_bonded(const BondedLaunch &b, bool with_theta, hipStream_t st);
 
-// Sums the energy slots listed per system and writes either e_out
-// [n_sys][NV] or an energy-log row [n_sys][NE]; adds the pair-evaluation
-// counts to npairs[2]; with dtheta, writes grad_e * dV/dtheta [n_sys][6].
-// n_wg workgroups each sum a contiguous share of the list into the global
-// per-system sums; the last one to finish (ticket) writes the outputs and
-// clears the sums and the ticket.
+// Sums the energy slots of each system and writes either e_out [n_sys][NV]
+// or an energy-log row [n_sys][NE]; adds the pair-evaluation counts to
+// npairs[2]; with dtheta, writes grad_e * dV/dtheta [n_sys][6].  A system's
+// slots are a few contiguous runs of the slot array; workgroup w owns the
+// whole systems wg_sys[w] .. wg_sys[w+1]-1, so every sum has one writer and
+// a fixed order.
 struct ReduceLaunch {
     const double *eslot;
-    const int *order;          // slot indices grouped by system
-    const int *order_sys;      // system of each entry of order (non-decreasing)
-    int n;                     // entries of order
+    const int *wg_sys;         // [n_wg + 1] first system of each workgroup
+    const int *sys_run;        // [n_sys + 1] first run of each system
+    const int *run_begin;      // first slot of each run
+    const int *run_len;        // slots in each run
     int n_wg;                  // reducer workgroups
     const SysDev *sys;
     int n_sys;
-    double *sums;              // [n_sys][A_N], zero between reductions
-    unsigned *ticket;          // zero between reductions
     double *e_out;             // [n_sys][NV] or null
     double *elog;              // [n_sys][NE] or null
     double *dtheta;            // [n_sys][6] or null
@@ -152,7 +159,7 @@ struct ReduceLaunch {
     unsigned long long *npairs;
     int *nonfinite;
 };
-constexpr int kReduceSysPerWg = 64;   // systems one reducer workgroup may span
+constexpr int kReduceThreads = 256;   // a multiple of A_N
 
 struct RpLaunch {
     const RpItem *items;
@@ -161,6 +168,8 @@ struct RpLaunch {
     const double *basis;     // dense bases C[j*N+k] then C^T, per N
     const double2 *twiddle;  // per N, stage-major exp(-2 pi i pos / 2^s), N - 1 entries
     const double *prop;      // [rows][5] a, b, c, d, spring coefficient
+    const double *circ;      // circulant propagator rows a_d, b_d, c_d per particle
+    const double *stage;     // circulant rings' step inputs [stage rows][6]: q, p + dt/2 F
     int op;
     const double *in_q;      // OP_STEP: q (in/out via out_q); FWD/BWD: input
     double *out_q;
@@ -192,12 +201,24 @@ struct FinishLaunch {
     double *f;                 // written: gathered forces
     const double *q, *cent;
     double *eslot;             // energy slot of block b: eslot + b * A_N
+    const int *row_stage;      // [rows] stage row of a circulant ring's bead row, or -1
+    double *stage;             // written for those rows: q, p + dt/2 F (next step's input)
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);
+
+// Fills the circulant rings' stage rows from (q, p, f): q, p + dt/2 f.
+struct StageLaunch {
+    const long long *rows;     // [n] bead row of each stage row
+    int n;
+    const double *q, *p, *f, *row_hk;
+    double *stage;
+};
+void launch_stage(const StageLaunch &a, hipStream_t st);
 
 void launch_reduce(const ReduceLaunch &a, hipStream_t st);
 
 void launch_fill(double *x, long long n, double v, hipStream_t st);
+void launch_delay(long long ticks_100mhz, hipStream_t st);
 void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);
 void launch_scale_rows(long long rows, const int *row_sys, const double *grad_e, double *dq,
                        hipStream_t st);

@@ -295,9 +295,28 @@ void launch_pair_tj(const PairLaunch &a, const BondedLaunch &b, int precision, b
     }
 }
 
+// The bonded workgroups alone (a system without pair work, and the
+// per-kernel timing).
+template <bool THETA>
+__global__ __launch_bounds__(64) void k_bonded(BondedLaunch bl)
+{
+    bonded_block<THETA>(bl, bl.blocks[blockIdx.x], bl.eslot + (long long)blockIdx.x * A_N, nullptr);
+}
+
+void launch_bonded(const BondedLaunch &b, bool with_theta, hipStream_t st)
+{
+    if (b.n_blocks <= 0) return;
+    if (with_theta) hipLaunchKernelGGL((k_bonded<true>), dim3(b.n_blocks), dim3(64), 0, st, b);
+    else hipLaunchKernelGGL((k_bonded<false>), dim3(b.n_blocks), dim3(64), 0, st, b);
+}
+
 void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
                  hipStream_t st)
 {
+    if (a.n_items <= 0) {
+        launch_bonded(b, with_theta, st);
+        return;
+    }
     if (a.n_items + b.n_blocks <= 0) return;
     if (a.tj == 32) launch_pair_tj<32>(a, b, precision, with_theta, st);
     else launch_pair_tj<64>(a, b, precision, with_theta, st);

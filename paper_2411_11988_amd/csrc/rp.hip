@@ -16,6 +16,10 @@
 //     N - m from Im Z_m, scaled by sqrt(2/N)), so the result equals the dense
 //     transform up to rounding with O(N log N) work instead of O(N^2).
 //
+//   * rings with N > 64 and few columns (up to a work budget): in the step,
+//     "circulant" items that propagate in bead space (rp_circ below) with
+//     many workgroups per column; the transforms still use the FFT items.
+//
 // OP_STEP fuses: first half-kick p += dt/2 F on load, forward transform,
 // exact propagation of every mode with tabulated coefficients
 // (xi, pi) <- (a xi + b pi, c xi + d pi), spring energy sum_k k lambda_k/2
@@ -289,18 +293,159 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
     }
 }
 
+// Free ring-polymer step in bead space for a many-bead ring with few
+// columns.  Its inputs (q and the half-kicked p) come from the ring's stage
+// rows, because the items of a column write q and p in place.  The exact free propagator C diag(f_k) C^T of each of the maps
+// (q <- a q + b p, p <- c q + a p) depends on the bead index only through
+// j - j' (every f_k depends on lambda_k, shared by modes k and N - k), so
+// it is circulant: a_d = (1/N) sum_k f_k cos(2 pi k d / N), tabulated per
+// particle on the host.  An item computes kCircOut consecutive bead outputs
+// of one column from the whole ring: the centroid parts move exactly
+// (q_bar' = q_bar + dt/m_f p_bar, p_bar' = p_bar), the rest is the
+// convolution of the centroid-free ring with a, b, c.  Thread (og, jg) sums
+// 4 consecutive outputs over a contiguous 1/32 of the ring, sliding its
+// coefficient window by one per bead; LDS rows are padded by one double per
+// 1/32 segment so the lanes of a wave hit distinct banks.  The spring
+// energy of the item's bead steps (j, j+1), j in the item, needs one more
+// output, formed as a block-wide dot product.
+__device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, double *red)
+{
+    const int N = it.N, n = it.n, L = it.logN;
+    const int col = it.c0, i = col / 3;
+    const int tid = threadIdx.x;
+    const int lseg = L - 5;                      // segment of N/32 beads
+    const int seg = 1 << lseg;
+    const int NP = N + 32;                       // padded row length
+    auto pad = [&](int x) { return x + (x >> lseg); };
+    double *sq = smem, *sp = sq + NP, *ca = sp + NP, *cb = ca + NP, *cc = cb + NP;
+    double *part = cc + NP;                      // [32 jg][kCircOut][2]
+    __shared__ double s_mean[2];
+    const double *coef = a.circ + it.circ_off;
+    auto gaddr = [&](int j) { return (it.row + (long long)j * n) * 3 + col; };
+
+    // inputs from the stage rows (written before the launch): other items of
+    // this column overwrite q and p in place while this one still reads
+    const int d = col - 3 * i;
+    double sum_q = 0.0, sum_p = 0.0;
+    for (int j = tid; j < N; j += 256) {
+        const double *sr = a.stage + 6LL * (it.stage0 + (long long)j * n + i);
+        const double qv = sr[d];
+        const double pv = sr[3 + d];
+        const int x = pad(j);
+        sq[x] = qv;
+        sp[x] = pv;
+        ca[x] = coef[j];
+        cb[x] = coef[N + j];
+        cc[x] = coef[2 * N + j];
+        sum_q += qv;
+        sum_p += pv;
+    }
+    sum_q = bsum256(sum_q, red);
+    sum_p = bsum256(sum_p, red);
+    if (tid == 0) {
+        s_mean[0] = sum_q / N;
+        s_mean[1] = sum_p / N;
+    }
+    __syncthreads();
+    const double qbar = s_mean[0], pbar = s_mean[1];
+    for (int j = tid; j < N; j += 256) {
+        const int x = pad(j);
+        sq[x] -= qbar;
+        sp[x] -= pbar;
+    }
+    __syncthreads();
+
+    // thread (og, jg): outputs o0 + 4 og + r, beads jg*seg .. jg*seg + seg - 1
+    const int lane = tid & 63;
+    const int og = lane & 7, jg = ((tid >> 6) << 3) + (lane >> 3);
+    const int i0 = it.o0 + 4 * og;
+    const int jb = jg * seg;
+    double wa[4], wb[4], wc[4], dq[4], dp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = pad((i0 + r - jb) & (N - 1));
+        wa[r] = ca[x];
+        wb[r] = cb[x];
+        wc[r] = cc[x];
+        dq[r] = 0.0;
+        dp[r] = 0.0;
+    }
+#pragma unroll 4
+    for (int t = 0; t < seg; ++t) {
+        const int j = jb + t;
+        const double qj = sq[pad(j)], pj = sp[pad(j)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dq[r] += wa[r] * qj + wb[r] * pj;
+            dp[r] += wc[r] * qj + wa[r] * pj;
+        }
+        const int x = pad((i0 - j - 1) & (N - 1));
+#pragma unroll
+        for (int r = 3; r > 0; --r) {
+            wa[r] = wa[r - 1];
+            wb[r] = wb[r - 1];
+            wc[r] = wc[r - 1];
+        }
+        wa[0] = ca[x];
+        wb[0] = cb[x];
+        wc[0] = cc[x];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        part[(jg * kCircOut + 4 * og + r) * 2] = dq[r];
+        part[(jg * kCircOut + 4 * og + r) * 2 + 1] = dp[r];
+    }
+    // the output after the item (for its last bead step): block dot product
+    const int inext = (it.o0 + kCircOut) & (N - 1);
+    double nx = 0.0;
+    for (int j = tid; j < N; j += 256) {
+        const int x = pad((inext - j) & (N - 1));
+        nx += ca[x] * sq[pad(j)] + cb[x] * sp[pad(j)];
+    }
+    nx = bsum256(nx, red);      // valid in thread 0; the barriers also cover `part`
+    __shared__ double s_out[kCircOut + 1];
+    const double dtm = a.prop[5 * (it.row + i) + 1];   // mode 0: dt / m_f
+    const double qc = qbar + dtm * pbar;               // new centroid
+    if (tid < kCircOut) {
+        double vq = 0.0, vp = 0.0;
+        for (int g = 0; g < 32; ++g) {
+            vq += part[(g * kCircOut + tid) * 2];
+            vp += part[(g * kCircOut + tid) * 2 + 1];
+        }
+        s_out[tid] = vq;
+        const long long gq = gaddr(it.o0 + tid);
+        a.out_q[gq] = qc + vq;
+        a.p[gq] = pbar + vp;
+        a.cent[gq] = qc;
+    }
+    if (tid == 0) s_out[kCircOut] = nx;
+    __syncthreads();
+    double esp = 0.0;
+    if (tid < kCircOut) {
+        const double dlt = s_out[tid] - s_out[tid + 1];
+        esp = it.wsp * dlt * dlt;
+    }
+    esp = bsum256(esp, red);
+    if (tid == 0) {
+        double *e = a.eslot + (long long)blockIdx.x * A_N;
+        for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+        e[A_SPRING] = esp;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
 {
     extern __shared__ __align__(16) double smem[];
     __shared__ double red[4];
     if ((int)blockIdx.x >= a.n_items) {
         // the extra workgroups: energy reducer of the previous step
-        // (the dynamic LDS holds at least kReduceSysPerWg * A_N doubles)
+        // (the dynamic LDS holds at least kReduceThreads + A_N doubles)
         reduce_part(a.reduce, blockIdx.x - a.n_items, smem);
         return;
     }
     const RpItem it = a.items[blockIdx.x];
     if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);
+    else if (it.kind == RP_CIRC) rp_circ(a, it, smem, red);
     else rp_fft(a, it, reinterpret_cast<double2 *>(smem), red);
 }
 

@@ -87,7 +87,7 @@ def load():
         "mixpi_pair_candidates": ([P, P], C.c_int),
         "mixpi_pair_evals": ([P, P, I32, P], C.c_int),
         "mixpi_step_prepare": ([P, I32, P, P, P, P], C.c_int),
-        "mixpi_kernel_time": ([P, I32, I32, P, P, P, P], C.c_int),
+        "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -217,11 +217,13 @@ def mixpi_step_prepare(h, nsteps: int, q, p, f, elog) -> None:
 KERNEL_PAIR, KERNEL_BONDED, KERNEL_RP, KERNEL_FINISH = 0, 1, 2, 3
 
 
-def mixpi_kernel_time(h, which: int, reps: int, q, p, stream=None) -> float:
-    v = C.c_double()
-    _check(load().mixpi_kernel_time(h, int(which), int(reps), _ptr(q), _ptr(p), C.byref(v),
+def mixpi_kernel_time(h, reps: int, q, p, f, stream=None) -> dict:
+    """Mean in-step durations (us) of the force, free ring-polymer and
+    epilogue launches over `reps` eager steps on library copies of q, p, f."""
+    v = (C.c_double * 3)()
+    _check(load().mixpi_kernel_time(h, int(reps), _ptr(q), _ptr(p), _ptr(f), v,
                                     _stream(stream)))
-    return v.value
+    return {"force": v[0], "free_rp": v[1], "finish": v[2]}
 
 
 # ---- convenience object ------------------------------------------------------
@@ -313,8 +315,8 @@ class System:
     def step_prepare(self, nsteps: int, q, p, f, elog=None):
         mixpi_step_prepare(self.h, nsteps, q, p, f, elog)
 
-    def kernel_time(self, which: int, reps: int, q, p, stream=None) -> float:
-        return mixpi_kernel_time(self.h, which, reps, q, p, stream)
+    def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
+        return mixpi_kernel_time(self.h, reps, q, p, f, stream)
 
 
 def energy_function():

@@ -156,41 +156,145 @@ def _min_image_dist(a: np.ndarray, b: np.ndarray, box: np.ndarray) -> np.ndarray
     return np.sqrt((d * d).sum(axis=1))
 
 
+def _rotations(u: np.ndarray) -> np.ndarray:
+    """Rotation matrices [K, 3, 3] from uniform unit quaternions built from
+    u [K, 3] uniform in [0, 1) (the same map as ``_random_rotation``)."""
+    u1, u2, u3 = u[:, 0], u[:, 1], u[:, 2]
+    x = np.sqrt(1 - u1) * np.sin(2 * np.pi * u2)
+    y = np.sqrt(1 - u1) * np.cos(2 * np.pi * u2)
+    z = np.sqrt(u1) * np.sin(2 * np.pi * u3)
+    w = np.sqrt(u1) * np.cos(2 * np.pi * u3)
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1),
+    ], 1)
+
+
+class _Grid:
+    """Cell grid over a cubic periodic box holding at most one point per
+    cell (cell diagonal below the smallest allowed point distance)."""
+
+    def __init__(self, box: float, min_sep: float, reach: float):
+        self.box = box
+        self.n = max(1, int(math.ceil(box / (0.99 * min_sep / math.sqrt(3.0)))))
+        self.h = box / self.n
+        self.cell = np.full(self.n ** 3, -1, dtype=np.int64)
+        self.pos = np.zeros((0, 3))
+        r = int(math.ceil(reach / self.h))
+        o = np.arange(-r, r + 1)
+        off = np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3)
+        # keep the cells that can hold a point within `reach` of the centre cell
+        gap = np.maximum(np.abs(off) - 1, 0) * self.h
+        self.off = off[(gap * gap).sum(-1) <= reach * reach]
+
+    def _flat(self, c):
+        c = np.mod(c, self.n)
+        return (c[..., 0] * self.n + c[..., 1]) * self.n + c[..., 2]
+
+    def min_dist(self, x: np.ndarray) -> np.ndarray:
+        """Nearest-image distance from each x [K, 3] to the closest stored
+        point (inf if none is within the grid reach)."""
+        if len(self.pos) == 0:
+            return np.full(len(x), np.inf)
+        c = np.floor(np.mod(x, self.box) / self.h).astype(np.int64)
+        idx = self.cell[self._flat(c[:, None, :] + self.off[None])]   # [K, M]
+        d = x[:, None, :] - self.pos[np.maximum(idx, 0)]
+        d -= self.box * np.rint(d / self.box)
+        r = np.sqrt((d * d).sum(-1))
+        r[idx < 0] = np.inf
+        return r.min(axis=1)
+
+    def add(self, x: np.ndarray):
+        c = np.floor(np.mod(x, self.box) / self.h).astype(np.int64)
+        f = self._flat(c)
+        if np.any(self.cell[f] >= 0):
+            raise RuntimeError("grid cell already occupied")
+        self.cell[f] = np.arange(len(self.pos), len(self.pos) + len(x))
+        self.pos = np.vstack([self.pos, x])
+
+
 def _place_waters(rng, n_waters: int, box: float, centre_excl: float,
                   min_dist: float = 1.6, min_oo: float = 2.6,
                   ion_pos: np.ndarray | None = None):
     """Rigid waters by random sequential addition with random orientations.
 
-    Each molecule draws (oxygen position uniform in the box, rotation) until
-    its oxygen is ``min_oo`` from every placed oxygen, each of its atoms is
-    ``min_dist`` from every placed atom, and its oxygen is ``centre_excl``
-    from the cation (hydrogens ``centre_excl - 0.6``).
+    A candidate is an oxygen position drawn uniformly from the part of the
+    box not yet known to be excluded, and a uniform random rotation.  It is
+    placed if its oxygen is ``min_oo`` from every placed oxygen, its atoms
+    are ``min_dist`` from every placed atom, and its oxygen (hydrogens) keep
+    ``centre_excl`` (``centre_excl - 0.6``) from the cation.  Excluded space
+    is tracked on a fine cell grid: a cell lying wholly within ``min_oo`` of
+    a placed oxygen (or ``centre_excl`` of the cation) can hold no oxygen of
+    a later water, so drawing from any superset of the remaining cells gives
+    the same distribution of placements as drawing from the whole box.
     """
     geo = _water_geometry()
     boxv = np.full(3, float(box))
-    oxy = np.zeros((0, 3))
-    atoms = np.zeros((0, 3))
+    g_o = _Grid(box, min_oo, min_oo)
+    g_a = _Grid(box, 0.999, min_dist)
+    # free-space cells for oxygen candidates
+    nf = max(1, int(math.ceil(box / 0.4)))
+    hf = box / nf
+    free = np.ones(nf ** 3, dtype=bool)
+    half_diag = 0.5 * math.sqrt(3.0) * hf
+    ctr = (np.arange(nf) + 0.5) * hf
+
+    def block(x, radius):
+        r_in = radius - half_diag
+        if r_in <= 0:
+            return
+        k = int(math.ceil(r_in / hf)) + 1
+        c = np.floor(np.mod(x, box) / hf).astype(np.int64)
+        o = np.arange(-k, k + 1)
+        cells = (c[None, :] + np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3))
+        cw = np.mod(cells, nf)
+        d = ctr[cw] - np.mod(x, box)[None, :]
+        d -= box * np.rint(d / box)
+        inside = (d * d).sum(-1) < r_in * r_in
+        cw = cw[inside]
+        free[(cw[:, 0] * nf + cw[:, 1]) * nf + cw[:, 2]] = False
+
+    if ion_pos is not None:
+        block(ion_pos, centre_excl)
     coords = []
-    for _ in range(n_waters):
-        for attempt in range(100000):
-            centre = rng.uniform(0.0, box, 3)
-            mol = centre + geo @ _random_rotation(rng).T
-            if len(oxy) and _min_image_dist(mol[0], oxy, boxv).min() < min_oo:
-                continue
-            if len(atoms) and min(_min_image_dist(a, atoms, boxv).min()
-                                  for a in mol) < min_dist:
-                continue
+    chunk = 16
+    cells = np.flatnonzero(free)
+    for w in range(n_waters):
+        if w % 16 == 0:
+            # a stale list is a superset of the free cells: still exact
+            cells = np.flatnonzero(free)
+        if len(cells) == 0:
+            raise RuntimeError("water placement failed; box too dense")
+        for attempt in range(2000):
+            pick = cells[rng.integers(0, len(cells), chunk)]
+            cz, cy, cx = pick % nf, (pick // nf) % nf, pick // (nf * nf)
+            base = np.stack([cx, cy, cz], -1) * hf
+            centres = base + rng.uniform(0.0, hf, (chunk, 3))
+            mols = centres[:, None, :] + np.einsum("aj,kij->kai", geo,
+                                                  _rotations(rng.random((chunk, 3))))
+            ok = np.ones(chunk, dtype=bool)
             if ion_pos is not None:
-                if _min_image_dist(ion_pos, mol[:1], boxv)[0] < centre_excl:
-                    continue
-                if _min_image_dist(ion_pos, mol[1:], boxv).min() < centre_excl - 0.6:
-                    continue
-            break
+                d = mols - ion_pos[None, None, :]
+                d -= boxv * np.rint(d / boxv)
+                r = np.sqrt((d * d).sum(-1))
+                ok &= (r[:, 0] >= centre_excl) & (r[:, 1:].min(axis=1) >= centre_excl - 0.6)
+            cand = np.flatnonzero(ok)
+            cand = cand[g_o.min_dist(mols[cand, 0]) >= min_oo]
+            if len(cand):
+                da = g_a.min_dist(mols[cand].reshape(-1, 3)).reshape(len(cand), 3)
+                cand = cand[da.min(axis=1) >= min_dist]
+            if len(cand):
+                mol = mols[cand[0]]
+                chunk = int(min(256, max(16, 2 * (cand[0] + 1))))
+                break
+            chunk = min(256, 2 * chunk)
         else:
             raise RuntimeError("water placement failed; box too dense")
         coords.append(mol)
-        oxy = np.vstack([oxy, mol[:1]])
-        atoms = np.vstack([atoms, mol])
+        g_o.add(mol[:1])
+        g_a.add(mol)
+        block(mol[0], min_oo)
     return np.array(coords)  # [n_waters, 3 atoms, 3]
 
 

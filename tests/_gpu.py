@@ -54,6 +54,17 @@ def energy_err(e, eo):
     return float((np.abs(e - eo) / den).max())
 
 
+def energy_err_scale(e, eo):
+    """Largest error of any energy term relative to the potential-energy
+    scale sum_k |V_k| (LJ, Coulomb, pseudopotential, bond, angle): the
+    bar of the FP32 form, whose pair arithmetic cannot resolve a net term
+    below the rounding of its own cancelling contributions."""
+    e, eo = np.asarray(e, dtype=np.float64), np.asarray(eo, dtype=np.float64)
+    scale = np.abs(eo[1:6]).sum()
+    n = min(len(e), len(eo))
+    return float(np.abs(e[:n] - eo[:n]).max() / scale)
+
+
 def dev(x):
     import torch
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
