@@ -105,7 +105,7 @@ typedef struct {
     const double *fict_mass;       /* [n] fictitious bead mass m_f, amu (> 0) */
     const double *charge;          /* [n] e */
     const int32_t *lj_type;        /* [n] in [0, n_lj_types) or -1 (no LJ) */
-    const int32_t *mol_id;         /* [n] equal ids exclude nonbonded pairs */
+    const int32_t *mol_id;         /* [n] in [0, 2^27); equal ids exclude nonbonded pairs */
     const int32_t *is_electron;    /* [n] 0/1 */
     int32_t n_lj_types;            /* <= 8 */
     const double *lj_eps;          /* [n_lj_types^2] kcal/mol, symmetric */

@@ -81,6 +81,7 @@ struct mixpi_system {
     long long candidates = 0;
     std::vector<long long> bead_index;
     int pair_tj = 64;
+    int pair_waves = 1;
 
     SysDev *d_sys = nullptr;
     double *d_lj_eps = nullptr, *d_lj_sig = nullptr, *d_charge = nullptr;
@@ -111,7 +112,7 @@ struct mixpi_system {
     double *d_prop = nullptr;
     // partial forces and their per-row gather lists
     long long *d_row_ptr = nullptr;
-    int *d_slot = nullptr;
+    int *d_dest = nullptr;
     double *d_part = nullptr;
     long long n_slots = 0, part_bonded = 0;
     // epilogue blocks (4 rows of one system)
@@ -122,10 +123,12 @@ struct mixpi_system {
     // the force-only range and for the whole step
     double *d_eslot = nullptr;
     // reducer plans: the force-only slots [0, e_rp) and the whole step
-    int *d_red_f = nullptr, *d_red_a = nullptr;   // packed wg_sys | sys_run | begin | len
-    int red_f_off[4] = {0, 0, 0, 0}, red_a_off[4] = {0, 0, 0, 0};
+    int *d_red_f = nullptr, *d_red_a = nullptr;   // packed chunk_begin | chunk_len | sys_chunk
+    int red_f_off[3] = {0, 0, 0}, red_a_off[3] = {0, 0, 0};
+    int nch_f = 0, nch_a = 0;         // chunks of each list
+    double *d_partial = nullptr;      // [max chunks][A_N] stage-A sums
     int n_eslots = 0, e_bonded = 0, e_rp = 0, e_fin = 0;
-    int nwg_f = 1, nwg_a = 1;         // reducer workgroups for each list
+
     unsigned long long *d_npairs = nullptr;
     int *d_nonfinite = nullptr;
     double *d_cent = nullptr;
@@ -149,7 +152,8 @@ void release(mixpi_system *s)
                     s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
                     s->d_row_stage, s->d_stage_rows, s->d_basis, s->d_tw,
                     s->d_prop, s->d_row_ptr,
-                    s->d_slot, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
+                    s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
+                    s->d_partial,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -192,6 +196,9 @@ int validate(const mixpi_system_desc *d, int idx)
                         d->lj_type[i]);
         if (d->is_electron[i] != 0 && d->is_electron[i] != 1)
             return fail(MIXPI_E_INVALID, "system %d: is_electron must be 0 or 1", idx);
+        if (d->mol_id[i] < 0 || d->mol_id[i] >= (1 << 27))
+            return fail(MIXPI_E_INVALID, "system %d: particle %d has mol_id %d (range [0, 2^27))",
+                        idx, i, d->mol_id[i]);
     }
     const int nt = d->n_lj_types;
     for (int k = 0; k < nt * nt; ++k)
@@ -607,7 +614,7 @@ void add_circulant(Build &B, const RpItem &rg, int stage0, std::vector<RpItem> &
                 items.push_back(it);
             }
     }
-    B.rp_lds = std::max(B.rp_lds, (unsigned)((5 * (N + 32) + 2 * 32 * kCircOut) * sizeof(double)));
+    B.rp_lds = std::max(B.rp_lds, (unsigned)((5 * (kCircMaxN + 64) + 2 * (256 / (kCircOut / 4)) * kCircOut) * sizeof(double)));
 }
 
 // Cuts the pair blocks with block_slow == slow into 64 x tj tiles: for each
@@ -655,57 +662,37 @@ std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin,
     return out;
 }
 
-// Reducer plan for the slots [0, n): each system's slots as maximal
-// contiguous runs (in slot order), and whole systems dealt to at most 32
-// workgroups in order, balanced by slot count.  Packed as
-// wg_sys[n_wg + 1] | sys_run[n_sys + 1] | run_begin[runs] | run_len[runs];
-// off[] receives the four offsets.  Returns n_wg.
+// Reducer plan for the slots [0, n): each system's slots (in slot order)
+// cut into chunks of at most kChunkSlots consecutive slots of that system.
+// Packed as chunk_begin[n_chunks] | chunk_len[n_chunks] | sys_chunk[n_sys + 1];
+// off[] receives the three offsets.  Returns n_chunks.
 int reducer_plan(const std::vector<int> &eslot_sys, int n, int n_sys, std::vector<int> &out,
-                 int off[4])
+                 int off[3])
 {
     std::vector<std::vector<std::pair<int, int>>> runs(n_sys);
     for (int k = 0; k < n;) {
         int e = k;
-        while (e < n && eslot_sys[e] == eslot_sys[k]) ++e;
+        while (e < n && eslot_sys[e] == eslot_sys[k] && e - k < kChunkSlots) ++e;
         runs[eslot_sys[k]].push_back({k, e - k});
         k = e;
     }
-    std::vector<long long> cnt(n_sys, 0);
-    for (int x = 0; x < n_sys; ++x)
-        for (auto &r : runs[x]) cnt[x] += r.second;
-    const int n_wg = std::max(1, std::min(n_sys, 32));
-    std::vector<int> wg_sys(n_wg + 1, n_sys);
-    wg_sys[0] = 0;
-    long long done = 0;
-    int w = 1, x = 0;
-    for (; x < n_sys && w < n_wg; ++x) {
-        done += cnt[x];
-        // close workgroup w-1 once it holds its share, leaving a system for
-        // each remaining workgroup
-        if (done * n_wg >= (long long)w * std::max<long long>(n, 1) || n_sys - (x + 1) <= n_wg - w)
-            wg_sys[w++] = x + 1;
-    }
-    for (; w <= n_wg; ++w) wg_sys[w] = n_sys;
-    std::vector<int> sys_run(n_sys + 1, 0), rb, rl;
+    std::vector<int> cb, cl, sys_chunk(n_sys + 1, 0);
     for (int y = 0; y < n_sys; ++y) {
-        sys_run[y] = (int)rb.size();
+        sys_chunk[y] = (int)cb.size();
         for (auto &r : runs[y]) {
-            rb.push_back(r.first);
-            rl.push_back(r.second);
+            cb.push_back(r.first);
+            cl.push_back(r.second);
         }
     }
-    sys_run[n_sys] = (int)rb.size();
+    sys_chunk[n_sys] = (int)cb.size();
     out.clear();
     off[0] = 0;
-    out.insert(out.end(), wg_sys.begin(), wg_sys.end());
+    out.insert(out.end(), cb.begin(), cb.end());
     off[1] = (int)out.size();
-    out.insert(out.end(), sys_run.begin(), sys_run.end());
+    out.insert(out.end(), cl.begin(), cl.end());
     off[2] = (int)out.size();
-    out.insert(out.end(), rb.begin(), rb.end());
-    off[3] = (int)out.size();
-    out.insert(out.end(), rl.begin(), rl.end());
-    if (out.empty()) out.push_back(0);
-    return n_wg;
+    out.insert(out.end(), sys_chunk.begin(), sys_chunk.end());
+    return (int)cb.size();
 }
 
 // Partial-force slots and the per-row gather lists.  Slot numbering: pair
@@ -714,9 +701,9 @@ int reducer_plan(const std::vector<int> &eslot_sys, int n, int n_sys, std::vecto
 // beads r[0], r[1] (and r[2] of an angle).  Rows list their slots in this
 // order, so every gather sums in a fixed order.
 struct Gather {
-    std::vector<long long> row_ptr;
-    std::vector<int> slot;
-    long long n_slots = 0;
+    std::vector<long long> row_ptr;   // [rows + 1] CSR positions of each row's slots
+    std::vector<int> dest;            // [n_slots] position of each natural slot, -1 unused
+    long long n_slots = 0;            // natural slots (pair items, then bonded terms)
 };
 
 Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
@@ -750,9 +737,9 @@ Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
     G.n_slots = visit([&](long long row, long long) { ++cnt[row + 1]; });
     for (long long r = 0; r < rows; ++r) cnt[r + 1] += cnt[r];
     G.row_ptr = cnt;
-    G.slot.resize(cnt[rows]);
+    G.dest.assign((size_t)G.n_slots, -1);
     std::vector<long long> fill(cnt.begin(), cnt.end() - 1);
-    visit([&](long long row, long long sl) { G.slot[fill[row]++] = (int)sl; });
+    visit([&](long long row, long long sl) { G.dest[sl] = (int)fill[row]++; });
     return G;
 }
 
@@ -801,6 +788,13 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         items.insert(items.end(), slow.begin(), slow.end());
     }
     S->n_items = (int)items.size();
+    // two waves per tile while the launch has fewer than ~4 tiles per SIMD
+    // (1024 SIMDs): more, shorter waves even out the SIMDs and hide latency
+    S->pair_waves = S->n_items < 4096 ? 2 : 1;
+    if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
+        const int v = atoi(env);
+        if (v == 1 || v == 2) S->pair_waves = v;
+    }
 
     // bonded terms and their system-pure blocks
     std::vector<BondedTerm> terms = B.bterms;
@@ -847,7 +841,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         S->n_stage = (int)stage_rows.size();
     }
     S->n_rp = (int)rp.size();
-    S->rp_lds = std::max<unsigned>(B.rp_lds, (kReduceThreads + A_N) * sizeof(double));
+    S->rp_lds = std::max<unsigned>(B.rp_lds, kReduceThreads * sizeof(double));
 
     // epilogue blocks: 4 rows of one system
     std::vector<BlockRange> fblocks;
@@ -877,8 +871,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
     // per-system slot lists (stable order) for the reducer
     std::vector<int> red_f, red_a;
-    S->nwg_f = reducer_plan(eslot_sys, S->e_rp, n_sys, red_f, S->red_f_off);
-    S->nwg_a = reducer_plan(eslot_sys, S->n_eslots, n_sys, red_a, S->red_a_off);
+    S->nch_f = reducer_plan(eslot_sys, S->e_rp, n_sys, red_f, S->red_f_off);
+    S->nch_a = reducer_plan(eslot_sys, S->n_eslots, n_sys, red_a, S->red_a_off);
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -911,12 +905,13 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_tw, B.tw));
     T(upload(&S->d_prop, B.prop));
     T(upload(&S->d_row_ptr, G.row_ptr));
-    T(upload(&S->d_slot, G.slot));
-    T(upload(&S->d_part, std::vector<double>((size_t)3 * std::max<long long>(G.n_slots, 1), 0.0)));
+    T(upload(&S->d_dest, G.dest.empty() ? std::vector<int>(1, -1) : G.dest));
+    T(upload(&S->d_part, std::vector<double>((size_t)3 * std::max<long long>(G.row_ptr.back(), 1), 0.0)));
     T(upload(&S->d_fblocks, fblocks));
     T(upload(&S->d_eslot, std::vector<double>((size_t)2 * A_N * std::max(S->n_eslots, 1), 0.0)));
     T(upload(&S->d_red_f, red_f));
     T(upload(&S->d_red_a, red_a));
+    T(upload(&S->d_partial, std::vector<double>((size_t)A_N * std::max(1, std::max(S->nch_f, S->nch_a)), 0.0)));
     T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
     T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
@@ -959,6 +954,7 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.items = s->d_items + lo;
     a.n_items = hi - lo;
     a.tj = s->pair_tj;
+    a.waves = s->pair_waves;
     a.blocks = s->d_blocks;
     a.sys = s->d_sys;
     a.lj_eps = s->d_lj_eps;
@@ -968,6 +964,7 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.mol = s->d_mol;
     a.q = q;
     a.part = s->d_part;
+    a.dest = s->d_dest;
     a.item0 = lo;
     a.theta = theta;
     a.eslot = eslot_buf(s, buf);
@@ -990,6 +987,7 @@ BondedLaunch bonded_args(mixpi_system *s, const double *q, const double *theta, 
     b.angle_t0 = s->d_angle_t0;
     b.q = q;
     b.part = s->d_part;
+    b.dest = s->d_dest;
     b.part_base = s->part_bonded;
     b.theta = theta;
     b.eslot = eslot_buf(s, buf) + (long long)(s->e_bonded + lo) * A_N;
@@ -998,22 +996,30 @@ BondedLaunch bonded_args(mixpi_system *s, const double *q, const double *theta, 
 
 GatherArgs gather_args(mixpi_system *s)
 {
-    return GatherArgs{s->d_row_ptr, s->d_slot, s->d_part};
+    return GatherArgs{s->d_row_ptr, s->d_part};
 }
 
-// Reducer over buffer buf: the force-only slots (pair + bonded) or the
-// slots of a whole step.
-ReduceLaunch reduce_args(mixpi_system *s, int buf, bool whole_step)
+// Stage A over buffer buf and stage B of the force-only slots (pair +
+// bonded) or of the slots of a whole step.
+ReduceA reduce_a_args(mixpi_system *s, int buf, bool whole_step)
 {
-    ReduceLaunch r{};
+    ReduceA r{};
     r.eslot = eslot_buf(s, buf);
     const int *plan = whole_step ? s->d_red_a : s->d_red_f;
     const int *off = whole_step ? s->red_a_off : s->red_f_off;
-    r.wg_sys = plan + off[0];
-    r.sys_run = plan + off[1];
-    r.run_begin = plan + off[2];
-    r.run_len = plan + off[3];
-    r.n_wg = whole_step ? s->nwg_a : s->nwg_f;
+    r.chunk_begin = plan + off[0];
+    r.chunk_len = plan + off[1];
+    r.n_chunks = whole_step ? s->nch_a : s->nch_f;
+    r.partial = s->d_partial;
+    return r;
+}
+
+ReduceB reduce_b_args(mixpi_system *s, bool whole_step)
+{
+    ReduceB r{};
+    r.partial = s->d_partial;
+    r.sys_chunk = (whole_step ? s->d_red_a : s->d_red_f) + (whole_step ? s->red_a_off : s->red_f_off)[2];
+    r.n_wg = s->n_sys;
     r.sys = s->d_sys;
     r.n_sys = s->n_sys;
     r.npairs = s->d_npairs;
@@ -1100,25 +1106,33 @@ StageLaunch stage_args(mixpi_system *s, const double *q, const double *p, const 
     return a;
 }
 
-// Step k of a sequence: free ring polymers (with the first half-kick; one
-// extra workgroup reduces the energies of step k-1 into its log row), pair
-// and bonded partial forces, epilogue (gather F, second half-kick, kinetic
-// sums).  Steps alternate between the two energy-slot buffers so that the
-// reducer of step k-1 never meets the writers of step k.
+// Step k of a sequence: free ring polymers (with the first half-kick; extra
+// workgroups sum the energy slots of step k-1 into chunk partials), pair and
+// bonded partial forces, epilogue (gather F, second half-kick, kinetic sums;
+// extra workgroups turn the partials into the log row of step k-1).  Steps
+// alternate between the two energy-slot buffers so that the reduction of
+// step k-1 never meets the writers of step k.
 void enqueue_step(mixpi_system *s, int k, double *q, double *p, double *f, double *elog_prev,
-                  hipStream_t st)
+                  hipStream_t st, bool count = true)
 {
     const int buf = k & 1;
     RpLaunch r = rp_args(s, OP_STEP, q, q, p, f, buf);
+    FinishLaunch fl = finish_args(s, q, p, f, buf);
     if (k > 0) {
         r.with_reduce = 1;
-        r.reduce = reduce_args(s, buf ^ 1, true);
-        r.reduce.elog = elog_prev;
+        r.reduce = reduce_a_args(s, buf ^ 1, true);
+        fl.with_reduce = 1;
+        fl.reduce = reduce_b_args(s, true);
+        fl.reduce.elog = elog_prev;
+        if (!count) {
+            fl.reduce.npairs = nullptr;
+            fl.reduce.nonfinite = nullptr;
+        }
     }
     launch_rp(r, st);
     launch_pair(pair_args(s, q, nullptr, buf), bonded_args(s, q, nullptr, buf), s->precision,
                 false, st);
-    launch_finish(finish_args(s, q, p, f, buf), st);
+    launch_finish(fl, st);
 }
 
 // Finds or captures the graph of nsteps steps for these pointers.
@@ -1149,9 +1163,9 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
     for (int k = 0; k < nsteps; ++k)
         enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream);
     {
-        ReduceLaunch r = reduce_args(sys, (nsteps - 1) & 1, true);
-        r.elog = row(nsteps - 1);
-        launch_reduce(r, sys->cap_stream);
+        ReduceB rb = reduce_b_args(sys, true);
+        rb.elog = row(nsteps - 1);
+        launch_reduce(reduce_a_args(sys, (nsteps - 1) & 1, true), rb, sys->cap_stream);
     }
     HIP_TRY(hipStreamEndCapture(sys->cap_stream, &g.graph));
     hipError_t e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
@@ -1218,9 +1232,9 @@ int mixpi_forces(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     enqueue_forces(sys, q, theta, f, false, st);
-    ReduceLaunch r = reduce_args(sys, 0, false);
-    r.e_out = e_out;
-    launch_reduce(r, st);
+    ReduceB rb = reduce_b_args(sys, false);
+    rb.e_out = e_out;
+    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
     return last_launch_error();
 }
 
@@ -1232,9 +1246,9 @@ int mixpi_energy(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, false, st);
-    ReduceLaunch r = reduce_args(sys, 0, false);
-    r.e_out = e_out;
-    launch_reduce(r, st);
+    ReduceB rb = reduce_b_args(sys, false);
+    rb.e_out = e_out;
+    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
     return last_launch_error();
 }
 
@@ -1251,10 +1265,10 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
         launch_gather(gather_args(sys), sys->rows, dq, st);
         launch_scale_rows(sys->rows, sys->d_row_sys, grad_e, dq, st);
     }
-    ReduceLaunch r = reduce_args(sys, 0, false);
-    r.dtheta = dtheta;
-    r.grad_e = grad_e;
-    launch_reduce(r, st);
+    ReduceB rb = reduce_b_args(sys, false);
+    rb.dtheta = dtheta;
+    rb.grad_e = grad_e;
+    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
     return last_launch_error();
 }
 
@@ -1335,17 +1349,20 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const do
             const int buf = (r + 1) & 1;
             RpLaunch ra = rp_args(sys, OP_STEP, sq, sq, sp, sf, buf);
             ra.with_reduce = 1;
-            ra.reduce = reduce_args(sys, buf ^ 1, true);
-            ra.reduce.elog = selog;
-            ra.reduce.npairs = nullptr;
-            ra.reduce.nonfinite = nullptr;
+            ra.reduce = reduce_a_args(sys, buf ^ 1, true);
+            FinishLaunch fl = finish_args(sys, sq, sp, sf, buf);
+            fl.with_reduce = 1;
+            fl.reduce = reduce_b_args(sys, true);
+            fl.reduce.elog = selog;
+            fl.reduce.npairs = nullptr;
+            fl.reduce.nonfinite = nullptr;
             (void)hipEventRecord(ev[4 * r], st);
             launch_rp(ra, st);
             (void)hipEventRecord(ev[4 * r + 1], st);
             launch_pair(pair_args(sys, sq, nullptr, buf), bonded_args(sys, sq, nullptr, buf),
                         sys->precision, false, st);
             (void)hipEventRecord(ev[4 * r + 2], st);
-            launch_finish(finish_args(sys, sq, sp, sf, buf), st);
+            launch_finish(fl, st);
             if (hipEventRecord(ev[4 * r + 3], st) != hipSuccess)
                 rc = fail(MIXPI_E_HIP, "hipEventRecord failed");
         }

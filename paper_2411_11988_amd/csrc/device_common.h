@@ -36,8 +36,8 @@ __device__ __forceinline__ void min_img(double &x, double L, double iL) { x -= L
 // terms): one thread per (term, slice); the slice's beads were resolved on
 // the host, so a thread sees plain bead rows and the weight 1/N_max.  FP64
 // throughout: bonded terms are stiff and cheap.  Forces go to the term's own
-// partial-force slots (summed later by the per-row gather); the energy sums
-// go to the workgroup's energy slot `e`.
+// partial-force slots, stored at their row-contiguous positions (summed later
+// by the per-row gather); the energy sums go to the workgroup's slot `e`.
 template <bool THETA>
 __device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double *e, double *red)
 {
@@ -47,7 +47,7 @@ __device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double
     double eb = 0, ea = 0, gb = 0, ga = 0;
     if ((int)threadIdx.x < br.count) {
         const BondedTerm bt = a.terms[t];
-        double *slot = a.part + 3 * (a.part_base + 3LL * t);
+        const int *dst = a.dest + a.part_base + 3LL * t;
         if (bt.kind == 0) {
             const bool t0 = bt.type == S.bond_off;
             const double k = t0 ? th[4] : a.bond_k[bt.type];
@@ -62,9 +62,10 @@ __device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double
             eb = bt.w * 0.5 * k * dr * dr;
             if (THETA && t0) gb = bt.w * 0.5 * dr * dr;
             const double g = -bt.w * k * dr / r;
+            double *o0 = a.part + 3LL * dst[0], *o1 = a.part + 3LL * dst[1];
             for (int c = 0; c < 3; ++c) {
-                slot[c] = g * d[c];
-                slot[3 + c] = -g * d[c];
+                o0[c] = g * d[c];
+                o1[c] = -g * d[c];
             }
         } else {
             const bool t0 = bt.type == S.angle_off;
@@ -87,12 +88,14 @@ __device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double
             const double s = sqrt(1.0 - c * c);
             const double pref = bt.w * k * dth / s;
             const double i12 = 1.0 / (l1 * l2), i11 = 1.0 / (l1 * l1), i22 = 1.0 / (l2 * l2);
+            double *o0 = a.part + 3LL * dst[0], *o1 = a.part + 3LL * dst[1];
+            double *o2 = a.part + 3LL * dst[2];
             for (int x = 0; x < 3; ++x) {
                 const double fa = pref * (r2[x] * i12 - c * r1[x] * i11);
                 const double fb = pref * (r1[x] * i12 - c * r2[x] * i22);
-                slot[x] = fa;              // end a
-                slot[3 + x] = -(fa + fb);  // vertex
-                slot[6 + x] = fb;          // end b
+                o0[x] = fa;                // end a
+                o1[x] = -(fa + fb);        // vertex
+                o2[x] = fb;                // end b
             }
         }
     }
@@ -113,7 +116,7 @@ __device__ void bonded_block(const BondedLaunch &a, const BlockRange &br, double
 
 // Energies of system s from its summed slot row r: writes the requested
 // outputs and adds its pair-evaluation counts (exact integers in FP64).
-__device__ inline void energy_outputs(const ReduceLaunch &a, int s, const double *r)
+__device__ inline void energy_outputs(const ReduceB &a, int s, const double *r)
 {
     const SysDev &S = a.sys[s];
     double e[MIXPI_NE];
@@ -144,34 +147,48 @@ __device__ inline void energy_outputs(const ReduceLaunch &a, int s, const double
     }
 }
 
-// One reducer workgroup (kReduceThreads threads) of a ReduceLaunch: for
-// each of its systems, thread t sums component t % A_N of the system's slots
-// (the runs start on slot boundaries and A_N divides the block size), then
-// the A_N-strided partials are added in LDS and thread 0 writes the outputs.
-// lds: >= kReduceThreads + A_N doubles.
-__device__ inline void reduce_part(const ReduceLaunch &a, int wg, double *lds)
+// Stage A, one workgroup (kReduceThreads threads) per chunk: thread t sums
+// component t % A_N of the chunk's slots (A_N divides the block size), the
+// A_N-strided partials are added in LDS.  lds: >= kReduceThreads doubles.
+__device__ inline void reduce_a_part(const ReduceA &a, int c, double *lds)
 {
-    const int T = kReduceThreads;
     const int t = threadIdx.x;
-    for (int s = a.wg_sys[wg]; s < a.wg_sys[wg + 1]; ++s) {
-        double acc = 0.0;
-        for (int r = a.sys_run[s]; r < a.sys_run[s + 1]; ++r) {
-            const double *base = a.eslot + (long long)a.run_begin[r] * A_N;
-            const int n = a.run_len[r] * A_N;
-#pragma unroll 8
-            for (int k = t; k < n; k += T) acc += base[k];
-        }
-        lds[t] = acc;
-        __syncthreads();
-        if (t < A_N) {
-            double v = 0.0;
-            for (int x = t; x < T; x += A_N) v += lds[x];
-            lds[T + t] = v;
-        }
-        __syncthreads();
-        if (t == 0) energy_outputs(a, s, lds + T);
-        __syncthreads();
+    const double *base = a.eslot + (long long)a.chunk_begin[c] * A_N;
+    const int n = a.chunk_len[c] * A_N;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int k = t; k < n; k += kReduceThreads) acc += base[k];
+    lds[t] = acc;
+    __syncthreads();
+    if (t < A_N) {
+        double v = 0.0;
+        for (int x = t; x < kReduceThreads; x += A_N) v += lds[x];
+        a.partial[(long long)c * A_N + t] = v;
     }
+}
+
+// Stage B, one workgroup (kReduceThreads threads) per system s: thread t
+// adds component t % A_N over the chunks g, g + G, ... of the system
+// (g = t / A_N, G = kReduceThreads / A_N), the G partials per component are
+// added in LDS in order, and thread 0 writes the outputs.
+// lds: >= kReduceThreads + A_N doubles.
+__device__ inline void reduce_b_part(const ReduceB &a, int s, double *lds)
+{
+    const int t = threadIdx.x;
+    const int comp = t % A_N, g = t / A_N;
+    constexpr int G = kReduceThreads / A_N;
+    double v = 0.0;
+    for (int c = a.sys_chunk[s] + g; c < a.sys_chunk[s + 1]; c += G)
+        v += a.partial[(long long)c * A_N + comp];
+    lds[t] = v;
+    __syncthreads();
+    if (t < A_N) {
+        double r = 0.0;
+        for (int x = t; x < kReduceThreads; x += A_N) r += lds[x];
+        lds[kReduceThreads + t] = r;
+    }
+    __syncthreads();
+    if (t == 0) energy_outputs(a, s, lds + kReduceThreads);
 }
 
 }  // namespace mixpi

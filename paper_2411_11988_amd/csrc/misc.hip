@@ -7,9 +7,10 @@
 namespace mixpi {
 
 // ---------------------------------------------------------------------------
-// F[row] = sum over the row's partial-force slots, in the fixed CSR order
-// (so forces are reproducible bit for bit).  One wave per row: lane l takes
-// slots l, l + 64, ...; the wave then reduces the three components.
+// F[row] = sum over the row's partial-force slots, a contiguous run in the
+// fixed CSR order (so forces are reproducible bit for bit).  One wave per
+// row: lane l takes slots l, l + 64, ...; the wave then reduces the three
+// components.
 struct Vec3 {
     double x, y, z;
 };
@@ -19,7 +20,7 @@ __device__ __forceinline__ Vec3 gather_row(const GatherArgs &g, long long row)
     double x = 0.0, y = 0.0, z = 0.0;
     const long long e = g.row_ptr[row + 1];
     for (long long k = g.row_ptr[row] + lane; k < e; k += 64) {
-        const double *p = g.part + 3LL * g.slot[k];
+        const double *p = g.part + 3 * k;
         x += p[0];
         y += p[1];
         z += p[2];
@@ -53,26 +54,34 @@ void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t s
 __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
 {
     __shared__ double red[4];
+    if ((int)blockIdx.x >= a.n_blocks) {
+        // the extra workgroups: energy reduction (stage B) of the previous step
+        __shared__ double racc[kReduceThreads + A_N];
+        reduce_b_part(a.reduce, blockIdx.x - a.n_blocks, racc);
+        return;
+    }
     const BlockRange br = a.blocks[blockIdx.x];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double ke = 0.0, vir = 0.0;
     if (w < br.count) {
         const long long row = (long long)br.begin + w;
+        // the row's own state, loaded before the gather so both are in flight
+        const long long x = 3 * row + (lane < 3 ? lane : 0);
+        const double p0 = a.p[x], q0 = a.q[x], c0 = a.cent[x];
+        const double hk = a.row_hk[row], fm = a.row_fm[row];
+        const int st = a.row_stage[row];
         const Vec3 fv = gather_row(a.gather, row);
         if (lane < 3) {
-            const long long x = 3 * row + lane;
             const double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
             a.f[x] = fx;
-            const double hk = a.row_hk[row];
-            const double pv = a.p[x] + hk * fx;
+            const double pv = p0 + hk * fx;
             a.p[x] = pv;
-            const int st = a.row_stage[row];
             if (st >= 0) {
-                a.stage[6LL * st + lane] = a.q[x];
+                a.stage[6LL * st + lane] = q0;
                 a.stage[6LL * st + 3 + lane] = pv + hk * fx;
             }
-            ke = pv * pv / (2.0 * a.row_fm[row]);
-            vir = (a.q[x] - a.cent[x]) * fx;
+            ke = pv * pv / (2.0 * fm);
+            vir = (q0 - c0) * fx;
         }
     }
     ke = bsum(ke, red);
@@ -87,8 +96,9 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
 
 void launch_finish(const FinishLaunch &a, hipStream_t st)
 {
-    if (a.n_blocks <= 0) return;
-    hipLaunchKernelGGL(k_finish, dim3(a.n_blocks), dim3(256), 0, st, a);
+    const int grid = a.n_blocks + (a.with_reduce ? a.reduce.n_wg : 0);
+    if (grid <= 0) return;
+    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -110,15 +120,23 @@ void launch_stage(const StageLaunch &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceLaunch a)
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_a(ReduceA a)
 {
-    __shared__ double acc[kReduceThreads + A_N];
-    reduce_part(a, blockIdx.x, acc);
+    __shared__ double acc[kReduceThreads];
+    reduce_a_part(a, blockIdx.x, acc);
 }
 
-void launch_reduce(const ReduceLaunch &a, hipStream_t st)
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_b(ReduceB b)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(a.n_wg), dim3(kReduceThreads), 0, st, a);
+    __shared__ double acc[kReduceThreads + A_N];
+    reduce_b_part(b, blockIdx.x, acc);
+}
+
+void launch_reduce(const ReduceA &a, const ReduceB &b, hipStream_t st)
+{
+    if (a.n_chunks > 0)
+        hipLaunchKernelGGL(k_reduce_a, dim3(a.n_chunks), dim3(kReduceThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_b, dim3(b.n_wg), dim3(kReduceThreads), 0, st, b);
 }
 
 // ---------------------------------------------------------------------------

@@ -84,7 +84,7 @@ struct BlockRange {
 
 // free ring-polymer / normal-mode work item
 enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
-constexpr int kCircOut = 32;       // bead outputs per circulant item
+constexpr int kCircOut = 16;       // bead outputs per circulant item
 constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
 enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2 };
 struct RpItem {
@@ -106,14 +106,16 @@ struct PairLaunch {
     const PairItem *items;
     int n_items;
     int tj;                  // j-tile width (32 or 64)
+    int waves;               // waves per tile (1 or 2)
     const PairBlock *blocks;
     const SysDev *sys;
     const double *lj_eps, *lj_sig;
     const double *charge;
     const int *ljt, *mol;
     const double *q;
-    double *part;            // partial-force slots [n_slots][3]
-    int item0;               // global index of items[0] (slot base = index * (64 + tj))
+    double *part;            // partial forces [positions][3], row-contiguous
+    const int *dest;         // position of every natural slot (-1: unused)
+    int item0;               // global index of items[0] (natural slot base = index * (64 + tj))
     const double *theta;
     double *eslot;           // energy slot of global item k: eslot + k * A_N
     int n_bblocks;           // bonded workgroups run after the pair tiles
@@ -126,8 +128,9 @@ struct BondedLaunch {
     const SysDev *sys;
     const double *bond_k, *bond_r0, *angle_k, *angle_t0;
     const double *q;
-    double *part;            // partial-force slots; term t owns part_base + 3t .. +2
-    long long part_base;
+    double *part;            // partial forces [positions][3], row-contiguous
+    const int *dest;         // position of every natural slot
+    long long part_base;     // term t owns natural slots part_base + 3t .. +2
     const double *theta;
     double *eslot;           // energy slot of this launch's block b: eslot + b * A_N
 };
@@ -137,19 +140,27 @@ void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool
 // The bonded workgroups alone.
 void launch_bonded(const BondedLaunch &b, bool with_theta, hipStream_t st);
 
-// Sums the energy slots of each system and writes either e_out [n_sys][NV]
-// or an energy-log row [n_sys][NE]; adds the pair-evaluation counts to
-// npairs[2]; with dtheta, writes grad_e * dV/dtheta [n_sys][6].  A system's
-// slots are a few contiguous runs of the slot array; workgroup w owns the
-// whole systems wg_sys[w] .. wg_sys[w+1]-1, so every sum has one writer and
-// a fixed order.
-struct ReduceLaunch {
+// Energy reduction in two stages, each a few workgroups that ride along in
+// the launches of the next step (or run alone):
+//   A: chunk c of a slot list (at most kChunkSlots slots of one system)
+//      summed into partial[c][A_N];
+//   B: the chunks of each system summed in order and turned into the
+//      outputs: e_out [n_sys][NV] or an energy-log row [n_sys][NE], the
+//      pair-evaluation counts (npairs[2]) and grad_e * dV/dtheta.
+// Every sum has one writer and a fixed order.
+constexpr int kChunkSlots = 64;
+constexpr int kReduceThreads = 256;   // a multiple of A_N
+struct ReduceA {
     const double *eslot;
-    const int *wg_sys;         // [n_wg + 1] first system of each workgroup
-    const int *sys_run;        // [n_sys + 1] first run of each system
-    const int *run_begin;      // first slot of each run
-    const int *run_len;        // slots in each run
-    int n_wg;                  // reducer workgroups
+    const int *chunk_begin;    // [n_chunks] first slot
+    const int *chunk_len;      // [n_chunks] slots
+    int n_chunks;
+    double *partial;           // [n_chunks][A_N]
+};
+struct ReduceB {
+    const double *partial;
+    const int *sys_chunk;      // [n_sys + 1] first chunk of each system
+    int n_wg;                  // workgroups: one per system
     const SysDev *sys;
     int n_sys;
     double *e_out;             // [n_sys][NV] or null
@@ -159,7 +170,6 @@ struct ReduceLaunch {
     unsigned long long *npairs;
     int *nonfinite;
 };
-constexpr int kReduceThreads = 256;   // a multiple of A_N
 
 struct RpLaunch {
     const RpItem *items;
@@ -178,17 +188,18 @@ struct RpLaunch {
     double *cent;            // OP_STEP only: [rows][3] centroid of each bead's ring
     double *eslot;           // OP_STEP only: energy slot of item b: eslot + b * A_N
     unsigned lds_bytes;      // dynamic LDS: max over the items
-    int with_reduce;         // reduce.n_wg extra workgroups run `reduce`
-    ReduceLaunch reduce;
+    int with_reduce;         // reduce.n_chunks extra workgroups run stage A
+    ReduceA reduce;
 };
 void launch_rp(const RpLaunch &a, hipStream_t st);
 const void *rp_kernel_symbol();
 
-// Gathers F[row] = sum of its partial-force slots, in the fixed CSR order.
+// Gathers F[row] = sum of its partial-force slots.  The slots of a row are
+// contiguous (CSR order): writers store each partial at its position
+// dest[natural slot], so a row reads one contiguous run.
 struct GatherArgs {
     const long long *row_ptr;  // [rows + 1]
-    const int *slot;           // [nnz] slot indices
-    const double *part;        // [n_slots][3]
+    const double *part;        // [positions][3]
 };
 
 struct FinishLaunch {
@@ -203,6 +214,8 @@ struct FinishLaunch {
     double *eslot;             // energy slot of block b: eslot + b * A_N
     const int *row_stage;      // [rows] stage row of a circulant ring's bead row, or -1
     double *stage;             // written for those rows: q, p + dt/2 F (next step's input)
+    int with_reduce;           // reduce.n_wg extra workgroups run stage B
+    ReduceB reduce;
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);
 
@@ -215,7 +228,7 @@ struct StageLaunch {
 };
 void launch_stage(const StageLaunch &a, hipStream_t st);
 
-void launch_reduce(const ReduceLaunch &a, hipStream_t st);
+void launch_reduce(const ReduceA &a, const ReduceB &b, hipStream_t st);
 
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);

@@ -8,8 +8,10 @@
 // with N_b = N_a >> shift, the slice-pairs that meet bead b of group b are
 // exactly the rows [b << shift, (b + 1) << shift) of group a -- a contiguous
 // run of n_a << shift beads.  One work item is a 64 x TJ tile of that
-// rectangle (or of the upper triangle for a group with itself): one wave,
-// one lane per i-bead, the TJ j-beads staged in LDS.  Lane l visits j-slot
+// rectangle (or of the upper triangle for a group with itself): one lane per
+// i-bead, the TJ j-beads staged in LDS; with WAVES = 2 two waves share the
+// tile, each taking half of the j-beads (more, shorter waves when a launch
+// has few tiles per SIMD), and hand their i-forces to wave 0 at the end.  Lane l visits j-slot
 // (l + t) mod TJ at step t, so the lanes spread over distinct j-beads and
 // the Newton-3 reaction goes to a per-j LDS accumulator with a return-less
 // LDS atomic add; i-forces stay in registers.  The loop body has no
@@ -33,6 +35,24 @@ template <typename R> __device__ __forceinline__ R rcp_r(R x);
 template <> __device__ __forceinline__ double rcp_r<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// A j-bead of the tile in LDS: position, charge and (LJ type | mol id << 4),
+// read with two (float form) or three (double form) 128-bit LDS loads.
+template <typename R> struct JRec;
+template <> struct alignas(16) JRec<float> {
+    double x, y, z;
+    float q;
+    int tm;
+};
+template <> struct alignas(16) JRec<double> {
+    double x, y, z, q;
+    int tm, pad[3];
+};
+// LJ parameters of one type pair: 4 eps, sigma^2 and the two cutoff-shift
+// constants, one 128-bit (float) or two (double) LDS loads.
+template <typename R> struct alignas(16) LjPar {
+    R e4, s2, c0, c1;
+};
+
 __device__ __forceinline__ int wave_sum_i(int v)
 {
 #pragma unroll
@@ -40,26 +60,30 @@ __device__ __forceinline__ int wave_sum_i(int v)
     return v;
 }
 
-template <typename R, bool THETA, int TJ>
-__global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
+template <typename R, bool THETA, int TJ, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch bl)
 {
+    __shared__ double red[WAVES];
     if ((int)blockIdx.x >= a.n_items) {
         // bonded workgroups of the same launch (64 terms each)
         const int bb = blockIdx.x - a.n_items;
-        bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, nullptr);
+        bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, red);
         return;
     }
     const PairItem it = a.items[blockIdx.x];
     const PairBlock bk = a.blocks[it.block];
     const SysDev &S = a.sys[bk.sys];
     const double *th = a.theta ? a.theta + 6 * bk.sys : S.theta0;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = (int)threadIdx.x >> 6;        // wave: j-slots wv*TJ/WAVES ...
+    // output positions of this lane's slots, fetched early
+    const long long sb = (long long)(a.item0 + blockIdx.x) * (64 + TJ);
+    const int di = a.dest[sb + lane];
+    const int dj = (int)threadIdx.x < TJ ? a.dest[sb + 64 + threadIdx.x] : -1;
 
-    __shared__ double sx[TJ], sy[TJ], sz[TJ];
-    __shared__ R sq[TJ];
-    __shared__ int st[TJ], sm[TJ];
+    __shared__ JRec<R> sj[TJ];
     __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
-    __shared__ R t_e4[kLjTab], t_s2[kLjTab], t_c0[kLjTab], t_c1[kLjTab];
+    __shared__ LjPar<R> tlj[kLjTab];
 
     const int nt1 = S.nt1;
     const double rc_lj = S.rc_lj, rc_c = S.rc_c;
@@ -71,38 +95,35 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
             double c6 = s2 / (rc_lj * rc_lj);
             c6 = c6 * c6 * c6;
             double c12 = c6 * c6;
-            t_e4[tp] = (R)(4.0 * eps);
-            t_s2[tp] = (R)s2;
-            t_c0[tp] = (R)(4.0 * eps * (c12 - c6));
-            t_c1[tp] = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+            LjPar<R> lp;
+            lp.e4 = (R)(4.0 * eps);
+            lp.s2 = (R)s2;
+            lp.c0 = (R)(4.0 * eps * (c12 - c6));
+            lp.c1 = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+            tlj[tp] = lp;
         }
     }
 
     // j tile: bead b of group b, particles j0 .. j0 + jn; padding slots get
     // harmless values and are masked out
     const int jn = min(TJ, bk.nb - it.j0);
-    if (lane < TJ) {
-        if (lane < jn) {
-            const int j = it.j0 + lane;
+    if ((int)threadIdx.x < TJ) {
+        const int js = threadIdx.x;
+        JRec<R> jr{};
+        if (js < jn) {
+            const int j = it.j0 + js;
             const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
             const int pj = bk.pb0 + j;
-            sx[lane] = a.q[3 * rowj];
-            sy[lane] = a.q[3 * rowj + 1];
-            sz[lane] = a.q[3 * rowj + 2];
-            sq[lane] = (R)a.charge[pj];
-            st[lane] = a.ljt[pj];
-            sm[lane] = a.mol[pj];
-        } else {
-            sx[lane] = 0.0;
-            sy[lane] = 0.0;
-            sz[lane] = 0.0;
-            sq[lane] = (R)0;
-            st[lane] = 0;
-            sm[lane] = -1;
+            jr.x = a.q[3 * rowj];
+            jr.y = a.q[3 * rowj + 1];
+            jr.z = a.q[3 * rowj + 2];
+            jr.q = (R)a.charge[pj];
+            jr.tm = a.ljt[pj] | (a.mol[pj] << 4);
         }
-        fjx[lane] = 0.0;
-        fjy[lane] = 0.0;
-        fjz[lane] = 0.0;
+        sj[js] = jr;
+        fjx[js] = 0.0;
+        fjy[js] = 0.0;
+        fjz[js] = 0.0;
     }
 
     // i bead
@@ -111,7 +132,7 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
     const bool vi = idx < li;
     const long long rowi = bk.rowa + ((long long)it.b << bk.shift) * bk.na + idx;
     double xi = 0, yi = 0, zi = 0, qi = 0;
-    int ti = 0, mi = -2;
+    int ti = 0, mi = -1;
     if (vi) {
         const int pi = bk.pa0 + (int)(idx % bk.na);
         xi = a.q[3 * rowi];
@@ -126,8 +147,9 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
     const double Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
     const double iLx = S.ibox[0], iLy = S.ibox[1], iLz = S.ibox[2];
     double fxi = 0, fyi = 0, fzi = 0;
-    double e0 = 0, e1 = 0;            // atom: LJ, Coulomb; electron: pp
-    double g0 = 0, g1 = 0;            // theta partials (pp: q_e, a; atom: eps, sigma)
+    // per-lane sums of at most TJ terms in R, then FP64 across lanes/tiles
+    R e0r = 0, e1r = 0;               // atom: LJ, Coulomb; electron: pp
+    R g0r = 0, g1r = 0;               // theta partials (pp: q_e, a; atom: eps, sigma)
     int cnt = 0;
     // slots that may interact: real j, and for a group with itself j > i
     const int jlo = bk.same ? (int)max(-1LL, min((long long)TJ, idx - it.j0)) : -1;
@@ -143,25 +165,27 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
         const int trow = ti * nt1;
         const R th_eps = (R)th[2], th_sig = (R)th[3];
 #pragma unroll 4
-        for (int t = 0; t < TJ; ++t) {
-            const int jj = (lane + t) & (TJ - 1);
-            double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-            const R qj = sq[jj];
-            const int tp = trow + st[jj];
-            const int mj = sm[jj];
+        for (int t = 0; t < TJ / WAVES; ++t) {
+            const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
+            const JRec<R> jr = sj[jj];
+            double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
+            const R qj = jr.q;
+            const int tp = trow + (jr.tm & 15);
+            const int mj = jr.tm >> 4;
             dx -= Lx * rint(dx * iLx);
             dy -= Ly * rint(dy * iLy);
             dz -= Lz * rint(dz * iLz);
             const double r2d = dx * dx + dy * dy + dz * dz;
             const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
             const R r2 = ok ? (R)r2d : (R)1;
-            const R e4 = t_e4[tp], c1l = t_c1[tp];
+            const LjPar<R> lp = tlj[tp];
+            const R e4 = lp.e4, c1l = lp.c1;
             const R ir2 = rcp_r<R>(r2);
-            const R s2 = t_s2[tp] * ir2;
+            const R s2 = lp.s2 * ir2;
             const R s6 = s2 * s2 * s2;
             const R s12 = s6 * s6;
             const bool in_lj = ok && r2d < rc2_lj && e4 != (R)0;
-            const R vlj = e4 * (s12 - s6) - t_c0[tp] - (R)0.5 * (r2 - rl2) * c1l;
+            const R vlj = e4 * (s12 - s6) - lp.c0 - (R)0.5 * (r2 - rl2) * c1l;
             const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
             const R K = kqi * qj;
             const bool in_c = ok && r2d < rc2_c && K != (R)0;
@@ -169,19 +193,19 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
             const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
             const R gc = K * (ir * ir * ir - irc3);
             const R g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
-            e0 += in_lj ? (double)vlj : 0.0;
-            e1 += in_c ? (double)vc : 0.0;
+            e0r += in_lj ? vlj : (R)0;
+            e1r += in_c ? vc : (R)0;
             cnt += (in_lj || in_c) ? 1 : 0;
             if (THETA) {
                 // d/d eps and d/d sigma of the (0,0) LJ term
                 const bool on = in_lj && tp == 0;
-                const R c6 = t_s2[0] / rl2;
+                const R c6 = tlj[0].s2 / rl2;
                 const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
                 const R fs = (R)4 * th_eps / th_sig;
                 const R dsg = fs * ((R)12 * s12 - (R)6 * s6) - fs * ((R)12 * c12c - (R)6 * c6c) -
                               (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2;
-                g0 += on ? (double)(vlj / th_eps) : 0.0;
-                g1 += on ? (double)dsg : 0.0;
+                g0r += on ? vlj / th_eps : (R)0;
+                g1r += on ? dsg : (R)0;
             }
             const double gd = (double)g;
             const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
@@ -205,11 +229,12 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
         const R kqi = (R)(kCoulombKcal * qi);
         const R kc = (R)kCoulombKcal;
 #pragma unroll 4
-        for (int t = 0; t < TJ; ++t) {
-            const int jj = (lane + t) & (TJ - 1);
-            double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-            const R qj = sq[jj];
-            const int mj = sm[jj];
+        for (int t = 0; t < TJ / WAVES; ++t) {
+            const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
+            const JRec<R> jr = sj[jj];
+            double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
+            const R qj = jr.q;
+            const int mj = jr.tm >> 4;
             dx -= Lx * rint(dx * iLx);
             dy -= Ly * rint(dy * iLy);
             dz -= Lz * rint(dz * iLz);
@@ -221,13 +246,13 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
             const R ir3 = ir * ir * ir;
             const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
             const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
-            e0 += ok ? (double)(rpq * vq) : 0.0;
+            e0r += ok ? rpq * vq : (R)0;
             cnt += ok ? 1 : 0;
             if (THETA) {
-                g0 += ok ? (double)vq : 0.0;
-                g1 += ok ? (double)(rpq * kq * (-rpa * ir3 - rpa * psic -
-                                                (R)1.5 * rpa * (r2 - rrc2) * chic))
-                         : 0.0;
+                g0r += ok ? vq : (R)0;
+                g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
+                                        (R)1.5 * rpa * (r2 - rrc2) * chic)
+                          : (R)0;
             }
             const double gd = (double)gq;
             const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
@@ -239,29 +264,59 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
             atomicAdd(&fjz[jj], -fz);
         }
     }
-    __syncthreads();
-
-    // partial forces of this tile go to its own slots (64 i-slots, then TJ
-    // j-slots); the per-row gather sums them, so no two workgroups write the
-    // same address
-    const double w = bk.w;
-    double *slot = a.part + 3 * ((long long)(a.item0 + blockIdx.x) * (64 + TJ));
-    if (vi) {
-        slot[3 * lane] = w * fxi;
-        slot[3 * lane + 1] = w * fyi;
-        slot[3 * lane + 2] = w * fzi;
-    }
-    if (lane < jn) {
-        slot[3 * (64 + lane)] = w * fjx[lane];
-        slot[3 * (64 + lane) + 1] = w * fjy[lane];
-        slot[3 * (64 + lane) + 2] = w * fjz[lane];
-    }
-    e0 = wsum(e0);
-    e1 = wsum(e1);
+    double e0 = wsum((double)e0r), e1 = wsum((double)e1r), g0 = 0.0, g1 = 0.0;
     cnt = wave_sum_i(cnt);
     if (THETA) {
-        g0 = wsum(g0);
-        g1 = wsum(g1);
+        g0 = wsum((double)g0r);
+        g1 = wsum((double)g1r);
+    }
+    if (WAVES > 1) {
+        // the other waves hand their i-forces and sums to wave 0
+        __shared__ double xs[WAVES][3][64];
+        __shared__ double es[WAVES][5];
+        if (wv > 0) {
+            xs[wv][0][lane] = fxi;
+            xs[wv][1][lane] = fyi;
+            xs[wv][2][lane] = fzi;
+            if (lane == 0) {
+                es[wv][0] = e0;
+                es[wv][1] = e1;
+                es[wv][2] = g0;
+                es[wv][3] = g1;
+                es[wv][4] = (double)cnt;
+            }
+        }
+        __syncthreads();
+        if (wv > 0) return;
+        for (int v = 1; v < WAVES; ++v) {
+            fxi += xs[v][0][lane];
+            fyi += xs[v][1][lane];
+            fzi += xs[v][2][lane];
+            e0 += es[v][0];
+            e1 += es[v][1];
+            g0 += es[v][2];
+            g1 += es[v][3];
+            cnt += (int)es[v][4];
+        }
+    } else {
+        __syncthreads();
+    }
+
+    // partial forces of this tile go to its own slots (64 i-slots, then TJ
+    // j-slots), each stored at its row-contiguous position; the per-row
+    // gather sums them, so no two workgroups write the same address
+    const double w = bk.w;
+    if (vi) {
+        double *o = a.part + 3LL * di;
+        o[0] = w * fxi;
+        o[1] = w * fyi;
+        o[2] = w * fzi;
+    }
+    if (lane < jn) {
+        double *o = a.part + 3LL * dj;
+        o[0] = w * fjx[lane];
+        o[1] = w * fjy[lane];
+        o[2] = w * fjz[lane];
     }
     if (lane == 0) {
         double *e = a.eslot + (long long)(a.item0 + blockIdx.x) * A_N;
@@ -281,17 +336,17 @@ __global__ __launch_bounds__(64) void k_pair(PairLaunch a, BondedLaunch bl)
     }
 }
 
-template <int TJ>
+template <int TJ, int WAVES>
 void launch_pair_tj(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
                     hipStream_t st)
 {
-    dim3 grid(a.n_items + b.n_blocks), block(64);
+    dim3 grid(a.n_items + b.n_blocks), block(64 * WAVES);
     if (precision == 0) {
-        if (with_theta) hipLaunchKernelGGL((k_pair<double, true, TJ>), grid, block, 0, st, a, b);
-        else hipLaunchKernelGGL((k_pair<double, false, TJ>), grid, block, 0, st, a, b);
+        if (with_theta) hipLaunchKernelGGL((k_pair<double, true, TJ, WAVES>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<double, false, TJ, WAVES>), grid, block, 0, st, a, b);
     } else {
-        if (with_theta) hipLaunchKernelGGL((k_pair<float, true, TJ>), grid, block, 0, st, a, b);
-        else hipLaunchKernelGGL((k_pair<float, false, TJ>), grid, block, 0, st, a, b);
+        if (with_theta) hipLaunchKernelGGL((k_pair<float, true, TJ, WAVES>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<float, false, TJ, WAVES>), grid, block, 0, st, a, b);
     }
 }
 
@@ -318,8 +373,13 @@ void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool
         return;
     }
     if (a.n_items + b.n_blocks <= 0) return;
-    if (a.tj == 32) launch_pair_tj<32>(a, b, precision, with_theta, st);
-    else launch_pair_tj<64>(a, b, precision, with_theta, st);
+    if (a.tj == 32) {
+        if (a.waves == 2) launch_pair_tj<32, 2>(a, b, precision, with_theta, st);
+        else launch_pair_tj<32, 1>(a, b, precision, with_theta, st);
+    } else {
+        if (a.waves == 2) launch_pair_tj<64, 2>(a, b, precision, with_theta, st);
+        else launch_pair_tj<64, 1>(a, b, precision, with_theta, st);
+    }
 }
 
 }  // namespace mixpi

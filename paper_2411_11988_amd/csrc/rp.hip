@@ -294,70 +294,101 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 }
 
 // Free ring-polymer step in bead space for a many-bead ring with few
-// columns.  Its inputs (q and the half-kicked p) come from the ring's stage
-// rows, because the items of a column write q and p in place.  The exact free propagator C diag(f_k) C^T of each of the maps
+// columns.  The exact free propagator C diag(f_k) C^T of each of the maps
 // (q <- a q + b p, p <- c q + a p) depends on the bead index only through
 // j - j' (every f_k depends on lambda_k, shared by modes k and N - k), so
 // it is circulant: a_d = (1/N) sum_k f_k cos(2 pi k d / N), tabulated per
 // particle on the host.  An item computes kCircOut consecutive bead outputs
 // of one column from the whole ring: the centroid parts move exactly
-// (q_bar' = q_bar + dt/m_f p_bar, p_bar' = p_bar), the rest is the
-// convolution of the centroid-free ring with a, b, c.  Thread (og, jg) sums
-// 4 consecutive outputs over a contiguous 1/32 of the ring, sliding its
-// coefficient window by one per bead; LDS rows are padded by one double per
-// 1/32 segment so the lanes of a wave hit distinct banks.  The spring
-// energy of the item's bead steps (j, j+1), j in the item, needs one more
-// output, formed as a block-wide dot product.
+// (q_bar' = q_bar + dt/m_f p_bar, p_bar' = p_bar, as sum_d a_d = 1,
+// sum_d b_d = dt/m_f, sum_d c_d = 0), the rest is the convolution of the
+// centroid-free ring with a, b, c.
+//
+// Inputs (q and the half-kicked p) come from the ring's stage rows, since
+// the items of a column write q and p in place.  All global loads of a
+// thread are issued before its first LDS store.  Thread (og, jg) sums 4
+// consecutive outputs over a contiguous 1/64 of the ring, sliding its
+// coefficient window by one bead per step; LDS rows are padded by one
+// double per 1/64 of the ring, so the 16 j-groups of a wave read 16
+// distinct banks and the coefficient reads spread evenly over the banks.
+// The spring energy of the item's bead steps (j, j+1) needs the output
+// after the item; it is the dot product of raw (q, p) with the coefficients
+// minus the centroid parts, accumulated with the loads.
+constexpr int kCircJg = 256 / (kCircOut / 4);     // j-groups per item
 __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, double *red)
 {
     const int N = it.N, n = it.n, L = it.logN;
-    const int col = it.c0, i = col / 3;
+    const int col = it.c0, i = col / 3, d = col - 3 * i;
     const int tid = threadIdx.x;
-    const int lseg = L - 5;                      // segment of N/32 beads
-    const int seg = 1 << lseg;
-    const int NP = N + 32;                       // padded row length
-    auto pad = [&](int x) { return x + (x >> lseg); };
-    double *sq = smem, *sp = sq + NP, *ca = sp + NP, *cb = ca + NP, *cc = cb + NP;
-    double *part = cc + NP;                      // [32 jg][kCircOut][2]
-    __shared__ double s_mean[2];
+    const int lpad = L - 6;                      // one pad double per N/64 (a j-group)
+    constexpr int CS = kCircMaxN + 64;           // row stride: q, p, a, b, c rows
+    auto pad = [&](int x) { return x + (x >> lpad); };
+    double *sq = smem, *sp = sq + CS, *ca = sp + CS, *cb = ca + CS, *cc = cb + CS;
+    double *part = cc + CS;                      // [kCircJg][kCircOut][2]
+    __shared__ double s_sum[3][4];
+    __shared__ double s_out[kCircOut + 1];
     const double *coef = a.circ + it.circ_off;
-    auto gaddr = [&](int j) { return (it.row + (long long)j * n) * 3 + col; };
+    const int inext = (it.o0 + kCircOut) & (N - 1);
 
-    // inputs from the stage rows (written before the launch): other items of
-    // this column overwrite q and p in place while this one still reads
-    const int d = col - 3 * i;
-    double sum_q = 0.0, sum_p = 0.0;
-    for (int j = tid; j < N; j += 256) {
-        const double *sr = a.stage + 6LL * (it.stage0 + (long long)j * n + i);
-        const double qv = sr[d];
-        const double pv = sr[3 + d];
-        const int x = pad(j);
-        sq[x] = qv;
-        sp[x] = pv;
-        ca[x] = coef[j];
-        cb[x] = coef[N + j];
-        cc[x] = coef[2 * N + j];
-        sum_q += qv;
-        sum_p += pv;
-    }
-    sum_q = bsum256(sum_q, red);
-    sum_p = bsum256(sum_p, red);
-    if (tid == 0) {
-        s_mean[0] = sum_q / N;
-        s_mean[1] = sum_p / N;
+    // loads: up to kCircMaxN / 256 beads per thread, all issued first
+    constexpr int KB = kCircMaxN / 256;
+    double vq[KB], vp[KB], va[KB], vb[KB], vc[KB], na[KB], nb[KB];
+    const int per = N >> 8;
+#pragma unroll
+    for (int u = 0; u < KB; ++u)
+        if (u < per) {
+            const int j = tid + (u << 8);
+            const double *sr = a.stage + 6LL * (it.stage0 + (long long)j * n + i);
+            vq[u] = sr[d];
+            vp[u] = sr[3 + d];
+            va[u] = coef[j];
+            vb[u] = coef[N + j];
+            vc[u] = coef[2 * N + j];
+            const int jn = (inext - j) & (N - 1);
+            na[u] = coef[jn];
+            nb[u] = coef[N + jn];
+        }
+    double sum_q = 0.0, sum_p = 0.0, nx = 0.0;
+#pragma unroll
+    for (int u = 0; u < KB; ++u)
+        if (u < per) {
+            const int x = pad(tid + (u << 8));
+            sq[x] = vq[u];
+            sp[x] = vp[u];
+            ca[x] = va[u];
+            cb[x] = vb[u];
+            cc[x] = vc[u];
+            sum_q += vq[u];
+            sum_p += vp[u];
+            nx += na[u] * vq[u] + nb[u] * vp[u];
+        }
+    // one block reduction of the three sums
+    sum_q = wsum(sum_q);
+    sum_p = wsum(sum_p);
+    nx = wsum(nx);
+    if ((tid & 63) == 0) {
+        s_sum[0][tid >> 6] = sum_q;
+        s_sum[1][tid >> 6] = sum_p;
+        s_sum[2][tid >> 6] = nx;
     }
     __syncthreads();
-    const double qbar = s_mean[0], pbar = s_mean[1];
-    for (int j = tid; j < N; j += 256) {
-        const int x = pad(j);
-        sq[x] -= qbar;
-        sp[x] -= pbar;
-    }
+    const double qbar = (s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3]) / N;
+    const double pbar = (s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3]) / N;
+    const double dtm = a.prop[5 * (it.row + i) + 1];   // mode 0: dt / m_f
+    const double qc = qbar + dtm * pbar;               // new centroid
+#pragma unroll
+    for (int u = 0; u < KB; ++u)
+        if (u < per) {
+            const int x = pad(tid + (u << 8));
+            sq[x] = vq[u] - qbar;
+            sp[x] = vp[u] - pbar;
+        }
     __syncthreads();
 
     // thread (og, jg): outputs o0 + 4 og + r, beads jg*seg .. jg*seg + seg - 1
-    const int lane = tid & 63;
-    const int og = lane & 7, jg = ((tid >> 6) << 3) + (lane >> 3);
+    constexpr int OG = kCircOut / 4;
+    const int og = tid % OG, jg = tid / OG;
+    const int seg = N / kCircJg;
     const int i0 = it.o0 + 4 * og;
     const int jb = jg * seg;
     double wa[4], wb[4], wc[4], dq[4], dp[4];
@@ -370,55 +401,62 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
         dq[r] = 0.0;
         dp[r] = 0.0;
     }
+    // this thread's beads lie in one pad segment: pad(j) = j + jg
+    const double *qrow = sq + jb + jg;
+    int dn = (i0 - jb - 1) & (N - 1);            // next coefficient index
 #pragma unroll 4
     for (int t = 0; t < seg; ++t) {
-        const int j = jb + t;
-        const double qj = sq[pad(j)], pj = sp[pad(j)];
+        const double qj = qrow[t], pj = qrow[t + CS];
+        const int x = dn + (dn >> lpad);
+        const double na0 = ca[x], nb0 = ca[x + CS], nc0 = ca[x + 2 * CS];
+        dn = (dn - 1) & (N - 1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            dq[r] += wa[r] * qj + wb[r] * pj;
-            dp[r] += wc[r] * qj + wa[r] * pj;
+            dq[r] = fma(wa[r], qj, dq[r]);
+            dq[r] = fma(wb[r], pj, dq[r]);
+            dp[r] = fma(wc[r], qj, dp[r]);
+            dp[r] = fma(wa[r], pj, dp[r]);
         }
-        const int x = pad((i0 - j - 1) & (N - 1));
 #pragma unroll
         for (int r = 3; r > 0; --r) {
             wa[r] = wa[r - 1];
             wb[r] = wb[r - 1];
             wc[r] = wc[r - 1];
         }
-        wa[0] = ca[x];
-        wb[0] = cb[x];
-        wc[0] = cc[x];
+        wa[0] = na0;
+        wb[0] = nb0;
+        wc[0] = nc0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         part[(jg * kCircOut + 4 * og + r) * 2] = dq[r];
         part[(jg * kCircOut + 4 * og + r) * 2 + 1] = dp[r];
     }
-    // the output after the item (for its last bead step): block dot product
-    const int inext = (it.o0 + kCircOut) & (N - 1);
-    double nx = 0.0;
-    for (int j = tid; j < N; j += 256) {
-        const int x = pad((inext - j) & (N - 1));
-        nx += ca[x] * sq[pad(j)] + cb[x] * sp[pad(j)];
+    __syncthreads();
+    // thread (o, v, h): half h of the j-groups of output o, value v (q or p)
+    double acc = 0.0;
+    if (tid < 4 * kCircOut) {
+        const int o = tid % kCircOut, v = (tid / kCircOut) & 1, h = tid / (2 * kCircOut);
+        for (int g = h * (kCircJg / 2); g < (h + 1) * (kCircJg / 2); ++g)
+            acc += part[(g * kCircOut + o) * 2 + v];
     }
-    nx = bsum256(nx, red);      // valid in thread 0; the barriers also cover `part`
-    __shared__ double s_out[kCircOut + 1];
-    const double dtm = a.prop[5 * (it.row + i) + 1];   // mode 0: dt / m_f
-    const double qc = qbar + dtm * pbar;               // new centroid
+    __syncthreads();
+    if (tid < 4 * kCircOut) part[tid] = acc;
+    __syncthreads();
     if (tid < kCircOut) {
-        double vq = 0.0, vp = 0.0;
-        for (int g = 0; g < 32; ++g) {
-            vq += part[(g * kCircOut + tid) * 2];
-            vp += part[(g * kCircOut + tid) * 2 + 1];
-        }
-        s_out[tid] = vq;
-        const long long gq = gaddr(it.o0 + tid);
-        a.out_q[gq] = qc + vq;
-        a.p[gq] = pbar + vp;
+        const double vq2 = part[tid] + part[2 * kCircOut + tid];
+        const double vp2 = part[kCircOut + tid] + part[3 * kCircOut + tid];
+        s_out[tid] = vq2;
+        const long long gq = (it.row + (long long)(it.o0 + tid) * n) * 3 + col;
+        a.out_q[gq] = qc + vq2;
+        a.p[gq] = pbar + vp2;
         a.cent[gq] = qc;
     }
-    if (tid == 0) s_out[kCircOut] = nx;
+    if (tid == 0) {
+        // the centroid-free part of the output after the item
+        const double nraw = s_sum[2][0] + s_sum[2][1] + s_sum[2][2] + s_sum[2][3];
+        s_out[kCircOut] = nraw - qc;
+    }
     __syncthreads();
     double esp = 0.0;
     if (tid < kCircOut) {
@@ -438,9 +476,9 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
     extern __shared__ __align__(16) double smem[];
     __shared__ double red[4];
     if ((int)blockIdx.x >= a.n_items) {
-        // the extra workgroups: energy reducer of the previous step
-        // (the dynamic LDS holds at least kReduceThreads + A_N doubles)
-        reduce_part(a.reduce, blockIdx.x - a.n_items, smem);
+        // the extra workgroups: energy reduction (stage A) of the previous
+        // step (the dynamic LDS holds at least kReduceThreads doubles)
+        reduce_a_part(a.reduce, blockIdx.x - a.n_items, smem);
         return;
     }
     const RpItem it = a.items[blockIdx.x];
@@ -453,7 +491,7 @@ const void *rp_kernel_symbol() { return (const void *)k_rp; }
 
 void launch_rp(const RpLaunch &a, hipStream_t st)
 {
-    const int grid = a.n_items + (a.with_reduce ? a.reduce.n_wg : 0);
+    const int grid = a.n_items + (a.with_reduce ? a.reduce.n_chunks : 0);
     if (grid <= 0) return;
     hipLaunchKernelGGL(k_rp, dim3(grid), dim3(256), a.lds_bytes, st, a);
 }

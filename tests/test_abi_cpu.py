@@ -103,3 +103,14 @@ def test_null_handle_and_out(mp):
     assert lib.mixpi_create(None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_destroy(None) == mp.MIXPI_OK
     assert b"null" in lib.mixpi_last_error()
+
+
+def test_rejects_out_of_range_mol_id(mp):
+    s = synth.tiny_random(0)
+    for bad in (-1, 1 << 27):
+        s2 = synth.tiny_random(0)
+        s2.mol_id = s.mol_id.copy()
+        s2.mol_id[2] = bad
+        with pytest.raises(mp.MixPIError) as e:
+            mp.System(s2)
+        assert e.value.code == mp.MIXPI_E_INVALID and "mol_id" in str(e.value)

@@ -253,3 +253,20 @@ def test_steps_are_bit_reproducible(mp, name, s):
         del sysm
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tj,waves", [(32, 1), (32, 2), (64, 1), (64, 2)])
+def test_pair_tile_variants(mp, tj, waves, monkeypatch):
+    """Every tile shape of the force launch (j-tile width, waves per tile)
+    gives the oracle's forces and energies in both forms."""
+    monkeypatch.setenv("MIXPI_PAIR_TJ", str(tj))
+    monkeypatch.setenv("MIXPI_PAIR_WAVES", str(waves))
+    for name, s in (SYSTEMS[4], SYSTEMS[7]):
+        Fo, eo = oracle.OracleSystem(s).forces(s.q)
+        for prec in (FP64, FP32):
+            print(f"[tiles] tj={tj} waves={waves} {name} prec={prec}", flush=True)
+            sysm = mp.System(s, precision=prec)
+            f, e = sysm.forces(dev(to_rows(s, s.q)))
+            F = from_rows(s, host(f))
+            assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
+            assert e_err(prec, host(e)[0], eo) <= TOL_E[prec]
