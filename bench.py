@@ -46,7 +46,7 @@ PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # one it was measured on (sha256 over KERNEL_SOURCES).
 KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/csrc/device_common.h",
                   "paper_2411_11988_amd/csrc/mixpi_internal.h")
-TRAFFIC = {"workload": "c3",
+TRAFFIC = {"workload": "c3", "tile": "32x2",
            "sha256": "207465dfd25401c77c4522124951a0196eedc00a872e2f50c320907d4a3b54fb",
            "bytes": (836.54 * 2.0 + 6544.6 * 1.0) * 1024}
 
@@ -79,10 +79,10 @@ def _as_list(s):
     return list(s) if isinstance(s, (list, tuple)) else [s]
 
 
-def _run(s, precision, steps, warmup, mixpi, torch):
+def _run(s, precision, steps, warmup, mixpi, torch, flags=0):
     import numpy as np
     systems = _as_list(s)
-    sysm = mixpi.System(s, precision=precision)
+    sysm = mixpi.System(s, precision=precision, flags=flags)
     idx = sysm.bead_index
     n_sys = len(systems)
 
@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--tile", default="auto", choices=["auto", "heuristic"],
+                    help="pair-sweep tile shape: autotuned per workload bucket (default) or "
+                         "the library's size heuristic")
     ap.add_argument("--kernel-sha", action="store_true",
                     help="print the sha256 of the force-kernel sources and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -204,9 +207,19 @@ def main():
     torch.cuda.set_device(0)
     s, wname = _workload(args.workload)
 
+    flags32 = flags64 = 0
+    tile = "heuristic"
+    if args.tile == "auto":
+        from paper_2411_11988_amd import tune
+        print("[bench] autotuning the pair tile shape", file=sys.stderr, flush=True)
+        cache = os.path.join(ROOT, "gpurun_out", "tiles.json")
+        flags32 = tune.tile_flags(s, mixpi.MIXPI_FP32_ACC64, cache=cache)
+        flags64 = tune.tile_flags(s, mixpi.MIXPI_FP64, cache=cache)
+        inv = {v: k for k, v in mixpi.TILE_FLAGS.items()}
+        tile = {"fp32": "%dx%d" % inv[flags32], "fp64": "%dx%d" % inv[flags64]}
     print(f"[bench] {wname}: FP32 pair form, {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
-    r32 = _run(s, mixpi.MIXPI_FP32_ACC64, args.steps, args.warmup, mixpi, torch)
+    r32 = _run(s, mixpi.MIXPI_FP32_ACC64, args.steps, args.warmup, mixpi, torch, flags32)
     sysm = r32["sysm"]
     ev_step = (r32["ev"][0] + r32["ev"][1]) / args.steps
     value = (r32["ev"][0] + r32["ev"][1]) / (r32["ms"] * 1e-3)
@@ -240,20 +253,23 @@ def main():
         "config": {"workload": wname, "beads": int(sysm.rows), "particles": int(sysm.n_particles),
                    "candidate_slice_pairs": int(cand), "in_cutoff_slice_pairs": ev_step,
                    "systems": len(_as_list(s)), "dt_fs": _as_list(s)[0].dt,
-                   "precision": "fp32 pair potentials, fp64 state and sums"},
+                   "precision": "fp32 pair potentials, fp64 state and sums",
+                   "pair_tile_jxwaves": tile},
         "steps_per_s": steps_per_s,
         "kernel_us": k_us,
         "energy_drift_kcal": r32["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": (TRAFFIC["bytes"] if args.workload == TRAFFIC["workload"]
-                                 and TRAFFIC["sha256"] == _kernel_sha() else None),
-                     "kernel": "k_pair<float,false,32>",
+                                 and TRAFFIC["sha256"] == _kernel_sha()
+                                 and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
+                                 else None),
+                     "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"]},
     }
     if not args.no_fp64:
         print("[bench] FP64 form", file=sys.stderr, flush=True)
-        r64 = _run(s, mixpi.MIXPI_FP64, args.steps, args.warmup, mixpi, torch)
+        r64 = _run(s, mixpi.MIXPI_FP64, args.steps, args.warmup, mixpi, torch, flags64)
         out["fp64"] = {"value": (r64["ev"][0] + r64["ev"][1]) / (r64["ms"] * 1e-3),
                        "steps_per_s": args.steps / (r64["ms"] * 1e-3),
                        "ms_per_step": r64["ms"] / args.steps,

@@ -93,6 +93,14 @@ typedef enum {
 
 /* flags */
 #define MIXPI_FLAG_CHECK_FINITE 1   /* mixpi_step syncs and reports non-finite H */
+/* Tile shape of the pair sweep (at most one of each pair; none = the
+ * library's choice from the work size): the j-tile width and the waves that
+ * share a 64-bead i-tile.  Results agree to rounding for every shape; an
+ * autotuner times them and picks one per workload. */
+#define MIXPI_FLAG_TILE_J32 (1 << 4)
+#define MIXPI_FLAG_TILE_J64 (1 << 5)
+#define MIXPI_FLAG_TILE_WAVES1 (1 << 6)
+#define MIXPI_FLAG_TILE_WAVES2 (1 << 7)
 
 typedef struct mixpi_system mixpi_system;   /* opaque, owned by the library */
 

@@ -176,6 +176,14 @@ int validate(const mixpi_system_desc *d, int idx)
                     kMaxLjTypes);
     if (d->n_lj_types > 0 && (!d->lj_eps || !d->lj_sigma))
         return fail(MIXPI_E_INVALID, "system %d: LJ tables are null", idx);
+    {
+        const int known = MIXPI_FLAG_CHECK_FINITE | MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_J64 |
+                          MIXPI_FLAG_TILE_WAVES1 | MIXPI_FLAG_TILE_WAVES2;
+        const int f = d->flags;
+        if ((f & ~known) || ((f & MIXPI_FLAG_TILE_J32) && (f & MIXPI_FLAG_TILE_J64)) ||
+            ((f & MIXPI_FLAG_TILE_WAVES1) && (f & MIXPI_FLAG_TILE_WAVES2)))
+            return fail(MIXPI_E_INVALID, "system %d: bad flags 0x%x", idx, f);
+    }
     for (int i = 0; i < n; ++i) {
         const int N = d->n_beads[i];
         if (!is_pow2(N))
@@ -777,6 +785,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
 
     // pair items: fast groups first, then items touching an FFT group
     S->pair_tj = choose_tj(B.blocks, B.block_slow);
+    if (S->flags & MIXPI_FLAG_TILE_J32) S->pair_tj = 32;
+    if (S->flags & MIXPI_FLAG_TILE_J64) S->pair_tj = 64;
     if (const char *env = getenv("MIXPI_PAIR_TJ")) {
         const int v = atoi(env);
         if (v == 32 || v == 64) S->pair_tj = v;
@@ -791,6 +801,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     // two waves per tile while the launch has fewer than ~4 tiles per SIMD
     // (1024 SIMDs): more, shorter waves even out the SIMDs and hide latency
     S->pair_waves = S->n_items < 4096 ? 2 : 1;
+    if (S->flags & MIXPI_FLAG_TILE_WAVES1) S->pair_waves = 1;
+    if (S->flags & MIXPI_FLAG_TILE_WAVES2) S->pair_waves = 2;
     if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
         const int v = atoi(env);
         if (v == 1 || v == 2) S->pair_waves = v;

@@ -31,6 +31,14 @@ MIXPI_NTHETA = 6
 MIXPI_FP64 = 0
 MIXPI_FP32_ACC64 = 1
 MIXPI_FLAG_CHECK_FINITE = 1
+MIXPI_FLAG_TILE_J32 = 1 << 4
+MIXPI_FLAG_TILE_J64 = 1 << 5
+MIXPI_FLAG_TILE_WAVES1 = 1 << 6
+MIXPI_FLAG_TILE_WAVES2 = 1 << 7
+TILE_FLAGS = {(32, 1): MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_WAVES1,
+              (32, 2): MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_WAVES2,
+              (64, 1): MIXPI_FLAG_TILE_J64 | MIXPI_FLAG_TILE_WAVES1,
+              (64, 2): MIXPI_FLAG_TILE_J64 | MIXPI_FLAG_TILE_WAVES2}
 
 
 class MixPIError(RuntimeError):

@@ -114,3 +114,12 @@ def test_rejects_out_of_range_mol_id(mp):
         with pytest.raises(mp.MixPIError) as e:
             mp.System(s2)
         assert e.value.code == mp.MIXPI_E_INVALID and "mol_id" in str(e.value)
+
+
+def test_rejects_conflicting_tile_flags(mp):
+    s = synth.tiny_random(0)
+    for bad in (mp.MIXPI_FLAG_TILE_J32 | mp.MIXPI_FLAG_TILE_J64,
+                mp.MIXPI_FLAG_TILE_WAVES1 | mp.MIXPI_FLAG_TILE_WAVES2, 1 << 12):
+        with pytest.raises(mp.MixPIError) as e:
+            mp.System(s, flags=bad)
+        assert e.value.code == mp.MIXPI_E_INVALID and "flags" in str(e.value)
