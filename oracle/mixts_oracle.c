@@ -25,6 +25,10 @@
  *     (Sec. "Evaluation", the symmetric Liouvillian splitting).  [orc_step]
  *   - Energies and kinetic estimators written after each step (Sec. "Output
  *     and Analysis").  [orc_observables]
+ *   - The path-integral Langevin thermostat the paper's NVT runs use (Sec.
+ *     "Examples and Discussion", PILE): an Ornstein-Uhlenbeck step of the
+ *     momenta in each ring's normal modes, friction 1/tau0 on the centroid
+ *     and 2 omega_k on mode k; noise is an input.  [orc_pile, orc_step_nvt]
  *
  * Force field (the paper names q-SPC/Fw water, a cation-water LJ and an
  * electron pseudopotential; the functional forms below are the readings this
@@ -693,6 +697,73 @@ void orc_step(const orc_sys *S, int nsteps, double *q, double *p, double *F,
         orc_forces_o2(S, q, F, vpot);
         for (long x = 0; x < 3 * B; ++x) p[x] += kick * F[x];
         if (elog) orc_observables(S, q, p, F, vpot, elog + (size_t)st * E_N);
+    }
+}
+
+/* ---------------- path-integral Langevin thermostat ---------------------- */
+
+/* Friction of mode k of particle i: the centroid (k = 0) gets 1/tau0 (0 for
+ * tau0 <= 0 or infinite), every internal mode 2 omega_k (the local PILE
+ * choice: critical damping of each free-ring mode). */
+double orc_pile_gamma(const orc_sys *S, int i, int k, double tau0)
+{
+    if (k == 0) return (tau0 > 0.0 && isfinite(tau0)) ? 1.0 / tau0 : 0.0;
+    return 2.0 * orc_nm_omega(S, i, k);
+}
+
+/* One Ornstein-Uhlenbeck half step of the momenta in the normal modes of
+ * each ring: pi_k <- c1 pi_k + c2 sqrt(m_f k_B T) eta_k with
+ * c1 = exp(-gamma_k t), c2 = sqrt(1 - c1^2).  eta is a bead table [B][3]
+ * of standard normals indexed by mode: particle i, mode k, component c at
+ * eta[3 (off_i + k) + c]. */
+void orc_pile(const orc_sys *S, double *p, const double *eta, double t, double tau0)
+{
+    double kT = o_kb() * S->temperature;      /* amu A^2 / fs^2 */
+    for (int i = 0; i < S->n; ++i) {
+        int N = S->nb[i];
+        double *C = (double *)malloc(sizeof(double) * N * N);
+        double *pi = (double *)malloc(sizeof(double) * N);
+        orc_nm_basis(N, C);
+        double sd = sqrt(S->fm[i] * kT);
+        for (int c = 0; c < 3; ++c) {
+            for (int k = 0; k < N; ++k) {
+                double b = 0.0;
+                for (int j = 0; j < N; ++j) b += C[j * N + k] * p[3 * (S->off[i] + j) + c];
+                double c1 = exp(-orc_pile_gamma(S, i, k, tau0) * t);
+                double c2 = sqrt(1.0 - c1 * c1);
+                pi[k] = c1 * b + c2 * sd * eta[3 * (S->off[i] + k) + c];
+            }
+            for (int j = 0; j < N; ++j) {
+                double b = 0.0;
+                for (int k = 0; k < N; ++k) b += C[j * N + k] * pi[k];
+                p[3 * (S->off[i] + j) + c] = b;
+            }
+        }
+        free(C);
+        free(pi);
+    }
+}
+
+/* nsteps of the thermostatted split propagator O B A B O: a Langevin half
+ * step of length dt/2 (noise[st][0]), p += dt/2 F, exact free ring polymers
+ * for dt, F = F_mix(q), p += dt/2 F, a Langevin half step (noise[st][1]).
+ * noise: [nsteps][2][B][3] standard normals, mode-indexed as in orc_pile.
+ * elog (may be NULL) gets the energies after the second half kick (before
+ * the closing Langevin half step). */
+void orc_step_nvt(const orc_sys *S, int nsteps, double *q, double *p, double *F,
+                  const double *noise, double tau0, double *elog)
+{
+    long B = S->off[S->n];
+    double kick = 0.5 * S->dt * o_kcal();
+    double vpot[E_N];
+    for (int st = 0; st < nsteps; ++st) {
+        orc_pile(S, p, noise + (size_t)(2 * st) * 3 * B, 0.5 * S->dt, tau0);
+        for (long x = 0; x < 3 * B; ++x) p[x] += kick * F[x];
+        orc_free_propagate(S, q, p, S->dt);
+        orc_forces_o2(S, q, F, vpot);
+        for (long x = 0; x < 3 * B; ++x) p[x] += kick * F[x];
+        if (elog) orc_observables(S, q, p, F, vpot, elog + (size_t)st * E_N);
+        orc_pile(S, p, noise + (size_t)(2 * st + 1) * 3 * B, 0.5 * S->dt, tau0);
     }
 }
 

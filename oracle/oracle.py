@@ -86,6 +86,10 @@ def lib():
         _lib.orc_free_propagate.argtypes = [P, P, P, C.c_double]
         _lib.orc_observables.argtypes = [P, P, P, P, P, P]
         _lib.orc_step.argtypes = [P, C.c_int, P, P, P, P]
+        _lib.orc_pile_gamma.argtypes = [P, C.c_int, C.c_int, C.c_double]
+        _lib.orc_pile_gamma.restype = C.c_double
+        _lib.orc_pile.argtypes = [P, P, P, C.c_double, C.c_double]
+        _lib.orc_step_nvt.argtypes = [P, C.c_int, P, P, P, P, C.c_double, P]
         _lib.orc_beta.argtypes = [P]
         _lib.orc_beta.restype = C.c_double
         _lib.orc_constants.argtypes = [P]
@@ -228,6 +232,32 @@ class OracleSystem:
         F = np.array(F, dtype=np.float64, copy=True)
         elog = np.zeros((nsteps, E_N))
         lib().orc_step(self.ptr, int(nsteps), _p(q), _p(p), _p(F), _p(elog))
+        return q, p, F, elog
+
+    def pile_gamma(self, i: int, k: int, tau0: float) -> float:
+        return lib().orc_pile_gamma(self.ptr, int(i), int(k), float(tau0))
+
+    def pile(self, p, eta, t: float, tau0: float):
+        """One Langevin step of length t of the momenta in normal modes."""
+        p = np.array(p, dtype=np.float64, copy=True)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        lib().orc_pile(self.ptr, _p(p), _p(eta), float(t), float(tau0))
+        return p
+
+    def step_nvt(self, q, p, noise, tau0: float, F=None):
+        """Thermostatted steps O B A B O; noise [nsteps][2][B][3] standard
+        normals (mode-indexed).  Returns (q, p, F, elog[nsteps, E_N])."""
+        noise = np.ascontiguousarray(noise, dtype=np.float64)
+        nsteps = noise.shape[0]
+        assert noise.shape == (nsteps, 2, self.B, 3)
+        q = np.array(q, dtype=np.float64, copy=True)
+        p = np.array(p, dtype=np.float64, copy=True)
+        if F is None:
+            F, _ = self.forces(q)
+        F = np.array(F, dtype=np.float64, copy=True)
+        elog = np.zeros((nsteps, E_N))
+        lib().orc_step_nvt(self.ptr, int(nsteps), _p(q), _p(p), _p(F), _p(noise),
+                           float(tau0), _p(elog))
         return q, p, F, elog
 
     @property
