@@ -119,6 +119,42 @@ def _run(s, precision, steps, warmup, mixpi, torch, flags=0):
                 drift=float(drift[np.argmax(np.abs(drift))]), hstd=float(ham.std(axis=0).max()))
 
 
+def _run_nvt(s, precision, steps, mixpi, torch, flags=0, tau0=50.0):
+    """Thermostatted steps (O B A B O) with the noise drawn beforehand and
+    resident in HBM; returns steps/s and the time per step."""
+    import numpy as np
+    systems = _as_list(s)
+    sysm = mixpi.System(s, precision=precision, flags=flags)
+    sysm.set_thermostat(tau0)
+    idx = sysm.bead_index
+
+    def dev(x):
+        out = np.empty_like(x)
+        out[idx] = x
+        return torch.from_numpy(out).cuda()
+
+    q = dev(np.concatenate([x.q for x in systems]))
+    p = dev(np.concatenate([x.p for x in systems]))
+    f, _ = sysm.forces(q)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    noise = torch.randn((steps, 2, sysm.rows, 3), dtype=torch.float64, device="cuda",
+                        generator=gen)
+    elog = torch.zeros((steps, len(systems), mixpi.MIXPI_NE), dtype=torch.float64,
+                       device="cuda")
+    sysm.step_nvt(2, q, p, f, noise[:2], elog[:2])                # warm-up
+    sysm.step_nvt(steps, q, p, f, noise, elog)                    # captures the graph
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    t0.record(stream)
+    sysm.step_nvt(steps, q, p, f, noise, elog)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return {"steps_per_s": steps / (ms * 1e-3), "ms_per_step": ms / steps, "tau0_fs": tau0}
+
+
 def _bonded_slices(s):
     """Bond and angle slices: each term is evaluated on N_max slices."""
     n_bond = n_angle = 0
@@ -182,6 +218,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--nvt", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time thermostatted (path-integral Langevin) steps")
     ap.add_argument("--tile", default="auto", choices=["auto", "heuristic"],
                     help="pair-sweep tile shape: autotuned per workload bucket (default) or "
                          "the library's size heuristic")
@@ -267,6 +305,9 @@ def main():
                      "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"]},
     }
+    if args.nvt:
+        print("[bench] thermostatted steps (FP32 form)", file=sys.stderr, flush=True)
+        out["nvt"] = _run_nvt(s, mixpi.MIXPI_FP32_ACC64, args.steps, mixpi, torch, flags32)
     if not args.no_fp64:
         print("[bench] FP64 form", file=sys.stderr, flush=True)
         r64 = _run(s, mixpi.MIXPI_FP64, args.steps, args.warmup, mixpi, torch, flags64)

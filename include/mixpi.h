@@ -210,10 +210,33 @@ int mixpi_nm_transform(mixpi_system *sys, int32_t dir, const double *in, double 
  *   F = F_mix(q);  p += dt/2 F;  energies -> elog.
  * q, p, f: device double [rows][3], updated in place; on entry f must hold
  * F_mix(q) (from mixpi_forces).  elog: device double
- * [nsteps][n_systems][MIXPI_NE] or NULL.  Allocates nothing; repeated calls
- * with the same pointers and nsteps replay a cached HIP graph. */
+ * [nsteps][n_systems][MIXPI_NE] or NULL.  The first call with a set of
+ * pointers and nsteps captures and instantiates a HIP graph (see
+ * mixpi_step_prepare); later calls with the same pointers replay it. */
 int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
                double *elog, void *stream);
+
+/* Path-integral Langevin thermostat (the PILE thermostat of the paper's NVT
+ * runs, Sec. "Examples and Discussion"), for mixpi_step_nvt.  Each ring's
+ * momenta take Ornstein-Uhlenbeck steps in its normal modes (the basis of
+ * mixpi_nm_transform): pi_k <- c1 pi_k + c2 eta_k with c1 = exp(-gamma_k
+ * dt/2), c2 = sqrt(1 - c1^2) sqrt(m_f k_B T); gamma_0 = 1/tau0 for the
+ * centroid (0 when tau0 <= 0 or infinite), gamma_k = 2 omega_k for mode k
+ * (critical damping of the free-ring mode).  tau0 in fs; the system's own
+ * temperature and dt.  Builds the coefficient table (host work and one
+ * device copy); may be called again to change tau0. */
+int mixpi_set_thermostat(mixpi_system *sys, double tau0);
+
+/* nsteps of the thermostatted split propagator O B A B O: a Langevin half
+ * step (noise slice [k][0]), p += dt/2 F, free ring polymers for dt,
+ * F = F_mix(q), p += dt/2 F, energies -> elog (after the second half kick),
+ * a Langevin half step (noise slice [k][1]).  noise: device double
+ * [nsteps][2][rows][3] standard normals indexed by mode (mode k of a group
+ * in the place of bead k, as in mixpi_nm_transform), read only; the caller
+ * draws it.  Other arguments as mixpi_step; requires mixpi_set_thermostat.
+ * The first call with a set of pointers captures a HIP graph. */
+int mixpi_step_nvt(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+                   const double *noise, double *elog, void *stream);
 
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems

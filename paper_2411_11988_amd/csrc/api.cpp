@@ -58,6 +58,7 @@ struct GraphEntry {
     int nsteps;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    const void *noise = nullptr;   // thermostatted sequences: their noise
 };
 
 template <typename T>
@@ -106,6 +107,12 @@ struct mixpi_system {
     int *d_row_stage = nullptr;
     long long *d_stage_rows = nullptr;
     int n_stage = 0;
+    // thermostat: Langevin coefficients per mode row, and the host data to build them
+    double *d_lang = nullptr;
+    bool lang_set = false;
+    std::vector<double> h_prop, h_row_fm;
+    std::vector<int> h_row_sys;
+    std::vector<SysDev> h_sys;
     unsigned rp_lds = 0;
     double *d_basis = nullptr;
     double2 *d_tw = nullptr;
@@ -150,7 +157,7 @@ void release(mixpi_system *s)
                     s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
                     s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
-                    s->d_row_stage, s->d_stage_rows, s->d_basis, s->d_tw,
+                    s->d_row_stage, s->d_stage_rows, s->d_lang, s->d_basis, s->d_tw,
                     s->d_prop, s->d_row_ptr,
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_partial,
@@ -916,6 +923,10 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_basis, B.basis));
     T(upload(&S->d_tw, B.tw));
     T(upload(&S->d_prop, B.prop));
+    S->h_prop = B.prop;
+    S->h_row_fm = B.row_fm;
+    S->h_row_sys = B.row_sys;
+    S->h_sys = B.sys;
     T(upload(&S->d_row_ptr, G.row_ptr));
     T(upload(&S->d_dest, G.dest.empty() ? std::vector<int>(1, -1) : G.dest));
     T(upload(&S->d_part, std::vector<double>((size_t)3 * std::max<long long>(G.row_ptr.back(), 1), 0.0)));
@@ -1070,6 +1081,9 @@ RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double 
     }
     r.circ = s->d_circ;
     r.stage = s->d_stage;
+    r.lang = s->d_lang;
+    r.row_stage = s->d_row_stage;
+    r.row_hk = s->d_row_hk;
     r.sys = s->d_sys;
     r.basis = s->d_basis;
     r.twiddle = s->d_tw;
@@ -1148,18 +1162,36 @@ void enqueue_step(mixpi_system *s, int k, double *q, double *p, double *f, doubl
 }
 
 // Finds or captures the graph of nsteps steps for these pointers.
+// Langevin half steps (noise1, then noise2; either may be null) of the
+// momenta of every ring in normal modes.
+void enqueue_lang(mixpi_system *s, double *q, double *p, double *f, const double *noise1,
+                  const double *noise2, hipStream_t st)
+{
+    RpLaunch r = rp_args(s, OP_LANG, q, q, p, f);
+    r.noise1 = noise1;
+    r.noise2 = noise2;
+    launch_rp(r, st);
+}
+
+// Finds or captures the graph of nsteps steps for these pointers.  With
+// noise ([nsteps][2][rows][3]) every step is O B A B O: the closing
+// Langevin half step of step k and the opening one of step k+1 share one
+// launch.
 int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, double *elog,
-               GraphEntry **out)
+               GraphEntry **out, const double *noise = nullptr)
 {
     *out = nullptr;
     if (int rc = check_sys(sys)) return rc;
     if (nsteps < 0) return fail(MIXPI_E_INVALID, "nsteps must be >= 0");
     if (!q || !p || !f) return fail(MIXPI_E_INVALID, "q, p and f must be non-null");
     if (q == p || q == f || p == f) return fail(MIXPI_E_INVALID, "q, p and f must be distinct");
+    if (noise && !sys->lang_set)
+        return fail(MIXPI_E_INVALID, "no thermostat set (mixpi_set_thermostat)");
     if (nsteps == 0) return MIXPI_OK;
     HIP_TRY(hipSetDevice(sys->device));
     for (auto &g : sys->graphs)
-        if (g.q == q && g.p == p && g.f == f && g.elog == elog && g.nsteps == nsteps) {
+        if (g.q == q && g.p == p && g.f == f && g.elog == elog && g.nsteps == nsteps &&
+            g.noise == noise) {
             *out = &g;
             return MIXPI_OK;
         }
@@ -1168,12 +1200,19 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
         (void)hipGraphDestroy(sys->graphs.front().graph);
         sys->graphs.erase(sys->graphs.begin());
     }
-    GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr};
+    GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr, noise};
     auto row = [&](int k) { return elog ? elog + (size_t)k * sys->n_sys * MIXPI_NE : nullptr; };
+    const size_t slice = (size_t)3 * sys->rows;    // one [rows][3] noise slice
+    auto nz = [&](int k, int half) { return noise + (2 * (size_t)k + half) * slice; };
     HIP_TRY(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeRelaxed));
-    launch_stage(stage_args(sys, q, p, f), sys->cap_stream);
-    for (int k = 0; k < nsteps; ++k)
+    if (noise) enqueue_lang(sys, q, p, f, nz(0, 0), nullptr, sys->cap_stream);
+    else launch_stage(stage_args(sys, q, p, f), sys->cap_stream);
+    for (int k = 0; k < nsteps; ++k) {
         enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream);
+        if (noise)
+            enqueue_lang(sys, q, p, f, nz(k, 1), k + 1 < nsteps ? nz(k + 1, 0) : nullptr,
+                         sys->cap_stream);
+    }
     {
         ReduceB rb = reduce_b_args(sys, true);
         rb.elog = row(nsteps - 1);
@@ -1304,11 +1343,62 @@ int mixpi_step_prepare(mixpi_system *sys, int32_t nsteps, double *q, double *p, 
     return step_graph(sys, nsteps, q, p, f, elog, &ge);
 }
 
+namespace {
+int run_graph(mixpi_system *sys, GraphEntry *ge, void *stream);
+}
+
 int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f, double *elog,
                void *stream)
 {
     GraphEntry *ge = nullptr;
     if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge)) return rc;
+    return run_graph(sys, ge, stream);
+}
+
+int mixpi_set_thermostat(mixpi_system *sys, double tau0)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (std::isnan(tau0)) return fail(MIXPI_E_INVALID, "tau0 is NaN");
+    HIP_TRY(hipSetDevice(sys->device));
+    // c1 = exp(-gamma dt/2), c2 = sqrt(1 - c1^2) sqrt(m_f k_B T) per mode row;
+    // gamma = 1/tau0 for the centroid (0 if tau0 <= 0 or infinite), 2 omega_k
+    // for mode k, omega_k^2 = k_spring lambda_k / m_f = 2 w4 / m_f with w4 the
+    // spring entry k lambda_k / 2 of the propagation table
+    const long long rows = sys->rows;
+    std::vector<double> lang((size_t)2 * rows);
+    const double g0 = (tau0 > 0.0 && std::isfinite(tau0)) ? 1.0 / tau0 : 0.0;
+    for (long long r = 0; r < rows; ++r) {
+        const SysDev &S = sys->h_sys[sys->h_row_sys[r]];
+        const double dt = 2.0 * S.hkick / kKcal;
+        const double fm = sys->h_row_fm[r];
+        const double w4 = sys->h_prop[5 * (size_t)r + 4] * kKcal;     // amu A^2/fs^2 per A^2
+        const double w = std::sqrt(2.0 * w4 / fm);
+        const double gam = w4 > 0.0 ? 2.0 * w : g0;
+        const double c1 = std::exp(-gam * 0.5 * dt);
+        lang[2 * r] = c1;
+        lang[2 * r + 1] = std::sqrt(1.0 - c1 * c1) * std::sqrt(fm * S.kT * kKcal);
+    }
+    if (!sys->d_lang) {
+        hipError_t e = hipMalloc(&sys->d_lang, sizeof(double) * lang.size());
+        if (e != hipSuccess) return fail(MIXPI_E_HIP, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpy(sys->d_lang, lang.data(), sizeof(double) * lang.size(), hipMemcpyHostToDevice));
+    sys->lang_set = true;
+    return MIXPI_OK;
+}
+
+int mixpi_step_nvt(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+                   const double *noise, double *elog, void *stream)
+{
+    if (!noise) return fail(MIXPI_E_INVALID, "noise must be non-null");
+    GraphEntry *ge = nullptr;
+    if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge, noise)) return rc;
+    return run_graph(sys, ge, stream);
+}
+
+namespace {
+int run_graph(mixpi_system *sys, GraphEntry *ge, void *stream)
+{
     if (!ge) return MIXPI_OK;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipGraphLaunch(ge->exec, st));
@@ -1324,6 +1414,7 @@ int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *
     }
     return MIXPI_OK;
 }
+}  // namespace
 
 int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const double *p,
                       const double *f, double *avg_us, void *stream)

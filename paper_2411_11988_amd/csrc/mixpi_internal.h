@@ -86,7 +86,7 @@ struct BlockRange {
 enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
 constexpr int kCircOut = 16;       // bead outputs per circulant item
 constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
-enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2 };
+enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2, OP_LANG = 3 };
 struct RpItem {
     int kind, sys, N, logN;
     int n;                // particles in the group
@@ -179,7 +179,14 @@ struct RpLaunch {
     const double2 *twiddle;  // per N, stage-major exp(-2 pi i pos / 2^s), N - 1 entries
     const double *prop;      // [rows][5] a, b, c, d, spring coefficient
     const double *circ;      // circulant propagator rows a_d, b_d, c_d per particle
-    const double *stage;     // circulant rings' step inputs [stage rows][6]: q, p + dt/2 F
+    double *stage;           // circulant rings' step inputs [stage rows][6]: q, p + dt/2 F
+                             // (read by OP_STEP, written by OP_LANG)
+    // OP_LANG: Langevin half steps of p in normal modes, pi <- c1 pi + c2 eta
+    const double *lang;      // [rows][2] c1, c2 (momentum units) per mode row
+    const double *noise1;    // [rows][3] mode-indexed standard normals, or null
+    const double *noise2;    // a second half step after the first, or null
+    const int *row_stage;    // [rows] stage row of a circulant ring's bead row, or -1
+    const double *row_hk;    // [rows] dt/2 in momentum units
     int op;
     const double *in_q;      // OP_STEP: q (in/out via out_q); FWD/BWD: input
     double *out_q;

@@ -471,6 +471,115 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Path-integral Langevin thermostat (the PILE thermostat of the paper's NVT
+// runs): each ring's momenta are projected onto the normal modes, every mode
+// takes one or two Ornstein-Uhlenbeck half steps pi <- c1 pi + c2 eta
+// (c1 = exp(-gamma_k dt/2), c2 = sqrt(1 - c1^2) sqrt(m_f k_B T), friction
+// 1/tau0 on the centroid and 2 omega_k on mode k), and projected back.  The
+// noise is an input, indexed by mode like the mode coordinates.  Rows of
+// circulant rings also get their stage rows (q, p + dt/2 F) for the next
+// step, since p changed after the epilogue wrote them.
+__device__ __forceinline__ double lang_o(const RpLaunch &a, long long rowm, int d, double x)
+{
+    const double c1 = a.lang[2 * rowm], c2 = a.lang[2 * rowm + 1];
+    if (a.noise1) x = c1 * x + c2 * a.noise1[3 * rowm + d];
+    if (a.noise2) x = c1 * x + c2 * a.noise2[3 * rowm + d];
+    return x;
+}
+
+__device__ __forceinline__ void lang_store(const RpLaunch &a, long long row, long long g, int d,
+                                           double pn)
+{
+    a.p[g] = pn;
+    const int st = a.row_stage[row];
+    if (st >= 0) {
+        a.stage[6LL * st + d] = a.in_q[g];
+        a.stage[6LL * st + 3 + d] = pn + a.row_hk[row] * a.f[g];
+    }
+}
+
+__device__ void rp_lang_dense(const RpLaunch &a, const RpItem &it, double *smem)
+{
+    const int N = it.N, n = it.n;
+    const int CB = 256 / N;
+    const int tid = threadIdx.x;
+    double *sC = smem;              // C[j*N + k]
+    double *sCT = sC + N * N;       // C^T[k*N + j]
+    double *s0 = sCT + N * N;       // [N][CB] momenta
+    double *s2 = s0 + 256;          // [N][CB] modes
+    const double *Cg = a.basis + it.basis_off;
+    for (int x = tid; x < 2 * N * N; x += 256) sC[x] = Cg[x];
+    const int cl = tid % CB, k = tid / CB;
+    const bool valid = cl < it.ncols;
+    const int c = it.c0 + cl, i = c / 3, d = c - 3 * i;
+    {
+        const long long g = (it.row + (long long)k * n) * 3 + c;
+        s0[k * CB + cl] = valid ? a.p[g] : 0.0;
+    }
+    __syncthreads();
+    double pi = 0.0;
+    for (int j = 0; j < N; ++j) pi += sC[j * N + k] * s0[j * CB + cl];
+    if (valid) pi = lang_o(a, it.row + (long long)k * n + i, d, pi);
+    s2[k * CB + cl] = pi;
+    __syncthreads();
+    const int j = k;
+    double pn = 0.0;
+    for (int m = 0; m < N; ++m) pn += sCT[m * N + j] * s2[m * CB + cl];
+    if (valid) {
+        const long long row = it.row + (long long)j * n + i;
+        lang_store(a, row, row * 3 + d, d, pn);
+    }
+}
+
+constexpr int kLangKeep = (kMaxBeads / 2 + 1 + 255) / 256;
+__device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
+{
+    const int N = it.N, L = it.logN, n = it.n;
+    const int col = it.c0, i = col / 3, d = col - 3 * i;
+    double2 *tw = z + N;
+    for (int m = threadIdx.x; m < N - 1; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
+    const int tid = threadIdx.x;
+    const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
+    auto rowm = [&](int k) { return it.row + (long long)k * n + i; };
+    for (int j = tid; j < N; j += blockDim.x) z[brev(j, L)] = make_double2(a.p[rowm(j) * 3 + d], 0.0);
+    fft_stages(z, tw, N, L);
+    // modes of p (as the forward transform), thermostatted, then the
+    // conjugated Hermitian spectrum of the new modes (as the backward one)
+    double2 keep[kLangKeep];
+#pragma unroll
+    for (int r = 0; r < kLangKeep; ++r) {
+        const int m = tid + r * 256;
+        if (m > N / 2) break;
+        const double2 Z = z[m];
+        if (m == 0 || 2 * m == N) {
+            const double x = lang_o(a, rowm(m), d, Z.x / rN);
+            keep[r] = make_double2(rN * x, 0.0);
+        } else {
+            const double x1 = lang_o(a, rowm(m), d, r2N * Z.x);
+            const double x2 = lang_o(a, rowm(N - m), d, r2N * Z.y);
+            keep[r] = make_double2(rN2 * x1, rN2 * x2);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLangKeep; ++r) {
+        const int m = tid + r * 256;
+        if (m > N / 2) break;
+        if (m == 0 || 2 * m == N) {
+            z[brev(m, L)] = keep[r];
+        } else {
+            z[brev(m, L)] = make_double2(keep[r].x, -keep[r].y);
+            z[brev(N - m, L)] = make_double2(keep[r].x, keep[r].y);
+        }
+    }
+    fft_stages(z, tw, N, L);
+    for (int j = tid; j < N; j += blockDim.x) {
+        const long long row = rowm(j);
+        lang_store(a, row, row * 3 + d, d, z[j].x / N);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
 {
     extern __shared__ __align__(16) double smem[];
@@ -482,6 +591,11 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
         return;
     }
     const RpItem it = a.items[blockIdx.x];
+    if (a.op == OP_LANG) {
+        if (it.kind == RP_DENSE) rp_lang_dense(a, it, smem);
+        else rp_lang_fft(a, it, reinterpret_cast<double2 *>(smem));
+        return;
+    }
     if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);
     else if (it.kind == RP_CIRC) rp_circ(a, it, smem, red);
     else rp_fft(a, it, reinterpret_cast<double2 *>(smem), red);

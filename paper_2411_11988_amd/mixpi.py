@@ -96,6 +96,8 @@ def load():
         "mixpi_pair_evals": ([P, P, I32, P], C.c_int),
         "mixpi_step_prepare": ([P, I32, P, P, P, P], C.c_int),
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
+        "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
+        "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -225,6 +227,15 @@ def mixpi_step_prepare(h, nsteps: int, q, p, f, elog) -> None:
 KERNEL_PAIR, KERNEL_BONDED, KERNEL_RP, KERNEL_FINISH = 0, 1, 2, 3
 
 
+def mixpi_set_thermostat(h, tau0: float):
+    _check(load().mixpi_set_thermostat(h, float(tau0)))
+
+
+def mixpi_step_nvt(h, nsteps: int, q, p, f, noise, elog=None, stream=None):
+    _check(load().mixpi_step_nvt(h, int(nsteps), _ptr(q), _ptr(p), _ptr(f), _ptr(noise),
+                                 _ptr(elog), _stream(stream)))
+
+
 def mixpi_kernel_time(h, reps: int, q, p, f, stream=None) -> dict:
     """Mean in-step durations (us) of the force, free ring-polymer and
     epilogue launches over `reps` eager steps on library copies of q, p, f."""
@@ -322,6 +333,13 @@ class System:
 
     def step_prepare(self, nsteps: int, q, p, f, elog=None):
         mixpi_step_prepare(self.h, nsteps, q, p, f, elog)
+
+    def set_thermostat(self, tau0: float):
+        mixpi_set_thermostat(self.h, tau0)
+
+    def step_nvt(self, nsteps: int, q, p, f, noise, elog=None, stream=None):
+        mixpi_step_nvt(self.h, nsteps, q, p, f, noise, elog, stream)
+        return elog
 
     def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
         return mixpi_kernel_time(self.h, reps, q, p, f, stream)

@@ -1,0 +1,168 @@
+"""The thermostatted step (path-integral Langevin thermostat, O B A B O)
+through the C-ABI: identical noise gives the oracle's trajectory, and the
+dynamics sample the exact finite-P distribution of a quantum harmonic
+dimer."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import dev, energy_err, from_rows, host, layout_rows, to_rows
+from tests._systems import custom
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    from paper_2411_11988_amd import mixpi
+    mixpi.load()
+    return mixpi
+
+
+def _noise_rows(s, noise, rows):
+    """Bead-table noise [n][2][B][3] -> library rows (mode k of a particle
+    sits where its bead k does)."""
+    out = np.empty_like(noise)
+    out[:, :, rows, :] = noise
+    return out
+
+
+def _nvt_compare(mp, s, nsteps, tau0, seed, tol_q, tol_p, tol_e):
+    rows = layout_rows(s)
+    o = oracle.OracleSystem(s)
+    B = len(rows)
+    noise = np.random.default_rng(seed).normal(size=(nsteps, 2, B, 3))
+    Fo0, _ = o.forces(s.q)
+    qo, po, _, elo = o.step_nvt(s.q, s.p, noise, tau0, F=Fo0)
+    import torch
+    sysm = mp.System(s)
+    sysm.set_thermostat(tau0)
+    q, p = dev(to_rows(s, s.q, rows)), dev(to_rows(s, s.p, rows))
+    f = dev(to_rows(s, Fo0, rows))
+    nz = dev(_noise_rows(s, noise, rows))
+    elog = torch.zeros((nsteps, 1, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+    sysm.step_nvt(nsteps, q, p, f, nz, elog)
+    qg, pg = from_rows(s, host(q), rows), from_rows(s, host(p), rows)
+    el = host(elog)[:, 0, :]
+    assert np.abs(qg - qo).max() <= tol_q
+    assert np.abs(pg - po).max() <= tol_p * np.abs(po).max()
+    assert max(energy_err(el[k], elo[k]) for k in range(nsteps)) <= tol_e
+
+
+CASES = [
+    ("tiny1", lambda: synth.tiny_random(1)),
+    ("c1", synth.config_c1),
+    ("water-h8-o2", lambda: synth.water_box(40, 11.0, 8, 2, seed=4, rc=5.4)),
+    ("e256-water", lambda: synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4, rc_aa=6.0,
+                                                   n_h=2, n_o=1)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_nvt_matches_oracle(mp, name, make):
+    """Dense (N <= 64) and FFT / circulant (N = 256) rings, 5 steps."""
+    print(f"[nvt] {name}", flush=True)
+    _nvt_compare(mp, make(), 5, 25.0, 7, 1e-11, 1e-10, 1e-10)
+
+
+def test_nvt_full_size_e1024(mp):
+    """The 1024-bead electron workload, 2 thermostatted steps."""
+    print("[nvt] e1024-ion-512w", flush=True)
+    _nvt_compare(mp, synth.config_c3(), 2, 50.0, 8, 1e-11, 1e-10, 1e-10)
+
+
+def test_nvt_without_centroid_friction(mp):
+    """tau0 = inf: only the internal modes are thermostatted."""
+    _nvt_compare(mp, synth.tiny_random(2), 4, math.inf, 9, 1e-11, 1e-10, 1e-10)
+
+
+def test_nvt_requires_thermostat(mp):
+    import torch
+    s = synth.tiny_random(0)
+    sysm = mp.System(s)
+    q, p = dev(to_rows(s, s.q)), dev(to_rows(s, s.p))
+    f, _ = sysm.forces(q)
+    nz = torch.zeros((1, 2, sysm.rows, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MixPIError) as e:
+        sysm.step_nvt(1, q, p, f, nz)
+    assert e.value.code == mp.MIXPI_E_INVALID
+
+
+def test_nvt_steps_are_bit_reproducible(mp):
+    import torch
+    s = synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4, rc_aa=6.0, n_h=2, n_o=1)
+    nz = torch.randn((6, 2, sum(s.n_beads), 3), dtype=torch.float64,
+                     generator=torch.Generator().manual_seed(3)).cuda()
+    out = []
+    for _ in range(2):
+        sysm = mp.System(s)
+        sysm.set_thermostat(30.0)
+        q, p = dev(to_rows(s, s.q)), dev(to_rows(s, s.p))
+        f, _ = sysm.forces(q)
+        elog = torch.zeros((6, 1, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+        sysm.step_nvt(6, q, p, f, nz, elog)
+        out.append([host(x).copy() for x in (q, p, f, elog)])
+        del sysm
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_nvt_samples_quantum_harmonic_dimers(mp):
+    """64 independent dimers (harmonic bond k/2 |r1 - r2|^2, P = 8 beads,
+    beta hbar omega = 4) in one batched handle: the bead-averaged
+    <|r1 - r2|^2> (= 2 V_bond / k per system) over 36,000 thermostatted
+    steps of 0.5 fs matches the exact finite-P value 3/(beta mu) sum_k
+    1/(omega^2 + omega_k^2) within 4 standard errors, and differs from the
+    classical value 3/(beta mu omega^2).  (At dt = 1 fs the splitting bias,
+    about +0.4 % in the oracle too, is comparable to the statistical
+    error.)"""
+    import torch
+    P, T, m = 8, 300.0, 1.00794
+    mu = m / 2
+    c = oracle.constants()
+    bh = c["hbar"] / (c["kb"] * T)
+    w = 4.0 / bh
+    kb = mu * w * w / c["kcal"]
+    systems = []
+    for i in range(64):
+        q = np.zeros((2 * P, 3))
+        q[P:, 0] = 0.1
+        systems.append(custom([P, P], q, mass=[m, m], bonds=[(0, 1)], bond_k=kb, bond_r0=0.0,
+                              temperature=T, dt=0.5))
+    beta = 1.0 / (c["kb"] * T)
+    wk = [2.0 * (P / bh) * math.sin(math.pi * k / P) for k in range(P)]
+    want = 3.0 / (beta * mu) * sum(1.0 / (w * w + x * x) for x in wk)
+    classical = 3.0 / (beta * mu * w * w)
+    sysm = mp.System(systems)
+    sysm.set_thermostat(50.0)
+    q0 = np.concatenate([s.q for s in systems])
+    rows_all = sysm.bead_index
+    qr = np.empty_like(q0)
+    qr[rows_all] = q0
+    q = dev(qr)
+    p = torch.zeros_like(q)
+    f, _ = sysm.forces(q)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    chunk, nchunks = 2000, 20
+    ibond = mp.E_NAMES.index("bond")
+    samples = []
+    # the same buffers every chunk, so the captured graph is reused
+    nz = torch.empty((chunk, 2, sysm.rows, 3), dtype=torch.float64, device="cuda")
+    elog = torch.zeros((chunk, 64, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+    for k in range(nchunks):
+        torch.randn((chunk, 2, sysm.rows, 3), dtype=torch.float64, device="cuda",
+                    generator=gen, out=nz)
+        sysm.step_nvt(chunk, q, p, f, nz, elog)
+        if k >= 2:
+            samples.append(2.0 * host(elog)[:, :, ibond] / kb)
+    x = np.concatenate(samples)                  # [steps][64 systems]
+    per_system = x.mean(axis=0)                  # 64 independent estimates
+    mean = per_system.mean()
+    err = per_system.std(ddof=1) / math.sqrt(len(per_system))
+    print(f"[dimers] <r^2> = {mean:.5f} +- {err:.5f}, exact {want:.5f}, classical {classical:.5f}")
+    assert err < 0.02 * want
+    assert abs(mean - want) < 4.0 * err
+    assert abs(mean - classical) > 20.0 * err
