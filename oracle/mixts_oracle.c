@@ -29,6 +29,8 @@
  *     "Examples and Discussion", PILE): an Ornstein-Uhlenbeck step of the
  *     momenta in each ring's normal modes, friction 1/tau0 on the centroid
  *     and 2 omega_k on mode k; noise is an input.  [orc_pile, orc_step_nvt]
+ *   - The alternative velocity-Verlet integration with the springs as
+ *     forces (Sec. "Evaluation").  [orc_step_vv]
  *
  * Force field (the paper names q-SPC/Fw water, a cation-water LJ and an
  * electron pseudopotential; the functional forms below are the readings this
@@ -765,6 +767,31 @@ void orc_step_nvt(const orc_sys *S, int nsteps, double *q, double *p, double *F,
         if (elog) orc_observables(S, q, p, F, vpot, elog + (size_t)st * E_N);
         orc_pile(S, p, noise + (size_t)(2 * st + 1) * 3 * B, 0.5 * S->dt, tau0);
     }
+}
+
+/* nsteps of velocity Verlet with the ring-polymer springs as forces (the
+ * paper's "manual" integrator, Sec. "Evaluation"): with G = F_mix + F_sp,
+ * p += dt/2 G(q); q += dt p / m_f; p += dt/2 G(q).  On entry F must hold
+ * F_mix(q).  elog (may be NULL) gets the energies after each step. */
+void orc_step_vv(const orc_sys *S, int nsteps, double *q, double *p, double *F,
+                 double *elog)
+{
+    long B = S->off[S->n];
+    double kick = 0.5 * S->dt * o_kcal();
+    double vpot[E_N];
+    double *Fsp = (double *)malloc(sizeof(double) * 3 * B);
+    orc_springs(S, q, Fsp);
+    for (int st = 0; st < nsteps; ++st) {
+        for (long x = 0; x < 3 * B; ++x) p[x] += kick * (F[x] + Fsp[x]);
+        for (int i = 0; i < S->n; ++i)
+            for (long a = S->off[i]; a < S->off[i + 1]; ++a)
+                for (int c = 0; c < 3; ++c) q[3 * a + c] += S->dt * p[3 * a + c] / S->fm[i];
+        orc_forces_o2(S, q, F, vpot);
+        orc_springs(S, q, Fsp);
+        for (long x = 0; x < 3 * B; ++x) p[x] += kick * (F[x] + Fsp[x]);
+        if (elog) orc_observables(S, q, p, F, vpot, elog + (size_t)st * E_N);
+    }
+    free(Fsp);
 }
 
 /* Constants as the oracle uses them, for tests: kcal, hbar, kB, k_e, kB(kcal). */

@@ -90,6 +90,7 @@ def lib():
         _lib.orc_pile_gamma.restype = C.c_double
         _lib.orc_pile.argtypes = [P, P, P, C.c_double, C.c_double]
         _lib.orc_step_nvt.argtypes = [P, C.c_int, P, P, P, P, C.c_double, P]
+        _lib.orc_step_vv.argtypes = [P, C.c_int, P, P, P, P]
         _lib.orc_beta.argtypes = [P]
         _lib.orc_beta.restype = C.c_double
         _lib.orc_constants.argtypes = [P]
@@ -232,6 +233,17 @@ class OracleSystem:
         F = np.array(F, dtype=np.float64, copy=True)
         elog = np.zeros((nsteps, E_N))
         lib().orc_step(self.ptr, int(nsteps), _p(q), _p(p), _p(F), _p(elog))
+        return q, p, F, elog
+
+    def step_vv(self, q, p, nsteps: int, F=None):
+        """Velocity Verlet with spring forces; returns (q, p, F, elog)."""
+        q = np.array(q, dtype=np.float64, copy=True)
+        p = np.array(p, dtype=np.float64, copy=True)
+        if F is None:
+            F, _ = self.forces(q)
+        F = np.array(F, dtype=np.float64, copy=True)
+        elog = np.zeros((nsteps, E_N))
+        lib().orc_step_vv(self.ptr, int(nsteps), _p(q), _p(p), _p(F), _p(elog))
         return q, p, F, elog
 
     def pile_gamma(self, i: int, k: int, tau0: float) -> float:

@@ -576,3 +576,42 @@ def test_pile_samples_the_quantum_harmonic_dimer():
     mean, err = blocks.mean(), blocks.std(ddof=1) / math.sqrt(len(blocks))
     assert err < 0.02 * want
     assert abs(mean - want) < 4.0 * err, (mean, want, err)
+
+
+# ------------------------------------------------- velocity Verlet with springs
+
+def test_vv_equals_split_propagator_without_springs():
+    """One bead per particle: no springs, the free motion is a plain drift,
+    and both integrators are the same velocity-Verlet step."""
+    s = synth.tiny_random(6, bead_choices=(1,))
+    o = oracle.OracleSystem(s)
+    a = o.step(s.q, s.p, 4)
+    b = o.step_vv(s.q, s.p, 4)
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, rtol=1e-13, atol=1e-13)
+
+
+def test_vv_converges_to_exact_free_rings_as_dt_squared():
+    """Free rings: velocity Verlet approaches the exact normal-mode motion
+    with an error that falls by about 4 when dt halves."""
+    def err(dt, n):
+        s = _free_rings(3, 8)
+        s.dt = dt
+        rng = np.random.default_rng(4)
+        s.p = rng.normal(scale=0.02, size=s.q.shape)
+        o = oracle.OracleSystem(s)
+        q, p, _, _ = o.step_vv(s.q, s.p, n)
+        qe, pe = o.free_propagate(s.q, s.p, dt * n)
+        return np.abs(q - qe).max()
+    e1, e2 = err(0.4, 10), err(0.2, 20)
+    assert 3.5 < e1 / e2 < 4.5, (e1, e2)
+
+
+def test_vv_conserves_energy_as_dt_squared():
+    s1 = synth.water_box(8, 7.0, 4, 2, seed=2, rc=3.4, dt=0.05)
+    s2 = synth.water_box(8, 7.0, 4, 2, seed=2, rc=3.4, dt=0.025)
+    h = []
+    for s, n in ((s1, 200), (s2, 400)):
+        _, _, _, el = oracle.OracleSystem(s).step_vv(s.q, s.p, n)
+        h.append(el[:, oracle.E_NAMES.index("ham")].std())
+    assert 3.0 < h[0] / h[1] < 5.5, h
