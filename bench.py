@@ -155,6 +155,36 @@ def _run_nvt(s, precision, steps, mixpi, torch, flags=0, tau0=50.0):
     return {"steps_per_s": steps / (ms * 1e-3), "ms_per_step": ms / steps, "tau0_fs": tau0}
 
 
+def _run_vv(s, precision, steps, mixpi, torch, flags=0):
+    """Velocity-Verlet steps with spring forces: steps/s and time per step."""
+    import numpy as np
+    systems = _as_list(s)
+    sysm = mixpi.System(s, precision=precision, flags=flags)
+    idx = sysm.bead_index
+
+    def dev(x):
+        out = np.empty_like(x)
+        out[idx] = x
+        return torch.from_numpy(out).cuda()
+
+    q = dev(np.concatenate([x.q for x in systems]))
+    p = dev(np.concatenate([x.p for x in systems]))
+    f, _ = sysm.forces(q)
+    elog = torch.zeros((steps, len(systems), mixpi.MIXPI_NE), dtype=torch.float64,
+                       device="cuda")
+    sysm.step_vv(steps, q, p, f, elog)                            # captures the graph
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    t0.record(stream)
+    sysm.step_vv(steps, q, p, f, elog)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return {"steps_per_s": steps / (ms * 1e-3), "ms_per_step": ms / steps}
+
+
 def _bonded_slices(s):
     """Bond and angle slices: each term is evaluated on N_max slices."""
     n_bond = n_angle = 0
@@ -219,7 +249,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--nvt", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time thermostatted (path-integral Langevin) steps")
+                    help="also time thermostatted (path-integral Langevin) steps and "
+                         "velocity-Verlet steps")
     ap.add_argument("--tile", default="auto", choices=["auto", "heuristic"],
                     help="pair-sweep tile shape: autotuned per workload bucket (default) or "
                          "the library's size heuristic")
@@ -308,6 +339,8 @@ def main():
     if args.nvt:
         print("[bench] thermostatted steps (FP32 form)", file=sys.stderr, flush=True)
         out["nvt"] = _run_nvt(s, mixpi.MIXPI_FP32_ACC64, args.steps, mixpi, torch, flags32)
+        print("[bench] velocity-Verlet steps (FP32 form)", file=sys.stderr, flush=True)
+        out["vv"] = _run_vv(s, mixpi.MIXPI_FP32_ACC64, args.steps, mixpi, torch, flags32)
     if not args.no_fp64:
         print("[bench] FP64 form", file=sys.stderr, flush=True)
         r64 = _run(s, mixpi.MIXPI_FP64, args.steps, args.warmup, mixpi, torch, flags64)

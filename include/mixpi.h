@@ -238,6 +238,17 @@ int mixpi_set_thermostat(mixpi_system *sys, double tau0);
 int mixpi_step_nvt(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
                    const double *noise, double *elog, void *stream);
 
+/* nsteps of velocity Verlet with the ring-polymer springs as forces (the
+ * paper's alternative to the exact normal-mode propagation, Sec.
+ * "Evaluation"): with G = F_mix + F_sp, F_sp the force of the springs of
+ * Eq. (mts-hamiltonian-b),
+ *   p += dt/2 G(q);  q += dt p / m_f;  F = F_mix(q);  p += dt/2 G(q);
+ *   energies -> elog.
+ * Arguments as mixpi_step (f must hold F_mix(q) on entry).  The time step
+ * must resolve the highest ring frequency, unlike the exact propagator. */
+int mixpi_step_vv(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+                  double *elog, void *stream);
+
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems
  * (from the work lists; no device work). */

@@ -59,6 +59,7 @@ struct GraphEntry {
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void *noise = nullptr;   // thermostatted sequences: their noise
+    int mode = 0;                  // NVE split propagator, thermostatted, velocity Verlet
 };
 
 template <typename T>
@@ -131,8 +132,11 @@ struct mixpi_system {
     double *d_eslot = nullptr;
     // reducer plans: the force-only slots [0, e_rp) and the whole step
     int *d_red_f = nullptr, *d_red_a = nullptr;   // packed chunk_begin | chunk_len | sys_chunk
-    int red_f_off[3] = {0, 0, 0}, red_a_off[3] = {0, 0, 0};
-    int nch_f = 0, nch_a = 0;         // chunks of each list
+    int *d_red_v = nullptr;                       // the same for velocity-Verlet steps
+    int red_f_off[3] = {0, 0, 0}, red_a_off[3] = {0, 0, 0}, red_v_off[3] = {0, 0, 0};
+    int nch_f = 0, nch_a = 0, nch_v = 0;          // chunks of each list
+    long long *d_row_prev = nullptr, *d_row_next = nullptr;
+    double *d_row_ksp = nullptr;
     double *d_partial = nullptr;      // [max chunks][A_N] stage-A sums
     int n_eslots = 0, e_bonded = 0, e_rp = 0, e_fin = 0;
 
@@ -160,7 +164,7 @@ void release(mixpi_system *s)
                     s->d_row_stage, s->d_stage_rows, s->d_lang, s->d_basis, s->d_tw,
                     s->d_prop, s->d_row_ptr,
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
-                    s->d_partial,
+                    s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -262,7 +266,8 @@ struct Build {
     std::vector<SysDev> sys;
     std::vector<double> lj_eps, lj_sig, charge, bond_k, bond_r0, angle_k, angle_t0;
     std::vector<int> ljt, mol, row_part, row_sys;
-    std::vector<double> row_fm, row_hk;
+    std::vector<double> row_fm, row_hk, row_ksp;
+    std::vector<long long> row_prev, row_next;
     std::vector<PairBlock> blocks;
     std::vector<char> block_slow;              // block touches an FFT group
     std::vector<BondedTerm> bterms, bterms_slow;
@@ -383,6 +388,9 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
     B.row_sys.resize(row, s);
     B.row_fm.resize(row, 0.0);
     B.row_hk.resize(row, S.hkick);
+    B.row_ksp.resize(row, 0.0);
+    B.row_prev.resize(row, 0);
+    B.row_next.resize(row, 0);
     for (const Group &g : groups)
         for (int a = 0; a < g.N; ++a)
             for (int i = 0; i < g.n; ++i) {
@@ -390,6 +398,10 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 rows_of[part_first[g.p0 + i] + a] = r;
                 B.row_part[r] = p_base + g.p0 + i;
                 B.row_fm[r] = d->fict_mass[g.p0 + i];
+                // ring neighbours and spring constant N m / (beta hbar)^2 in kcal/mol/A^2
+                B.row_prev[r] = g.row + (long long)((a + g.N - 1) % g.N) * g.n + i;
+                B.row_next[r] = g.row + (long long)((a + 1) % g.N) * g.n + i;
+                B.row_ksp[r] = g.N > 1 ? g.N * d->mass[g.p0 + i] / (bh * bh) / kKcal : 0.0;
             }
     B.bead_index.insert(B.bead_index.end(), rows_of.begin(), rows_of.end());
     auto bead_row = [&](int i, int a) { return rows_of[part_first[i] + a]; };
@@ -677,20 +689,22 @@ std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin,
     return out;
 }
 
-// Reducer plan for the slots [0, n): each system's slots (in slot order)
-// cut into chunks of at most kChunkSlots consecutive slots of that system.
+// Reducer plan for the slot ranges [begin, end): each system's slots (in
+// range and slot order) cut into chunks of at most kChunkSlots consecutive
+// slots of that system.
 // Packed as chunk_begin[n_chunks] | chunk_len[n_chunks] | sys_chunk[n_sys + 1];
 // off[] receives the three offsets.  Returns n_chunks.
-int reducer_plan(const std::vector<int> &eslot_sys, int n, int n_sys, std::vector<int> &out,
-                 int off[3])
+int reducer_plan(const std::vector<int> &eslot_sys, const std::vector<std::pair<int, int>> &ranges,
+                 int n_sys, std::vector<int> &out, int off[3])
 {
     std::vector<std::vector<std::pair<int, int>>> runs(n_sys);
-    for (int k = 0; k < n;) {
-        int e = k;
-        while (e < n && eslot_sys[e] == eslot_sys[k] && e - k < kChunkSlots) ++e;
-        runs[eslot_sys[k]].push_back({k, e - k});
-        k = e;
-    }
+    for (const auto &rg : ranges)
+        for (int k = rg.first, n = rg.second; k < n;) {
+            int e = k;
+            while (e < n && eslot_sys[e] == eslot_sys[k] && e - k < kChunkSlots) ++e;
+            runs[eslot_sys[k]].push_back({k, e - k});
+            k = e;
+        }
     std::vector<int> cb, cl, sys_chunk(n_sys + 1, 0);
     for (int y = 0; y < n_sys; ++y) {
         sys_chunk[y] = (int)cb.size();
@@ -890,8 +904,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
     // per-system slot lists (stable order) for the reducer
     std::vector<int> red_f, red_a;
-    S->nch_f = reducer_plan(eslot_sys, S->e_rp, n_sys, red_f, S->red_f_off);
-    S->nch_a = reducer_plan(eslot_sys, S->n_eslots, n_sys, red_a, S->red_a_off);
+    S->nch_f = reducer_plan(eslot_sys, {{0, S->e_rp}}, n_sys, red_f, S->red_f_off);
+    S->nch_a = reducer_plan(eslot_sys, {{0, S->n_eslots}}, n_sys, red_a, S->red_a_off);
+    std::vector<int> red_v;   // velocity Verlet: no ring-polymer slots
+    S->nch_v = reducer_plan(eslot_sys, {{0, S->e_rp}, {S->e_fin, S->n_eslots}}, n_sys, red_v,
+                            S->red_v_off);
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -934,7 +951,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_eslot, std::vector<double>((size_t)2 * A_N * std::max(S->n_eslots, 1), 0.0)));
     T(upload(&S->d_red_f, red_f));
     T(upload(&S->d_red_a, red_a));
-    T(upload(&S->d_partial, std::vector<double>((size_t)A_N * std::max(1, std::max(S->nch_f, S->nch_a)), 0.0)));
+    T(upload(&S->d_red_v, red_v));
+    T(upload(&S->d_row_prev, B.row_prev));
+    T(upload(&S->d_row_next, B.row_next));
+    T(upload(&S->d_row_ksp, B.row_ksp));
+    T(upload(&S->d_partial, std::vector<double>((size_t)A_N * std::max(1, std::max(S->nch_v, std::max(S->nch_f, S->nch_a))), 0.0)));
     T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
     T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
@@ -1024,24 +1045,36 @@ GatherArgs gather_args(mixpi_system *s)
 
 // Stage A over buffer buf and stage B of the force-only slots (pair +
 // bonded) or of the slots of a whole step.
-ReduceA reduce_a_args(mixpi_system *s, int buf, bool whole_step)
+enum { LIST_FORCE = 0, LIST_STEP = 1, LIST_VV = 2 };
+const int *plan_of(mixpi_system *s, int list, const int **off, int *n)
+{
+    if (list == LIST_STEP) { *off = s->red_a_off; *n = s->nch_a; return s->d_red_a; }
+    if (list == LIST_VV) { *off = s->red_v_off; *n = s->nch_v; return s->d_red_v; }
+    *off = s->red_f_off;
+    *n = s->nch_f;
+    return s->d_red_f;
+}
+
+ReduceA reduce_a_args(mixpi_system *s, int buf, int list)
 {
     ReduceA r{};
     r.eslot = eslot_buf(s, buf);
-    const int *plan = whole_step ? s->d_red_a : s->d_red_f;
-    const int *off = whole_step ? s->red_a_off : s->red_f_off;
+    const int *off;
+    const int *plan = plan_of(s, list, &off, &r.n_chunks);
     r.chunk_begin = plan + off[0];
     r.chunk_len = plan + off[1];
-    r.n_chunks = whole_step ? s->nch_a : s->nch_f;
     r.partial = s->d_partial;
     return r;
 }
 
-ReduceB reduce_b_args(mixpi_system *s, bool whole_step)
+ReduceB reduce_b_args(mixpi_system *s, int list)
 {
     ReduceB r{};
     r.partial = s->d_partial;
-    r.sys_chunk = (whole_step ? s->d_red_a : s->d_red_f) + (whole_step ? s->red_a_off : s->red_f_off)[2];
+    const int *off;
+    int nch;
+    const int *plan = plan_of(s, list, &off, &nch);
+    r.sys_chunk = plan + off[2];
     r.n_wg = s->n_sys;
     r.sys = s->d_sys;
     r.n_sys = s->n_sys;
@@ -1114,6 +1147,9 @@ FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f,
     fl.eslot = eslot_buf(s, buf) + (long long)s->e_fin * A_N;
     fl.row_stage = s->d_row_stage;
     fl.stage = s->d_stage;
+    fl.row_prev = s->d_row_prev;
+    fl.row_next = s->d_row_next;
+    fl.row_ksp = s->d_row_ksp;
     return fl;
 }
 
@@ -1139,16 +1175,20 @@ StageLaunch stage_args(mixpi_system *s, const double *q, const double *p, const 
 // alternate between the two energy-slot buffers so that the reduction of
 // step k-1 never meets the writers of step k.
 void enqueue_step(mixpi_system *s, int k, double *q, double *p, double *f, double *elog_prev,
-                  hipStream_t st, bool count = true)
+                  hipStream_t st, bool count = true, bool vv = false)
 {
     const int buf = k & 1;
-    RpLaunch r = rp_args(s, OP_STEP, q, q, p, f, buf);
+    const int list = vv ? LIST_VV : LIST_STEP;
+    // velocity Verlet: kick + drift on whole columns (transform items), the
+    // spring force of the new positions and the spring energy in the epilogue
+    RpLaunch r = rp_args(s, vv ? OP_VV : OP_STEP, q, q, p, f, buf);
     FinishLaunch fl = finish_args(s, q, p, f, buf);
+    fl.vv = vv ? 1 : 0;
     if (k > 0) {
         r.with_reduce = 1;
-        r.reduce = reduce_a_args(s, buf ^ 1, true);
+        r.reduce = reduce_a_args(s, buf ^ 1, list);
         fl.with_reduce = 1;
-        fl.reduce = reduce_b_args(s, true);
+        fl.reduce = reduce_b_args(s, list);
         fl.reduce.elog = elog_prev;
         if (!count) {
             fl.reduce.npairs = nullptr;
@@ -1177,8 +1217,9 @@ void enqueue_lang(mixpi_system *s, double *q, double *p, double *f, const double
 // noise ([nsteps][2][rows][3]) every step is O B A B O: the closing
 // Langevin half step of step k and the opening one of step k+1 share one
 // launch.
+enum { MODE_NVE = 0, MODE_NVT = 1, MODE_VV = 2 };
 int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, double *elog,
-               GraphEntry **out, const double *noise = nullptr)
+               GraphEntry **out, const double *noise = nullptr, int mode = MODE_NVE)
 {
     *out = nullptr;
     if (int rc = check_sys(sys)) return rc;
@@ -1191,7 +1232,7 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
     HIP_TRY(hipSetDevice(sys->device));
     for (auto &g : sys->graphs)
         if (g.q == q && g.p == p && g.f == f && g.elog == elog && g.nsteps == nsteps &&
-            g.noise == noise) {
+            g.noise == noise && g.mode == mode) {
             *out = &g;
             return MIXPI_OK;
         }
@@ -1200,23 +1241,25 @@ int step_graph(mixpi_system *sys, int nsteps, double *q, double *p, double *f, d
         (void)hipGraphDestroy(sys->graphs.front().graph);
         sys->graphs.erase(sys->graphs.begin());
     }
-    GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr, noise};
+    GraphEntry g{q, p, f, elog, nsteps, nullptr, nullptr, noise, mode};
     auto row = [&](int k) { return elog ? elog + (size_t)k * sys->n_sys * MIXPI_NE : nullptr; };
     const size_t slice = (size_t)3 * sys->rows;    // one [rows][3] noise slice
     auto nz = [&](int k, int half) { return noise + (2 * (size_t)k + half) * slice; };
     HIP_TRY(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeRelaxed));
+    const bool vv = mode == MODE_VV;
     if (noise) enqueue_lang(sys, q, p, f, nz(0, 0), nullptr, sys->cap_stream);
-    else launch_stage(stage_args(sys, q, p, f), sys->cap_stream);
+    else if (!vv) launch_stage(stage_args(sys, q, p, f), sys->cap_stream);
     for (int k = 0; k < nsteps; ++k) {
-        enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream);
+        enqueue_step(sys, k, q, p, f, k > 0 ? row(k - 1) : nullptr, sys->cap_stream, true, vv);
         if (noise)
             enqueue_lang(sys, q, p, f, nz(k, 1), k + 1 < nsteps ? nz(k + 1, 0) : nullptr,
                          sys->cap_stream);
     }
     {
-        ReduceB rb = reduce_b_args(sys, true);
+        const int list = vv ? LIST_VV : LIST_STEP;
+        ReduceB rb = reduce_b_args(sys, list);
         rb.elog = row(nsteps - 1);
-        launch_reduce(reduce_a_args(sys, (nsteps - 1) & 1, true), rb, sys->cap_stream);
+        launch_reduce(reduce_a_args(sys, (nsteps - 1) & 1, list), rb, sys->cap_stream);
     }
     HIP_TRY(hipStreamEndCapture(sys->cap_stream, &g.graph));
     hipError_t e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
@@ -1283,9 +1326,9 @@ int mixpi_forces(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     enqueue_forces(sys, q, theta, f, false, st);
-    ReduceB rb = reduce_b_args(sys, false);
+    ReduceB rb = reduce_b_args(sys, LIST_FORCE);
     rb.e_out = e_out;
-    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
+    launch_reduce(reduce_a_args(sys, 0, LIST_FORCE), rb, st);
     return last_launch_error();
 }
 
@@ -1297,9 +1340,9 @@ int mixpi_energy(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, false, st);
-    ReduceB rb = reduce_b_args(sys, false);
+    ReduceB rb = reduce_b_args(sys, LIST_FORCE);
     rb.e_out = e_out;
-    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
+    launch_reduce(reduce_a_args(sys, 0, LIST_FORCE), rb, st);
     return last_launch_error();
 }
 
@@ -1316,10 +1359,10 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
         launch_gather(gather_args(sys), sys->rows, dq, st);
         launch_scale_rows(sys->rows, sys->d_row_sys, grad_e, dq, st);
     }
-    ReduceB rb = reduce_b_args(sys, false);
+    ReduceB rb = reduce_b_args(sys, LIST_FORCE);
     rb.dtheta = dtheta;
     rb.grad_e = grad_e;
-    launch_reduce(reduce_a_args(sys, 0, false), rb, st);
+    launch_reduce(reduce_a_args(sys, 0, LIST_FORCE), rb, st);
     return last_launch_error();
 }
 
@@ -1392,7 +1435,15 @@ int mixpi_step_nvt(mixpi_system *sys, int32_t nsteps, double *q, double *p, doub
 {
     if (!noise) return fail(MIXPI_E_INVALID, "noise must be non-null");
     GraphEntry *ge = nullptr;
-    if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge, noise)) return rc;
+    if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge, noise, MODE_NVT)) return rc;
+    return run_graph(sys, ge, stream);
+}
+
+int mixpi_step_vv(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
+                  double *elog, void *stream)
+{
+    GraphEntry *ge = nullptr;
+    if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge, nullptr, MODE_VV)) return rc;
     return run_graph(sys, ge, stream);
 }
 
@@ -1452,10 +1503,10 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const do
             const int buf = (r + 1) & 1;
             RpLaunch ra = rp_args(sys, OP_STEP, sq, sq, sp, sf, buf);
             ra.with_reduce = 1;
-            ra.reduce = reduce_a_args(sys, buf ^ 1, true);
+            ra.reduce = reduce_a_args(sys, buf ^ 1, LIST_STEP);
             FinishLaunch fl = finish_args(sys, sq, sp, sf, buf);
             fl.with_reduce = 1;
-            fl.reduce = reduce_b_args(sys, true);
+            fl.reduce = reduce_b_args(sys, LIST_STEP);
             fl.reduce.elog = selog;
             fl.reduce.npairs = nullptr;
             fl.reduce.nonfinite = nullptr;

@@ -50,7 +50,9 @@ void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t s
 // Second half-kick and per-step energies.  One wave per bead row (a
 // workgroup covers up to 4 rows of one system): F gathered from its partial
 // slots and stored, p += dt/2 F, then the kinetic energy p^2/(2 m_f) and the
-// centroid-virial term (q - qbar) . F summed into the workgroup's slot.
+// centroid-virial term (q - qbar) . F summed into the workgroup's slot.  In
+// velocity-Verlet mode the kick also carries the ring's spring force at the
+// new positions, and the spring energy is summed here.
 __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
 {
     __shared__ double red[4];
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
     }
     const BlockRange br = a.blocks[blockIdx.x];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double ke = 0.0, vir = 0.0;
+    double ke = 0.0, vir = 0.0, esp = 0.0;
     if (w < br.count) {
         const long long row = (long long)br.begin + w;
         // the row's own state, loaded before the gather so both are in flight
@@ -70,11 +72,21 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
         const double p0 = a.p[x], q0 = a.q[x], c0 = a.cent[x];
         const double hk = a.row_hk[row], fm = a.row_fm[row];
         const int st = a.row_stage[row];
+        double fsp = 0.0;
+        if (a.vv) {
+            // spring force of the ring at the new positions, and the energy
+            // of the step (row, next): k/2 (q - q_next)^2
+            const double k = a.row_ksp[row];
+            const double qp = a.q[3 * a.row_prev[row] + (x - 3 * row)];
+            const double qn = a.q[3 * a.row_next[row] + (x - 3 * row)];
+            fsp = -k * (2.0 * q0 - qp - qn);
+            if (lane < 3) esp = 0.5 * k * (q0 - qn) * (q0 - qn);
+        }
         const Vec3 fv = gather_row(a.gather, row);
         if (lane < 3) {
             const double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
             a.f[x] = fx;
-            const double pv = p0 + hk * fx;
+            const double pv = p0 + hk * (fx + fsp);
             a.p[x] = pv;
             if (st >= 0) {
                 a.stage[6LL * st + lane] = q0;
@@ -86,11 +98,13 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
     }
     ke = bsum(ke, red);
     vir = bsum(vir, red);
+    if (a.vv) esp = bsum(esp, red);
     if (threadIdx.x == 0) {
         double *e = a.eslot + (long long)blockIdx.x * A_N;
         for (int k = 0; k < A_N; ++k) e[k] = 0.0;
         e[A_KIN] = ke;
         e[A_VIR] = vir;
+        e[A_SPRING] = esp;
     }
 }
 

@@ -86,7 +86,7 @@ struct BlockRange {
 enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
 constexpr int kCircOut = 16;       // bead outputs per circulant item
 constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
-enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2, OP_LANG = 3 };
+enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2, OP_LANG = 3, OP_VV = 4 };
 struct RpItem {
     int kind, sys, N, logN;
     int n;                // particles in the group
@@ -223,6 +223,11 @@ struct FinishLaunch {
     double *stage;             // written for those rows: q, p + dt/2 F (next step's input)
     int with_reduce;           // reduce.n_wg extra workgroups run stage B
     ReduceB reduce;
+    // velocity Verlet with spring forces: the kick adds F_sp of the new q
+    // (neighbour bead rows), and the spring energy of (row, next) is summed
+    int vv;
+    const long long *row_prev, *row_next;  // [rows] neighbour bead rows of the ring
+    const double *row_ksp;                 // [rows] spring constant, kcal/mol/A^2
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);
 

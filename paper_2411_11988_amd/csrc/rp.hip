@@ -580,6 +580,64 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Velocity Verlet with the springs as forces (the paper's alternative to the
+// exact normal-mode propagation), first half: for every bead of the item's
+// whole columns, p += dt/2 (F + F_sp(q)) with F_sp = -k (2 q_j - q_{j-1} -
+// q_{j+1}), then q += dt p / m_f; the centroid of the new ring is stored
+// for the virial estimator.  Spring energies are summed in the epilogue.
+__device__ void rp_vv(const RpLaunch &a, const RpItem &it, double *smem, double *red)
+{
+    const int N = it.N, n = it.n;
+    const int nc = it.ncols;
+    const int tid = threadIdx.x;
+    double *sq = smem;                  // [N][nc] old q
+    double *sn = smem + N * nc;         // [N][nc] new q
+    const double hk = a.sys[it.sys].hkick;
+    auto gaddr = [&](int j, int cl) { return (it.row + (long long)j * n) * 3 + it.c0 + cl; };
+    for (int e = tid; e < N * nc; e += 256) sq[e] = a.in_q[gaddr(e / nc, e % nc)];
+    __syncthreads();
+    const double s1 = sin(kPi / N), lam1 = 4.0 * s1 * s1;
+    for (int e = tid; e < N * nc; e += 256) {
+        const int j = e / nc, cl = e % nc;
+        const int i = (it.c0 + cl) / 3;
+        // k = 2 (k lambda_1 / 2) / lambda_1 from mode 1's spring entry; dt/m_f from mode 0
+        const double k = N > 1 ? 2.0 * a.prop[5 * (it.row + (long long)n + i) + 4] / lam1 : 0.0;
+        const double dtm = a.prop[5 * (it.row + i) + 1];
+        const double qj = sq[e];
+        const double qp = sq[((j + N - 1) % N) * nc + cl], qn = sq[((j + 1) % N) * nc + cl];
+        const double fsp = -k * (2.0 * qj - qp - qn);
+        const long long g = gaddr(j, cl);
+        const double pn = a.p[g] + hk * (a.f[g] + fsp);
+        const double qnew = qj + dtm * pn;
+        a.p[g] = pn;
+        a.out_q[g] = qnew;
+        sn[e] = qnew;
+    }
+    __syncthreads();
+    // centroids: one column per workgroup (many beads) by a block sum, else
+    // a thread per column
+    if (nc == 1) {
+        double v = 0.0;
+        for (int j = tid; j < N; j += 256) v += sn[j];
+        v = bsum256(v, red);
+        __shared__ double s_c;
+        if (tid == 0) s_c = v / N;
+        __syncthreads();
+        for (int j = tid; j < N; j += 256) a.cent[gaddr(j, 0)] = s_c;
+    } else {
+        double *cs = sq;                // reuse: column centroids
+        __syncthreads();
+        if (tid < nc) {
+            double v = 0.0;
+            for (int j = 0; j < N; ++j) v += sn[j * nc + tid];
+            cs[tid] = v / N;
+        }
+        __syncthreads();
+        for (int e = tid; e < N * nc; e += 256) a.cent[gaddr(e / nc, e % nc)] = cs[e % nc];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
 {
     extern __shared__ __align__(16) double smem[];
@@ -594,6 +652,10 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
     if (a.op == OP_LANG) {
         if (it.kind == RP_DENSE) rp_lang_dense(a, it, smem);
         else rp_lang_fft(a, it, reinterpret_cast<double2 *>(smem));
+        return;
+    }
+    if (a.op == OP_VV) {
+        rp_vv(a, it, smem, red);
         return;
     }
     if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);

@@ -98,6 +98,7 @@ def load():
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
         "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
         "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
+        "mixpi_step_vv": ([P, I32, P, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +237,11 @@ def mixpi_step_nvt(h, nsteps: int, q, p, f, noise, elog=None, stream=None):
                                  _ptr(elog), _stream(stream)))
 
 
+def mixpi_step_vv(h, nsteps: int, q, p, f, elog=None, stream=None):
+    _check(load().mixpi_step_vv(h, int(nsteps), _ptr(q), _ptr(p), _ptr(f), _ptr(elog),
+                                _stream(stream)))
+
+
 def mixpi_kernel_time(h, reps: int, q, p, f, stream=None) -> dict:
     """Mean in-step durations (us) of the force, free ring-polymer and
     epilogue launches over `reps` eager steps on library copies of q, p, f."""
@@ -339,6 +345,10 @@ class System:
 
     def step_nvt(self, nsteps: int, q, p, f, noise, elog=None, stream=None):
         mixpi_step_nvt(self.h, nsteps, q, p, f, noise, elog, stream)
+        return elog
+
+    def step_vv(self, nsteps: int, q, p, f, elog=None, stream=None):
+        mixpi_step_vv(self.h, nsteps, q, p, f, elog, stream)
         return elog
 
     def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
