@@ -31,6 +31,8 @@
  *     and 2 omega_k on mode k; noise is an input.  [orc_pile, orc_step_nvt]
  *   - The alternative velocity-Verlet integration with the springs as
  *     forces (Sec. "Evaluation").  [orc_step_vv]
+ *   - The radial distribution functions the paper reports (Sec. "Examples
+ *     and Discussion"), as bead-averaged slice-pair histograms.  [orc_rdf]
  *
  * Force field (the paper names q-SPC/Fw water, a cation-water LJ and an
  * electron pseudopotential; the functional forms below are the readings this
@@ -329,6 +331,38 @@ void orc_forces_o2(const orc_sys *S, const double *q, double *F, double *eout)
     }
     finish_potential(S, e);
     for (int k = 0; k <= E_ANGLE; ++k) eout[k] = e[k];
+}
+
+/* Path-integral radial distribution: every non-excluded particle pair of
+ * V_mix (different molecules, not two electrons) on its N_max slices with
+ * weight 1/N_max (the bead average of Eq. (mts-hamiltonian) applied to a
+ * pair count), binned by nearest-image distance, r < rmax, nbins bins of
+ * rmax/nbins.  hist[a][b][bin] with a <= b the species (LJ type; the null
+ * type nt for particles without one), nspec species per axis; added to. */
+void orc_rdf(const orc_sys *S, const double *q, double rmax, int nbins, int nspec, double *hist)
+{
+    double dr = rmax / nbins;
+    for (int i = 0; i < S->n; ++i)
+        for (int j = i + 1; j < S->n; ++j) {
+            if (S->mol[i] == S->mol[j]) continue;
+            if (S->ele[i] && S->ele[j]) continue;
+            int ti = S->ljt[i] < 0 ? S->nt : S->ljt[i];
+            int tj = S->ljt[j] < 0 ? S->nt : S->ljt[j];
+            int a = ti < tj ? ti : tj, b = ti < tj ? tj : ti;
+            int ni = S->nb[i], nj = S->nb[j];
+            int nmax = ni > nj ? ni : nj;
+            for (int s = 0; s < nmax; ++s) {
+                long bi = S->off[i] + orc_slice_bead(s, ni, nmax);
+                long bj = S->off[j] + orc_slice_bead(s, nj, nmax);
+                double d[3];
+                min_image(S, q + 3 * bi, q + 3 * bj, d);
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (r >= rmax) continue;
+                int bin = (int)(r / dr);
+                if (bin >= nbins) bin = nbins - 1;
+                hist[((long)a * nspec + b) * nbins + bin] += 1.0 / nmax;
+            }
+        }
 }
 
 /* Counts the slice-pairs of orc_forces_o2 with at least one term inside its

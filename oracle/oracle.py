@@ -91,6 +91,7 @@ def lib():
         _lib.orc_pile.argtypes = [P, P, P, C.c_double, C.c_double]
         _lib.orc_step_nvt.argtypes = [P, C.c_int, P, P, P, P, C.c_double, P]
         _lib.orc_step_vv.argtypes = [P, C.c_int, P, P, P, P]
+        _lib.orc_rdf.argtypes = [P, P, C.c_double, C.c_int, C.c_int, P]
         _lib.orc_beta.argtypes = [P]
         _lib.orc_beta.restype = C.c_double
         _lib.orc_constants.argtypes = [P]
@@ -245,6 +246,13 @@ class OracleSystem:
         elog = np.zeros((nsteps, E_N))
         lib().orc_step_vv(self.ptr, int(nsteps), _p(q), _p(p), _p(F), _p(elog))
         return q, p, F, elog
+
+    def rdf(self, q, rmax: float, nbins: int, nspec: int = 9):
+        """Bead-averaged slice-pair histogram [nspec][nspec][nbins] (a <= b)."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        h = np.zeros((nspec, nspec, nbins))
+        lib().orc_rdf(self.ptr, _p(q), float(rmax), int(nbins), int(nspec), _p(h))
+        return h
 
     def pile_gamma(self, i: int, k: int, tau0: float) -> float:
         return lib().orc_pile_gamma(self.ptr, int(i), int(k), float(tau0))

@@ -615,3 +615,42 @@ def test_vv_conserves_energy_as_dt_squared():
         _, _, _, el = oracle.OracleSystem(s).step_vv(s.q, s.p, n)
         h.append(el[:, oracle.E_NAMES.index("ham")].std())
     assert 3.0 < h[0] / h[1] < 5.5, h
+
+
+# --------------------------------------------------- radial distribution
+
+def test_rdf_shell_counts_of_a_simple_cubic_lattice():
+    """Particles on a periodic simple cubic lattice of 4^3 sites (M sites,
+    spacing a, box 4a): by nearest image the unordered pair counts at a,
+    sqrt(2) a, sqrt(3) a and 2 a are 3M, 6M, 4M and 3M/2 (the site two steps
+    along an axis is the same one both ways); rings collapsed on their sites
+    count each pair once (weights 1/N_max over N_max slices)."""
+    n, a = 4, 2.5
+    M = n ** 3
+    sites = np.array([(x, y, z) for x in range(n) for y in range(n) for z in range(n)]) * a
+    for nb in (1, 4):
+        q = np.repeat(sites, nb, axis=0)
+        s = custom([nb] * M, q, box=n * a, rc=4.0, lj_type=[0] * M)
+        h = oracle.OracleSystem(s).rdf(q, 5.1, 510)[0, 0]
+        dr = 5.1 / 510
+        def count(r):
+            return h[int(r / dr)]
+        assert count(a) == 3 * M
+        assert count(math.sqrt(2) * a) == 6 * M
+        assert count(math.sqrt(3) * a) == 4 * M
+        assert count(2 * a) == 3 * M // 2
+        assert h.sum() == (3 + 6 + 4) * M + 3 * M // 2
+
+
+def test_rdf_pair_set_and_weights():
+    """A 4-bead particle and a 2-bead particle: 4 slice-pairs of weight 1/4;
+    equal molecule ids and two electrons contribute nothing."""
+    q = np.array([[0, 0, 0], [0, 0, 0.1], [0, 0, 0.2], [0, 0, 0.3],
+                  [1.0, 0, 0], [1.5, 0, 0]], dtype=float)
+    s = custom([4, 2], q, lj_type=[0, 1])
+    h = oracle.OracleSystem(s).rdf(q, 3.0, 300)
+    assert h[0, 1].sum() == pytest.approx(1.0, abs=0) and h[1, 0].sum() == 0
+    s_same = custom([4, 2], q, lj_type=[0, 1], mol=[5, 5])
+    assert oracle.OracleSystem(s_same).rdf(q, 3.0, 300).sum() == 0
+    s_ele = custom([4, 2], q, lj_type=[0, 1], ele=[1, 1])
+    assert oracle.OracleSystem(s_ele).rdf(q, 3.0, 300).sum() == 0
