@@ -249,6 +249,26 @@ int mixpi_step_nvt(mixpi_system *sys, int32_t nsteps, double *q, double *p, doub
 int mixpi_step_vv(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
                   double *elog, void *stream);
 
+/* Path-integral radial distribution functions (the g(r) of Sec. "Examples
+ * and Discussion"): the bead average of the pair count, taken like V_mix of
+ * Eq. (mts-hamiltonian) -- every unordered, non-excluded particle pair
+ * (different molecule ids, not two electrons) on its N_max slices, particle
+ * p at bead floor(s N_p / N_max), weight 1/N_max -- binned by
+ * nearest-image distance r < r_max into nbins bins of width r_max / nbins.
+ * q: device [rows][3] in the handle's layout.  hist: device FP64
+ * [n_systems][nspec][nspec][nbins] from hipMalloc (coarse-grained memory),
+ * ADDED to, entry [s][a][b][k] with a <= b the species of the two particles
+ * (their LJ type; the null type n_lj_types for particles without one);
+ * entries with a > b are left alone.  nspec >= n_lj_types + 1 of every
+ * system.  The sums are exact (dyadic addends), so the result is
+ * independent of scheduling.  g_ab(r) follows by dividing by the number of
+ * frames, the ideal-gas pair count of the bin and the number of pairs.
+ * Asynchronous on stream.  Errors: MIXPI_E_INVALID (null pointer, r_max not
+ * positive and finite, nbins < 1, nspec too small), MIXPI_E_UNSUPPORTED
+ * (more than 14336 bins times species pairs (a <= b)). */
+int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, int32_t nspec,
+              double *hist, void *stream);
+
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems
  * (from the work lists; no device work). */

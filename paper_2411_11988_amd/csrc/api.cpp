@@ -93,6 +93,9 @@ struct mixpi_system {
     PairBlock *d_blocks = nullptr;
     PairItem *d_items = nullptr;
     int n_items = 0, n_items_fast = 0;
+    // radial distribution: system-pure runs of pair items, largest bead count
+    BlockRange *d_rdf_ranges = nullptr;
+    int n_rdf_ranges = 0, top_beads = 1, max_nt1 = 1;
     // bonded sweep: terms and system-pure blocks of 256 (fast blocks first)
     BondedTerm *d_bterms = nullptr;
     BlockRange *d_bblocks = nullptr;
@@ -165,7 +168,8 @@ void release(mixpi_system *s)
                     s->d_prop, s->d_row_ptr,
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
-                    s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch};
+                    s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch,
+                    s->d_rdf_ranges};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -902,6 +906,21 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int b = 0; b < S->n_bblocks; ++b) eslot_sys[S->e_bonded + b] = bblocks[b].sys;
     for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
+    // radial distribution: runs of at most K items of one system, K chosen
+    // for about 2048 workgroups and so that no LDS count can pass 2^32
+    std::vector<BlockRange> rdf_ranges;
+    {
+        for (const SysDev &sd : B.sys) S->max_nt1 = std::max(S->max_nt1, sd.nt1);
+        for (const PairBlock &pb : B.blocks)
+            S->top_beads = std::max(S->top_beads, pb.nbeads_b << pb.shift);
+        const long long per_item = 64LL * S->pair_tj * S->top_beads;
+        const long long cap = std::max(1LL, std::min(64LL, 0xffffffffLL / per_item));
+        const long long want = (S->n_items + 2047) / 2048;
+        const int K = (int)std::max(1LL, std::min(cap, want));
+        rdf_ranges = system_blocks(std::vector<int>(eslot_sys.begin(), eslot_sys.begin() + S->n_items),
+                                   0, S->n_items, K);
+        S->n_rdf_ranges = (int)rdf_ranges.size();
+    }
     // per-system slot lists (stable order) for the reducer
     std::vector<int> red_f, red_a;
     S->nch_f = reducer_plan(eslot_sys, {{0, S->e_rp}}, n_sys, red_f, S->red_f_off);
@@ -925,6 +944,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_row_hk, B.row_hk));
     T(upload(&S->d_blocks, B.blocks));
     T(upload(&S->d_items, items));
+    T(upload(&S->d_rdf_ranges, rdf_ranges));
     T(upload(&S->d_bterms, terms));
     T(upload(&S->d_bblocks, bblocks));
     T(upload(&S->d_bond_k, B.bond_k));
@@ -1542,6 +1562,42 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const do
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     return last_launch_error();
+}
+
+int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, int32_t nspec,
+              double *hist, void *stream)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!q || !hist) return fail(MIXPI_E_INVALID, "q or hist is null");
+    if (!(r_max > 0.0) || !std::isfinite(r_max))
+        return fail(MIXPI_E_INVALID, "r_max must be positive and finite (got %g)", r_max);
+    if (nbins < 1) return fail(MIXPI_E_INVALID, "nbins must be >= 1 (got %d)", nbins);
+    if (nspec < sys->max_nt1)
+        return fail(MIXPI_E_INVALID, "nspec = %d < %d species (LJ types + the null type)", nspec,
+                    sys->max_nt1);
+    const long long lds = (long long)sys->max_nt1 * (sys->max_nt1 + 1) / 2 * nbins * 4;
+    if (lds > kRdfLdsBytes)
+        return fail(MIXPI_E_UNSUPPORTED, "%d bins x %d species pairs exceed the %d-byte histogram",
+                    nbins, sys->max_nt1 * (sys->max_nt1 + 1) / 2, kRdfLdsBytes);
+    HIP_TRY(hipSetDevice(sys->device));
+    RdfLaunch a{};
+    a.items = sys->d_items;
+    a.ranges = sys->d_rdf_ranges;
+    a.blocks = sys->d_blocks;
+    a.sys = sys->d_sys;
+    a.ljt = sys->d_ljt;
+    a.mol = sys->d_mol;
+    a.q = q;
+    a.hist = hist;
+    a.rmax = r_max;
+    a.unit = 1.0 / sys->top_beads;
+    a.nbins = nbins;
+    a.nspec = nspec;
+    a.tj = sys->pair_tj;
+    a.top = sys->top_beads;
+    launch_rdf(a, sys->n_rdf_ranges, (int)lds, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return MIXPI_OK;
 }
 
 int mixpi_pair_candidates(const mixpi_system *sys, int64_t *candidates)

@@ -242,6 +242,22 @@ void launch_stage(const StageLaunch &a, hipStream_t st);
 
 void launch_reduce(const ReduceA &a, const ReduceB &b, hipStream_t st);
 
+// Radial-distribution histogram over the pair tiles (one workgroup per
+// system-pure range of tiles; dynamic LDS = (nt1 (nt1 + 1) / 2) nbins words).
+struct RdfLaunch {
+    const PairItem *items;
+    const BlockRange *ranges;
+    const PairBlock *blocks;
+    const SysDev *sys;
+    const int *ljt, *mol;
+    const double *q;
+    double *hist;            // [systems][nspec][nspec][nbins], added to
+    double rmax, unit;       // unit = 1 / top
+    int nbins, nspec, tj, top;
+};
+constexpr int kRdfLdsBytes = 56 * 1024;
+void launch_rdf(const RdfLaunch &a, int n_ranges, int lds_bytes, hipStream_t st);
+
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);
 void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);

@@ -96,6 +96,7 @@ def load():
         "mixpi_pair_evals": ([P, P, I32, P], C.c_int),
         "mixpi_step_prepare": ([P, I32, P, P, P, P], C.c_int),
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
+        "mixpi_rdf": ([P, P, C.c_double, I32, I32, P, P], C.c_int),
         "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
         "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
         "mixpi_step_vv": ([P, I32, P, P, P, P, P], C.c_int),
@@ -251,6 +252,11 @@ def mixpi_kernel_time(h, reps: int, q, p, f, stream=None) -> dict:
     return {"force": v[0], "free_rp": v[1], "finish": v[2]}
 
 
+def mixpi_rdf(h, q, r_max: float, nbins: int, nspec: int, hist, stream=None):
+    _check(load().mixpi_rdf(h, _ptr(q), float(r_max), int(nbins), int(nspec), _ptr(hist),
+                            _stream(stream)))
+
+
 # ---- convenience object ------------------------------------------------------
 
 class System:
@@ -353,6 +359,16 @@ class System:
 
     def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
         return mixpi_kernel_time(self.h, reps, q, p, f, stream)
+
+    def rdf(self, q, r_max: float, nbins: int, hist=None, nspec: int = 9, stream=None):
+        """Adds the bead-averaged slice-pair histogram of q to hist
+        ([systems][nspec][nspec][nbins] FP64 on the device; zeros if None)."""
+        if hist is None:
+            import torch
+            hist = torch.zeros((self.n_systems, nspec, nspec, nbins), dtype=torch.float64,
+                               device=q.device)
+        mixpi_rdf(self.h, q, r_max, nbins, nspec, hist, stream)
+        return hist
 
 
 def energy_function():
