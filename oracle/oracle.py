@@ -254,6 +254,33 @@ class OracleSystem:
         lib().orc_rdf(self.ptr, _p(q), float(rmax), int(nbins), int(nspec), _p(h))
         return h
 
+    def centroid_velocity(self, p):
+        """Velocity of every ring-polymer centroid, the bead average
+        (1/N_i) sum_j p_ij / m_f,i of the bead velocities (the centroid of the
+        ring polymer of Eq. (mts-hamiltonian-b)); p is the bead table."""
+        p = np.asarray(p, dtype=np.float64)
+        v = np.empty((self.n, 3))
+        for i in range(self.n):
+            v[i] = p[self.off[i]:self.off[i + 1]].sum(axis=0) / (self.nb[i] * self.fm[i])
+        return v
+
+    def vacf(self, ps, L: int, nspec: int = 9):
+        """RPMD centroid velocity correlation sums from the bead momenta ps[t]
+        of an NVE ring-polymer trajectory sampled at t = 0 .. T-1:
+        acc[a][tau] = sum over t = tau .. T-1 and particles i of species a
+        (LJ type; the null type nt for none) of v_i(t - tau) . v_i(t), for
+        tau < L.  Dividing by (T - tau), the particle count and 3 gives the
+        Kubo-transformed correlation function of one velocity component."""
+        vs = [self.centroid_velocity(p) for p in ps]
+        spec = np.where(self.ljt < 0, self.nt, self.ljt)
+        acc = np.zeros((nspec, L))
+        for t in range(len(vs)):
+            for tau in range(min(t + 1, L)):
+                d = np.einsum("ij,ij->i", vs[t - tau], vs[t])
+                for i in range(self.n):
+                    acc[spec[i], tau] += d[i]
+        return acc
+
     def pile_gamma(self, i: int, k: int, tau0: float) -> float:
         return lib().orc_pile_gamma(self.ptr, int(i), int(k), float(tau0))
 

@@ -654,3 +654,55 @@ def test_rdf_pair_set_and_weights():
     assert oracle.OracleSystem(s_same).rdf(q, 3.0, 300).sum() == 0
     s_ele = custom([4, 2], q, lj_type=[0, 1], ele=[1, 1])
     assert oracle.OracleSystem(s_ele).rdf(q, 3.0, 300).sum() == 0
+
+
+# --------------------------------------------------- velocity correlation
+
+def test_centroid_velocity_of_a_ring():
+    """Bead momenta m_f (v + u_j) with sum_j u_j = 0 have centroid velocity v."""
+    rng = np.random.default_rng(0)
+    nb = [8, 1, 4]
+    q = rng.normal(size=(13, 3))
+    s = custom(nb, q, mass=[4.0, 2.0, 16.0])
+    o = oracle.OracleSystem(s)
+    v = rng.normal(size=(3, 3))
+    p = np.zeros((13, 3))
+    for i in range(3):
+        u = rng.normal(size=(nb[i], 3))
+        u -= u.mean(axis=0)
+        p[o.off[i]:o.off[i + 1]] = o.fm[i] * (v[i] + u)
+    assert np.allclose(o.centroid_velocity(p), v, rtol=1e-14, atol=1e-15)
+
+
+def test_vacf_of_constant_and_oscillating_velocities():
+    """Constant centroid velocities give (T - tau) sum_i |v_i|^2; velocities
+    v0 cos(w t) give |v0|^2 sum_{t=tau}^{T-1} cos(w (t - tau)) cos(w t)
+    = |v0|^2 / 2 [(T - tau) cos(w tau) + sin(w (T - tau)) cos(w (T - 1)) / sin(w)],
+    the product-to-sum identity with the closed form of a cosine sum."""
+    rng = np.random.default_rng(1)
+    nb = [4, 2]
+    s = custom(nb, rng.normal(size=(6, 3)), lj_type=[0, 2], mass=[3.0, 5.0])
+    o = oracle.OracleSystem(s)
+    T, L = 12, 5
+    v = rng.normal(size=(2, 3))
+
+    def moments(vel):
+        p = np.zeros((6, 3))
+        for i in range(2):
+            p[o.off[i]:o.off[i + 1]] = o.fm[i] * vel[i]
+        return p
+
+    acc = o.vacf([moments(v)] * T, L)
+    for tau in range(L):
+        assert acc[0, tau] == pytest.approx((T - tau) * v[0] @ v[0], rel=1e-13)
+        assert acc[2, tau] == pytest.approx((T - tau) * v[1] @ v[1], rel=1e-13)
+    assert np.count_nonzero(acc) == 2 * L
+    w = 0.7
+    acc = o.vacf([moments(v * math.cos(w * t)) for t in range(T)], L)
+    for tau in range(L):
+        want = 0.5 * ((T - tau) * math.cos(w * tau)
+                      + math.sin(w * (T - tau)) * math.cos(w * (T - 1)) / math.sin(w))
+        assert acc[0, tau] == pytest.approx(want * (v[0] @ v[0]), rel=1e-12, abs=1e-12)
+    # a window longer than the trajectory: lags past T - 1 stay zero
+    acc = o.vacf([moments(v)] * 3, 6)
+    assert np.all(acc[:, 3:] == 0) and acc[0, 2] == pytest.approx(v[0] @ v[0], rel=1e-13)
