@@ -269,6 +269,26 @@ int mixpi_step_vv(mixpi_system *sys, int32_t nsteps, double *q, double *p, doubl
 int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, int32_t nspec,
               double *hist, void *stream);
 
+/* One sample of the ring-polymer molecular dynamics (RPMD) centroid
+ * velocity correlation function (real-time correlation functions from NVE
+ * ring-polymer trajectories, Sec. "Implementation"; for the velocity, a
+ * linear operator, the Kubo-transformed correlation is estimated from the
+ * centroids).  p: device [rows][3] bead momenta at sample t.  The centroid
+ * velocity v_i = (1/N_i) sum_j p_ij / m_f,i of every particle (handle
+ * order: systems, then particles) is written to slot t mod L of ring
+ * (device FP64 [L][n_particles][3], caller-owned, kept between calls);
+ * then for every lag tau < min(t + 1, L),
+ *   acc[s][a][tau] += sum over particles i of system s with species a of
+ *                     v_i(t - tau) . v_i(t),
+ * species as in mixpi_rdf; acc is device FP64 [n_systems][nspec][L].
+ * Calls must come with t = 0, 1, 2, ... on the same ring and L.  After T
+ * samples, acc[s][a][tau] / ((T - tau) n_a 3) is the correlation function
+ * of one velocity component at lag tau sample intervals.  Asynchronous on
+ * stream.  Errors: MIXPI_E_INVALID (null pointer, t < 0, L < 1 or L times
+ * the number of systems above 2^30, nspec too small). */
+int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, int32_t nspec,
+                      double *ring, double *acc, void *stream);
+
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems
  * (from the work lists; no device work). */

@@ -96,6 +96,9 @@ struct mixpi_system {
     // radial distribution: system-pure runs of pair items, largest bead count
     BlockRange *d_rdf_ranges = nullptr;
     int n_rdf_ranges = 0, top_beads = 1, max_nt1 = 1;
+    // centroid quantities: particles in handle order, first particle per system
+    PartDev *d_parts = nullptr;
+    int *d_sys_part = nullptr;
     // bonded sweep: terms and system-pure blocks of 256 (fast blocks first)
     BondedTerm *d_bterms = nullptr;
     BlockRange *d_bblocks = nullptr;
@@ -169,7 +172,7 @@ void release(mixpi_system *s)
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch,
-                    s->d_rdf_ranges};
+                    s->d_rdf_ranges, s->d_parts, s->d_sys_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -281,6 +284,8 @@ struct Build {
     std::vector<double2> tw;
     std::map<int, int> basis_off, tw_off;
     std::vector<long long> bead_index;
+    std::vector<PartDev> parts;
+    std::vector<int> sys_part;                 // first particle of each system
     std::vector<std::pair<long long, long long>> sys_rows;   // [begin, end) per system
     long long rows = 0;
     long long candidates = 0;
@@ -377,6 +382,18 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         i = j;
     }
     B.n_groups += (int)groups.size();
+    B.sys_part.push_back(p_base);
+    for (const Group &g : groups)
+        for (int i = 0; i < g.n; ++i) {
+            PartDev pd{};
+            pd.row0 = g.row + i;
+            pd.stride = g.n;
+            pd.nb = g.N;
+            pd.inv_nm = 1.0 / (g.N * d->fict_mass[g.p0 + i]);
+            pd.spec = d->lj_type[g.p0 + i] < 0 ? nt : d->lj_type[g.p0 + i];
+            pd.sys = s;
+            B.parts.push_back(pd);
+        }
 
     // layout: bead index and row -> particle
     std::vector<long long> part_first(n);
@@ -945,6 +962,12 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_blocks, B.blocks));
     T(upload(&S->d_items, items));
     T(upload(&S->d_rdf_ranges, rdf_ranges));
+    {
+        std::vector<int> sp = B.sys_part;
+        sp.push_back(B.n_part);
+        T(upload(&S->d_parts, B.parts));
+        T(upload(&S->d_sys_part, sp));
+    }
     T(upload(&S->d_bterms, terms));
     T(upload(&S->d_bblocks, bblocks));
     T(upload(&S->d_bond_k, B.bond_k));
@@ -1596,6 +1619,36 @@ int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, i
     a.tj = sys->pair_tj;
     a.top = sys->top_beads;
     launch_rdf(a, sys->n_rdf_ranges, (int)lds, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return MIXPI_OK;
+}
+
+int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, int32_t nspec,
+                      double *ring, double *acc, void *stream)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!p || !ring || !acc) return fail(MIXPI_E_INVALID, "p, ring or acc is null");
+    if (t < 0) return fail(MIXPI_E_INVALID, "t must be >= 0 (got %lld)", (long long)t);
+    if (L < 1 || (long long)L * sys->n_sys > (1LL << 30))
+        return fail(MIXPI_E_INVALID, "L must be in [1, 2^30 / systems] (got %d)", L);
+    if (nspec < sys->max_nt1)
+        return fail(MIXPI_E_INVALID, "nspec = %d < %d species (LJ types + the null type)", nspec,
+                    sys->max_nt1);
+    HIP_TRY(hipSetDevice(sys->device));
+    TcfLaunch a{};
+    a.parts = sys->d_parts;
+    a.sys_part = sys->d_sys_part;
+    a.sys = sys->d_sys;
+    a.ring = ring;
+    a.acc = acc;
+    a.t = t;
+    a.L = L;
+    a.slot = (int)(t % L);
+    a.n_lag = (int)std::min<int64_t>(t + 1, L);
+    a.n_part = sys->n_part;
+    a.n_sys = sys->n_sys;
+    a.nspec = nspec;
+    launch_tcf(a, p, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return MIXPI_OK;
 }

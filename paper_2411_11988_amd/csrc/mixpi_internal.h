@@ -258,6 +258,26 @@ struct RdfLaunch {
 constexpr int kRdfLdsBytes = 56 * 1024;
 void launch_rdf(const RdfLaunch &a, int n_ranges, int lds_bytes, hipStream_t st);
 
+// A particle for centroid quantities: bead j sits at row row0 + j * stride.
+struct PartDev {
+    long long row0;
+    int stride, nb;
+    double inv_nm;           // 1 / (N m_f)
+    int spec, sys;           // species (LJ type, null type nt), system
+};
+
+// One sample of the centroid velocity correlator.
+struct TcfLaunch {
+    const PartDev *parts;
+    const int *sys_part;     // [n_sys + 1] first particle of each system
+    const SysDev *sys;
+    double *ring;            // [L][n_part][3]
+    double *acc;             // [n_sys][nspec][L], added to
+    long long t;
+    int L, slot, n_lag, n_part, n_sys, nspec;
+};
+void launch_tcf(const TcfLaunch &a, const double *p, hipStream_t st);
+
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);
 void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);

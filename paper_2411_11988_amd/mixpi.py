@@ -97,6 +97,7 @@ def load():
         "mixpi_step_prepare": ([P, I32, P, P, P, P], C.c_int),
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
         "mixpi_rdf": ([P, P, C.c_double, I32, I32, P, P], C.c_int),
+        "mixpi_vacf_sample": ([P, P, C.c_int64, I32, I32, P, P, P], C.c_int),
         "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
         "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
         "mixpi_step_vv": ([P, I32, P, P, P, P, P], C.c_int),
@@ -257,6 +258,11 @@ def mixpi_rdf(h, q, r_max: float, nbins: int, nspec: int, hist, stream=None):
                             _stream(stream)))
 
 
+def mixpi_vacf_sample(h, p, t: int, L: int, nspec: int, ring, acc, stream=None):
+    _check(load().mixpi_vacf_sample(h, _ptr(p), int(t), int(L), int(nspec), _ptr(ring), _ptr(acc),
+                                    _stream(stream)))
+
+
 # ---- convenience object ------------------------------------------------------
 
 class System:
@@ -359,6 +365,12 @@ class System:
 
     def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
         return mixpi_kernel_time(self.h, reps, q, p, f, stream)
+
+    def vacf_sample(self, p, t: int, ring, acc, nspec: int = 9, stream=None):
+        """Adds sample t of the centroid velocity correlation sums to acc
+        ([systems][nspec][L]); ring ([L][particles][3]) keeps the history."""
+        mixpi_vacf_sample(self.h, p, t, ring.shape[0], nspec, ring, acc, stream)
+        return acc
 
     def rdf(self, q, r_max: float, nbins: int, hist=None, nspec: int = 9, stream=None):
         """Adds the bead-averaged slice-pair histogram of q to hist
