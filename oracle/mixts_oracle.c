@@ -33,6 +33,8 @@
  *     forces (Sec. "Evaluation").  [orc_step_vv]
  *   - The radial distribution functions the paper reports (Sec. "Examples
  *     and Discussion"), as bead-averaged slice-pair histograms.  [orc_rdf]
+ *   - Long-range electrostatics on the ring-polymer centroids (Sec.
+ *     "Theory"): the Ewald sum by its definition.  [orc_ewald]
  *
  * Force field (the paper names q-SPC/Fw water, a cation-water LJ and an
  * electron pseudopotential; the functional forms below are the readings this
@@ -331,6 +333,116 @@ void orc_forces_o2(const orc_sys *S, const double *q, double *F, double *eout)
     }
     finish_potential(S, e);
     for (int k = 0; k <= E_ANGLE; ++k) eout[k] = e[k];
+}
+
+/* Centroid of particle i: the mean of its bead positions. */
+static void centroid(const orc_sys *S, const double *q, int i, double c[3])
+{
+    c[0] = c[1] = c[2] = 0.0;
+    for (int j = 0; j < S->nb[i]; ++j)
+        for (int k = 0; k < 3; ++k) c[k] += q[3 * (S->off[i] + j) + k];
+    for (int k = 0; k < 3; ++k) c[k] /= S->nb[i];
+}
+
+/* Long-range electrostatics of the atoms in the centroid approximation
+ * (Sec. "Theory", the smooth-particle-mesh Ewald treatment of the example
+ * systems: the bead-bead electrostatic energies and forces are replaced by
+ * those between the ring-polymer centroids).  The Ewald sum of the atom
+ * charges z_i at the centroids c_i (electrons carry no Ewald charge; pairs
+ * of one molecule are excluded; conducting boundary), with k_e the
+ * Coulomb constant, V the cell volume and Q = sum_i z_i:
+ *   real   sum over non-excluded pairs with r < rc of k_e z_i z_j erfc(alpha r)/r,
+ *          minus the excluded pairs' k_e z_i z_j erf(alpha r)/r (any r),
+ *   recip  (2 pi k_e / V) sum over k = 2 pi (n1/L1, n2/L2, n3/L3), 0 < |n_a| <= kmax
+ *          per component, of exp(-k^2 / (4 alpha^2)) / k^2 |sum_j z_j exp(i k.c_j)|^2,
+ *   const  -k_e alpha / sqrt(pi) sum_i z_i^2 - k_e pi Q^2 / (2 V alpha^2),
+ * all with nearest-image separations.  e[0..2] = real, recip, const; the
+ * reciprocal sum is skipped (e[1] = 0) for kmax < 0.  Each bead j of
+ * particle i receives F_i / N_i (the gradient of a function of the centroid
+ * with respect to one of its N_i beads); forces are added to F. */
+void orc_ewald(const orc_sys *S, const double *q, double alpha, double rc, int kmax, double *F,
+               double e[3])
+{
+    const int n = S->n;
+    double *c = (double *)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    double *fc = (double *)calloc(3 * (n > 0 ? n : 1), sizeof(double));
+    double *z = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) {
+        centroid(S, q, i, c + 3 * i);
+        z[i] = S->ele[i] ? 0.0 : S->charge[i];
+    }
+    const double V = S->box[0] * S->box[1] * S->box[2];
+    double er = 0.0, ek = 0.0, e0 = 0.0, Q = 0.0, z2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        Q += z[i];
+        z2 += z[i] * z[i];
+    }
+    /* real space and exclusions */
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double zz = z[i] * z[j];
+            if (zz == 0.0) continue;
+            double d[3];
+            min_image(S, c + 3 * i, c + 3 * j, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double r = sqrt(r2);
+            double gauss = 2.0 * alpha / sqrt(O_PI) * exp(-alpha * alpha * r2);
+            double g;   /* F_i = g d */
+            if (S->mol[i] == S->mol[j]) {
+                /* -erf(alpha r)/r; d/dr = -(gauss r - erf) / r^2 */
+                double v = erf(alpha * r) / r;
+                er -= O_KE_KCAL * zz * v;
+                double dv = (gauss * r - erf(alpha * r)) / r2;   /* d/dr of erf(ar)/r */
+                g = O_KE_KCAL * zz * dv / r;                  /* -d(-v)/dr / r */
+            } else if (r < rc) {
+                double v = erfc(alpha * r) / r;
+                er += O_KE_KCAL * zz * v;
+                double dv = -(gauss * r + erfc(alpha * r)) / r2;  /* d/dr of erfc(ar)/r */
+                g = -O_KE_KCAL * zz * dv / r;
+            } else {
+                continue;
+            }
+            for (int k = 0; k < 3; ++k) {
+                fc[3 * i + k] += g * d[k];
+                fc[3 * j + k] -= g * d[k];
+            }
+        }
+    /* reciprocal space by the direct sum over wave vectors */
+    if (kmax >= 0) {
+        for (int n1 = -kmax; n1 <= kmax; ++n1)
+            for (int n2 = -kmax; n2 <= kmax; ++n2)
+                for (int n3 = -kmax; n3 <= kmax; ++n3) {
+                    if (n1 == 0 && n2 == 0 && n3 == 0) continue;
+                    double kv[3] = {2.0 * O_PI * n1 / S->box[0], 2.0 * O_PI * n2 / S->box[1],
+                                    2.0 * O_PI * n3 / S->box[2]};
+                    double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+                    double A = 2.0 * O_PI * O_KE_KCAL / V * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                    double sr = 0.0, si = 0.0;
+                    for (int j = 0; j < n; ++j) {
+                        double ph = kv[0] * c[3 * j] + kv[1] * c[3 * j + 1] + kv[2] * c[3 * j + 2];
+                        sr += z[j] * cos(ph);
+                        si += z[j] * sin(ph);
+                    }
+                    ek += A * (sr * sr + si * si);
+                    /* F_j = 2 A z_j k Im(exp(i k.c_j) conj(S)) */
+                    for (int j = 0; j < n; ++j) {
+                        if (z[j] == 0.0) continue;
+                        double ph = kv[0] * c[3 * j] + kv[1] * c[3 * j + 1] + kv[2] * c[3 * j + 2];
+                        double im = sin(ph) * sr - cos(ph) * si;
+                        for (int k = 0; k < 3; ++k) fc[3 * j + k] += 2.0 * A * z[j] * kv[k] * im;
+                    }
+                }
+    }
+    e0 = -O_KE_KCAL * alpha / sqrt(O_PI) * z2 - O_KE_KCAL * O_PI * Q * Q / (2.0 * V * alpha * alpha);
+    e[0] = er;
+    e[1] = ek;
+    e[2] = e0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < S->nb[i]; ++j)
+            for (int k = 0; k < 3; ++k) F[3 * (S->off[i] + j) + k] += fc[3 * i + k] / S->nb[i];
+    free(c);
+    free(fc);
+    free(z);
 }
 
 /* Path-integral radial distribution: every non-excluded particle pair of

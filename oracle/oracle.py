@@ -92,6 +92,7 @@ def lib():
         _lib.orc_step_nvt.argtypes = [P, C.c_int, P, P, P, P, C.c_double, P]
         _lib.orc_step_vv.argtypes = [P, C.c_int, P, P, P, P]
         _lib.orc_rdf.argtypes = [P, P, C.c_double, C.c_int, C.c_int, P]
+        _lib.orc_ewald.argtypes = [P, P, C.c_double, C.c_double, C.c_int, P, P]
         _lib.orc_beta.argtypes = [P]
         _lib.orc_beta.restype = C.c_double
         _lib.orc_constants.argtypes = [P]
@@ -102,6 +103,18 @@ def lib():
 
 def _p(a: np.ndarray) -> int:
     return a.ctypes.data
+
+
+def _bspline(n: int, u):
+    """Cardinal B-spline M_n(u) (support [0, n]) by the recursion
+    M_2(u) = 1 - |u - 1| on [0, 2], M_n(u) = (u M_{n-1}(u) + (n - u)
+    M_{n-1}(u - 1)) / (n - 1)."""
+    u = np.asarray(u, dtype=np.float64)
+    if n == 1:
+        return np.where((u >= 0) & (u < 1), 1.0, 0.0)
+    if n == 2:
+        return np.where((u >= 0) & (u <= 2), 1.0 - np.abs(u - 1.0), 0.0)
+    return (u * _bspline(n - 1, u) + (n - u) * _bspline(n - 1, u - 1.0)) / (n - 1)
 
 
 class OracleSystem:
@@ -253,6 +266,81 @@ class OracleSystem:
         h = np.zeros((nspec, nspec, nbins))
         lib().orc_rdf(self.ptr, _p(q), float(rmax), int(nbins), int(nspec), _p(h))
         return h
+
+    def centroids(self, q):
+        """Mean bead position of every particle."""
+        q = np.asarray(q, dtype=np.float64)
+        return np.array([q[self.off[i]:self.off[i + 1]].mean(axis=0) for i in range(self.n)])
+
+    def ewald(self, q, alpha: float, rc: float, kmax: int):
+        """Centroid Ewald electrostatics by definition (orc_ewald): bead
+        forces and (real, reciprocal, constant) energies in kcal/mol.
+        kmax < 0 leaves the reciprocal part out."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        F = np.zeros_like(q)
+        e = np.zeros(3)
+        lib().orc_ewald(self.ptr, _p(q), float(alpha), float(rc), int(kmax), _p(F), _p(e))
+        return F, e
+
+    def spme_recip(self, q, alpha: float, K: int, order: int):
+        """Reciprocal part of the centroid Ewald sum by smooth particle-mesh
+        Ewald (Essmann et al., J. Chem. Phys. 103, 8577 (1995)), in that
+        paper's steps: charges z_i at scaled fractional coordinates
+        u = K c / L spread with cardinal B-splines M_n onto a K^3 grid Q;
+        E = (k_e / 2) sum_m B(m) C(m) |F(Q)(m)|^2 with the Euler
+        exponential spline moduli B and C(m) = exp(-pi^2 m^2 / alpha^2) /
+        (pi V m^2) (C(0) = 0); forces from the B-spline derivatives against
+        the convolution F^-1[B C F(Q)].  Returns (bead forces, energy)."""
+        c = self.centroids(q)
+        z = np.where(self.ele != 0, 0.0, self.charge)
+        L = np.asarray(self.src.box, dtype=np.float64).reshape(3)
+        V = float(np.prod(L))
+        ke = constants()["ke"]
+        n = int(order)
+        u = K * np.mod(c / L, 1.0)
+        base = np.floor(u).astype(np.int64)
+        w = u - base
+        # spline support: grid points base - j, argument w + j, j = 0 .. n-1
+        j = np.arange(n)
+        M = _bspline(n, w[:, :, None] + j)          # [particles][3][n]
+        dM = _bspline(n - 1, w[:, :, None] + j) - _bspline(n - 1, w[:, :, None] + j - 1)
+        idx = np.mod(base[:, :, None] - j, K)       # [particles][3][n]
+        Q = np.zeros((K, K, K))
+        for i in range(self.n):
+            if z[i] == 0.0:
+                continue
+            wgt = z[i] * M[i, 0][:, None, None] * M[i, 1][None, :, None] * M[i, 2][None, None, :]
+            Q[np.ix_(idx[i, 0], idx[i, 1], idx[i, 2])] += wgt
+        m = np.arange(K)
+        mp = np.where(m <= K // 2, m, m - K)
+        bmod = np.zeros(K)
+        kk = np.arange(n - 1)
+        Mk = _bspline(n, kk + 1.0)
+        for a in range(K):
+            den = np.sum(Mk * np.exp(2j * np.pi * a * kk / K))
+            bmod[a] = 1.0 / abs(den) ** 2
+        m2 = ((mp[:, None, None] / L[0]) ** 2 + (mp[None, :, None] / L[1]) ** 2 +
+              (mp[None, None, :] / L[2]) ** 2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Cm = np.exp(-np.pi ** 2 * m2 / alpha ** 2) / (np.pi * V * m2)
+        Cm[0, 0, 0] = 0.0
+        G = bmod[:, None, None] * bmod[None, :, None] * bmod[None, None, :] * Cm
+        FQ = np.fft.fftn(Q)
+        E = 0.5 * ke * float(np.sum(G * np.abs(FQ) ** 2))
+        conv = np.real(np.fft.ifftn(G * FQ)) * K ** 3
+        Fc = np.zeros((self.n, 3))
+        for i in range(self.n):
+            if z[i] == 0.0:
+                continue
+            cv = conv[np.ix_(idx[i, 0], idx[i, 1], idx[i, 2])]
+            gx = np.einsum("abc,a,b,c->", cv, dM[i, 0], M[i, 1], M[i, 2]) * K / L[0]
+            gy = np.einsum("abc,a,b,c->", cv, M[i, 0], dM[i, 1], M[i, 2]) * K / L[1]
+            gz = np.einsum("abc,a,b,c->", cv, M[i, 0], M[i, 1], dM[i, 2]) * K / L[2]
+            Fc[i] = -ke * z[i] * np.array([gx, gy, gz])
+        F = np.zeros((self.B, 3))
+        for i in range(self.n):
+            F[self.off[i]:self.off[i + 1]] = Fc[i] / self.nb[i]
+        return F, E
 
     def centroid_velocity(self, p):
         """Velocity of every ring-polymer centroid, the bead average

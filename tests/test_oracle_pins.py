@@ -706,3 +706,128 @@ def test_vacf_of_constant_and_oscillating_velocities():
     # a window longer than the trajectory: lags past T - 1 stay zero
     acc = o.vacf([moments(v)] * 3, 6)
     assert np.all(acc[:, 3:] == 0) and acc[0, 2] == pytest.approx(v[0] @ v[0], rel=1e-13)
+
+
+# --------------------------------------------------- centroid electrostatics
+
+def _rock_salt(cells: int, a: float, nb: int = 1):
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    pos, chg = [], []
+    for x in range(cells):
+        for y in range(cells):
+            for z in range(cells):
+                for b in base:
+                    pos.append((np.array([x, y, z]) + b) * a)
+                    chg.append(1.0)
+                    pos.append((np.array([x, y, z]) + b + [0.5, 0, 0]) * a)
+                    chg.append(-1.0)
+    pos = np.array(pos)
+    n = len(pos)
+    return custom([nb] * n, np.repeat(pos, nb, axis=0), charge=chg, box=cells * a, rc=cells * a / 2)
+
+
+def test_ewald_madelung_constant_of_rock_salt():
+    """Rock salt (2 x 2 x 2 conventional cells, 64 ions, nearest-neighbour
+    distance r0): E = -(N/2) M k_e / r0 with M = 1.747564594633...; the
+    force on every ion vanishes by symmetry; two splitting parameters give
+    the same energy.  Collapsed 2-bead rings are their centroids."""
+    a = 5.64
+    for nb in (1, 2):
+        s = _rock_salt(2, a, nb)
+        o = oracle.OracleSystem(s)
+        ke = oracle.constants()["ke"]
+        want = -(64 / 2) * 1.747564594633182 * ke / (a / 2)
+        for alpha, kmax in ((1.0, 22), (1.2, 26)):
+            F, e = o.ewald(s.q, alpha, a, kmax)
+            assert e.sum() == pytest.approx(want, rel=1e-10)
+            assert np.abs(F).max() < 1e-9
+
+
+def test_ewald_dipole_in_a_large_cube():
+    """Charges +-1 at distance d in a cube of side L (conducting boundary):
+    E = -k_e/d - 2 pi k_e d^2 / (3 L^3) up to O(d^4 / L^5) (the cubic dipole
+    lattice has no dipole-dipole field at its sites); the force on the
+    positive charge along the bond is -dE/dd = k_e / d^2 - 4 pi k_e d / (3 L^3)."""
+    L, d = 30.0, 1.0
+    q = np.array([[10.0, 10.0, 10.0], [10.0 + d, 10.0, 10.0]])
+    s = custom([1, 1], q, charge=[1.0, -1.0], box=L, rc=L / 2)
+    ke = oracle.constants()["ke"]
+    F, e = oracle.OracleSystem(s).ewald(q, 0.35, L / 2, 22)
+    want = -ke / d - 2 * math.pi * ke * d * d / (3 * L ** 3)
+    assert abs(e.sum() - want) < 1e-6 * ke
+    assert abs(e.sum() - (-ke / d)) > 50e-6 * ke          # the volume term is resolved
+    assert F[0, 0] == pytest.approx(ke / d ** 2 - 4 * math.pi * ke * d / (3 * L ** 3), rel=2e-6)
+    assert np.allclose(F[0], -F[1], rtol=0, atol=1e-10)
+
+
+def test_ewald_is_independent_of_the_splitting():
+    """The converged Ewald sum does not depend on alpha; this holds only
+    with the self term, the excluded pairs' erf correction and (net charge
+    +3 here) the neutralising-background term all correct."""
+    s = synth.config_c1()
+    o = oracle.OracleSystem(s)
+    L = float(s.box[0])
+    out = [o.ewald(s.q, al, L / 2, km) for al, km in ((1.1, 24), (1.4, 30))]
+    (F1, e1), (F2, e2) = out
+    assert e1.sum() == pytest.approx(e2.sum(), rel=1e-9)
+    assert abs(e1[2] - e2[2]) > 1.0                        # the parts do move
+    rms = np.sqrt((F1 ** 2).sum(axis=1).mean())
+    assert np.abs(F1 - F2).max() < 1e-7 * rms
+
+
+def test_ewald_forces_are_minus_the_gradient():
+    """Central differences of the energy in one bead coordinate: the bead
+    force is 1/N_i of the centroid force."""
+    s = synth.config_c1()
+    o = oracle.OracleSystem(s)
+    L = float(s.box[0])
+    F, _ = o.ewald(s.q, 0.6, L / 2, 10)
+    rng = np.random.default_rng(2)
+    for b in rng.integers(0, s.q.shape[0], 5):
+        for k in range(3):
+            qp, qm = s.q.copy(), s.q.copy()
+            qp[b, k] += 1e-5
+            qm[b, k] -= 1e-5
+            fd = -(o.ewald(qp, 0.6, L / 2, 10)[1].sum() - o.ewald(qm, 0.6, L / 2, 10)[1].sum()) / 2e-5
+            assert F[b, k] == pytest.approx(fd, rel=1e-5, abs=1e-6)
+
+
+def test_bspline_partition_of_unity():
+    from oracle.oracle import _bspline
+    w = np.linspace(0, 1, 17, endpoint=False)
+    for n in (4, 6, 8):
+        tot = sum(_bspline(n, w + j) for j in range(n))
+        assert np.allclose(tot, 1.0, rtol=0, atol=1e-14)
+        # M_n is the n-fold convolution of the unit box: M_n(n/2) is the
+        # peak, symmetric about it
+        assert _bspline(n, n / 2 - 0.3) == pytest.approx(_bspline(n, n / 2 + 0.3), rel=1e-14)
+    assert _bspline(4, 2.0) == pytest.approx(2.0 / 3.0, rel=1e-15)
+    assert _bspline(4, 1.0) == pytest.approx(1.0 / 6.0, rel=1e-15)
+
+
+def test_spme_converges_to_the_ewald_reciprocal_sum():
+    """SPME's reciprocal energy and forces approach the direct sum as the
+    grid and the spline order grow; its forces are minus the gradient of
+    its own energy."""
+    s = synth.config_c1()
+    o = oracle.OracleSystem(s)
+    L = float(s.box[0])
+    al = 0.45
+    Fd, ed = o.ewald(s.q, al, L / 2, 16)
+    Fr, _ = o.ewald(s.q, al, L / 2, -1)
+    Fk = Fd - Fr
+    rms = np.sqrt((Fk ** 2).sum(axis=1).mean())
+    errs = []
+    for K, n in ((16, 4), (32, 6), (64, 8)):
+        F, E = o.spme_recip(s.q, al, K, n)
+        errs.append((abs(E - ed[1]) / abs(ed[1]), np.abs(F - Fk).max() / rms))
+    assert errs[0][0] > errs[1][0] > errs[2][0] and errs[2][0] < 1e-8
+    assert errs[0][1] > errs[1][1] > errs[2][1] and errs[2][1] < 1e-6
+    F, E = o.spme_recip(s.q, al, 16, 4)
+    b = 7
+    for k in range(3):
+        qp, qm = s.q.copy(), s.q.copy()
+        qp[b, k] += 1e-5
+        qm[b, k] -= 1e-5
+        fd = -(o.spme_recip(qp, al, 16, 4)[1] - o.spme_recip(qm, al, 16, 4)[1]) / 2e-5
+        assert F[b, k] == pytest.approx(fd, rel=1e-5, abs=1e-6)
