@@ -289,6 +289,38 @@ int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, i
 int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, int32_t nspec,
                       double *ring, double *acc, void *stream);
 
+/* Long-range electrostatics between ring-polymer centroids (Sec. "Theory":
+ * the example systems' electrostatics by smooth-particle-mesh Ewald, with
+ * the bead-bead energies and forces replaced by those between centroids).
+ * Configures the Ewald sum of the atom charges (electrons carry none) at
+ * the particles' centroids for every system of the handle: splitting
+ * parameter alpha (1/A), real-space cutoff r_cut (A, at most half of every
+ * box edge), a grid^3 reciprocal mesh (grid a power of two in [16, 128])
+ * and cardinal B-splines of order 4, 6 or 8 (Essmann et al., J. Chem. Phys.
+ * 103, 8577 (1995)).  Builds the influence function on the host and
+ * allocates the handle's Ewald buffers (32 grid^3 bytes per system plus
+ * O(particles)); a second call replaces the first.  Synchronous.  Errors:
+ * MIXPI_E_INVALID (bad parameter), MIXPI_E_HIP. */
+int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid, int32_t order);
+
+/* The centroid Ewald electrostatics configured by mixpi_set_ewald, for the
+ * bead positions q (device [rows][3]).  Energies, kcal/mol, to e_out
+ * (device FP64 [n_systems][3]): [0] real space -- k_e z_i z_j
+ * erfc(alpha r)/r over pairs of different molecules within r_cut, minus
+ * k_e z_i z_j erf(alpha r)/r over pairs of one molecule (excluded pairs,
+ * any distance); [1] reciprocal space (SPME); [2] the self term
+ * -k_e alpha/sqrt(pi) sum z_i^2 and the neutralising background
+ * -k_e pi Q^2/(2 V alpha^2); all with nearest-image centroid separations.
+ * Forces: each bead of particle i gets F_i / N_i (the gradient with respect
+ * to one of its beads), ADDED to f (device [rows][3]; null: energies
+ * only).  Use with rc_coul = 0 in the system description, which turns the
+ * bead-resolved cut atom-atom Coulomb term off.  The charge grid is summed
+ * in fixed point (2^-50 e resolution or finer), so results are
+ * independent of scheduling.  Asynchronous on stream; calls on one handle
+ * must not overlap (they share its buffers).  Errors: MIXPI_E_INVALID (not
+ * configured, null q or e_out). */
+int mixpi_ewald(mixpi_system *sys, const double *q, double *f, double *e_out, void *stream);
+
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems
  * (from the work lists; no device work). */

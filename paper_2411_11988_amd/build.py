@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmixpi.so")
-SOURCES = ["pair.hip", "rp.hip", "misc.hip", "rdf.hip", "tcf.hip", "api.cpp"]
+SOURCES = ["pair.hip", "rp.hip", "misc.hip", "rdf.hip", "tcf.hip", "ewald.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MIXPI_OFFLOAD_ARCH", "gfx950")
 

@@ -72,6 +72,15 @@ int upload(T **dst, const std::vector<T> &v)
     return MIXPI_OK;
 }
 
+template <typename T>
+int alloc(T **dst, size_t n)
+{
+    *dst = nullptr;
+    if (n == 0) return MIXPI_OK;
+    HIP_TRY(hipMalloc((void **)dst, sizeof(T) * n));
+    return MIXPI_OK;
+}
+
 }  // namespace
 
 struct mixpi_system {
@@ -99,6 +108,21 @@ struct mixpi_system {
     // centroid quantities: particles in handle order, first particle per system
     PartDev *d_parts = nullptr;
     int *d_sys_part = nullptr;
+    std::vector<PartDev> h_parts;
+    std::vector<int> h_sys_part;
+    std::vector<double> h_ew_z;
+    // centroid Ewald electrostatics (mixpi_set_ewald)
+    struct Ewald {
+        bool on = false;
+        double alpha = 0, r_cut = 0, scale = 1;
+        int K = 0, logK = 0, order = 0, recip_wg = 1, n_real = 0;
+        double *z = nullptr, *cpos = nullptr, *freal = nullptr, *fcent = nullptr, *G = nullptr;
+        long long *grid_i = nullptr;
+        double2 *grid_c = nullptr, *tw = nullptr;
+        double *e_real_part = nullptr, *e_recip_part = nullptr, *e_const = nullptr;
+        BlockRange *real_ranges = nullptr;
+        int *real_first = nullptr;
+    } ew;
     // bonded sweep: terms and system-pure blocks of 256 (fast blocks first)
     BondedTerm *d_bterms = nullptr;
     BlockRange *d_bblocks = nullptr;
@@ -156,9 +180,20 @@ struct mixpi_system {
 
 namespace {
 
+void release_ewald(mixpi_system *s)
+{
+    auto &e = s->ew;
+    void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.grid_i, e.grid_c, e.tw,
+                    e.e_real_part, e.e_recip_part, e.e_const, e.real_ranges, e.real_first};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    e = mixpi_system::Ewald{};
+}
+
 void release(mixpi_system *s)
 {
     if (!s) return;
+    release_ewald(s);
     for (auto &g : s->graphs) {
         (void)hipGraphExecDestroy(g.exec);
         (void)hipGraphDestroy(g.graph);
@@ -257,7 +292,7 @@ int validate(const mixpi_system_desc *d, int idx)
         if (!std::isfinite(d->angle_k[k]) || !std::isfinite(d->angle_t0[k]))
             return fail(MIXPI_E_INVALID, "system %d: angle type %d is not finite", idx, k);
     if (!finite_pos(d->pp_a) || !std::isfinite(d->pp_q) || !finite_pos(d->rc_pp) ||
-        !finite_pos(d->rc_coul) || !finite_pos(d->rc_lj))
+        !(std::isfinite(d->rc_coul) && d->rc_coul >= 0.0) || !finite_pos(d->rc_lj))
         return fail(MIXPI_E_INVALID, "system %d: bad pseudopotential or cutoff", idx);
     for (int k = 0; k < 3; ++k)
         if (!finite_pos(d->box[k])) return fail(MIXPI_E_INVALID, "system %d: bad box", idx);
@@ -285,6 +320,7 @@ struct Build {
     std::map<int, int> basis_off, tw_off;
     std::vector<long long> bead_index;
     std::vector<PartDev> parts;
+    std::vector<double> ew_z;                  // Ewald charge per particle (0 for electrons)
     std::vector<int> sys_part;                 // first particle of each system
     std::vector<std::pair<long long, long long>> sys_rows;   // [begin, end) per system
     long long rows = 0;
@@ -394,6 +430,7 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
             pd.sys = s;
             B.parts.push_back(pd);
         }
+    for (int i = 0; i < n; ++i) B.ew_z.push_back(d->is_electron[i] ? 0.0 : d->charge[i]);
 
     // layout: bead index and row -> particle
     std::vector<long long> part_first(n);
@@ -967,6 +1004,9 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         sp.push_back(B.n_part);
         T(upload(&S->d_parts, B.parts));
         T(upload(&S->d_sys_part, sp));
+        S->h_parts = B.parts;
+        S->h_sys_part = sp;
+        S->h_ew_z = B.ew_z;
     }
     T(upload(&S->d_bterms, terms));
     T(upload(&S->d_bblocks, bblocks));
@@ -1649,6 +1689,168 @@ int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, 
     a.n_sys = sys->n_sys;
     a.nspec = nspec;
     launch_tcf(a, p, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return MIXPI_OK;
+}
+
+namespace {
+// Cardinal B-spline M_n(u) by its recursion (host tables of the SPME moduli).
+double card_bspline(int n, double u)
+{
+    if (n == 2) return (u >= 0.0 && u <= 2.0) ? 1.0 - std::fabs(u - 1.0) : 0.0;
+    return (u * card_bspline(n - 1, u) + (n - u) * card_bspline(n - 1, u - 1.0)) / (n - 1);
+}
+}  // namespace
+
+int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid, int32_t order)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!finite_pos(alpha)) return fail(MIXPI_E_INVALID, "alpha must be positive and finite");
+    if (!finite_pos(r_cut)) return fail(MIXPI_E_INVALID, "r_cut must be positive and finite");
+    if (grid < 16 || grid > 128 || (grid & (grid - 1)))
+        return fail(MIXPI_E_INVALID, "grid must be a power of two in [16, 128] (got %d)", grid);
+    if (order != 4 && order != 6 && order != 8)
+        return fail(MIXPI_E_INVALID, "order must be 4, 6 or 8 (got %d)", order);
+    const int n_sys = sys->n_sys, K = grid;
+    for (int s = 0; s < n_sys; ++s)
+        for (int k = 0; k < 3; ++k)
+            if (r_cut > 0.5 * sys->h_sys[s].box[k])
+                return fail(MIXPI_E_INVALID, "system %d: r_cut %g exceeds half the box (%g)", s,
+                            r_cut, sys->h_sys[s].box[k]);
+    HIP_TRY(hipSetDevice(sys->device));
+    release_ewald(sys);
+    auto &e = sys->ew;
+    e.alpha = alpha;
+    e.r_cut = r_cut;
+    e.K = K;
+    e.logK = ilog2(K);
+    e.order = order;
+    const long long K3 = (long long)K * K * K;
+    e.recip_wg = (int)std::max<long long>(1, K3 / 4096);
+
+    // Euler exponential spline moduli |b(m)|^2, the same on every axis
+    std::vector<double> bmod(K);
+    for (int m = 0; m < K; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= order - 2; ++k) {
+            const double Mk = card_bspline(order, k + 1.0);
+            re += Mk * std::cos(2.0 * kPi * m * k / K);
+            im += Mk * std::sin(2.0 * kPi * m * k / K);
+        }
+        bmod[m] = 1.0 / (re * re + im * im);
+    }
+    // influence function G = B C per system, constants, fixed-point scale
+    std::vector<double> G((size_t)n_sys * K3), e_const(n_sys);
+    double max_abs = 0.0;
+    for (int s = 0; s < n_sys; ++s) {
+        const SysDev &S = sys->h_sys[s];
+        const double V = S.box[0] * S.box[1] * S.box[2];
+        double Q = 0.0, z2 = 0.0, za = 0.0;
+        for (int i = sys->h_sys_part[s]; i < sys->h_sys_part[s + 1]; ++i) {
+            Q += sys->h_ew_z[i];
+            z2 += sys->h_ew_z[i] * sys->h_ew_z[i];
+            za += std::fabs(sys->h_ew_z[i]);
+        }
+        max_abs = std::max(max_abs, za);
+        e_const[s] = -kCoulombKcal * alpha / std::sqrt(kPi) * z2 -
+                     kCoulombKcal * kPi * Q * Q / (2.0 * V * alpha * alpha);
+        double *g = G.data() + (size_t)s * K3;
+        for (int m1 = 0; m1 < K; ++m1)
+            for (int m2 = 0; m2 < K; ++m2)
+                for (int m3 = 0; m3 < K; ++m3) {
+                    const int a1 = m1 <= K / 2 ? m1 : m1 - K;
+                    const int a2 = m2 <= K / 2 ? m2 : m2 - K;
+                    const int a3 = m3 <= K / 2 ? m3 : m3 - K;
+                    const double x = a1 / S.box[0], y = a2 / S.box[1], z = a3 / S.box[2];
+                    const double msq = x * x + y * y + z * z;
+                    const size_t k = ((size_t)m1 * K + m2) * K + m3;
+                    g[k] = msq == 0.0 ? 0.0
+                                      : bmod[m1] * bmod[m2] * bmod[m3] *
+                                            std::exp(-kPi * kPi * msq / (alpha * alpha)) /
+                                            (kPi * V * msq);
+                }
+    }
+    // grid cells hold at most sum |z| (the weights of one particle sum to 1)
+    const int bits = std::min(50, 61 - (int)std::ceil(std::log2(max_abs + 1.0)));
+    e.scale = std::ldexp(1.0, bits);
+    std::vector<double2> tw(K / 2);
+    for (int j = 0; j < K / 2; ++j)
+        tw[j] = make_double2(std::cos(2.0 * kPi * j / K), -std::sin(2.0 * kPi * j / K));
+    // real-space workgroups: runs of at most 256 particles of one system
+    std::vector<int> psys(sys->n_part);
+    for (int i = 0; i < sys->n_part; ++i) psys[i] = sys->h_parts[i].sys;
+    std::vector<BlockRange> ranges = system_blocks(psys, 0, sys->n_part, 256);
+    std::vector<int> first(n_sys + 1, (int)ranges.size());
+    for (int r = (int)ranges.size() - 1; r >= 0; --r) first[ranges[r].sys] = r;
+    for (int s = n_sys - 1; s >= 0; --s) first[s] = std::min(first[s], first[s + 1]);
+    e.n_real = (int)ranges.size();
+
+    int rc = MIXPI_OK;
+    auto T = [&](int r) {
+        if (r && !rc) rc = r;
+    };
+    const size_t np3 = (size_t)std::max(1, sys->n_part) * 3;
+    T(upload(&e.z, sys->h_ew_z));
+    T(upload(&e.G, G));
+    T(upload(&e.tw, tw));
+    T(upload(&e.e_const, e_const));
+    T(upload(&e.real_ranges, ranges));
+    T(upload(&e.real_first, first));
+    T(alloc(&e.cpos, np3));
+    T(alloc(&e.freal, np3));
+    T(alloc(&e.fcent, np3));
+    T(alloc(&e.grid_i, (size_t)n_sys * K3));
+    T(alloc(&e.grid_c, (size_t)n_sys * K3));
+    T(alloc(&e.e_real_part, (size_t)std::max(1, e.n_real)));
+    T(alloc(&e.e_recip_part, (size_t)n_sys * e.recip_wg));
+    if (rc) {
+        release_ewald(sys);
+        return rc;
+    }
+    e.on = true;
+    return MIXPI_OK;
+}
+
+int mixpi_ewald(mixpi_system *sys, const double *q, double *f, double *e_out, void *stream)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!sys->ew.on) return fail(MIXPI_E_INVALID, "call mixpi_set_ewald first");
+    if (!q || !e_out) return fail(MIXPI_E_INVALID, "q or e_out is null");
+    HIP_TRY(hipSetDevice(sys->device));
+    const auto &e = sys->ew;
+    EwaldLaunch a{};
+    a.parts = sys->d_parts;
+    a.sys = sys->d_sys;
+    a.sys_part = sys->d_sys_part;
+    a.z = e.z;
+    a.mol = sys->d_mol;
+    a.q = q;
+    a.f = f;
+    a.cpos = e.cpos;
+    a.freal = e.freal;
+    a.fcent = e.fcent;
+    a.grid_i = e.grid_i;
+    a.grid_c = e.grid_c;
+    a.G = e.G;
+    a.tw = e.tw;
+    a.e_real_part = e.e_real_part;
+    a.e_recip_part = e.e_recip_part;
+    a.real_ranges = e.real_ranges;
+    a.real_first = e.real_first;
+    a.e_const = e.e_const;
+    a.e_out = e_out;
+    a.alpha = e.alpha;
+    a.r_cut = e.r_cut;
+    a.scale = e.scale;
+    a.inv_scale = 1.0 / e.scale;
+    a.K = e.K;
+    a.logK = e.logK;
+    a.order = e.order;
+    a.n_part = sys->n_part;
+    a.n_sys = sys->n_sys;
+    a.recip_wg = e.recip_wg;
+    a.n_real = e.n_real;
+    launch_ewald(a, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return MIXPI_OK;
 }

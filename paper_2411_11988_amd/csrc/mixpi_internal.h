@@ -278,6 +278,31 @@ struct TcfLaunch {
 };
 void launch_tcf(const TcfLaunch &a, const double *p, hipStream_t st);
 
+// Centroid Ewald electrostatics (all systems of a handle, one grid each).
+struct EwaldLaunch {
+    const PartDev *parts;
+    const SysDev *sys;
+    const int *sys_part;         // [n_sys + 1]
+    const double *z;             // Ewald charge per particle (0 for electrons)
+    const int *mol;
+    const double *q;             // bead rows
+    double *f;                   // bead rows, added to (may be null)
+    double *cpos, *freal, *fcent;   // [n_part][3]
+    long long *grid_i;           // [n_sys][K^3] fixed-point charge grid
+    double2 *grid_c;             // [n_sys][K^3]
+    const double *G;             // [n_sys][K^3] influence function B C
+    const double2 *tw;           // exp(-2 pi i j / K), j < K/2
+    double *e_real_part;         // [n_real]
+    double *e_recip_part;        // [n_sys][recip_wg]
+    const BlockRange *real_ranges;
+    const int *real_first;       // [n_sys + 1] first real range of each system
+    const double *e_const;       // [n_sys] self + background
+    double *e_out;               // [n_sys][3]
+    double alpha, r_cut, scale, inv_scale;
+    int K, logK, order, n_part, n_sys, recip_wg, n_real;
+};
+void launch_ewald(const EwaldLaunch &a, hipStream_t st);
+
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);
 void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);

@@ -98,6 +98,8 @@ def load():
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
         "mixpi_rdf": ([P, P, C.c_double, I32, I32, P, P], C.c_int),
         "mixpi_vacf_sample": ([P, P, C.c_int64, I32, I32, P, P, P], C.c_int),
+        "mixpi_set_ewald": ([P, C.c_double, C.c_double, I32, I32], C.c_int),
+        "mixpi_ewald": ([P, P, P, P, P], C.c_int),
         "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
         "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
         "mixpi_step_vv": ([P, I32, P, P, P, P, P], C.c_int),
@@ -263,6 +265,14 @@ def mixpi_vacf_sample(h, p, t: int, L: int, nspec: int, ring, acc, stream=None):
                                     _stream(stream)))
 
 
+def mixpi_set_ewald(h, alpha: float, r_cut: float, grid: int, order: int):
+    _check(load().mixpi_set_ewald(h, float(alpha), float(r_cut), int(grid), int(order)))
+
+
+def mixpi_ewald(h, q, f, e_out, stream=None):
+    _check(load().mixpi_ewald(h, _ptr(q), _ptr(f), _ptr(e_out), _stream(stream)))
+
+
 # ---- convenience object ------------------------------------------------------
 
 class System:
@@ -365,6 +375,18 @@ class System:
 
     def kernel_time(self, reps: int, q, p, f, stream=None) -> dict:
         return mixpi_kernel_time(self.h, reps, q, p, f, stream)
+
+    def set_ewald(self, alpha: float, r_cut: float, grid: int, order: int):
+        mixpi_set_ewald(self.h, alpha, r_cut, grid, order)
+
+    def ewald(self, q, f=None, e_out=None, stream=None):
+        """Centroid Ewald energies [systems][3] (real, reciprocal, constant);
+        bead forces are added to f when given."""
+        if e_out is None:
+            import torch
+            e_out = torch.zeros((self.n_systems, 3), dtype=torch.float64, device=q.device)
+        mixpi_ewald(self.h, q, f, e_out, stream)
+        return e_out
 
     def vacf_sample(self, p, t: int, ring, acc, nspec: int = 9, stream=None):
         """Adds sample t of the centroid velocity correlation sums to acc
