@@ -185,6 +185,52 @@ def _run_vv(s, precision, steps, mixpi, torch, flags=0):
     return {"steps_per_s": steps / (ms * 1e-3), "ms_per_step": ms / steps}
 
 
+def _run_observables(sysm, q, p, s, mixpi, torch, reps=50):
+    """The observables and the long-range electrostatics on the workload's
+    configuration: mean time per call over `reps` calls (HIP events on the
+    stream the library launches on), after warmup calls."""
+    import numpy as np
+    box = float(np.min(_as_list(s)[0].box))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(n):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) * 1e3 / n
+
+    nb, rmax = 256, 0.5 * box
+    hist = torch.zeros((sysm.n_systems, 9, 9, nb), dtype=torch.float64, device="cuda")
+    rdf_us = timed(lambda: sysm.rdf(q, rmax, nb, hist), reps)
+    L = 1000
+    ring = torch.zeros((L, sysm.n_particles, 3), dtype=torch.float64, device="cuda")
+    acc = torch.zeros((sysm.n_systems, 9, L), dtype=torch.float64, device="cuda")
+    t = [0]
+
+    def sample():
+        sysm.vacf_sample(p, t[0] + L, ring, acc)    # a full window of lags
+        t[0] += 1
+    vacf_us = timed(sample, reps)
+    alpha, rcut, grid, order = 0.35, min(9.0, 0.5 * box), 32, 6
+    sysm.set_ewald(alpha, rcut, grid, order)
+    f = torch.zeros_like(q)
+    e = torch.zeros((sysm.n_systems, 3), dtype=torch.float64, device="cuda")
+    ew_us = timed(lambda: sysm.ewald(q, f, e), reps)
+    cand = sysm.pair_candidates()
+    return {"rdf": {"us_per_call": rdf_us, "nbins": nb, "r_max": rmax,
+                    "slice_pairs_per_s": cand / (rdf_us * 1e-6)},
+            "vacf": {"us_per_sample": vacf_us, "lags": L},
+            "ewald": {"us_per_call": ew_us, "alpha": alpha, "r_cut": rcut, "grid": grid,
+                      "order": order}}
+
+
 def _bonded_slices(s):
     """Bond and angle slices: each term is evaluated on N_max slices."""
     n_bond = n_angle = 0
@@ -251,6 +297,9 @@ def main():
     ap.add_argument("--nvt", action=argparse.BooleanOptionalAction, default=True,
                     help="also time thermostatted (path-integral Langevin) steps and "
                          "velocity-Verlet steps")
+    ap.add_argument("--observables", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the radial distribution, velocity correlation and centroid "
+                         "Ewald calls on the workload's configuration")
     ap.add_argument("--tile", default="auto", choices=["auto", "heuristic"],
                     help="pair-sweep tile shape: autotuned per workload bucket (default) or "
                          "the library's size heuristic")
@@ -336,6 +385,9 @@ def main():
                      "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"]},
     }
+    if args.observables:
+        print("[bench] observables and centroid electrostatics", file=sys.stderr, flush=True)
+        out["observables"] = _run_observables(sysm, r32["q"], r32["p"], s, mixpi, torch)
     if args.nvt:
         print("[bench] thermostatted steps (FP32 form)", file=sys.stderr, flush=True)
         out["nvt"] = _run_nvt(s, mixpi.MIXPI_FP32_ACC64, args.steps, mixpi, torch, flags32)

@@ -295,7 +295,7 @@ int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, 
  * Configures the Ewald sum of the atom charges (electrons carry none) at
  * the particles' centroids for every system of the handle: splitting
  * parameter alpha (1/A), real-space cutoff r_cut (A, at most half of every
- * box edge), a grid^3 reciprocal mesh (grid a power of two in [16, 128])
+ * box edge), a grid^3 reciprocal mesh (grid 16, 32 or 64)
  * and cardinal B-splines of order 4, 6 or 8 (Essmann et al., J. Chem. Phys.
  * 103, 8577 (1995)).  Builds the influence function on the host and
  * allocates the handle's Ewald buffers (32 grid^3 bytes per system plus

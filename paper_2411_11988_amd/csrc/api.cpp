@@ -120,7 +120,7 @@ struct mixpi_system {
         long long *grid_i = nullptr;
         double2 *grid_c = nullptr, *tw = nullptr;
         double *e_real_part = nullptr, *e_recip_part = nullptr, *e_const = nullptr;
-        BlockRange *real_ranges = nullptr;
+        RealItem *real_items = nullptr;
         int *real_first = nullptr;
     } ew;
     // bonded sweep: terms and system-pure blocks of 256 (fast blocks first)
@@ -184,7 +184,7 @@ void release_ewald(mixpi_system *s)
 {
     auto &e = s->ew;
     void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.grid_i, e.grid_c, e.tw,
-                    e.e_real_part, e.e_recip_part, e.e_const, e.real_ranges, e.real_first};
+                    e.e_real_part, e.e_recip_part, e.e_const, e.real_items, e.real_first};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     e = mixpi_system::Ewald{};
@@ -1707,8 +1707,8 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     if (int rc = check_sys(sys)) return rc;
     if (!finite_pos(alpha)) return fail(MIXPI_E_INVALID, "alpha must be positive and finite");
     if (!finite_pos(r_cut)) return fail(MIXPI_E_INVALID, "r_cut must be positive and finite");
-    if (grid < 16 || grid > 128 || (grid & (grid - 1)))
-        return fail(MIXPI_E_INVALID, "grid must be a power of two in [16, 128] (got %d)", grid);
+    if (grid != 16 && grid != 32 && grid != 64)
+        return fail(MIXPI_E_INVALID, "grid must be 16, 32 or 64 (got %d)", grid);
     if (order != 4 && order != 6 && order != 8)
         return fail(MIXPI_E_INVALID, "order must be 4, 6 or 8 (got %d)", order);
     const int n_sys = sys->n_sys, K = grid;
@@ -1726,7 +1726,7 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     e.logK = ilog2(K);
     e.order = order;
     const long long K3 = (long long)K * K * K;
-    e.recip_wg = (int)std::max<long long>(1, K3 / 4096);
+    e.recip_wg = K * K / 16;   // x-line workgroups per system
 
     // Euler exponential spline moduli |b(m)|^2, the same on every axis
     std::vector<double> bmod(K);
@@ -1776,14 +1776,23 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     std::vector<double2> tw(K / 2);
     for (int j = 0; j < K / 2; ++j)
         tw[j] = make_double2(std::cos(2.0 * kPi * j / K), -std::sin(2.0 * kPi * j / K));
-    // real-space workgroups: runs of at most 256 particles of one system
-    std::vector<int> psys(sys->n_part);
-    for (int i = 0; i < sys->n_part; ++i) psys[i] = sys->h_parts[i].sys;
-    std::vector<BlockRange> ranges = system_blocks(psys, 0, sys->n_part, 256);
-    std::vector<int> first(n_sys + 1, (int)ranges.size());
-    for (int r = (int)ranges.size() - 1; r >= 0; --r) first[ranges[r].sys] = r;
-    for (int s = n_sys - 1; s >= 0; --s) first[s] = std::min(first[s], first[s + 1]);
-    e.n_real = (int)ranges.size();
+    // real-space workgroups: 64-particle i-tiles x kEwChunk-particle j-chunks
+    // of each system, in system order
+    std::vector<RealItem> items;
+    std::vector<int> first(n_sys + 1, 0);
+    int max_chunks = 1;
+    for (int s = 0; s < n_sys; ++s) {
+        first[s] = (int)items.size();
+        const int p0 = sys->h_sys_part[s], p1 = sys->h_sys_part[s + 1];
+        int c = 0;
+        for (int j0 = p0; j0 < p1; j0 += kEwChunk, ++c)
+            for (int i0 = p0; i0 < p1; i0 += 64)
+                items.push_back(RealItem{s, i0, std::min(64, p1 - i0), j0,
+                                         std::min(kEwChunk, p1 - j0), c});
+        max_chunks = std::max(max_chunks, c);
+    }
+    first[n_sys] = (int)items.size();
+    e.n_real = (int)items.size();
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -1794,15 +1803,20 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     T(upload(&e.G, G));
     T(upload(&e.tw, tw));
     T(upload(&e.e_const, e_const));
-    T(upload(&e.real_ranges, ranges));
+    T(upload(&e.real_items, items));
     T(upload(&e.real_first, first));
     T(alloc(&e.cpos, np3));
-    T(alloc(&e.freal, np3));
+    T(alloc(&e.freal, np3 * max_chunks));
     T(alloc(&e.fcent, np3));
     T(alloc(&e.grid_i, (size_t)n_sys * K3));
     T(alloc(&e.grid_c, (size_t)n_sys * K3));
     T(alloc(&e.e_real_part, (size_t)std::max(1, e.n_real)));
     T(alloc(&e.e_recip_part, (size_t)n_sys * e.recip_wg));
+    // the fixed-point grid starts at zero; every call clears it after reading
+    if (!rc && hipMemset(e.grid_i, 0, sizeof(long long) * (size_t)n_sys * K3) != hipSuccess)
+        rc = fail(MIXPI_E_HIP, "hipMemset of the charge grid failed");
+    if (!rc && hipDeviceSynchronize() != hipSuccess)
+        rc = fail(MIXPI_E_HIP, "device synchronisation failed");
     if (rc) {
         release_ewald(sys);
         return rc;
@@ -1835,7 +1849,7 @@ int mixpi_ewald(mixpi_system *sys, const double *q, double *f, double *e_out, vo
     a.tw = e.tw;
     a.e_real_part = e.e_real_part;
     a.e_recip_part = e.e_recip_part;
-    a.real_ranges = e.real_ranges;
+    a.real_items = e.real_items;
     a.real_first = e.real_first;
     a.e_const = e.e_const;
     a.e_out = e_out;

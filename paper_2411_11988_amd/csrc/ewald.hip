@@ -8,21 +8,24 @@
 // (1995)), and the self and neutralising-background constants.  Each bead
 // of particle i receives F_i / N_i.
 //
-// Launch sequence, every system of the handle at once:
-//   k_ew_prep     centroids; zero the fixed-point charge grid
-//   k_ew_spread   cardinal B-spline weights of order P; one lane per (x, y)
-//                 spline point adds its P z-points with int64 atomics in
-//                 fixed point (exact, so the grid is independent of order)
-//   k_ew_fft x3   3D FFT, forward; the first pass converts fixed point to
-//                 FP64 complex
-//   k_ew_recip    multiply by the influence function G = B C, energy
-//                 partials sum G |F(Q)|^2
-//   k_ew_fft x3   inverse (unnormalised): the convolution (theta * Q)
-//   k_ew_real     real-space and exclusion terms, one thread per particle
-//                 against its system's particles staged in LDS
-//   k_ew_gather   spline-derivative gather of the convolution, plus the
-//                 real-space force; bead forces F_i / N_i
-//   k_ew_reduce   per-system energies in a fixed order
+// Five launches, every system of the handle at once:
+//   k_ew_spread   one wave per particle: its centroid, then cardinal
+//                 B-spline weights of order P; one lane per (x, y) spline
+//                 point adds its P z-points with int64 atomics in fixed
+//                 point (exact, so the grid does not depend on the order)
+//   k_ew_plane    forward 2D FFT (z, then y) of each x-plane in LDS, reading
+//                 (and clearing) the fixed-point grid; the same grid runs the
+//                 real-space workgroups: erfc terms within r_cut and the erf
+//                 correction of excluded pairs, (64 i) x (kEwChunk j) tiles
+//   k_ew_xline    per 16 x-lines: forward FFT along x, multiply by the
+//                 influence function G = B C with the energy partial
+//                 sum G |F(Q)|^2, inverse FFT along x
+//   k_ew_plane    inverse 2D FFT (y, then z): the convolution (theta * Q)
+//   k_ew_gather   spline-derivative gather of the convolution plus the
+//                 real-space partials, bead forces F_i / N_i; one extra
+//                 workgroup per system sums its energies in a fixed order
+// FFTs are radix-2 decimation in time from bit-reversed order, sign -1
+// forward (exp(-2 pi i jk / K)), +1 inverse, unnormalised.
 #include "device_common.h"
 #include "mixpi_internal.h"
 
@@ -88,54 +91,39 @@ __device__ __forceinline__ int wrap(int i, int K)
     return i < 0 ? i + K : i;
 }
 
-// ---- centroids, grid clear --------------------------------------------------
-__global__ __launch_bounds__(kEwThreads) void k_ew_prep(EwaldLaunch a)
-{
-    const long long gid = (long long)blockIdx.x * kEwThreads + threadIdx.x;
-    const long long ngrid = (long long)a.n_sys * a.K * a.K * a.K;
-    for (long long k = gid; k < ngrid; k += (long long)gridDim.x * kEwThreads) a.grid_i[k] = 0;
-    // one wave per particle
-    const int wid = (int)(gid >> 6);
-    const int lane = threadIdx.x & 63;
-    for (int i = wid; i < a.n_part; i += (int)((long long)gridDim.x * kEwThreads / 64)) {
-        const PartDev pd = a.parts[i];
-        double sx = 0, sy = 0, sz = 0;
-        for (int j = lane; j < pd.nb; j += 64) {
-            const long long r = pd.row0 + (long long)j * pd.stride;
-            sx += a.q[3 * r];
-            sy += a.q[3 * r + 1];
-            sz += a.q[3 * r + 2];
-        }
-        sx = wave_sum(sx);
-        sy = wave_sum(sy);
-        sz = wave_sum(sz);
-        if (lane == 0) {
-            a.cpos[3LL * i] = sx / pd.nb;
-            a.cpos[3LL * i + 1] = sy / pd.nb;
-            a.cpos[3LL * i + 2] = sz / pd.nb;
-        }
-    }
-}
-
-// ---- charge spreading -------------------------------------------------------
+// ---- centroids and charge spreading ------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kEwThreads) void k_ew_spread(EwaldLaunch a)
 {
     const int i = blockIdx.x * (kEwThreads / 64) + ((int)threadIdx.x >> 6);
     if (i >= a.n_part) return;
+    const int lane = threadIdx.x & 63;
+    const PartDev pd = a.parts[i];
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int j = lane; j < pd.nb; j += 64) {
+        const long long r = pd.row0 + (long long)j * pd.stride;
+        c[0] += a.q[3 * r];
+        c[1] += a.q[3 * r + 1];
+        c[2] += a.q[3 * r + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = wave_sum(c[k]) / pd.nb;
+    if (lane == 0) {
+        a.cpos[3LL * i] = c[0];
+        a.cpos[3LL * i + 1] = c[1];
+        a.cpos[3LL * i + 2] = c[2];
+    }
     const double z = a.z[i];
     if (z == 0.0) return;
-    const int lane = threadIdx.x & 63;
-    const int s = a.parts[i].sys;
-    const SysDev &S = a.sys[s];
+    const SysDev &S = a.sys[pd.sys];
     const int K = a.K;
     int b[3];
     double v[3][P], dv[P];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int k = 0; k < 3; ++k) {
         double w;
-        grid_coord(a.cpos[3LL * i + c], S.box[c], K, b[c], w);
-        bspline<P>(w, v[c], dv);
+        grid_coord(c[k], S.box[k], K, b[k], w);
+        bspline<P>(w, v[k], dv);
     }
     if (lane >= P * P) return;
     const int ja = lane / P, jb = lane % P;
@@ -146,7 +134,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_spread(EwaldLaunch a)
         vy = j == jb ? v[1][j] : vy;
     }
     const double zxy = z * vx * vy * a.scale;
-    unsigned long long *g = (unsigned long long *)a.grid_i + (long long)s * K * K * K +
+    unsigned long long *g = (unsigned long long *)a.grid_i + (long long)pd.sys * K * K * K +
                             ((long long)wrap(b[0] - ja, K) * K + wrap(b[1] - jb, K)) * K;
 #pragma unroll
     for (int jc = 0; jc < P; ++jc) {
@@ -155,105 +143,152 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_spread(EwaldLaunch a)
     }
 }
 
-// ---- 3D FFT: kFftLines lines of K points per workgroup ------------------------
-// axis 2 (z): lines (x, y), contiguous; axis 1 (y): lines (x, z), stride K;
-// axis 0 (x): lines (y, z), stride K^2.  For axes 0 and 1 the workgroup's
-// lines are kFftLines consecutive z, so every point row is one contiguous
-// 256-byte run.  Radix-2 decimation in time from bit-reversed LDS order;
-// sign -1 forward (exp(-2 pi i jk / K)), +1 inverse (unnormalised).
-__global__ __launch_bounds__(kEwThreads) void k_ew_fft(EwaldLaunch a, int axis, int sign,
-                                                       int from_fixed)
+// ---- FFT building blocks in LDS ------------------------------------------------
+__device__ __forceinline__ int bitrev(int x, int logK)
 {
-    extern __shared__ double2 lds_fft[];
-    const int K = a.K, logK = a.logK;
-    const long long K2 = (long long)K * K;
-    const int groups = (int)(K2 / kFftLines);
-    const int s = blockIdx.x / groups;
-    const int g = blockIdx.x % groups;
-    double2 *data = a.grid_c + (long long)s * K2 * K;
-    const long long *fixed = a.grid_i + (long long)s * K2 * K;
-    long long base0;
-    long long lstep, stride;
-    if (axis == 2) {
-        base0 = (long long)g * kFftLines * K;
-        lstep = K;
-        stride = 1;
-    } else {
-        const int outer = g / (K / kFftLines), z0 = (g % (K / kFftLines)) * kFftLines;
-        base0 = (axis == 1 ? (long long)outer * K2 : (long long)outer * K) + z0;
-        lstep = 1;
-        stride = axis == 1 ? K : K2;
-    }
-    const int tot = kFftLines * K;
-    for (int e = threadIdx.x; e < tot; e += kEwThreads) {
-        int li, pt;
-        if (axis == 2) {
-            li = e / K;
-            pt = e % K;
-        } else {
-            li = e % kFftLines;
-            pt = e / kFftLines;
-        }
-        const long long addr = base0 + li * lstep + pt * stride;
-        double2 x;
-        if (from_fixed) {
-            x.x = (double)fixed[addr] * a.inv_scale;
-            x.y = 0.0;
-        } else {
-            x = data[addr];
-        }
-        const int rev = (int)(__builtin_bitreverse32((unsigned)pt) >> (32 - logK));
-        lds_fft[li * K + rev] = x;
-    }
-    __syncthreads();
-    const int half_tot = tot / 2;
+    return (int)(__builtin_bitreverse32((unsigned)x) >> (32 - logK));
+}
+
+__device__ __forceinline__ void butterfly(double2 *x0, double2 *x1, double2 w)
+{
+    const double2 u = *x0, v = *x1;
+    const double tr = w.x * v.x - w.y * v.y, ti = w.x * v.y + w.y * v.x;
+    *x0 = make_double2(u.x + tr, u.y + ti);
+    *x1 = make_double2(u.x - tr, u.y - ti);
+}
+
+// twiddle exp(sign 2 pi i pos / m) from the table exp(-2 pi i j / K)
+__device__ __forceinline__ double2 twiddle(const double2 *tw, int pos, int m, int K, int sign)
+{
+    double2 w = tw[pos * (K / m)];
+    if (sign > 0) w.y = -w.y;
+    return w;
+}
+
+// Radix-2 passes over `lines` lines of K points held in bit-reversed order:
+// point p of line l at buf[l * lstride + p * pstride].  With line_fast the
+// threads of a wave take consecutive lines at one butterfly position (use
+// when lstride is 1), otherwise consecutive positions of one line (use when
+// pstride is 1), so a wave's LDS accesses stay contiguous.
+__device__ void fft_lines(double2 *buf, int lines, int lstride, int pstride, bool line_fast,
+                          int K, int logK, const double2 *tw, int sign)
+{
+    const int half = K / 2, nb = lines * half;
     for (int st = 1; st <= logK; ++st) {
         const int m = 1 << st, h = m >> 1;
-        for (int bfly = threadIdx.x; bfly < half_tot; bfly += kEwThreads) {
-            const int li = bfly / (K / 2), bb = bfly % (K / 2);
+        for (int t = threadIdx.x; t < nb; t += kEwThreads) {
+            const int l = line_fast ? t % lines : t / half;
+            const int bb = line_fast ? t / lines : t % half;
             const int grp = bb / h, pos = bb % h;
-            const int i0 = li * K + grp * m + pos, i1 = i0 + h;
-            double2 w = a.tw[pos * (K / m)];
-            w.y *= sign == -1 ? 1.0 : -1.0;   // table holds exp(-2 pi i j / K)
-            const double2 u = lds_fft[i0], v = lds_fft[i1];
-            const double tr = w.x * v.x - w.y * v.y, ti = w.x * v.y + w.y * v.x;
-            lds_fft[i0] = make_double2(u.x + tr, u.y + ti);
-            lds_fft[i1] = make_double2(u.x - tr, u.y - ti);
+            const int p0 = grp * m + pos;
+            double2 *x0 = buf + l * lstride + p0 * pstride;
+            butterfly(x0, x0 + h * pstride, twiddle(tw, pos, m, K, sign));
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < tot; e += kEwThreads) {
-        int li, pt;
-        if (axis == 2) {
-            li = e / K;
-            pt = e % K;
-        } else {
-            li = e % kFftLines;
-            pt = e / kFftLines;
+}
+
+// In-place bit-reversal of every line (pairs p < rev(p) swapped).
+__device__ void bitrev_lines(double2 *buf, int lines, int lstride, int pstride, bool line_fast,
+                             int K, int logK)
+{
+    for (int t = threadIdx.x; t < lines * K; t += kEwThreads) {
+        const int l = line_fast ? t % lines : t / K;
+        const int p = line_fast ? t / lines : t % K;
+        const int r = bitrev(p, logK);
+        if (p < r) {
+            double2 *a = buf + l * lstride + p * pstride, *b = buf + l * lstride + r * pstride;
+            const double2 x = *a;
+            *a = *b;
+            *b = x;
         }
-        data[base0 + li * lstep + pt * stride] = lds_fft[li * K + pt];
+    }
+    __syncthreads();
+}
+
+__device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot);
+
+// ---- 2D FFT of x-planes (and the real-space workgroups) -------------------------
+// Plane x of system s as P[y][z] (row stride K).  Forward: from the
+// fixed-point grid (cleared for the next call), FFT along z then y.
+// Inverse: y then z.
+__global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign)
+{
+    extern __shared__ double2 plane[];
+    const int K = a.K, logK = a.logK;
+    const int s = blockIdx.x / K, x = blockIdx.x % K;
+    const long long off = (long long)s * K * K * K + (long long)x * K * K;
+    double2 *data = a.grid_c + off;
+    const int ld = K;
+    if (sign < 0) {
+        long long *fixed = a.grid_i + off;
+        for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+            const int y = e / K, z = e % K;
+            plane[y * ld + bitrev(z, logK)] = make_double2((double)fixed[e] * a.inv_scale, 0.0);
+            fixed[e] = 0;
+        }
+        __syncthreads();
+        fft_lines(plane, K, ld, 1, false, K, logK, a.tw, sign);   // along z
+        bitrev_lines(plane, K, 1, ld, true, K, logK);
+        fft_lines(plane, K, 1, ld, true, K, logK, a.tw, sign);    // along y
+    } else {
+        for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+            const int y = e / K, z = e % K;
+            plane[bitrev(y, logK) * ld + z] = data[e];
+        }
+        __syncthreads();
+        fft_lines(plane, K, 1, ld, true, K, logK, a.tw, sign);    // along y
+        bitrev_lines(plane, K, ld, 1, false, K, logK);
+        fft_lines(plane, K, ld, 1, false, K, logK, a.tw, sign);   // along z
+    }
+    for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+        const int y = e / K, z = e % K;
+        data[e] = plane[y * ld + z];
     }
 }
 
-// ---- influence function and reciprocal energy ----------------------------------
-__global__ __launch_bounds__(kEwThreads) void k_ew_recip(EwaldLaunch a)
+// ---- x-lines: forward FFT, influence function and energy, inverse FFT ---------
+__global__ __launch_bounds__(kEwThreads) void k_ew_xline(EwaldLaunch a)
 {
-    const long long K3 = (long long)a.K * a.K * a.K;
-    const int s = blockIdx.x / a.recip_wg;
-    const int w = blockIdx.x % a.recip_wg;
-    const long long per = K3 / a.recip_wg;
-    double2 *data = a.grid_c + (long long)s * K3;
-    const double *G = a.G + (long long)s * K3;
-    double e = 0.0;
-    for (long long k = w * per + threadIdx.x; k < (w + 1) * per; k += kEwThreads) {
-        const double2 f = data[k];
-        const double gk = G[k];
-        e += gk * (f.x * f.x + f.y * f.y);
-        data[k] = make_double2(gk * f.x, gk * f.y);
+    extern __shared__ double2 xl[];
+    const int K = a.K, logK = a.logK;
+    const int groups = K * K / kFftLines;
+    if ((int)blockIdx.x >= a.n_sys * groups) {
+        const int k = blockIdx.x - a.n_sys * groups;
+        real_space(a, a.real_items[k], k);
+        return;
+    }
+    const int s = blockIdx.x / groups, g = blockIdx.x % groups;
+    const int y = g / (K / kFftLines), z0 = (g % (K / kFftLines)) * kFftLines;
+    const long long K2 = (long long)K * K;
+    const long long base = (long long)s * K2 * K + (long long)y * K + z0;
+    double2 *data = a.grid_c + base;
+    const double *G = a.G + base;
+    // xl[l][x], line l = z0 + l, row stride K
+    for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
+        const int l = e % kFftLines, x = e / kFftLines;
+        xl[l * K + bitrev(x, logK)] = data[x * K2 + l];
+    }
+    __syncthreads();
+    fft_lines(xl, kFftLines, K, 1, false, K, logK, a.tw, -1);
+    double en = 0.0;
+    for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
+        const int l = e % kFftLines, x = e / kFftLines;
+        const double gk = G[x * K2 + l];
+        const double2 f = xl[l * K + x];
+        en += gk * (f.x * f.x + f.y * f.y);
+        xl[l * K + x] = make_double2(gk * f.x, gk * f.y);
+    }
+    __syncthreads();
+    bitrev_lines(xl, kFftLines, K, 1, false, K, logK);
+    fft_lines(xl, kFftLines, K, 1, false, K, logK, a.tw, 1);
+    for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
+        const int l = e % kFftLines, x = e / kFftLines;
+        data[x * K2 + l] = xl[l * K + x];
     }
     __shared__ double red[kEwThreads / 64];
-    e = wave_sum(e);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    en = wave_sum(en);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = en;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
@@ -263,13 +298,25 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_recip(EwaldLaunch a)
 }
 
 // ---- real space ---------------------------------------------------------------
-__global__ __launch_bounds__(kEwThreads) void k_ew_real(EwaldLaunch a)
+// Workgroup = (64-particle i-tile, kEwChunk-particle j-chunk) of one system;
+// wave w takes j-slots [w, w + 4, ...) of the chunk against its lane's i.
+// Partial forces go to part[chunk][i]; the gather sums the chunks in order.
+__device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot)
 {
-    const BlockRange rg = a.real_ranges[blockIdx.x];
-    const SysDev &S = a.sys[rg.sys];
-    const int p0 = a.sys_part[rg.sys], p1 = a.sys_part[rg.sys + 1];
-    const int i = rg.begin + (int)threadIdx.x;
-    const bool vi = (int)threadIdx.x < rg.count;
+    const SysDev &S = a.sys[it.sys];
+    const int lane = threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    const int i = it.i0 + lane;
+    const bool vi = lane < it.ni;
+    __shared__ double sx[kEwChunk], sy[kEwChunk], sz[kEwChunk], sq[kEwChunk];
+    __shared__ int sm[kEwChunk];
+    for (int t = threadIdx.x; t < it.nj; t += kEwThreads) {
+        const int j = it.j0 + t;
+        sx[t] = a.cpos[3LL * j];
+        sy[t] = a.cpos[3LL * j + 1];
+        sz[t] = a.cpos[3LL * j + 2];
+        sq[t] = a.z[j];
+        sm[t] = a.mol[j];
+    }
     double xi = 0, yi = 0, zi = 0, qi = 0;
     int mi = -1;
     if (vi) {
@@ -279,27 +326,14 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_real(EwaldLaunch a)
         qi = a.z[i];
         mi = a.mol[i];
     }
-    __shared__ double sx[kEwThreads], sy[kEwThreads], sz[kEwThreads], sq[kEwThreads];
-    __shared__ int sm[kEwThreads];
+    __syncthreads();
     const double alpha = a.alpha, rc2 = a.r_cut * a.r_cut;
     const double two_a_rpi = 2.0 * alpha / sqrt(kPi);
     double fx = 0, fy = 0, fz = 0, e = 0;
-    for (int j0 = p0; j0 < p1; j0 += kEwThreads) {
-        const int j = j0 + (int)threadIdx.x;
-        __syncthreads();
-        if (j < p1) {
-            sx[threadIdx.x] = a.cpos[3LL * j];
-            sy[threadIdx.x] = a.cpos[3LL * j + 1];
-            sz[threadIdx.x] = a.cpos[3LL * j + 2];
-            sq[threadIdx.x] = a.z[j];
-            sm[threadIdx.x] = a.mol[j];
-        }
-        __syncthreads();
-        const int jn = min(kEwThreads, p1 - j0);
-        if (!vi || qi == 0.0) continue;
-        for (int t = 0; t < jn; ++t) {
+    if (vi && qi != 0.0) {
+        for (int t = wv; t < it.nj; t += kEwThreads / 64) {
             const double qq = qi * sq[t];
-            if (qq == 0.0 || j0 + t == i) continue;
+            if (qq == 0.0 || it.j0 + t == i) continue;
             double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
             dx -= S.box[0] * rint(dx * S.ibox[0]);
             dy -= S.box[1] * rint(dy * S.ibox[1]);
@@ -325,32 +359,63 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_real(EwaldLaunch a)
             fz += g * dz;
         }
     }
-    if (vi) {
-        a.freal[3LL * i] = fx;
-        a.freal[3LL * i + 1] = fy;
-        a.freal[3LL * i + 2] = fz;
+    // the four waves' partial forces in a fixed order
+    __shared__ double pf[kEwThreads / 64 - 1][64][3];
+    if (wv > 0) {
+        pf[wv - 1][lane][0] = fx;
+        pf[wv - 1][lane][1] = fy;
+        pf[wv - 1][lane][2] = fz;
     }
     __shared__ double red[kEwThreads / 64];
     e = wave_sum(e);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    if (lane == 0) red[wv] = e;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < kEwThreads / 64; ++k) t += red[k];
-        a.e_real_part[blockIdx.x] = t;
+    if (wv == 0) {
+        for (int w = 0; w < kEwThreads / 64 - 1; ++w) {
+            fx += pf[w][lane][0];
+            fy += pf[w][lane][1];
+            fz += pf[w][lane][2];
+        }
+        if (vi) {
+            double *dst = a.freal + ((long long)it.chunk * a.n_part + i) * 3;
+            dst[0] = fx;
+            dst[1] = fy;
+            dst[2] = fz;
+        }
+        if (lane == 0) {
+            double t = 0.0;
+            for (int k = 0; k < kEwThreads / 64; ++k) t += red[k];
+            a.e_real_part[slot] = t;
+        }
     }
 }
 
 // ---- force gather and bead forces ---------------------------------------------
+__device__ void reduce_energies(const EwaldLaunch &a, int s);
+
 template <int P>
 __global__ __launch_bounds__(kEwThreads) void k_ew_gather(EwaldLaunch a)
 {
-    const int i = blockIdx.x * (kEwThreads / 64) + ((int)threadIdx.x >> 6);
+    const int per = kEwThreads / 64;
+    const int pblocks = (a.n_part + per - 1) / per;
+    if ((int)blockIdx.x >= pblocks) {
+        if (threadIdx.x < 64) reduce_energies(a, blockIdx.x - pblocks);
+        return;
+    }
+    const int i = blockIdx.x * per + ((int)threadIdx.x >> 6);
     if (i >= a.n_part) return;
     const int lane = threadIdx.x & 63;
     const PartDev pd = a.parts[i];
     const double z = a.z[i];
-    double F[3] = {a.freal[3LL * i], a.freal[3LL * i + 1], a.freal[3LL * i + 2]};
+    double F[3] = {0.0, 0.0, 0.0};
+    const int ns = a.sys_part[pd.sys + 1] - a.sys_part[pd.sys];
+    const int nch = (ns + kEwChunk - 1) / kEwChunk;
+    for (int c = 0; c < nch; ++c) {
+        const double *src = a.freal + ((long long)c * a.n_part + i) * 3;
+        F[0] += src[0];
+        F[1] += src[1];
+        F[2] += src[2];
+    }
     if (z != 0.0) {
         const SysDev &S = a.sys[pd.sys];
         const int K = a.K;
@@ -406,10 +471,9 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_gather(EwaldLaunch a)
     }
 }
 
-// ---- per-system energies ------------------------------------------------------
-__global__ __launch_bounds__(64) void k_ew_reduce(EwaldLaunch a)
+// ---- per-system energies (first wave of an extra gather workgroup) --------------
+__device__ void reduce_energies(const EwaldLaunch &a, int s)
 {
-    const int s = blockIdx.x;
     const int lane = threadIdx.x;
     double er = 0.0, ek = 0.0;
     for (int k = a.real_first[s] + lane; k < a.real_first[s + 1]; k += 64) er += a.e_real_part[k];
@@ -428,19 +492,15 @@ void launch_order(const EwaldLaunch &a, hipStream_t st)
 {
     const int per = kEwThreads / 64;
     const int pblocks = (a.n_part + per - 1) / per;
+    const int K = a.K;
     hipLaunchKernelGGL(k_ew_spread<P>, dim3(pblocks), dim3(kEwThreads), 0, st, a);
-    const int groups = a.K * a.K / kFftLines * a.n_sys;
-    const size_t lds = sizeof(double2) * kFftLines * a.K;
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 2, -1, 1);
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 1, -1, 0);
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 0, -1, 0);
-    hipLaunchKernelGGL(k_ew_recip, dim3(a.n_sys * a.recip_wg), dim3(kEwThreads), 0, st, a);
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 0, 1, 0);
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 1, 1, 0);
-    hipLaunchKernelGGL(k_ew_fft, dim3(groups), dim3(kEwThreads), lds, st, a, 2, 1, 0);
-    hipLaunchKernelGGL(k_ew_real, dim3(a.n_real), dim3(kEwThreads), 0, st, a);
-    hipLaunchKernelGGL(k_ew_gather<P>, dim3(pblocks), dim3(kEwThreads), 0, st, a);
-    hipLaunchKernelGGL(k_ew_reduce, dim3(a.n_sys), dim3(64), 0, st, a);
+    const size_t plane_lds = sizeof(double2) * K * K;
+    hipLaunchKernelGGL(k_ew_plane, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, a, -1);
+    const int xgroups = a.n_sys * (K * K / kFftLines);
+    hipLaunchKernelGGL(k_ew_xline, dim3(xgroups + a.n_real), dim3(kEwThreads),
+                       sizeof(double2) * kFftLines * K, st, a);
+    hipLaunchKernelGGL(k_ew_plane, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, a, 1);
+    hipLaunchKernelGGL(k_ew_gather<P>, dim3(pblocks + a.n_sys), dim3(kEwThreads), 0, st, a);
 }
 
 }  // namespace
@@ -448,11 +508,6 @@ void launch_order(const EwaldLaunch &a, hipStream_t st)
 void launch_ewald(const EwaldLaunch &a, hipStream_t st)
 {
     if (a.n_part <= 0) return;
-    const long long ngrid = (long long)a.n_sys * a.K * a.K * a.K;
-    const long long want = std::max<long long>((ngrid + kEwThreads - 1) / kEwThreads,
-                                               ((long long)a.n_part * 64 + kEwThreads - 1) / kEwThreads);
-    const int blocks = (int)std::min<long long>(want, 16384);
-    hipLaunchKernelGGL(k_ew_prep, dim3(blocks), dim3(kEwThreads), 0, st, a);
     switch (a.order) {
     case 4: launch_order<4>(a, st); break;
     case 6: launch_order<6>(a, st); break;

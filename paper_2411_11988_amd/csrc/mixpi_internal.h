@@ -278,6 +278,13 @@ struct TcfLaunch {
 };
 void launch_tcf(const TcfLaunch &a, const double *p, hipStream_t st);
 
+// Real-space Ewald work item: particles [i0, i0 + ni) against the j-chunk
+// [j0, j0 + nj) (chunk-th kEwChunk-particle chunk of the system).
+constexpr int kEwChunk = 128;
+struct RealItem {
+    int sys, i0, ni, j0, nj, chunk;
+};
+
 // Centroid Ewald electrostatics (all systems of a handle, one grid each).
 struct EwaldLaunch {
     const PartDev *parts;
@@ -287,15 +294,16 @@ struct EwaldLaunch {
     const int *mol;
     const double *q;             // bead rows
     double *f;                   // bead rows, added to (may be null)
-    double *cpos, *freal, *fcent;   // [n_part][3]
+    double *cpos, *fcent;        // [n_part][3]
+    double *freal;               // [max chunks][n_part][3] real-space partials
     long long *grid_i;           // [n_sys][K^3] fixed-point charge grid
     double2 *grid_c;             // [n_sys][K^3]
     const double *G;             // [n_sys][K^3] influence function B C
     const double2 *tw;           // exp(-2 pi i j / K), j < K/2
     double *e_real_part;         // [n_real]
     double *e_recip_part;        // [n_sys][recip_wg]
-    const BlockRange *real_ranges;
-    const int *real_first;       // [n_sys + 1] first real range of each system
+    const RealItem *real_items;
+    const int *real_first;       // [n_sys + 1] first real item of each system
     const double *e_const;       // [n_sys] self + background
     double *e_out;               // [n_sys][3]
     double alpha, r_cut, scale, inv_scale;

@@ -67,7 +67,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("K,order", [(16, 4), (32, 6), (32, 8)])
+@pytest.mark.parametrize("K,order", [(16, 4), (32, 6), (32, 8), (64, 6)])
 @pytest.mark.parametrize("name,make,alpha", CASES, ids=[c[0] for c in CASES])
 def test_ewald_matches_oracle_spme(mp, name, make, alpha, K, order):
     s = make()
@@ -192,7 +192,7 @@ def test_ewald_rejects_bad_arguments(mp):
     with pytest.raises(mp.MixPIError) as e:
         sysm.ewald(q)
     assert e.value.code == mp.MIXPI_E_INVALID
-    for args in ((0.0, 4.0, 32, 6), (0.5, 6.0, 32, 6), (0.5, 4.0, 24, 6), (0.5, 4.0, 256, 6),
+    for args in ((0.0, 4.0, 32, 6), (0.5, 6.0, 32, 6), (0.5, 4.0, 24, 6), (0.5, 4.0, 128, 6),
                  (0.5, 4.0, 32, 5), (0.5, -1.0, 32, 6)):
         with pytest.raises(mp.MixPIError) as e:
             sysm.set_ewald(*args)
