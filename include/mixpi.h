@@ -321,6 +321,20 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
  * configured, null q or e_out). */
 int mixpi_ewald(mixpi_system *sys, const double *q, double *f, double *e_out, void *stream);
 
+/* Switches the centroid Ewald electrostatics configured by mixpi_set_ewald
+ * into (on != 0) or out of (on = 0) the handle's force passes: with it on,
+ * mixpi_forces, mixpi_energy, mixpi_step, mixpi_step_nvt and mixpi_step_vv
+ * add the Ewald bead forces to F and the Ewald energy (real + reciprocal +
+ * constant) to V_Coul and V_mix of their energies and logs, so the
+ * dynamics run on V_mix + V_Ewald(centroids) (Sec. "Theory").  Use it with
+ * rc_coul = 0, or the atom-atom electrostatics count twice.  While on,
+ * mixpi_energy_adjoint and mixpi_kernel_time return MIXPI_E_UNSUPPORTED.
+ * Forces of mixpi_forces equal the pair forces plus those of mixpi_ewald,
+ * bit for bit, and the steps use the same sum.  Drops the handle's captured
+ * step graphs when the setting changes (so does mixpi_set_ewald).
+ * Synchronous.  Errors: MIXPI_E_INVALID (on without mixpi_set_ewald). */
+int mixpi_use_ewald(mixpi_system *sys, int32_t on);
+
 /* Candidate slice-pairs of one force evaluation: every unordered,
  * non-excluded particle pair times N_max of the pair, summed over systems
  * (from the work lists; no device work). */

@@ -395,6 +395,50 @@ class OracleSystem:
                            float(tau0), _p(elog))
         return q, p, F, elog
 
+    def step_extra(self, q, p, nsteps: int, extra, mode: str = "nve", noise=None,
+                   tau0: float = float("inf")):
+        """The oracle's split-propagator step ("nve"), velocity Verlet ("vv")
+        or thermostatted step ("nvt", noise [nsteps][2][B][3]) with an extra
+        potential term: extra(q) -> (bead forces, energy) is added to the
+        forces and to V_Coul and V_mix of the logged energies.  Composed from
+        the oracle's forces, free propagation, springs, PILE and observables
+        in the order of orc_step / orc_step_vv / orc_step_nvt.  Returns
+        (q, p, F, elog[nsteps, E_N])."""
+        q = np.array(q, dtype=np.float64, copy=True)
+        p = np.array(p, dtype=np.float64, copy=True)
+        dt = float(self.src.dt)
+        kick = 0.5 * dt * constants()["kcal"]
+        ic, iv = E_NAMES.index("coul"), E_NAMES.index("vmix")
+
+        def force(x):
+            F, v = self.forces(x)
+            Fe, ee = extra(x)
+            v = np.array(v, dtype=np.float64, copy=True)
+            v[ic] += ee
+            v[iv] += ee
+            return F + Fe, v
+
+        F, _ = force(q)
+        elog = np.zeros((nsteps, E_N))
+        fm = np.repeat(self.fm, self.nb)[:, None]
+        for k in range(nsteps):
+            if mode == "nvt":
+                p = self.pile(p, noise[k, 0], 0.5 * dt, tau0)
+            if mode == "vv":
+                p = p + kick * (F + self.springs(q)[1])
+                q = q + dt * p / fm
+                F, v = force(q)
+                p = p + kick * (F + self.springs(q)[1])
+            else:
+                p = p + kick * F
+                q, p = self.free_propagate(q, p, dt)
+                F, v = force(q)
+                p = p + kick * F
+            elog[k] = self.observables(q, p, F, v)
+            if mode == "nvt":
+                p = self.pile(p, noise[k, 1], 0.5 * dt, tau0)
+        return q, p, F, elog
+
     @property
     def beta(self) -> float:
         return lib().orc_beta(self.ptr)

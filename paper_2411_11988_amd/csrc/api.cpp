@@ -117,6 +117,7 @@ struct mixpi_system {
         double alpha = 0, r_cut = 0, scale = 1;
         int K = 0, logK = 0, order = 0, recip_wg = 1, n_real = 0;
         double *z = nullptr, *cpos = nullptr, *freal = nullptr, *fcent = nullptr, *G = nullptr;
+        double *rowf = nullptr;   // [rows][3] bead forces for the step's epilogue
         long long *grid_i = nullptr;
         double2 *grid_c = nullptr, *tw = nullptr;
         double *e_real_part = nullptr, *e_recip_part = nullptr, *e_const = nullptr;
@@ -165,6 +166,12 @@ struct mixpi_system {
     int *d_red_v = nullptr;                       // the same for velocity-Verlet steps
     int red_f_off[3] = {0, 0, 0}, red_a_off[3] = {0, 0, 0}, red_v_off[3] = {0, 0, 0};
     int nch_f = 0, nch_a = 0, nch_v = 0;          // chunks of each list
+    // the same three lists with the centroid-Ewald slots (one per system)
+    int *d_red_fE = nullptr, *d_red_aE = nullptr, *d_red_vE = nullptr;
+    int red_fE_off[3] = {0, 0, 0}, red_aE_off[3] = {0, 0, 0}, red_vE_off[3] = {0, 0, 0};
+    int nch_fE = 0, nch_aE = 0, nch_vE = 0;
+    int e_ew = 0;                                 // first centroid-Ewald slot
+    bool ew_use = false;                          // mixpi_use_ewald
     long long *d_row_prev = nullptr, *d_row_next = nullptr;
     double *d_row_ksp = nullptr;
     double *d_partial = nullptr;      // [max chunks][A_N] stage-A sums
@@ -180,10 +187,21 @@ struct mixpi_system {
 
 namespace {
 
+// Drops every captured step graph (their launches hold pointers and
+// settings that are about to change).
+void clear_graphs(mixpi_system *s)
+{
+    for (auto &g : s->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    s->graphs.clear();
+}
+
 void release_ewald(mixpi_system *s)
 {
     auto &e = s->ew;
-    void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.grid_i, e.grid_c, e.tw,
+    void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.grid_i, e.grid_c, e.tw, e.rowf,
                     e.e_real_part, e.e_recip_part, e.e_const, e.real_items, e.real_first};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -207,7 +225,8 @@ void release(mixpi_system *s)
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch,
-                    s->d_rdf_ranges, s->d_parts, s->d_sys_part};
+                    s->d_rdf_ranges, s->d_parts, s->d_sys_part, s->d_red_fE, s->d_red_aE,
+                    s->d_red_vE};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -954,8 +973,10 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->e_bonded = S->n_items;
     S->e_rp = S->e_bonded + S->n_bblocks;
     S->e_fin = S->e_rp + S->n_rp;
-    S->n_eslots = S->e_fin + S->n_fblocks;
+    S->e_ew = S->e_fin + S->n_fblocks;           // one centroid-Ewald slot per system
+    S->n_eslots = S->e_ew + n_sys;
     std::vector<int> eslot_sys(S->n_eslots);
+    for (int s = 0; s < n_sys; ++s) eslot_sys[S->e_ew + s] = s;
     for (int k = 0; k < S->n_items; ++k) eslot_sys[k] = B.blocks[items[k].block].sys;
     for (int b = 0; b < S->n_bblocks; ++b) eslot_sys[S->e_bonded + b] = bblocks[b].sys;
     for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
@@ -976,12 +997,18 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         S->n_rdf_ranges = (int)rdf_ranges.size();
     }
     // per-system slot lists (stable order) for the reducer
-    std::vector<int> red_f, red_a;
+    // (the "E" plans add the centroid-Ewald slots, used while it is switched on)
+    std::vector<int> red_f, red_a, red_fE, red_aE;
+    const std::pair<int, int> ew_range{S->e_ew, S->n_eslots};
     S->nch_f = reducer_plan(eslot_sys, {{0, S->e_rp}}, n_sys, red_f, S->red_f_off);
-    S->nch_a = reducer_plan(eslot_sys, {{0, S->n_eslots}}, n_sys, red_a, S->red_a_off);
-    std::vector<int> red_v;   // velocity Verlet: no ring-polymer slots
-    S->nch_v = reducer_plan(eslot_sys, {{0, S->e_rp}, {S->e_fin, S->n_eslots}}, n_sys, red_v,
+    S->nch_a = reducer_plan(eslot_sys, {{0, S->e_ew}}, n_sys, red_a, S->red_a_off);
+    S->nch_fE = reducer_plan(eslot_sys, {{0, S->e_rp}, ew_range}, n_sys, red_fE, S->red_fE_off);
+    S->nch_aE = reducer_plan(eslot_sys, {{0, S->e_ew}, ew_range}, n_sys, red_aE, S->red_aE_off);
+    std::vector<int> red_v, red_vE;   // velocity Verlet: no ring-polymer slots
+    S->nch_v = reducer_plan(eslot_sys, {{0, S->e_rp}, {S->e_fin, S->e_ew}}, n_sys, red_v,
                             S->red_v_off);
+    S->nch_vE = reducer_plan(eslot_sys, {{0, S->e_rp}, {S->e_fin, S->e_ew}, ew_range}, n_sys,
+                             red_vE, S->red_vE_off);
 
     int rc = MIXPI_OK;
     auto T = [&](int r) {
@@ -1035,10 +1062,16 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_red_f, red_f));
     T(upload(&S->d_red_a, red_a));
     T(upload(&S->d_red_v, red_v));
+    T(upload(&S->d_red_fE, red_fE));
+    T(upload(&S->d_red_aE, red_aE));
+    T(upload(&S->d_red_vE, red_vE));
     T(upload(&S->d_row_prev, B.row_prev));
     T(upload(&S->d_row_next, B.row_next));
     T(upload(&S->d_row_ksp, B.row_ksp));
-    T(upload(&S->d_partial, std::vector<double>((size_t)A_N * std::max(1, std::max(S->nch_v, std::max(S->nch_f, S->nch_a))), 0.0)));
+    {
+        const int nch = std::max({1, S->nch_v, S->nch_f, S->nch_a, S->nch_vE, S->nch_fE, S->nch_aE});
+        T(upload(&S->d_partial, std::vector<double>((size_t)A_N * nch, 0.0)));
+    }
     T(upload(&S->d_npairs, std::vector<unsigned long long>(2, 0ull)));
     T(upload(&S->d_nonfinite, std::vector<int>(1, 0)));
     T(upload(&S->d_cent, std::vector<double>((size_t)3 * B.rows, 0.0)));
@@ -1131,6 +1164,13 @@ GatherArgs gather_args(mixpi_system *s)
 enum { LIST_FORCE = 0, LIST_STEP = 1, LIST_VV = 2 };
 const int *plan_of(mixpi_system *s, int list, const int **off, int *n)
 {
+    if (s->ew_use) {
+        if (list == LIST_STEP) { *off = s->red_aE_off; *n = s->nch_aE; return s->d_red_aE; }
+        if (list == LIST_VV) { *off = s->red_vE_off; *n = s->nch_vE; return s->d_red_vE; }
+        *off = s->red_fE_off;
+        *n = s->nch_fE;
+        return s->d_red_fE;
+    }
     if (list == LIST_STEP) { *off = s->red_a_off; *n = s->nch_a; return s->d_red_a; }
     if (list == LIST_VV) { *off = s->red_v_off; *n = s->nch_v; return s->d_red_v; }
     *off = s->red_f_off;
@@ -1166,6 +1206,56 @@ ReduceB reduce_b_args(mixpi_system *s, int list)
     return r;
 }
 
+// Centroid-Ewald launch arguments for positions q (outputs left unset).
+EwaldLaunch ewald_args(mixpi_system *sys, const double *q)
+{
+    const auto &e = sys->ew;
+    EwaldLaunch a{};
+    a.parts = sys->d_parts;
+    a.sys = sys->d_sys;
+    a.sys_part = sys->d_sys_part;
+    a.z = e.z;
+    a.mol = sys->d_mol;
+    a.q = q;
+    a.cpos = e.cpos;
+    a.freal = e.freal;
+    a.fcent = e.fcent;
+    a.grid_i = e.grid_i;
+    a.grid_c = e.grid_c;
+    a.G = e.G;
+    a.tw = e.tw;
+    a.e_real_part = e.e_real_part;
+    a.e_recip_part = e.e_recip_part;
+    a.real_items = e.real_items;
+    a.real_first = e.real_first;
+    a.e_const = e.e_const;
+    a.alpha = e.alpha;
+    a.r_cut = e.r_cut;
+    a.scale = e.scale;
+    a.inv_scale = 1.0 / e.scale;
+    a.K = e.K;
+    a.logK = e.logK;
+    a.order = e.order;
+    a.n_part = sys->n_part;
+    a.n_sys = sys->n_sys;
+    a.recip_wg = e.recip_wg;
+    a.n_real = e.n_real;
+    return a;
+}
+
+// The centroid-Ewald terms inside a force, energy or step pass: energies
+// into the system's Ewald slot of buffer buf; bead forces added to f, or
+// (step epilogue) written per row for the epilogue to add.
+void enqueue_ewald_in_pass(mixpi_system *s, const double *q, double *f, int buf, bool rows,
+                           hipStream_t st)
+{
+    EwaldLaunch a = ewald_args(s, q);
+    a.f = rows ? nullptr : f;
+    a.rowf = rows ? s->ew.rowf : nullptr;
+    a.eslot_out = eslot_buf(s, buf) + (long long)s->e_ew * A_N;
+    launch_ewald(a, st);
+}
+
 // Enqueues F(q): pair and bonded partials, then the per-row gather into f.
 // The energy slots of the pair and bonded ranges are left for a reducer.
 void enqueue_forces(mixpi_system *s, const double *q, const double *theta, double *f,
@@ -1173,6 +1263,7 @@ void enqueue_forces(mixpi_system *s, const double *q, const double *theta, doubl
 {
     launch_pair(pair_args(s, q, theta), bonded_args(s, q, theta), s->precision, with_theta, st);
     launch_gather(gather_args(s), s->rows, f, st);
+    if (s->ew_use) enqueue_ewald_in_pass(s, q, f, 0, false, st);
 }
 
 int last_launch_error()
@@ -1281,6 +1372,10 @@ void enqueue_step(mixpi_system *s, int k, double *q, double *p, double *f, doubl
     launch_rp(r, st);
     launch_pair(pair_args(s, q, nullptr, buf), bonded_args(s, q, nullptr, buf), s->precision,
                 false, st);
+    if (s->ew_use) {
+        enqueue_ewald_in_pass(s, q, nullptr, buf, true, st);
+        fl.ew_rowf = s->ew.rowf;
+    }
     launch_finish(fl, st);
 }
 
@@ -1423,6 +1518,7 @@ int mixpi_energy(mixpi_system *sys, const double *q, const double *theta, double
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, false, st);
+    if (sys->ew_use) enqueue_ewald_in_pass(sys, q, nullptr, 0, false, st);
     ReduceB rb = reduce_b_args(sys, LIST_FORCE);
     rb.e_out = e_out;
     launch_reduce(reduce_a_args(sys, 0, LIST_FORCE), rb, st);
@@ -1435,6 +1531,9 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
     if (int rc = check_sys(sys)) return rc;
     if (!q) return fail(MIXPI_E_INVALID, "q must be non-null");
     if ((const void *)q == (const void *)dq) return fail(MIXPI_E_INVALID, "dq must not alias q");
+    if (sys->ew_use)
+        return fail(MIXPI_E_UNSUPPORTED, "the adjoint does not cover centroid Ewald terms "
+                                         "(mixpi_use_ewald(sys, 0) first)");
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, true, st);
@@ -1556,6 +1655,9 @@ int mixpi_kernel_time(mixpi_system *sys, int32_t reps, const double *q, const do
     if (int rc = check_sys(sys)) return rc;
     if (reps < 1 || reps > 1000 || !q || !p || !f || !avg_us)
         return fail(MIXPI_E_INVALID, "bad arguments (reps must be in [1, 1000])");
+    if (sys->ew_use)
+        return fail(MIXPI_E_UNSUPPORTED, "the per-launch timer covers the three step launches only "
+                                         "(mixpi_use_ewald(sys, 0) first)");
     HIP_TRY(hipSetDevice(sys->device));
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes = sizeof(double) * 3 * sys->rows;
@@ -1718,6 +1820,9 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
                 return fail(MIXPI_E_INVALID, "system %d: r_cut %g exceeds half the box (%g)", s,
                             r_cut, sys->h_sys[s].box[k]);
     HIP_TRY(hipSetDevice(sys->device));
+    HIP_TRY(hipDeviceSynchronize());
+    clear_graphs(sys);
+    sys->ew_use = false;
     release_ewald(sys);
     auto &e = sys->ew;
     e.alpha = alpha;
@@ -1808,6 +1913,7 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     T(alloc(&e.cpos, np3));
     T(alloc(&e.freal, np3 * max_chunks));
     T(alloc(&e.fcent, np3));
+    T(alloc(&e.rowf, (size_t)3 * std::max<long long>(1, sys->rows)));
     T(alloc(&e.grid_i, (size_t)n_sys * K3));
     T(alloc(&e.grid_c, (size_t)n_sys * K3));
     T(alloc(&e.e_real_part, (size_t)std::max(1, e.n_real)));
@@ -1831,41 +1937,24 @@ int mixpi_ewald(mixpi_system *sys, const double *q, double *f, double *e_out, vo
     if (!sys->ew.on) return fail(MIXPI_E_INVALID, "call mixpi_set_ewald first");
     if (!q || !e_out) return fail(MIXPI_E_INVALID, "q or e_out is null");
     HIP_TRY(hipSetDevice(sys->device));
-    const auto &e = sys->ew;
-    EwaldLaunch a{};
-    a.parts = sys->d_parts;
-    a.sys = sys->d_sys;
-    a.sys_part = sys->d_sys_part;
-    a.z = e.z;
-    a.mol = sys->d_mol;
-    a.q = q;
+    EwaldLaunch a = ewald_args(sys, q);
     a.f = f;
-    a.cpos = e.cpos;
-    a.freal = e.freal;
-    a.fcent = e.fcent;
-    a.grid_i = e.grid_i;
-    a.grid_c = e.grid_c;
-    a.G = e.G;
-    a.tw = e.tw;
-    a.e_real_part = e.e_real_part;
-    a.e_recip_part = e.e_recip_part;
-    a.real_items = e.real_items;
-    a.real_first = e.real_first;
-    a.e_const = e.e_const;
     a.e_out = e_out;
-    a.alpha = e.alpha;
-    a.r_cut = e.r_cut;
-    a.scale = e.scale;
-    a.inv_scale = 1.0 / e.scale;
-    a.K = e.K;
-    a.logK = e.logK;
-    a.order = e.order;
-    a.n_part = sys->n_part;
-    a.n_sys = sys->n_sys;
-    a.recip_wg = e.recip_wg;
-    a.n_real = e.n_real;
     launch_ewald(a, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    return MIXPI_OK;
+}
+
+int mixpi_use_ewald(mixpi_system *sys, int32_t on)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (on && !sys->ew.on) return fail(MIXPI_E_INVALID, "call mixpi_set_ewald first");
+    HIP_TRY(hipSetDevice(sys->device));
+    if ((bool)on != sys->ew_use) {
+        HIP_TRY(hipDeviceSynchronize());
+        clear_graphs(sys);
+    }
+    sys->ew_use = on != 0;
     return MIXPI_OK;
 }
 

@@ -460,13 +460,19 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_gather(EwaldLaunch a)
         a.fcent[3LL * i + 1] = F[1];
         a.fcent[3LL * i + 2] = F[2];
     }
-    if (a.f) {
+    if (a.f || a.rowf) {
         const double inv = 1.0 / pd.nb;
         for (int j = lane; j < pd.nb; j += 64) {
             const long long r = pd.row0 + (long long)j * pd.stride;
-            a.f[3 * r] += F[0] * inv;
-            a.f[3 * r + 1] += F[1] * inv;
-            a.f[3 * r + 2] += F[2] * inv;
+            if (a.f) {
+                a.f[3 * r] += F[0] * inv;
+                a.f[3 * r + 1] += F[1] * inv;
+                a.f[3 * r + 2] += F[2] * inv;
+            } else {
+                a.rowf[3 * r] = F[0] * inv;
+                a.rowf[3 * r + 1] = F[1] * inv;
+                a.rowf[3 * r + 2] = F[2] * inv;
+            }
         }
     }
 }
@@ -480,10 +486,14 @@ __device__ void reduce_energies(const EwaldLaunch &a, int s)
     for (int k = lane; k < a.recip_wg; k += 64) ek += a.e_recip_part[(long long)s * a.recip_wg + k];
     er = wave_sum(er);
     ek = wave_sum(ek);
-    if (lane == 0) {
+    if (lane == 0 && a.e_out) {
         a.e_out[3 * s] = er;
         a.e_out[3 * s + 1] = ek;
         a.e_out[3 * s + 2] = a.e_const[s];
+    }
+    if (a.eslot_out && lane < A_N) {
+        // the system's energy slot: the whole Ewald energy as Coulomb energy
+        a.eslot_out[(long long)s * A_N + lane] = lane == A_COUL ? er + ek + a.e_const[s] : 0.0;
     }
 }
 

@@ -82,9 +82,11 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
             fsp = -k * (2.0 * q0 - qp - qn);
             if (lane < 3) esp = 0.5 * k * (q0 - qn) * (q0 - qn);
         }
+        const double few = a.ew_rowf && lane < 3 ? a.ew_rowf[x] : 0.0;
         const Vec3 fv = gather_row(a.gather, row);
         if (lane < 3) {
-            const double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
+            double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
+            if (a.ew_rowf) fx += few;
             a.f[x] = fx;
             const double pv = p0 + hk * (fx + fsp);
             a.p[x] = pv;

@@ -228,6 +228,7 @@ struct FinishLaunch {
     int vv;
     const long long *row_prev, *row_next;  // [rows] neighbour bead rows of the ring
     const double *row_ksp;                 // [rows] spring constant, kcal/mol/A^2
+    const double *ew_rowf;                 // [rows][3] centroid-Ewald force, added (may be null)
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);
 
@@ -294,6 +295,8 @@ struct EwaldLaunch {
     const int *mol;
     const double *q;             // bead rows
     double *f;                   // bead rows, added to (may be null)
+    double *rowf;                // bead rows, written: F_i / N_i (may be null)
+    double *eslot_out;           // energy slot row per system (may be null): A_COUL = total
     double *cpos, *fcent;        // [n_part][3]
     double *freal;               // [max chunks][n_part][3] real-space partials
     long long *grid_i;           // [n_sys][K^3] fixed-point charge grid
@@ -305,7 +308,7 @@ struct EwaldLaunch {
     const RealItem *real_items;
     const int *real_first;       // [n_sys + 1] first real item of each system
     const double *e_const;       // [n_sys] self + background
-    double *e_out;               // [n_sys][3]
+    double *e_out;               // [n_sys][3] (may be null)
     double alpha, r_cut, scale, inv_scale;
     int K, logK, order, n_part, n_sys, recip_wg, n_real;
 };

@@ -100,6 +100,7 @@ def load():
         "mixpi_vacf_sample": ([P, P, C.c_int64, I32, I32, P, P, P], C.c_int),
         "mixpi_set_ewald": ([P, C.c_double, C.c_double, I32, I32], C.c_int),
         "mixpi_ewald": ([P, P, P, P, P], C.c_int),
+        "mixpi_use_ewald": ([P, I32], C.c_int),
         "mixpi_set_thermostat": ([P, C.c_double], C.c_int),
         "mixpi_step_nvt": ([P, I32, P, P, P, P, P, P], C.c_int),
         "mixpi_step_vv": ([P, I32, P, P, P, P, P], C.c_int),
@@ -269,6 +270,10 @@ def mixpi_set_ewald(h, alpha: float, r_cut: float, grid: int, order: int):
     _check(load().mixpi_set_ewald(h, float(alpha), float(r_cut), int(grid), int(order)))
 
 
+def mixpi_use_ewald(h, on: bool):
+    _check(load().mixpi_use_ewald(h, int(bool(on))))
+
+
 def mixpi_ewald(h, q, f, e_out, stream=None):
     _check(load().mixpi_ewald(h, _ptr(q), _ptr(f), _ptr(e_out), _stream(stream)))
 
@@ -378,6 +383,9 @@ class System:
 
     def set_ewald(self, alpha: float, r_cut: float, grid: int, order: int):
         mixpi_set_ewald(self.h, alpha, r_cut, grid, order)
+
+    def use_ewald(self, on: bool = True):
+        mixpi_use_ewald(self.h, on)
 
     def ewald(self, q, f=None, e_out=None, stream=None):
         """Centroid Ewald energies [systems][3] (real, reciprocal, constant);

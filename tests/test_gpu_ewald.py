@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests._gpu import dev, force_err, from_rows, host, layout_rows, to_rows
+from tests._gpu import dev, energy_err, force_err, from_rows, host, layout_rows, to_rows
 from tests._systems import custom
 
 pytestmark = pytest.mark.gpu
@@ -197,3 +197,117 @@ def test_ewald_rejects_bad_arguments(mp):
         with pytest.raises(mp.MixPIError) as e:
             sysm.set_ewald(*args)
         assert e.value.code == mp.MIXPI_E_INVALID, args
+
+
+# ------------------------------------------------ centroid Ewald in the passes
+
+def _no_cut_coulomb(s):
+    return dataclasses.replace(s, rc_coul=0.0)
+
+
+EW = (0.6, 5.0, 32, 6)
+
+
+def _ew_extra(s):
+    """The oracle's centroid Ewald term (real space + SPME) as an extra
+    potential for oracle.step_extra."""
+    def extra(q):
+        s2 = dataclasses.replace(s, q=q)
+        F, e = oracle_spme(s2, *EW[:2], *EW[2:])
+        return F, float(e.sum())
+    return extra
+
+
+def test_forces_and_energy_with_ewald_switched_on(mp):
+    """mixpi_forces with the Ewald terms on = pair forces + mixpi_ewald, bit
+    for bit; the Ewald energy is part of V_Coul and V_mix."""
+    import torch
+    s = _no_cut_coulomb(synth.config_c1())
+    sysm = mp.System(s)
+    sysm.set_ewald(*EW)
+    q = dev(to_rows(s, s.q))
+    f0, e0 = sysm.forces(q)
+    eew = host(sysm.ewald(q, f0))
+    sysm.use_ewald(True)
+    f1, e1 = sysm.forces(q)
+    assert np.array_equal(host(f1), host(f0))
+    ic, iv = mp.E_NAMES.index("coul"), mp.E_NAMES.index("vmix")
+    tot = float(eew.sum())
+    e0, e1 = host(e0)[0], host(e1)[0]
+    assert e1[ic] == pytest.approx(e0[ic] + tot, rel=1e-12, abs=1e-9)
+    assert e1[iv] == pytest.approx(e0[iv] + tot, rel=1e-12, abs=1e-9)
+    e2 = host(sysm.energy(q))[0]
+    assert np.allclose(e2[:6], e1[:6], rtol=1e-13, atol=1e-10)
+    with pytest.raises(mp.MixPIError) as e:
+        sysm.energy_adjoint(q)
+    assert e.value.code == mp.MIXPI_E_UNSUPPORTED
+    sysm.use_ewald(False)
+    f3, _ = sysm.forces(q)
+    sysm2 = mp.System(s)
+    f4, _ = sysm2.forces(q)
+    assert np.array_equal(host(f3), host(f4))
+
+
+CASES_STEP = [
+    ("c1", synth.config_c1),
+    ("e256-water", lambda: synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4, rc_aa=6.0,
+                                                   n_h=2, n_o=1)),
+]
+
+
+@pytest.mark.parametrize("mode", ["nve", "vv", "nvt"])
+@pytest.mark.parametrize("name,make", CASES_STEP, ids=[c[0] for c in CASES_STEP])
+def test_steps_with_ewald_match_oracle(mp, name, make, mode):
+    """Three steps of each integrator with the centroid Ewald terms on,
+    against the oracle's steps with the same extra term."""
+    import torch
+    s = _no_cut_coulomb(make())
+    print(f"[ewald step] {name} {mode}", flush=True)
+    rows = layout_rows(s)
+    o = oracle.OracleSystem(s)
+    noise = np.random.default_rng(6).normal(size=(3, 2, len(rows), 3))
+    qo, po, _, elo = o.step_extra(s.q, s.p, 3, _ew_extra(s), mode=mode, noise=noise, tau0=30.0)
+    sysm = mp.System(s)
+    sysm.set_ewald(*EW)
+    sysm.use_ewald(True)
+    q, p = dev(to_rows(s, s.q, rows)), dev(to_rows(s, s.p, rows))
+    f, _ = sysm.forces(q)
+    elog = torch.zeros((3, 1, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+    if mode == "nve":
+        sysm.step(3, q, p, f, elog)
+    elif mode == "vv":
+        sysm.step_vv(3, q, p, f, elog)
+    else:
+        sysm.set_thermostat(30.0)
+        nz = np.empty_like(noise)
+        nz[:, :, rows, :] = noise
+        sysm.step_nvt(3, q, p, f, dev(nz), elog)
+    qg, pg = from_rows(s, host(q), rows), from_rows(s, host(p), rows)
+    assert np.abs(qg - qo).max() <= 1e-10
+    assert np.abs(pg - po).max() <= 1e-9 * np.abs(po).max()
+    el = host(elog)[:, 0, :]
+    for k in range(3):
+        assert energy_err(el[k], elo[k]) <= 1e-9, (k, el[k], elo[k])
+
+
+def test_ewald_step_graphs_follow_the_switch(mp):
+    """Steps with the terms on, then off: the second sequence equals a
+    handle that never had them (cached graphs are dropped on the switch)."""
+    import torch
+    s = _no_cut_coulomb(synth.config_c1())
+    a = mp.System(s)
+    a.set_ewald(*EW)
+    b = mp.System(s)
+    outs = []
+    for h, on in ((a, True), (a, False), (b, None)):
+        if on is not None:
+            h.use_ewald(on)
+        q, p = dev(to_rows(s, s.q)), dev(to_rows(s, s.p))
+        f, _ = h.forces(q)
+        h.step(4, q, p, f)
+        outs.append((host(q).copy(), host(p).copy()))
+    assert not np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[1][0], outs[2][0]) and np.array_equal(outs[1][1], outs[2][1])
+    with pytest.raises(mp.MixPIError) as e:
+        mp.mixpi_use_ewald(b.h, 1)
+    assert e.value.code == mp.MIXPI_E_INVALID

@@ -831,3 +831,28 @@ def test_spme_converges_to_the_ewald_reciprocal_sum():
         qm[b, k] -= 1e-5
         fd = -(o.spme_recip(qp, al, 16, 4)[1] - o.spme_recip(qm, al, 16, 4)[1]) / 2e-5
         assert F[b, k] == pytest.approx(fd, rel=1e-5, abs=1e-6)
+
+
+def test_step_extra_with_zero_term_equals_the_c_steps():
+    """The Python composition used for steps with an extra (centroid Ewald)
+    term reproduces orc_step, orc_step_vv and orc_step_nvt exactly in
+    structure: with a zero extra term, trajectories and logs agree to
+    rounding."""
+    s = synth.tiny_random(3, n_particles=12, box=9.0, bead_choices=(1, 2, 4, 8))
+    o = oracle.OracleSystem(s)
+
+    def zero(q):
+        return np.zeros_like(q), 0.0
+
+    noise = np.random.default_rng(4).normal(size=(3, 2, o.B, 3))
+    for mode in ("nve", "vv", "nvt"):
+        q1, p1, _, e1 = o.step_extra(s.q, s.p, 3, zero, mode=mode, noise=noise, tau0=20.0)
+        if mode == "nve":
+            q2, p2, _, e2 = o.step(s.q, s.p, 3)
+        elif mode == "vv":
+            q2, p2, _, e2 = o.step_vv(s.q, s.p, 3)
+        else:
+            q2, p2, _, e2 = o.step_nvt(s.q, s.p, noise, 20.0)
+        assert np.allclose(q1, q2, rtol=0, atol=1e-12), mode
+        assert np.allclose(p1, p2, rtol=1e-12, atol=1e-12), mode
+        assert np.allclose(e1, e2, rtol=1e-12, atol=1e-10), mode
