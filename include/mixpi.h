@@ -298,7 +298,7 @@ int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, 
  * box edge), a grid^3 reciprocal mesh (grid 16, 32 or 64)
  * and cardinal B-splines of order 4, 6 or 8 (Essmann et al., J. Chem. Phys.
  * 103, 8577 (1995)).  Builds the influence function on the host and
- * allocates the handle's Ewald buffers (32 grid^3 bytes per system plus
+ * allocates the handle's Ewald buffers (24 grid^3 bytes per system plus
  * O(particles)); a second call replaces the first.  Synchronous.  Errors:
  * MIXPI_E_INVALID (bad parameter), MIXPI_E_HIP. */
 int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid, int32_t order);

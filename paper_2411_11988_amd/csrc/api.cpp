@@ -118,7 +118,8 @@ struct mixpi_system {
         int K = 0, logK = 0, order = 0, recip_wg = 1, n_real = 0;
         double *z = nullptr, *cpos = nullptr, *freal = nullptr, *fcent = nullptr, *G = nullptr;
         double *rowf = nullptr;   // [rows][3] bead forces for the step's epilogue
-        long long *grid_i = nullptr;
+        int *spl_base = nullptr;
+        double *spl_w = nullptr;
         double2 *grid_c = nullptr, *tw = nullptr;
         double *e_real_part = nullptr, *e_recip_part = nullptr, *e_const = nullptr;
         RealItem *real_items = nullptr;
@@ -201,7 +202,7 @@ void clear_graphs(mixpi_system *s)
 void release_ewald(mixpi_system *s)
 {
     auto &e = s->ew;
-    void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.grid_i, e.grid_c, e.tw, e.rowf,
+    void *ptrs[] = {e.z, e.cpos, e.freal, e.fcent, e.G, e.spl_base, e.spl_w, e.grid_c, e.tw, e.rowf,
                     e.e_real_part, e.e_recip_part, e.e_const, e.real_items, e.real_first};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1220,7 +1221,8 @@ EwaldLaunch ewald_args(mixpi_system *sys, const double *q)
     a.cpos = e.cpos;
     a.freal = e.freal;
     a.fcent = e.fcent;
-    a.grid_i = e.grid_i;
+    a.spl_base = e.spl_base;
+    a.spl_w = e.spl_w;
     a.grid_c = e.grid_c;
     a.G = e.G;
     a.tw = e.tw;
@@ -1914,13 +1916,11 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     T(alloc(&e.freal, np3 * max_chunks));
     T(alloc(&e.fcent, np3));
     T(alloc(&e.rowf, (size_t)3 * std::max<long long>(1, sys->rows)));
-    T(alloc(&e.grid_i, (size_t)n_sys * K3));
+    T(alloc(&e.spl_base, (size_t)4 * std::max(1, sys->n_part)));
+    T(alloc(&e.spl_w, (size_t)3 * kMaxOrder * std::max(1, sys->n_part)));
     T(alloc(&e.grid_c, (size_t)n_sys * K3));
     T(alloc(&e.e_real_part, (size_t)std::max(1, e.n_real)));
     T(alloc(&e.e_recip_part, (size_t)n_sys * e.recip_wg));
-    // the fixed-point grid starts at zero; every call clears it after reading
-    if (!rc && hipMemset(e.grid_i, 0, sizeof(long long) * (size_t)n_sys * K3) != hipSuccess)
-        rc = fail(MIXPI_E_HIP, "hipMemset of the charge grid failed");
     if (!rc && hipDeviceSynchronize() != hipSuccess)
         rc = fail(MIXPI_E_HIP, "device synchronisation failed");
     if (rc) {

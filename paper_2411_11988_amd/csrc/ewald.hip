@@ -9,17 +9,17 @@
 // of particle i receives F_i / N_i.
 //
 // Five launches, every system of the handle at once:
-//   k_ew_spread   one wave per particle: its centroid, then cardinal
-//                 B-spline weights of order P; one lane per (x, y) spline
-//                 point adds its P z-points with int64 atomics in fixed
-//                 point (exact, so the grid does not depend on the order)
-//   k_ew_plane    forward 2D FFT (z, then y) of each x-plane in LDS, reading
-//                 (and clearing) the fixed-point grid; the same grid runs the
-//                 real-space workgroups: erfc terms within r_cut and the erf
-//                 correction of excluded pairs, (64 i) x (kEwChunk j) tiles
+//   k_ew_prep     one wave per particle: its centroid, then the grid bases
+//                 and cardinal B-spline weights of order P of each axis
+//   k_ew_plane    per x-plane: spread the charges whose x-support holds the
+//                 plane into LDS as int64 fixed point (exact, so the grid
+//                 does not depend on the order of the adds), then the
+//                 forward 2D FFT (z, then y) in LDS
 //   k_ew_xline    per 16 x-lines: forward FFT along x, multiply by the
 //                 influence function G = B C with the energy partial
-//                 sum G |F(Q)|^2, inverse FFT along x
+//                 sum G |F(Q)|^2, inverse FFT along x; the same grid runs
+//                 the real-space workgroups: erfc terms within r_cut and the
+//                 erf correction of excluded pairs, (64 i) x (kEwChunk j) tiles
 //   k_ew_plane    inverse 2D FFT (y, then z): the convolution (theta * Q)
 //   k_ew_gather   spline-derivative gather of the convolution plus the
 //                 real-space partials, bead forces F_i / N_i; one extra
@@ -91,9 +91,11 @@ __device__ __forceinline__ int wrap(int i, int K)
     return i < 0 ? i + K : i;
 }
 
-// ---- centroids and charge spreading ------------------------------------------
+// ---- centroids and spline tables --------------------------------------------
+// One wave per particle: its centroid, and for a charged particle the grid
+// bases floor(u) and the order-P weights M_P(w + j) of the three axes.
 template <int P>
-__global__ __launch_bounds__(kEwThreads) void k_ew_spread(EwaldLaunch a)
+__global__ __launch_bounds__(kEwThreads) void k_ew_prep(EwaldLaunch a)
 {
     const int i = blockIdx.x * (kEwThreads / 64) + ((int)threadIdx.x >> 6);
     if (i >= a.n_part) return;
@@ -113,33 +115,25 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_spread(EwaldLaunch a)
         a.cpos[3LL * i + 1] = c[1];
         a.cpos[3LL * i + 2] = c[2];
     }
-    const double z = a.z[i];
-    if (z == 0.0) return;
+    if (a.z[i] == 0.0) return;
     const SysDev &S = a.sys[pd.sys];
-    const int K = a.K;
     int b[3];
     double v[3][P], dv[P];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double w;
-        grid_coord(c[k], S.box[k], K, b[k], w);
+        grid_coord(c[k], S.box[k], a.K, b[k], w);
         bspline<P>(w, v[k], dv);
     }
-    if (lane >= P * P) return;
-    const int ja = lane / P, jb = lane % P;
-    double vx = 0, vy = 0;
+    if (lane < 3) a.spl_base[4LL * i + lane] = b[lane];
+    if (lane < 3 * P) {
+        const int k = lane / P, j = lane % P;
+        double x = 0.0;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        vx = j == ja ? v[0][j] : vx;
-        vy = j == jb ? v[1][j] : vy;
-    }
-    const double zxy = z * vx * vy * a.scale;
-    unsigned long long *g = (unsigned long long *)a.grid_i + (long long)pd.sys * K * K * K +
-                            ((long long)wrap(b[0] - ja, K) * K + wrap(b[1] - jb, K)) * K;
+        for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-    for (int jc = 0; jc < P; ++jc) {
-        const long long fx = (long long)rint(zxy * v[2][jc]);
-        atomicAdd(&g[wrap(b[2] - jc, K)], (unsigned long long)fx);
+            for (int jj = 0; jj < P; ++jj) x = (kk == k && jj == j) ? v[kk][jj] : x;
+        a.spl_w[(long long)i * 3 * kMaxOrder + k * kMaxOrder + j] = x;
     }
 }
 
@@ -212,6 +206,7 @@ __device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot);
 // Plane x of system s as P[y][z] (row stride K).  Forward: from the
 // fixed-point grid (cleared for the next call), FFT along z then y.
 // Inverse: y then z.
+template <int P>
 __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign)
 {
     extern __shared__ double2 plane[];
@@ -220,26 +215,70 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
     const long long off = (long long)s * K * K * K + (long long)x * K * K;
     double2 *data = a.grid_c + off;
     const int ld = K;
+    // the twiddle table follows the plane in LDS when the launch made room
+    const double2 *tw = a.tw;
+    if (a.tw_in_lds) {
+        double2 *t = plane + K * K;
+        for (int j = threadIdx.x; j < K / 2; j += kEwThreads) t[j] = a.tw[j];
+        tw = t;
+    }
     if (sign < 0) {
-        long long *fixed = a.grid_i + off;
+        // charge spreading of this plane: every charged particle of the
+        // system whose x-support holds the plane adds z M(x) M(y) M(z) in
+        // fixed point (int64 in the real words, z at its bit-reversed
+        // place).  Batches of particles: the matching ones are listed in the
+        // plane's imaginary words (free until the conversion), then the
+        // (particle, y-point) items are shared out, P adds each.
+        unsigned long long *acc = (unsigned long long *)plane;   // real words 2e, free 2e + 1
+        __shared__ int n_match;
+        for (int e = threadIdx.x; e < K * K; e += kEwThreads) plane[e] = make_double2(0.0, 0.0);
+        const int batch = K * K < 1024 ? K * K : 1024;
+        for (int i0 = a.sys_part[s]; i0 < a.sys_part[s + 1]; i0 += batch) {
+            if (threadIdx.x == 0) n_match = 0;
+            __syncthreads();
+            const int i1 = min(i0 + batch, a.sys_part[s + 1]);
+            for (int i = i0 + threadIdx.x; i < i1; i += kEwThreads) {
+                if (a.z[i] == 0.0) continue;
+                const int ja = wrap(a.spl_base[4LL * i] - x, K);
+                if (ja >= P) continue;
+                const int m = atomicAdd(&n_match, 1);
+                acc[2 * m + 1] = (unsigned long long)i | ((unsigned long long)ja << 32);
+            }
+            __syncthreads();
+            const int items = n_match * P;
+            for (int it = threadIdx.x; it < items; it += kEwThreads) {
+                const unsigned long long e = acc[2 * (it / P) + 1];
+                const int i = (int)(e & 0xffffffffu), ja = (int)(e >> 32), jb = it % P;
+                const double *w = a.spl_w + (long long)i * 3 * kMaxOrder;
+                const int row = wrap(a.spl_base[4LL * i + 1] - jb, K) * ld;
+                const int bz = a.spl_base[4LL * i + 2];
+                const double zxy = a.z[i] * w[ja] * a.scale * w[kMaxOrder + jb];
+#pragma unroll
+                for (int jc = 0; jc < P; ++jc) {
+                    const long long fx = (long long)rint(zxy * w[2 * kMaxOrder + jc]);
+                    atomicAdd(&acc[2 * (row + bitrev(wrap(bz - jc, K), logK))],
+                              (unsigned long long)fx);
+                }
+            }
+            __syncthreads();
+        }
         for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
-            const int y = e / K, z = e % K;
-            plane[y * ld + bitrev(z, logK)] = make_double2((double)fixed[e] * a.inv_scale, 0.0);
-            fixed[e] = 0;
+            const long long fx = (long long)acc[2 * e];
+            plane[e] = make_double2((double)fx * a.inv_scale, 0.0);
         }
         __syncthreads();
-        fft_lines(plane, K, ld, 1, false, K, logK, a.tw, sign);   // along z
+        fft_lines(plane, K, ld, 1, false, K, logK, tw, sign);     // along z
         bitrev_lines(plane, K, 1, ld, true, K, logK);
-        fft_lines(plane, K, 1, ld, true, K, logK, a.tw, sign);    // along y
+        fft_lines(plane, K, 1, ld, true, K, logK, tw, sign);      // along y
     } else {
         for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
             const int y = e / K, z = e % K;
             plane[bitrev(y, logK) * ld + z] = data[e];
         }
         __syncthreads();
-        fft_lines(plane, K, 1, ld, true, K, logK, a.tw, sign);    // along y
+        fft_lines(plane, K, 1, ld, true, K, logK, tw, sign);      // along y
         bitrev_lines(plane, K, ld, 1, false, K, logK);
-        fft_lines(plane, K, ld, 1, false, K, logK, a.tw, sign);   // along z
+        fft_lines(plane, K, ld, 1, false, K, logK, tw, sign);     // along z
     }
     for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
         const int y = e / K, z = e % K;
@@ -264,13 +303,15 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_xline(EwaldLaunch a)
     const long long base = (long long)s * K2 * K + (long long)y * K + z0;
     double2 *data = a.grid_c + base;
     const double *G = a.G + base;
+    double2 *tw = xl + kFftLines * K;
+    for (int j = threadIdx.x; j < K / 2; j += kEwThreads) tw[j] = a.tw[j];
     // xl[l][x], line l = z0 + l, row stride K
     for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
         const int l = e % kFftLines, x = e / kFftLines;
         xl[l * K + bitrev(x, logK)] = data[x * K2 + l];
     }
     __syncthreads();
-    fft_lines(xl, kFftLines, K, 1, false, K, logK, a.tw, -1);
+    fft_lines(xl, kFftLines, K, 1, false, K, logK, tw, -1);
     double en = 0.0;
     for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
         const int l = e % kFftLines, x = e / kFftLines;
@@ -281,7 +322,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_xline(EwaldLaunch a)
     }
     __syncthreads();
     bitrev_lines(xl, kFftLines, K, 1, false, K, logK);
-    fft_lines(xl, kFftLines, K, 1, false, K, logK, a.tw, 1);
+    fft_lines(xl, kFftLines, K, 1, false, K, logK, tw, 1);
     for (int e = threadIdx.x; e < kFftLines * K; e += kEwThreads) {
         const int l = e % kFftLines, x = e / kFftLines;
         data[x * K2 + l] = xl[l * K + x];
@@ -342,16 +383,17 @@ __device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot)
             const bool excl = sm[t] == mi;
             if (!excl && !(r2 < rc2)) continue;
             const double r = sqrt(r2);
+            const double ir = 1.0 / r;
             const double gauss = two_a_rpi * exp(-alpha * alpha * r2);
             double v, g;
             if (excl) {
                 const double ef = erf(alpha * r);
-                v = -ef / r;
-                g = kCoulombKcal * qq * (gauss * r - ef) / (r2 * r);
+                v = -ef * ir;
+                g = kCoulombKcal * qq * (gauss * r - ef) * (ir * ir * ir);
             } else {
                 const double ec = erfc(alpha * r);
-                v = ec / r;
-                g = kCoulombKcal * qq * (gauss * r + ec) / (r2 * r);
+                v = ec * ir;
+                g = kCoulombKcal * qq * (gauss * r + ec) * (ir * ir * ir);
             }
             e += 0.5 * kCoulombKcal * qq * v;
             fx += g * dx;
@@ -407,15 +449,19 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_gather(EwaldLaunch a)
     const int lane = threadIdx.x & 63;
     const PartDev pd = a.parts[i];
     const double z = a.z[i];
+    // real-space chunk partials: lane c takes chunks c, c + 64, ...; the
+    // wave tree then adds the lanes in a fixed order
     double F[3] = {0.0, 0.0, 0.0};
     const int ns = a.sys_part[pd.sys + 1] - a.sys_part[pd.sys];
     const int nch = (ns + kEwChunk - 1) / kEwChunk;
-    for (int c = 0; c < nch; ++c) {
+    for (int c = lane; c < nch; c += 64) {
         const double *src = a.freal + ((long long)c * a.n_part + i) * 3;
         F[0] += src[0];
         F[1] += src[1];
         F[2] += src[2];
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] = wave_sum(F[k]);
     if (z != 0.0) {
         const SysDev &S = a.sys[pd.sys];
         const int K = a.K;
@@ -503,13 +549,17 @@ void launch_order(const EwaldLaunch &a, hipStream_t st)
     const int per = kEwThreads / 64;
     const int pblocks = (a.n_part + per - 1) / per;
     const int K = a.K;
-    hipLaunchKernelGGL(k_ew_spread<P>, dim3(pblocks), dim3(kEwThreads), 0, st, a);
-    const size_t plane_lds = sizeof(double2) * K * K;
-    hipLaunchKernelGGL(k_ew_plane, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, a, -1);
+    hipLaunchKernelGGL(k_ew_prep<P>, dim3(pblocks), dim3(kEwThreads), 0, st, a);
+    // the plane plus (when it stays within 64 KB) the twiddle table
+    EwaldLaunch b = a;
+    size_t plane_lds = sizeof(double2) * K * K;
+    b.tw_in_lds = plane_lds + sizeof(double2) * (K / 2) <= 65536 ? 1 : 0;
+    if (b.tw_in_lds) plane_lds += sizeof(double2) * (K / 2);
+    hipLaunchKernelGGL(k_ew_plane<P>, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, -1);
     const int xgroups = a.n_sys * (K * K / kFftLines);
     hipLaunchKernelGGL(k_ew_xline, dim3(xgroups + a.n_real), dim3(kEwThreads),
-                       sizeof(double2) * kFftLines * K, st, a);
-    hipLaunchKernelGGL(k_ew_plane, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, a, 1);
+                       sizeof(double2) * (kFftLines * K + K / 2), st, a);
+    hipLaunchKernelGGL(k_ew_plane<P>, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, 1);
     hipLaunchKernelGGL(k_ew_gather<P>, dim3(pblocks + a.n_sys), dim3(kEwThreads), 0, st, a);
 }
 

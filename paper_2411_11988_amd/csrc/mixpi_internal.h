@@ -281,7 +281,8 @@ void launch_tcf(const TcfLaunch &a, const double *p, hipStream_t st);
 
 // Real-space Ewald work item: particles [i0, i0 + ni) against the j-chunk
 // [j0, j0 + nj) (chunk-th kEwChunk-particle chunk of the system).
-constexpr int kEwChunk = 128;
+constexpr int kEwChunk = 64;
+constexpr int kMaxOrder = 8;     // largest B-spline order
 struct RealItem {
     int sys, i0, ni, j0, nj, chunk;
 };
@@ -299,7 +300,8 @@ struct EwaldLaunch {
     double *eslot_out;           // energy slot row per system (may be null): A_COUL = total
     double *cpos, *fcent;        // [n_part][3]
     double *freal;               // [max chunks][n_part][3] real-space partials
-    long long *grid_i;           // [n_sys][K^3] fixed-point charge grid
+    int *spl_base;               // [n_part][4] grid bases floor(u) of x, y, z
+    double *spl_w;               // [n_part][3][kMaxOrder] B-spline weights
     double2 *grid_c;             // [n_sys][K^3]
     const double *G;             // [n_sys][K^3] influence function B C
     const double2 *tw;           // exp(-2 pi i j / K), j < K/2
@@ -311,6 +313,7 @@ struct EwaldLaunch {
     double *e_out;               // [n_sys][3] (may be null)
     double alpha, r_cut, scale, inv_scale;
     int K, logK, order, n_part, n_sys, recip_wg, n_real;
+    int tw_in_lds;               // plane launches: twiddles staged after the plane
 };
 void launch_ewald(const EwaldLaunch &a, hipStream_t st);
 
