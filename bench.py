@@ -119,6 +119,38 @@ def _run(s, precision, steps, warmup, mixpi, torch, flags=0):
                 drift=float(drift[np.argmax(np.abs(drift))]), hstd=float(ham.std(axis=0).max()))
 
 
+def _run_sequential(systems, precision, steps, mixpi, torch):
+    """The batch's systems as separate handles, each running the same number
+    of steps (one captured graph per system) one after another on the
+    stream: the comparison for a batched handle."""
+    import numpy as np
+    handles = []
+    for x in systems:
+        h = mixpi.System(x, precision=precision)
+        idx = h.bead_index
+
+        def dev(a, idx=idx):
+            out = np.empty_like(a)
+            out[idx] = a
+            return torch.from_numpy(out).cuda()
+        q, p = dev(x.q), dev(x.p)
+        f, _ = h.forces(q)
+        h.step(steps, q, p, f)                                    # captures the graph
+        handles.append((h, q, p, f))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for h, q, p, f in handles:
+        h.step(steps, q, p, f)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return {"ms_per_batch_step": ms / steps,
+            "system_steps_per_s": len(systems) * steps / (ms * 1e-3)}
+
+
 def _run_nvt(s, precision, steps, mixpi, torch, flags=0, tau0=50.0):
     """Thermostatted steps (O B A B O) with the noise drawn beforehand and
     resident in HBM; returns steps/s and the time per step."""
@@ -190,7 +222,7 @@ def _run_observables(sysm, q, p, s, mixpi, torch, reps=50):
     configuration: mean time per call over `reps` calls (HIP events on the
     stream the library launches on), after warmup calls."""
     import numpy as np
-    box = float(np.min(_as_list(s)[0].box))
+    box = min(float(np.min(x.box)) for x in _as_list(s))      # every system's box
     stream = torch.cuda.current_stream()
 
     def timed(fn, n):
@@ -424,6 +456,13 @@ def main():
                      "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"]},
     }
+    if len(_as_list(s)) > 1:
+        print("[bench] the same systems as separate handles, one after another",
+              file=sys.stderr, flush=True)
+        seq = _run_sequential(_as_list(s), mixpi.MIXPI_FP32_ACC64, args.steps, mixpi, torch)
+        batched = len(_as_list(s)) * steps_per_s
+        out["sequential"] = dict(seq, batched_system_steps_per_s=batched,
+                                 batched_speedup=batched / seq["system_steps_per_s"])
     if args.observables:
         print("[bench] observables and centroid electrostatics", file=sys.stderr, flush=True)
         out["observables"] = _run_observables(sysm, r32["q"], r32["p"], s, mixpi, torch)

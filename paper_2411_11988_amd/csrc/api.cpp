@@ -158,6 +158,7 @@ struct mixpi_system {
     // epilogue blocks (4 rows of one system)
     BlockRange *d_fblocks = nullptr;
     int n_fblocks = 0;
+    int fin_rpw = 1;               // bead rows per wave in the epilogue
     // energy slots (two buffers, alternating by step): pair items | bonded
     // blocks | normal-mode items | epilogue blocks; per-system slot lists for
     // the force-only range and for the whole step
@@ -954,16 +955,28 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->n_rp = (int)rp.size();
     S->rp_lds = std::max<unsigned>(B.rp_lds, kReduceThreads * sizeof(double));
 
-    // epilogue blocks: 4 rows of one system
-    std::vector<BlockRange> fblocks;
-    for (int s = 0; s < n_sys; ++s)
-        for (long long r = B.sys_rows[s].first; r < B.sys_rows[s].second; r += 4)
-            fblocks.push_back(BlockRange{s, (int)r, (int)std::min<long long>(4, B.sys_rows[s].second - r), 0});
-    S->n_fblocks = (int)fblocks.size();
-
     // partial-force slots
     S->part_bonded = (long long)S->n_items * (64 + S->pair_tj);
     Gather G = build_gather(B.rows, B.blocks, items, S->pair_tj, terms, S->part_bonded);
+
+    // epilogue blocks: 4 waves of rpw rows of one system.  Many rows with
+    // short partial runs share a wave (64 / rpw lanes per row); few rows or
+    // long runs keep a whole wave each.
+    {
+        const double avg = B.rows > 0 ? (double)G.row_ptr.back() / B.rows : 0.0;
+        S->fin_rpw = B.rows < 4096 ? 1 : (avg <= 24.0 ? 4 : (avg <= 48.0 ? 2 : 1));
+        if (const char *env = getenv("MIXPI_FIN_RPW")) {
+            const int v = atoi(env);
+            if (v == 1 || v == 2 || v == 4) S->fin_rpw = v;
+        }
+    }
+    const int fin_rows = 4 * S->fin_rpw;
+    std::vector<BlockRange> fblocks;
+    for (int s = 0; s < n_sys; ++s)
+        for (long long r = B.sys_rows[s].first; r < B.sys_rows[s].second; r += fin_rows)
+            fblocks.push_back(BlockRange{s, (int)r,
+                                         (int)std::min<long long>(fin_rows, B.sys_rows[s].second - r), 0});
+    S->n_fblocks = (int)fblocks.size();
     if (G.n_slots > (1LL << 31) - 1) {
         delete S;
         return fail(MIXPI_E_UNSUPPORTED, "too many partial-force slots (%lld)", G.n_slots);
@@ -1264,7 +1277,7 @@ void enqueue_forces(mixpi_system *s, const double *q, const double *theta, doubl
                     bool with_theta, hipStream_t st)
 {
     launch_pair(pair_args(s, q, theta), bonded_args(s, q, theta), s->precision, with_theta, st);
-    launch_gather(gather_args(s), s->rows, f, st);
+    launch_gather(gather_args(s), s->rows, f, st, s->fin_rpw);
     if (s->ew_use) enqueue_ewald_in_pass(s, q, f, 0, false, st);
 }
 
@@ -1312,6 +1325,7 @@ FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f,
 {
     FinishLaunch fl{};
     fl.blocks = s->d_fblocks;
+    fl.rpw = s->fin_rpw;
     fl.n_blocks = s->n_fblocks;
     fl.gather = gather_args(s);
     fl.row_fm = s->d_row_fm;
@@ -1540,7 +1554,7 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
     hipStream_t st = (hipStream_t)stream;
     launch_pair(pair_args(sys, q, theta), bonded_args(sys, q, theta), sys->precision, true, st);
     if (dq) {
-        launch_gather(gather_args(sys), sys->rows, dq, st);
+        launch_gather(gather_args(sys), sys->rows, dq, st, sys->fin_rpw);
         launch_scale_rows(sys->rows, sys->d_row_sys, grad_e, dq, st);
     }
     ReduceB rb = reduce_b_args(sys, LIST_FORCE);

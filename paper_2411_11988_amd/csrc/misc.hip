@@ -8,42 +8,62 @@ namespace mixpi {
 
 // ---------------------------------------------------------------------------
 // F[row] = sum over the row's partial-force slots, a contiguous run in the
-// fixed CSR order (so forces are reproducible bit for bit).  One wave per
-// row: lane l takes slots l, l + 64, ...; the wave then reduces the three
-// components.
+// fixed CSR order (so forces are reproducible bit for bit).
 struct Vec3 {
     double x, y, z;
 };
-__device__ __forceinline__ Vec3 gather_row(const GatherArgs &g, long long row)
+// LPR lanes per row (lanes sl = 0 .. LPR-1 of an aligned group of the
+// wave; LPR = 64 is one wave per row): slots sl, sl + LPR, ...; the group's
+// lanes then reduce by shuffles that stay inside the group, in a fixed order.
+template <int LPR>
+__device__ __forceinline__ Vec3 gather_row_group(const GatherArgs &g, long long row, int sl)
 {
-    const int lane = threadIdx.x & 63;
     double x = 0.0, y = 0.0, z = 0.0;
     const long long e = g.row_ptr[row + 1];
-    for (long long k = g.row_ptr[row] + lane; k < e; k += 64) {
+    for (long long k = g.row_ptr[row] + sl; k < e; k += LPR) {
         const double *p = g.part + 3 * k;
         x += p[0];
         y += p[1];
         z += p[2];
     }
-    return Vec3{wsum(x), wsum(y), wsum(z)};
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o, 64);
+        y += __shfl_xor(y, o, 64);
+        z += __shfl_xor(z, o, 64);
+    }
+    return Vec3{x, y, z};
 }
 
+// RPW rows per wave, grouped exactly as in the step epilogue, so that a
+// force call and a step sum each row's partials in the same order.
+template <int RPW>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs g, long long rows, double *f)
 {
-    const long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= rows) return;   // whole waves leave together
-    const Vec3 v = gather_row(g, row);
-    if ((threadIdx.x & 63) == 0) {
+    constexpr int LPR = 64 / RPW;
+    const int lane = threadIdx.x & 63;
+    const long long row = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * RPW +
+                          lane / LPR;
+    if (row >= rows) return;   // whole groups leave together
+    const int sl = lane % LPR;
+    const Vec3 v = gather_row_group<LPR>(g, row, sl);
+    if (sl == 0) {
         f[3 * row] = v.x;
         f[3 * row + 1] = v.y;
         f[3 * row + 2] = v.z;
     }
 }
 
-void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st)
+void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st, int rpw)
 {
     if (rows <= 0) return;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, g, rows, f);
+    const long long waves = (rows + rpw - 1) / rpw;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    switch (rpw) {
+    case 4: hipLaunchKernelGGL(k_gather<4>, grid, dim3(256), 0, st, g, rows, f); break;
+    case 2: hipLaunchKernelGGL(k_gather<2>, grid, dim3(256), 0, st, g, rows, f); break;
+    default: hipLaunchKernelGGL(k_gather<1>, grid, dim3(256), 0, st, g, rows, f); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -53,6 +73,7 @@ void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t s
 // centroid-virial term (q - qbar) . F summed into the workgroup's slot.  In
 // velocity-Verlet mode the kick also carries the ring's spring force at the
 // new positions, and the spring energy is summed here.
+template <int RPW>
 __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
 {
     __shared__ double red[4];
@@ -63,12 +84,15 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
         return;
     }
     const BlockRange br = a.blocks[blockIdx.x];
+    // RPW rows per wave: row w * RPW + lane / LPR of the block, lane sl of it
+    constexpr int LPR = 64 / RPW;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = lane % LPR, ri = w * RPW + lane / LPR;
     double ke = 0.0, vir = 0.0, esp = 0.0;
-    if (w < br.count) {
-        const long long row = (long long)br.begin + w;
+    if (ri < br.count) {
+        const long long row = (long long)br.begin + ri;
         // the row's own state, loaded before the gather so both are in flight
-        const long long x = 3 * row + (lane < 3 ? lane : 0);
+        const long long x = 3 * row + (sl < 3 ? sl : 0);
         const double p0 = a.p[x], q0 = a.q[x], c0 = a.cent[x];
         const double hk = a.row_hk[row], fm = a.row_fm[row];
         const int st = a.row_stage[row];
@@ -80,19 +104,19 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
             const double qp = a.q[3 * a.row_prev[row] + (x - 3 * row)];
             const double qn = a.q[3 * a.row_next[row] + (x - 3 * row)];
             fsp = -k * (2.0 * q0 - qp - qn);
-            if (lane < 3) esp = 0.5 * k * (q0 - qn) * (q0 - qn);
+            if (sl < 3) esp = 0.5 * k * (q0 - qn) * (q0 - qn);
         }
-        const double few = a.ew_rowf && lane < 3 ? a.ew_rowf[x] : 0.0;
-        const Vec3 fv = gather_row(a.gather, row);
-        if (lane < 3) {
-            double fx = lane == 0 ? fv.x : (lane == 1 ? fv.y : fv.z);
+        const double few = a.ew_rowf && sl < 3 ? a.ew_rowf[x] : 0.0;
+        const Vec3 fv = gather_row_group<LPR>(a.gather, row, sl);
+        if (sl < 3) {
+            double fx = sl == 0 ? fv.x : (sl == 1 ? fv.y : fv.z);
             if (a.ew_rowf) fx += few;
             a.f[x] = fx;
             const double pv = p0 + hk * (fx + fsp);
             a.p[x] = pv;
             if (st >= 0) {
-                a.stage[6LL * st + lane] = q0;
-                a.stage[6LL * st + 3 + lane] = pv + hk * fx;
+                a.stage[6LL * st + sl] = q0;
+                a.stage[6LL * st + 3 + sl] = pv + hk * fx;
             }
             ke = pv * pv / (2.0 * fm);
             vir = (q0 - c0) * fx;
@@ -114,7 +138,11 @@ void launch_finish(const FinishLaunch &a, hipStream_t st)
 {
     const int grid = a.n_blocks + (a.with_reduce ? a.reduce.n_wg : 0);
     if (grid <= 0) return;
-    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, st, a);
+    switch (a.rpw) {
+    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(grid), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(grid), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_finish<1>, dim3(grid), dim3(256), 0, st, a); break;
+    }
 }
 
 // ---------------------------------------------------------------------------

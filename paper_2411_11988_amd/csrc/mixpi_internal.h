@@ -210,8 +210,9 @@ struct GatherArgs {
 };
 
 struct FinishLaunch {
-    const BlockRange *blocks;  // one per workgroup: 4 bead rows of one system
+    const BlockRange *blocks;  // one per workgroup: 4 rpw bead rows of one system
     int n_blocks;
+    int rpw;                   // bead rows per wave: 1, 2 or 4
     GatherArgs gather;
     const double *row_fm;      // [rows] fictitious mass of the bead row
     const double *row_hk;      // [rows] dt/2 in momentum units of its system
@@ -319,7 +320,7 @@ void launch_ewald(const EwaldLaunch &a, hipStream_t st);
 
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);
-void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st);
+void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st, int rpw);
 void launch_scale_rows(long long rows, const int *row_sys, const double *grad_e, double *dq,
                        hipStream_t st);
 

@@ -206,3 +206,72 @@ def test_adjoint_c4_full_size(mp, prec):
         assert theta_err(d, want) <= TOL_TH[prec], (d, want)
     else:
         assert theta_err_fp32(d, want, default_theta(s), eo) <= TOL_TH[prec], (d, want)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_c4_ten_seeds(mp):
+    """The gradient workload on its 10 seeded configurations (256 waters,
+    N_H = 32, N_O = 4): per seed, dq = -F and dV/dtheta against the oracle,
+    and central differences of the FP64 energy over 64 random bead
+    coordinates (h = 1e-6 A), 8 random unit directions in bead space and each
+    theta component (relative h = 1e-6), with vector norms over each set:
+        |g - g_FD| <= 1e-6 max(1, |g|) + sqrt(n) 1e-14 |E| / h.
+    The second term is the rounding floor of a difference quotient of the
+    energy: a sum of 8.5 M slice-pair terms whose FP64 value moves by about
+    1e-14 |E| (|E| ~ 2e3 kcal/mol) between neighbouring configurations,
+    i.e. ~2e-5 per quotient at h = 1e-6.  A wrong term or factor in the
+    gradient errs by O(|g|) and still fails; the oracle gradient is the
+    tight check (1e-12).  Along a unit vector spread over 52 k coordinates
+    the derivative is O(1), so the directions take h = 1e-4 A (the third
+    directional derivative there is negligible)."""
+    states = synth.config_c4_states(10)
+    for seed, s in enumerate(states):
+        print(f"[adjoint c4] seed {seed}", flush=True)
+        sysm = mp.System(s)
+        rows = layout_rows(s)
+        q0 = to_rows(s, s.q, rows)
+        th0 = default_theta(s)
+        thd = dev(th0.reshape(1, 6))
+        dq, dth = sysm.energy_adjoint(dev(q0), theta=thd)
+        dq, dth = host(dq), host(dth)[0]
+        o = oracle.OracleSystem(s)
+        Fo, _ = o.forces(s.q)
+        assert force_err(-from_rows(s, dq, rows), Fo) <= 1e-12
+        assert theta_err(dth, o.dvdtheta(s.q)) <= 1e-12
+
+        def energy(q, th):
+            return float(host(sysm.energy(dev(q), theta=dev(th.reshape(1, 6))))[0, 0])
+
+        rng = np.random.default_rng(100 + seed)
+        e_abs = abs(energy(q0, th0))
+        h = 1e-6
+        g, fd = [], []
+        for r, c in zip(rng.integers(0, q0.shape[0], 64), rng.integers(0, 3, 64)):
+            qp, qm = q0.copy(), q0.copy()
+            qp[r, c] += h
+            qm[r, c] -= h
+            fd.append((energy(qp, th0) - energy(qm, th0)) / (2 * h))
+            g.append(dq[r, c])
+        g, fd = np.array(g), np.array(fd)
+        floor = np.sqrt(len(g)) * 1e-14 * e_abs / h
+        assert np.linalg.norm(g - fd) <= 1e-6 * max(1.0, np.linalg.norm(g)) + floor, (seed, g - fd)
+        hu = 1e-4
+        g, fd = [], []
+        for _ in range(8):
+            u = rng.normal(size=q0.shape)
+            u /= np.linalg.norm(u)
+            fd.append((energy(q0 + hu * u, th0) - energy(q0 - hu * u, th0)) / (2 * hu))
+            g.append(float((dq * u).sum()))
+        g, fd = np.array(g), np.array(fd)
+        floor = np.sqrt(len(g)) * 1e-14 * e_abs / hu
+        assert np.linalg.norm(g - fd) <= 1e-6 * max(1.0, np.linalg.norm(g)) + floor, (seed, g, fd)
+        for k in range(6):
+            if th0[k] == 0.0:
+                continue
+            hk = 1e-6 * abs(th0[k])
+            tp, tm = th0.copy(), th0.copy()
+            tp[k] += hk
+            tm[k] -= hk
+            fd = (energy(q0, tp) - energy(q0, tm)) / (2 * hk)
+            assert abs(dth[k] - fd) <= 1e-6 * max(1.0, abs(dth[k])) + 1e-14 * e_abs / hk, \
+                (seed, k, dth[k], fd)

@@ -270,3 +270,20 @@ def test_pair_tile_variants(mp, tj, waves, monkeypatch):
             F = from_rows(s, host(f))
             assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
             assert e_err(prec, host(e)[0], eo) <= TOL_E[prec]
+
+
+@pytest.mark.parametrize("rpw", [1, 2, 4])
+def test_epilogue_rows_per_wave(mp, rpw, monkeypatch):
+    """Every epilogue grouping (1, 2 or 4 bead rows per wave): forces and
+    two FP64 steps match the oracle, and a force call and the step's
+    epilogue give the same F bit for bit (same summation order)."""
+    monkeypatch.setenv("MIXPI_FIN_RPW", str(rpw))
+    for name, s in (SYSTEMS[5], SYSTEMS[6], SYSTEMS[7]):
+        print(f"[epilogue] rpw={rpw} {name}", flush=True)
+        _step_compare(mp, s, FP64, 2, 1e-12, 1e-11, 1e-11)
+        sysm = mp.System(s)
+        q, p = dev(to_rows(s, s.q)), dev(to_rows(s, s.p))
+        f, _ = sysm.forces(q)
+        sysm.step(1, q, p, f)
+        f2, _ = sysm.forces(q)
+        assert np.array_equal(host(f), host(f2))
