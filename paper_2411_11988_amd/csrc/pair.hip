@@ -53,13 +53,6 @@ template <typename R> struct alignas(16) LjPar {
     R e4, s2, c0, c1;
 };
 
-__device__ __forceinline__ int wave_sum_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 template <typename R, bool THETA, int TJ, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch bl)
 {
@@ -150,6 +143,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     // per-lane sums of at most TJ terms in R, then FP64 across lanes/tiles
     R e0r = 0, e1r = 0;               // atom: LJ, Coulomb; electron: pp
     R g0r = 0, g1r = 0;               // theta partials (pp: q_e, a; atom: eps, sigma)
+    // in-cutoff slice-pairs of the wave, counted from lane masks on the
+    // scalar unit (wave-uniform)
     int cnt = 0;
     // slots that may interact: real j, and for a group with itself j > i
     const int jlo = bk.same ? (int)max(-1LL, min((long long)TJ, idx - it.j0)) : -1;
@@ -195,7 +190,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             const R g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
             e0r += in_lj ? vlj : (R)0;
             e1r += in_c ? vc : (R)0;
-            cnt += (in_lj || in_c) ? 1 : 0;
+            cnt += __popcll(__ballot(in_lj || in_c));
             if (THETA) {
                 // d/d eps and d/d sigma of the (0,0) LJ term
                 const bool on = in_lj && tp == 0;
@@ -247,7 +242,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
             const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
             e0r += ok ? rpq * vq : (R)0;
-            cnt += ok ? 1 : 0;
+            cnt += __popcll(__ballot(ok));
             if (THETA) {
                 g0r += ok ? vq : (R)0;
                 g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
@@ -265,7 +260,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         }
     }
     double e0 = wsum((double)e0r), e1 = wsum((double)e1r), g0 = 0.0, g1 = 0.0;
-    cnt = wave_sum_i(cnt);
+
     if (THETA) {
         g0 = wsum((double)g0r);
         g1 = wsum((double)g1r);
