@@ -299,7 +299,10 @@ int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, 
  * and cardinal B-splines of order 4, 6 or 8 (Essmann et al., J. Chem. Phys.
  * 103, 8577 (1995)).  Builds the influence function on the host and
  * allocates the handle's Ewald buffers (24 grid^3 bytes per system plus
- * O(particles)); a second call replaces the first.  Synchronous.  Errors:
+ * O(particles)); a second call replaces the first and keeps the
+ * mixpi_use_ewald setting.  A rejected parameter changes nothing; a failed
+ * allocation leaves the Ewald terms off and unconfigured.
+ * Synchronous.  Errors:
  * MIXPI_E_INVALID (bad parameter), MIXPI_E_HIP. */
 int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid, int32_t order);
 

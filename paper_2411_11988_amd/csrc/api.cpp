@@ -1838,6 +1838,7 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
     HIP_TRY(hipSetDevice(sys->device));
     HIP_TRY(hipDeviceSynchronize());
     clear_graphs(sys);
+    const bool was_in_use = sys->ew_use;   // kept across a successful reconfiguration
     sys->ew_use = false;
     release_ewald(sys);
     auto &e = sys->ew;
@@ -1942,6 +1943,7 @@ int mixpi_set_ewald(mixpi_system *sys, double alpha, double r_cut, int32_t grid,
         return rc;
     }
     e.on = true;
+    sys->ew_use = was_in_use;
     return MIXPI_OK;
 }
 

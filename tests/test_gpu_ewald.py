@@ -311,3 +311,32 @@ def test_ewald_step_graphs_follow_the_switch(mp):
     with pytest.raises(mp.MixPIError) as e:
         mp.mixpi_use_ewald(b.h, 1)
     assert e.value.code == mp.MIXPI_E_INVALID
+
+
+def test_ewald_batch_with_an_uncharged_system_and_reconfiguration(mp):
+    """A system without Ewald charges (two electrons) in a batch: zero
+    energies and forces for it, the others unchanged; a second
+    mixpi_set_ewald keeps the terms switched into the force passes."""
+    import torch
+    q = np.random.default_rng(1).normal(size=(32, 3)) + 5.0
+    bare = custom([16, 16], q, ele=[1, 1], box=11.0, rc=5.0, mass=[1.008, 1.008])
+    systems = [_no_cut_coulomb(synth.config_c1()), bare]
+    sysm = mp.System(systems)
+    sysm.set_ewald(*EW)
+    qd = dev(np.concatenate([to_rows(s, s.q) for s in systems]))
+    f = torch.zeros_like(qd)
+    e = host(sysm.ewald(qd, f))
+    assert np.all(e[1] == 0.0)
+    n0 = len(layout_rows(systems[0]))
+    assert np.all(host(f)[n0:] == 0.0)
+    Fo, eo = oracle_spme(systems[0], *EW[:2], *EW[2:])
+    assert force_err(from_rows(systems[0], host(f)[:n0]), Fo) <= 1e-10
+    sysm.use_ewald(True)
+    fa, _ = sysm.forces(qd)
+    sysm.set_ewald(0.7, 5.0, 32, 8)
+    fb, _ = sysm.forces(qd)
+    assert not np.array_equal(host(fa), host(fb))          # still on, new parameters
+    sysm.use_ewald(False)
+    fc, _ = sysm.forces(qd)
+    fp, _ = mp.System(systems).forces(qd)
+    assert np.array_equal(host(fc), host(fp))
