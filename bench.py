@@ -46,6 +46,11 @@ PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # one it was measured on (sha256 over KERNEL_SOURCES).
 KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/csrc/device_common.h",
                   "paper_2411_11988_amd/csrc/mixpi_internal.h")
+# VALU work of one force launch on the default workload, from rocprofv3
+# --pmc (SQ_INSTS_VALU and the FP32/FP64 add/mul/fma/transcendental
+# instruction counters, 64 lanes each, FMA = 2): executed FLOP including the
+# masked-off math of out-of-cutoff candidates; same source-hash condition.
+VALU = {"insts_valu": 3460961, "flop_executed": 158770070}
 TRAFFIC = {"workload": "c3", "tile": "32x2",
            "sha256": "76b0fac7bbdb7ac58754640cf4527327d7d474b17cf8f7e928c873d0f54afca3",
            "bytes": (836.05 * 2.0 + 6545.13 * 1.0) * 1024}
@@ -58,6 +63,18 @@ def _kernel_sha():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def _executed(launch_us):
+    """Counter-based work of the force launch over its measured duration:
+    executed TFLOP/s and its fraction of the ALU peak, and the share of the
+    launch the 1024 SIMDs spend issuing VALU instructions (4 cycles each at
+    2.4 GHz)."""
+    t = launch_us * 1e-6
+    tf = VALU["flop_executed"] / t / 1e12
+    return {"flop_per_launch": VALU["flop_executed"], "tflops": tf,
+            "frac": tf / PEAK_ALU_TFLOPS,
+            "valu_issue_frac": VALU["insts_valu"] * 4 / 1024 / (t * 2.4e9)}
 
 
 def _workload(name):
@@ -454,7 +471,11 @@ def main():
                                  and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
                                  else None),
                      "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
-                     "flop_per_launch": flops, "launch_us": k_us["force"]},
+                     "flop_per_launch": flops, "launch_us": k_us["force"],
+                     "executed": (_executed(k_us["force"]) if args.workload == TRAFFIC["workload"]
+                                  and TRAFFIC["sha256"] == _kernel_sha()
+                                  and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
+                                  else None)},
     }
     if len(_as_list(s)) > 1:
         print("[bench] the same systems as separate handles, one after another",
