@@ -503,6 +503,18 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
             pb.rowb = Bg.row;
             pb.w = 1.0 / A.N;
             pb.nbeads_b = Bg.N;
+            {
+                // LJ can act between the groups if a type pair of them has
+                // eps != 0, or both hold type 0 (its eps can be overridden)
+                std::vector<char> ta(nt + 1, 0), tb(nt + 1, 0);
+                for (int x = 0; x < A.n; ++x) ta[B.ljt[p_base + A.p0 + x]] = 1;
+                for (int x = 0; x < Bg.n; ++x) tb[B.ljt[p_base + Bg.p0 + x]] = 1;
+                pb.lj = 0;
+                for (int a = 0; a < nt; ++a)
+                    for (int b = 0; b < nt; ++b)
+                        if (ta[a] && tb[b] && (d->lj_eps[a * nt + b] != 0.0 || (a == 0 && b == 0)))
+                            pb.lj = 1;
+            }
             B.block_slow.push_back(A.N > kDenseMaxN || Bg.N > kDenseMaxN);
             B.blocks.push_back(pb);
             const long long pairs = pb.same ? (long long)A.n * (A.n - 1) / 2 : (long long)A.n * Bg.n;

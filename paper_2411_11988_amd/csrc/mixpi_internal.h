@@ -62,7 +62,7 @@ struct PairBlock {
     long long rowa, rowb; // first bead row of groups a, b
     double w;             // 1 / N_a
     int nbeads_b;         // N_b
-    int pad;
+    int lj;               // some type pair of the two groups may have LJ (atom blocks)
 };
 struct PairItem {
     int block, b, i0, j0;

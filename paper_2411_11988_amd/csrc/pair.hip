@@ -23,6 +23,8 @@
 // sit up to a box length from the origin); the pair potential is evaluated
 // in R (double, or float for the FP32 form); forces and energies are summed
 // in FP64.
+#include <type_traits>
+
 #include "device_common.h"
 #include "mixpi_internal.h"
 
@@ -159,58 +161,75 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         const R kqi = (R)(kCoulombKcal * qi);
         const int trow = ti * nt1;
         const R th_eps = (R)th[2], th_sig = (R)th[3];
+        // LJ: blocks whose type pairs all have eps = 0 (and cannot reach the
+        // theta-overridden pair (0, 0)) run a loop without the LJ terms; the
+        // masked LJ contribution there is an exact zero, so both loops give
+        // the same bits
+        auto sweep = [&](auto lj_tag) {
+            constexpr bool LJ = decltype(lj_tag)::value;
 #pragma unroll 4
-        for (int t = 0; t < TJ / WAVES; ++t) {
-            const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
-            const JRec<R> jr = sj[jj];
-            double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
-            const R qj = jr.q;
-            const int tp = trow + (jr.tm & 15);
-            const int mj = jr.tm >> 4;
-            dx -= Lx * rint(dx * iLx);
-            dy -= Ly * rint(dy * iLy);
-            dz -= Lz * rint(dz * iLz);
-            const double r2d = dx * dx + dy * dy + dz * dz;
-            const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
-            const R r2 = ok ? (R)r2d : (R)1;
-            const LjPar<R> lp = tlj[tp];
-            const R e4 = lp.e4, c1l = lp.c1;
-            const R ir2 = rcp_r<R>(r2);
-            const R s2 = lp.s2 * ir2;
-            const R s6 = s2 * s2 * s2;
-            const R s12 = s6 * s6;
-            const bool in_lj = ok && r2d < rc2_lj && e4 != (R)0;
-            const R vlj = e4 * (s12 - s6) - lp.c0 - (R)0.5 * (r2 - rl2) * c1l;
-            const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
-            const R K = kqi * qj;
-            const bool in_c = ok && r2d < rc2_c && K != (R)0;
-            const R ir = rsqrt_r<R>(r2);
-            const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
-            const R gc = K * (ir * ir * ir - irc3);
-            const R g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
-            e0r += in_lj ? vlj : (R)0;
-            e1r += in_c ? vc : (R)0;
-            cnt += __popcll(__ballot(in_lj || in_c));
-            if (THETA) {
-                // d/d eps and d/d sigma of the (0,0) LJ term
-                const bool on = in_lj && tp == 0;
-                const R c6 = tlj[0].s2 / rl2;
-                const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
-                const R fs = (R)4 * th_eps / th_sig;
-                const R dsg = fs * ((R)12 * s12 - (R)6 * s6) - fs * ((R)12 * c12c - (R)6 * c6c) -
-                              (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2;
-                g0r += on ? vlj / th_eps : (R)0;
-                g1r += on ? dsg : (R)0;
+            for (int t = 0; t < TJ / WAVES; ++t) {
+                const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
+                const JRec<R> jr = sj[jj];
+                double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
+                const R qj = jr.q;
+                const int tp = trow + (jr.tm & 15);
+                const int mj = jr.tm >> 4;
+                dx -= Lx * rint(dx * iLx);
+                dy -= Ly * rint(dy * iLy);
+                dz -= Lz * rint(dz * iLz);
+                const double r2d = dx * dx + dy * dy + dz * dz;
+                const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
+                const R r2 = ok ? (R)r2d : (R)1;
+                const R K = kqi * qj;
+                const bool in_c = ok && r2d < rc2_c && K != (R)0;
+                const R ir = rsqrt_r<R>(r2);
+                const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
+                const R gc = K * (ir * ir * ir - irc3);
+                R g;
+                bool hit = in_c;
+                if constexpr (LJ) {
+                    const LjPar<R> lp = tlj[tp];
+                    const R e4 = lp.e4, c1l = lp.c1;
+                    const R ir2 = rcp_r<R>(r2);
+                    const R s2 = lp.s2 * ir2;
+                    const R s6 = s2 * s2 * s2;
+                    const R s12 = s6 * s6;
+                    const bool in_lj = ok && r2d < rc2_lj && e4 != (R)0;
+                    const R vlj = e4 * (s12 - s6) - lp.c0 - (R)0.5 * (r2 - rl2) * c1l;
+                    const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
+                    g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
+                    e0r += in_lj ? vlj : (R)0;
+                    hit = in_lj || in_c;
+                    if (THETA) {
+                        // d/d eps and d/d sigma of the (0,0) LJ term
+                        const bool on = in_lj && tp == 0;
+                        const R c6 = tlj[0].s2 / rl2;
+                        const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
+                        const R fs = (R)4 * th_eps / th_sig;
+                        const R dsg = fs * ((R)12 * s12 - (R)6 * s6) -
+                                      fs * ((R)12 * c12c - (R)6 * c6c) -
+                                      (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2;
+                        g0r += on ? vlj / th_eps : (R)0;
+                        g1r += on ? dsg : (R)0;
+                    }
+                } else {
+                    g = in_c ? gc : (R)0;
+                }
+                e1r += in_c ? vc : (R)0;
+                cnt += __popcll(__ballot(hit));
+                const double gd = (double)g;
+                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+                fxi += fx;
+                fyi += fy;
+                fzi += fz;
+                atomicAdd(&fjx[jj], -fx);
+                atomicAdd(&fjy[jj], -fy);
+                atomicAdd(&fjz[jj], -fz);
             }
-            const double gd = (double)g;
-            const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
-            fxi += fx;
-            fyi += fy;
-            fzi += fz;
-            atomicAdd(&fjx[jj], -fx);
-            atomicAdd(&fjy[jj], -fy);
-            atomicAdd(&fjz[jj], -fz);
-        }
+        };
+        if (bk.lj) sweep(std::true_type{});
+        else sweep(std::false_type{});
     } else {
         // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom
         const double rc = S.rc_pp, rc2 = rc * rc;
