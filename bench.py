@@ -85,6 +85,9 @@ def _workload(name):
         return synth.config_c2(), "water256 N_H=32 N_O=4 (19.7 A)"
     if name == "c1":
         return synth.config_c1(), "e64-ion-32w (10 A)"
+    if name == "c4":
+        return (synth.config_c4_states(1)[0],
+                "water256 N_H=32 N_O=4, gradient workload seed 0 (19.7 A)")
     if name == "c5":
         print("[bench] generating the 64-system batch", file=sys.stderr, flush=True)
         return (synth.config_c5(),
@@ -319,6 +322,48 @@ def _run_ewald_step(s, precision, steps, mixpi, torch, flags=0):
             "ewald": {"alpha": alpha, "r_cut": rcut, "grid": grid, "order": order}}
 
 
+def _run_adjoint(sysm, q, s, mixpi, torch, reps=50):
+    """The gradient workload: one energy + adjoint evaluation (dV/dq and
+    dV/dtheta of the six parameters) per call, timed as the library call and
+    as torch.autograd forward + backward through energy_function()."""
+    import numpy as np
+    x = s if not isinstance(s, (list, tuple)) else s[0]
+    theta = torch.tensor([[x.pp_q, x.pp_a, x.lj_eps[0, 0], x.lj_sigma[0, 0],
+                           x.bond_k[0] if len(x.bond_k) else 0.0,
+                           x.angle_k[0] if len(x.angle_k) else 0.0]],
+                         dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    dq = torch.empty_like(q)
+    dth = torch.empty((1, 6), dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) * 1e3 / reps
+
+    adj_us = timed(lambda: sysm.energy_adjoint(q, theta, dq=dq, dtheta=dth))
+    fn = mixpi.energy_function()
+    qa = q.clone().requires_grad_(True)
+    ta = theta.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        qa.grad = None
+        ta.grad = None
+        fn.apply(qa, ta, sysm).sum().backward()
+    ag_us = timed(fwd_bwd)
+    f_us = timed(lambda: sysm.forces(q))
+    return {"adjoint_us": adj_us, "autograd_fwd_bwd_us": ag_us, "forces_us": f_us,
+            "theta": ["pp_q", "pp_a", "eps_00", "sigma_00", "k_bond0", "k_angle0"]}
+
+
 def _bonded_slices(s):
     """Bond and angle slices: each term is evaluated on N_max slices."""
     n_bond = n_angle = 0
@@ -379,7 +424,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--nvt", action=argparse.BooleanOptionalAction, default=True,
@@ -477,6 +522,9 @@ def main():
                                   and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
                                   else None)},
     }
+    if args.workload == "c4":
+        print("[bench] energy adjoint and autograd (FP32 form)", file=sys.stderr, flush=True)
+        out["adjoint"] = _run_adjoint(sysm, r32["q"], s, mixpi, torch)
     if len(_as_list(s)) > 1:
         print("[bench] the same systems as separate handles, one after another",
               file=sys.stderr, flush=True)
