@@ -166,3 +166,12 @@ def test_nvt_samples_quantum_harmonic_dimers(mp):
     assert err < 0.02 * want
     assert abs(mean - want) < 4.0 * err
     assert abs(mean - classical) > 20.0 * err
+
+
+@pytest.mark.parametrize("rpw", [2, 4])
+def test_nvt_with_grouped_epilogue_rows(mp, rpw, monkeypatch):
+    """Thermostatted steps with 2 or 4 bead rows per epilogue wave."""
+    monkeypatch.setenv("MIXPI_FIN_RPW", str(rpw))
+    print(f"[nvt rpw={rpw}]", flush=True)
+    _nvt_compare(mp, synth.water_box(40, 11.0, 8, 2, seed=4, rc=5.4), 3, 25.0, 7, 1e-11, 1e-10,
+                 1e-10)

@@ -69,3 +69,26 @@ def test_vv_then_split_propagator_on_one_handle(mp):
     sysm.step_vv(3, q, p, f, elog)
     assert np.abs(from_rows(s, host(q), rows) - q3).max() <= 1e-11
     assert max(energy_err(host(elog)[k, 0], el3[k]) for k in range(3)) <= 1e-10
+
+
+@pytest.mark.parametrize("rpw", [2, 4])
+def test_vv_with_grouped_epilogue_rows(mp, rpw, monkeypatch):
+    """The velocity-Verlet epilogue (neighbour-row spring forces, spring
+    energy) with 2 or 4 bead rows per wave matches the oracle."""
+    import torch
+    monkeypatch.setenv("MIXPI_FIN_RPW", str(rpw))
+    for name, make in CASES[1:]:
+        print(f"[vv rpw={rpw}] {name}", flush=True)
+        s = make()
+        rows = layout_rows(s)
+        o = oracle.OracleSystem(s)
+        Fo0, _ = o.forces(s.q)
+        qo, po, _, elo = o.step_vv(s.q, s.p, 3, F=Fo0)
+        sysm = mp.System(s)
+        q, p = dev(to_rows(s, s.q, rows)), dev(to_rows(s, s.p, rows))
+        f = dev(to_rows(s, Fo0, rows))
+        elog = torch.zeros((3, 1, mp.MIXPI_NE), dtype=torch.float64, device="cuda")
+        sysm.step_vv(3, q, p, f, elog)
+        assert np.abs(from_rows(s, host(q), rows) - qo).max() <= 1e-11
+        assert np.abs(from_rows(s, host(p), rows) - po).max() <= 1e-10 * np.abs(po).max()
+        assert max(energy_err(host(elog)[k, 0], elo[k]) for k in range(3)) <= 1e-10
