@@ -271,7 +271,7 @@ int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, i
 
 /* One sample of the ring-polymer molecular dynamics (RPMD) centroid
  * velocity correlation function (real-time correlation functions from NVE
- * ring-polymer trajectories, Sec. "Implementation"; for the velocity, a
+ * ring-polymer trajectories, Sec. "Output and Analysis"; for the velocity, a
  * linear operator, the Kubo-transformed correlation is estimated from the
  * centroids).  p: device [rows][3] bead momenta at sample t.  The centroid
  * velocity v_i = (1/N_i) sum_j p_ij / m_f,i of every particle (handle

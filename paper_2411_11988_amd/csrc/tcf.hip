@@ -1,5 +1,5 @@
 // Ring-polymer molecular dynamics (RPMD) velocity correlation functions
-// (arXiv 2411.11988, Sec. "Implementation": real-time correlation functions
+// (arXiv 2411.11988, Sec. "Output and Analysis": real-time correlation functions
 // from NVE ring-polymer trajectories; Kubo-transformed correlations of
 // linear operators are estimated from the centroids).
 //
