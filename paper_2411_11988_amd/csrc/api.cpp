@@ -765,6 +765,31 @@ int choose_tj(const std::vector<PairBlock> &blocks, const std::vector<char> &blo
     return n64 < 2048 ? 32 : 64;
 }
 
+// Whether an atom block is swept in compacted form.  p: the expected share
+// of candidates inside the cutoff, the cutoff sphere's volume over the box
+// volume (at most 1).  A wave visits W = tj / waves j-slots per lane.  Cost
+// model, in VALU instructions of the FP32 build rounded toward measured
+// launch times: the compacted sweep spends 24 per candidate on the
+// distance pass plus, per marked slot of the fullest lane (taken as the
+// mean W p plus 2.4 standard deviations, the largest of 64 binomial
+// counts), 79 on the pair math with LJ or 58 without; the masked sweep
+// spends 77 or 55.5 per candidate.
+// Compaction is chosen when it saves at least a tenth, and only for
+// W >= 32: with 16 slots per lane the marked-slot loop's serial LDS reads
+// (one slot per iteration, at scattered addresses) cost more than the
+// instructions it saves (measured on both forms).
+bool sparse_pays(const SysDev &S, bool lj, int W)
+{
+    if (W < 32) return false;
+    const double rc = std::max(S.rc_lj, S.rc_c);
+    const double vol = S.box[0] * S.box[1] * S.box[2];
+    const double p = std::min(1.0, 4.0 / 3.0 * kPi * rc * rc * rc / vol);
+    const double hits = std::min((double)W, W * p + 2.4 * std::sqrt(W * p * (1.0 - p)));
+    const double dense = (lj ? 77.0 : 55.5) * W;
+    const double compact = 24.0 * W + (lj ? 79.0 : 58.0) * hits;
+    return compact < 0.9 * dense;
+}
+
 // Workgroup ranges over a list sorted by system: chunks of at most `per`
 // entries that never span two systems.
 std::vector<BlockRange> system_blocks(const std::vector<int> &sys_of, int begin, int end, int per)
@@ -918,6 +943,21 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
         const int v = atoi(env);
         if (v == 1 || v == 2) S->pair_waves = v;
+    }
+    {
+        // compacted sweep for atom blocks with few in-cutoff candidates;
+        // MIXPI_PAIR_SPARSE=0 or 1 forces it off or on for every atom block
+        int force = -1;
+        if (const char *env = getenv("MIXPI_PAIR_SPARSE")) {
+            const int v = atoi(env);
+            if (v == 0 || v == 1) force = v;
+        }
+        for (PairBlock &pb : B.blocks) {
+            if (pb.kind != PK_ATOM) continue;
+            pb.sparse = force >= 0 ? force
+                                   : sparse_pays(B.sys[pb.sys], pb.lj != 0,
+                                                 S->pair_tj / S->pair_waves);
+        }
     }
 
     // bonded terms and their system-pure blocks

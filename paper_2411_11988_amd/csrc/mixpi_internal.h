@@ -63,6 +63,7 @@ struct PairBlock {
     double w;             // 1 / N_a
     int nbeads_b;         // N_b
     int lj;               // some type pair of the two groups may have LJ (atom blocks)
+    int sparse;           // atom block swept in compacted form (few in-cutoff candidates)
 };
 struct PairItem {
     int block, b, i0, j0;

@@ -37,17 +37,23 @@ template <typename R> __device__ __forceinline__ R rcp_r(R x);
 template <> __device__ __forceinline__ double rcp_r<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// A j-bead of the tile in LDS: position, charge and (LJ type | mol id << 4),
-// read with two (float form) or three (double form) 128-bit LDS loads.
-template <typename R> struct JRec;
-template <> struct alignas(16) JRec<float> {
-    double x, y, z;
+// The j-beads of a tile in LDS as separate arrays (x, y, z, and charge with
+// LJ type | mol id << 4), so that a wave's reads of consecutive j-slots are
+// consecutive 8-byte words: free of bank conflicts, where 32-byte records
+// put four of a wave's slots on the same banks.
+template <typename R> struct JQ;
+template <> struct alignas(8) JQ<float> {
     float q;
     int tm;
 };
-template <> struct alignas(16) JRec<double> {
-    double x, y, z, q;
-    int tm, pad[3];
+template <> struct alignas(16) JQ<double> {
+    double q;
+    int tm, pad;
+};
+template <typename R> struct JTile {
+    double x, y, z;
+    R q;
+    int tm;
 };
 // LJ parameters of one type pair: 4 eps, sigma^2 and the two cutoff-shift
 // constants, one 128-bit (float) or two (double) LDS loads.
@@ -76,7 +82,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     const int di = a.dest[sb + lane];
     const int dj = (int)threadIdx.x < TJ ? a.dest[sb + 64 + threadIdx.x] : -1;
 
-    __shared__ JRec<R> sj[TJ];
+    __shared__ double sjx[TJ], sjy[TJ], sjz[TJ];
+    __shared__ JQ<R> sjq[TJ];
+    // j-slot jj as read by the loops
+    auto jload = [&](int jj) {
+        const JQ<R> m = sjq[jj];
+        return JTile<R>{sjx[jj], sjy[jj], sjz[jj], m.q, m.tm};
+    };
     __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
     __shared__ LjPar<R> tlj[kLjTab];
 
@@ -104,18 +116,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     const int jn = min(TJ, bk.nb - it.j0);
     if ((int)threadIdx.x < TJ) {
         const int js = threadIdx.x;
-        JRec<R> jr{};
+        double x = 0, y = 0, z = 0;
+        JQ<R> jq{};
         if (js < jn) {
             const int j = it.j0 + js;
             const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
             const int pj = bk.pb0 + j;
-            jr.x = a.q[3 * rowj];
-            jr.y = a.q[3 * rowj + 1];
-            jr.z = a.q[3 * rowj + 2];
-            jr.q = (R)a.charge[pj];
-            jr.tm = a.ljt[pj] | (a.mol[pj] << 4);
+            x = a.q[3 * rowj];
+            y = a.q[3 * rowj + 1];
+            z = a.q[3 * rowj + 2];
+            jq.q = (R)a.charge[pj];
+            jq.tm = a.ljt[pj] | (a.mol[pj] << 4);
         }
-        sj[js] = jr;
+        sjx[js] = x;
+        sjy[js] = y;
+        sjz[js] = z;
+        sjq[js] = jq;
         fjx[js] = 0.0;
         fjy[js] = 0.0;
         fjz[js] = 0.0;
@@ -164,13 +180,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         // LJ: blocks whose type pairs all have eps = 0 (and cannot reach the
         // theta-overridden pair (0, 0)) run a loop without the LJ terms; the
         // masked LJ contribution there is an exact zero, so both loops give
-        // the same bits
-        auto sweep = [&](auto lj_tag) {
+        // the same bits.
+        // SP (compacted): blocks where few candidates are inside the cutoff
+        // first mark each lane's in-cutoff j-slots in a bit mask (distance
+        // pass only), then run the pair math once per marked slot, all lanes
+        // together until the fullest lane is done.  A lane visits its marked
+        // slots in the same cyclic order as the masked loop visits all of
+        // them; the j-reactions arrive in another order.
+        auto sweep = [&](auto lj_tag, auto sp_tag) {
             constexpr bool LJ = decltype(lj_tag)::value;
-#pragma unroll 4
-            for (int t = 0; t < TJ / WAVES; ++t) {
-                const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
-                const JRec<R> jr = sj[jj];
+            constexpr bool SP = decltype(sp_tag)::value;
+            constexpr int W = TJ / WAVES;
+            // candidate (this lane's i-bead, j-slot jj); with SP the distance
+            // pass has already established that it interacts iff `live`
+            auto body = [&](int jj, bool live) {
+                const JTile<R> jr = jload(jj);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
                 const R qj = jr.q;
                 const int tp = trow + (jr.tm & 15);
@@ -179,7 +203,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 dy -= Ly * rint(dy * iLy);
                 dz -= Lz * rint(dz * iLz);
                 const double r2d = dx * dx + dy * dy + dz * dz;
-                const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
+                bool ok = live;
+                if constexpr (!SP) ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
                 const R r2 = ok ? (R)r2d : (R)1;
                 const R K = kqi * qj;
                 const bool in_c = ok && r2d < rc2_c && K != (R)0;
@@ -223,13 +248,49 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 fxi += fx;
                 fyi += fy;
                 fzi += fz;
+                if (SP && !live) return;   // nothing to add: spare the LDS
                 atomicAdd(&fjx[jj], -fx);
                 atomicAdd(&fjy[jj], -fy);
                 atomicAdd(&fjz[jj], -fz);
+            };
+            if constexpr (!SP) {
+#pragma unroll 4
+                for (int t = 0; t < W; ++t) body(wv * W + ((lane + t) & (W - 1)), true);
+            } else {
+                using Mask = std::conditional_t<(W > 32), unsigned long long, unsigned>;
+                Mask m = 0;
+#pragma unroll 4
+                for (int t = 0; t < W; ++t) {
+                    const int jj = wv * W + ((lane + t) & (W - 1));
+                    const JTile<R> jr = jload(jj);
+                    double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
+                    dx -= Lx * rint(dx * iLx);
+                    dy -= Ly * rint(dy * iLy);
+                    dz -= Lz * rint(dz * iLz);
+                    const double r2d = dx * dx + dy * dy + dz * dz;
+                    // non-short-circuit: no branch, so the unrolled steps' LDS
+                    // reads are issued together
+                    const bool ok = (jj > jlo) & (jj < jhi) & (mi != (jr.tm >> 4)) & (r2d < rc2max);
+                    m |= ok ? (Mask(1) << t) : Mask(0);
+                }
+                // wave-uniform trip count: the most marked slots of any lane
+                while (__ballot(m != 0)) {
+                    const bool live = m != 0;
+                    int t = 0;
+                    if constexpr (W > 32) t = live ? __builtin_ctzll(m) : 0;
+                    else t = live ? __builtin_ctz(m) : 0;
+                    m &= m - 1;
+                    body(wv * W + ((lane + t) & (W - 1)), live);
+                }
             }
         };
-        if (bk.lj) sweep(std::true_type{});
-        else sweep(std::false_type{});
+        if (bk.lj) {
+            if (bk.sparse) sweep(std::true_type{}, std::true_type{});
+            else sweep(std::true_type{}, std::false_type{});
+        } else {
+            if (bk.sparse) sweep(std::false_type{}, std::true_type{});
+            else sweep(std::false_type{}, std::false_type{});
+        }
     } else {
         // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom
         const double rc = S.rc_pp, rc2 = rc * rc;
@@ -245,7 +306,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
 #pragma unroll 4
         for (int t = 0; t < TJ / WAVES; ++t) {
             const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
-            const JRec<R> jr = sj[jj];
+            const JTile<R> jr = jload(jj);
             double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
             const R qj = jr.q;
             const int mj = jr.tm >> 4;

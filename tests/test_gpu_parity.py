@@ -161,7 +161,12 @@ def test_e256_ten_steps_fp64(mp):
     _step_compare(mp, SYSTEMS[7][1], FP64, 10, 1e-10, 1e-9, 1e-9)
 
 
-def test_pair_counts(mp):
+@pytest.mark.parametrize("sparse", ["auto", "1"])
+def test_pair_counts(mp, sparse, monkeypatch):
+    """Candidate and in-cutoff counts equal the oracle's (masked and
+    compacted atom-atom sweeps)."""
+    if sparse != "auto":
+        monkeypatch.setenv("MIXPI_PAIR_SPARSE", sparse)
     s = synth.config_c1()
     sysm = mp.System(s)
     n = s.n_particles
@@ -270,6 +275,50 @@ def test_pair_tile_variants(mp, tj, waves, monkeypatch):
             F = from_rows(s, host(f))
             assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
             assert e_err(prec, host(e)[0], eo) <= TOL_E[prec]
+
+
+@pytest.mark.parametrize("tj,waves", [(32, 1), (32, 2), (64, 1), (64, 2)])
+def test_pair_compacted_sweep(mp, tj, waves, monkeypatch):
+    """The compacted atom-atom sweep (a distance pass marks each lane's
+    in-cutoff j-slots; the pair math runs for those only) against the masked
+    sweep and the oracle, in both forms and with the parameter derivatives.
+    The two sweeps add the same terms; they may round differently (the
+    order of the j-reaction sums, and the compiler's contraction of each
+    loop into fused multiply-adds, which can move an FP32 pair term by an
+    ulp), so they agree to rounding: forces and gradients to 1e-12 (FP64)
+    or 1e-6 (FP32) of the RMS force; energies and theta-weighted d/dtheta to
+    1e-12 (FP64) or 1e-7 (FP32) of the energy scale sum_k |V_k|."""
+    monkeypatch.setenv("MIXPI_PAIR_TJ", str(tj))
+    monkeypatch.setenv("MIXPI_PAIR_WAVES", str(waves))
+    for name, s in (SYSTEMS[4], SYSTEMS[6], SYSTEMS[7]):
+        osys = oracle.OracleSystem(s)
+        Fo, eo = osys.forces(s.q)
+        q = dev(to_rows(s, s.q))
+        for prec in (FP64, FP32):
+            print(f"[compacted] tj={tj} waves={waves} {name} prec={prec}", flush=True)
+            res = []
+            for sp in (0, 1):
+                monkeypatch.setenv("MIXPI_PAIR_SPARSE", str(sp))
+                sysm = mp.System(s, precision=prec)
+                f, e = sysm.forces(q)
+                dq, dth = sysm.energy_adjoint(q)
+                res.append([host(x).copy() for x in (f, e, dq, dth)])
+                del sysm
+            (f0, e0, dq0, dth0), (f1, e1, dq1, dth1) = res
+            scale = np.sqrt(np.mean(f0 ** 2))
+            tol = 1e-12 if prec == FP64 else 1e-6
+            assert np.max(np.abs(f1 - f0)) <= tol * scale
+            assert np.max(np.abs(dq1 - dq0)) <= tol * scale
+            escale = np.sum(np.abs(e0[0, 1:]))
+            tol_e = 1e-12 if prec == FP64 else 1e-7
+            theta = np.array([s.pp_q, s.pp_a, s.lj_eps[0, 0], s.lj_sigma[0, 0],
+                              s.bond_k[0] if len(s.bond_k) else 0.0,
+                              s.angle_k[0] if len(s.angle_k) else 0.0])
+            assert np.max(np.abs(e1 - e0)) <= tol_e * escale
+            assert np.max(np.abs(theta * (dth1 - dth0))) <= tol_e * escale
+            F1 = from_rows(s, f1)
+            assert force_err(F1, Fo) <= TOL_F[prec], force_err(F1, Fo)
+            assert e_err(prec, e1[0], eo) <= TOL_E[prec]
 
 
 @pytest.mark.parametrize("rpw", [1, 2, 4])
