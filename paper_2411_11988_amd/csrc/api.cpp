@@ -775,9 +775,10 @@ int choose_tj(const std::vector<PairBlock> &blocks, const std::vector<char> &blo
 // counts), 79 on the pair math with LJ or 58 without; the masked sweep
 // spends 77 or 55.5 per candidate.
 // Compaction is chosen when it saves at least a tenth, and only for
-// W >= 32: with 16 slots per lane the marked-slot loop's serial LDS reads
-// (one slot per iteration, at scattered addresses) cost more than the
-// instructions it saves (measured on both forms).
+// W >= 32: with 16 slots per lane the saving is small and the marked-slot
+// loop (not unrolled, one slot per iteration at scattered LDS addresses)
+// runs slower per instruction than the masked loop, so it loses (measured
+// on both forms).
 bool sparse_pays(const SysDev &S, bool lj, int W)
 {
     if (W < 32) return false;
