@@ -95,12 +95,15 @@ struct mixpi_system {
     int pair_waves = 1;
 
     SysDev *d_sys = nullptr;
-    double *d_lj_eps = nullptr, *d_lj_sig = nullptr, *d_charge = nullptr;
+    LjPar<float> *d_ljpar_f = nullptr;          // LJ tables in the pair sweep's form
+    LjPar<double> *d_ljpar_d = nullptr;
+    double *d_charge = nullptr;
     int *d_ljt = nullptr, *d_mol = nullptr, *d_row_sys = nullptr;
     double *d_row_fm = nullptr, *d_row_hk = nullptr;
     // pair sweep: items on fast groups first, then items touching FFT groups
     PairBlock *d_blocks = nullptr;
     PairItem *d_items = nullptr;
+    PairBlock *d_iblocks = nullptr;             // the block of every item
     int n_items = 0, n_items_fast = 0;
     // radial distribution: system-pure runs of pair items, largest bead count
     BlockRange *d_rdf_ranges = nullptr;
@@ -218,8 +221,8 @@ void release(mixpi_system *s)
         (void)hipGraphExecDestroy(g.exec);
         (void)hipGraphDestroy(g.graph);
     }
-    void *ptrs[] = {s->d_sys, s->d_lj_eps, s->d_lj_sig, s->d_charge, s->d_ljt, s->d_mol,
-                    s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items,
+    void *ptrs[] = {s->d_sys, s->d_ljpar_f, s->d_ljpar_d, s->d_charge, s->d_ljt, s->d_mol,
+                    s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items, s->d_iblocks,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
                     s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
                     s->d_row_stage, s->d_stage_rows, s->d_lang, s->d_basis, s->d_tw,
@@ -503,6 +506,8 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
             pb.rowb = Bg.row;
             pb.w = 1.0 / A.N;
             pb.nbeads_b = Bg.N;
+            pb.lj_off = S.lj_off;
+            pb.nt1 = S.nt1;
             {
                 // LJ can act between the groups if a type pair of them has
                 // eps != 0, or both hold type 0 (its eps can be overridden)
@@ -1082,8 +1087,28 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         if (r && !rc) rc = r;
     };
     T(upload(&S->d_sys, B.sys));
-    T(upload(&S->d_lj_eps, B.lj_eps));
-    T(upload(&S->d_lj_sig, B.lj_sig));
+    {
+        // LJ tables in the sweep's form: 4 eps, sigma^2, V(rc), V'(rc)/rc
+        std::vector<LjPar<float>> tf(B.lj_eps.size());
+        std::vector<LjPar<double>> td(B.lj_eps.size());
+        for (const SysDev &sd : B.sys) {
+            const double rc2 = sd.rc_lj * sd.rc_lj;
+            for (int tp = 0; tp < sd.nt1 * sd.nt1; ++tp) {
+                const size_t k = (size_t)sd.lj_off + tp;
+                const double eps = B.lj_eps[k], sig = B.lj_sig[k];
+                const double s2 = sig * sig;
+                double c6 = s2 / rc2;
+                c6 = c6 * c6 * c6;
+                const double c12 = c6 * c6;
+                const LjPar<double> v{4.0 * eps, s2, 4.0 * eps * (c12 - c6),
+                                      4.0 * eps * (-12.0 * c12 + 6.0 * c6) / rc2};
+                td[k] = v;
+                tf[k] = LjPar<float>{(float)v.e4, (float)v.s2, (float)v.c0, (float)v.c1};
+            }
+        }
+        T(upload(&S->d_ljpar_f, tf));
+        T(upload(&S->d_ljpar_d, td));
+    }
     T(upload(&S->d_charge, B.charge));
     T(upload(&S->d_ljt, B.ljt));
     T(upload(&S->d_mol, B.mol));
@@ -1092,6 +1117,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_row_hk, B.row_hk));
     T(upload(&S->d_blocks, B.blocks));
     T(upload(&S->d_items, items));
+    {
+        std::vector<PairBlock> ib(items.size());
+        for (size_t k = 0; k < items.size(); ++k) ib[k] = B.blocks[items[k].block];
+        T(upload(&S->d_iblocks, ib));
+    }
     T(upload(&S->d_rdf_ranges, rdf_ranges));
     {
         std::vector<int> sp = B.sys_part;
@@ -1182,10 +1212,10 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.n_items = hi - lo;
     a.tj = s->pair_tj;
     a.waves = s->pair_waves;
-    a.blocks = s->d_blocks;
+    a.iblocks = s->d_iblocks + lo;
     a.sys = s->d_sys;
-    a.lj_eps = s->d_lj_eps;
-    a.lj_sig = s->d_lj_sig;
+    a.ljpar_f = s->d_ljpar_f;
+    a.ljpar_d = s->d_ljpar_d;
     a.charge = s->d_charge;
     a.ljt = s->d_ljt;
     a.mol = s->d_mol;

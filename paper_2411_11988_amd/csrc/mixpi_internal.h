@@ -64,6 +64,14 @@ struct PairBlock {
     int nbeads_b;         // N_b
     int lj;               // some type pair of the two groups may have LJ (atom blocks)
     int sparse;           // atom block swept in compacted form (few in-cutoff candidates)
+    int lj_off, nt1;      // the system's LJ table offset and LJ types + 1
+};
+
+// LJ parameters of one type pair in the form the pair sweep uses: 4 eps,
+// sigma^2, c0 = V(rc) and c1 = V'(rc) / rc of the unshifted potential (one
+// 128-bit LDS load in the float form, two in the double form).
+template <typename R> struct alignas(16) LjPar {
+    R e4, s2, c0, c1;
 };
 struct PairItem {
     int block, b, i0, j0;
@@ -108,9 +116,10 @@ struct PairLaunch {
     int n_items;
     int tj;                  // j-tile width (32 or 64)
     int waves;               // waves per tile (1 or 2)
-    const PairBlock *blocks;
+    const PairBlock *iblocks; // the block of every item, copied per item
     const SysDev *sys;
-    const double *lj_eps, *lj_sig;
+    const LjPar<float> *ljpar_f;   // per system at lj_off: (nt+1)^2 type pairs
+    const LjPar<double> *ljpar_d;
     const double *charge;
     const int *ljt, *mol;
     const double *q;

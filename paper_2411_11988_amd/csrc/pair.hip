@@ -55,12 +55,6 @@ template <typename R> struct JTile {
     R q;
     int tm;
 };
-// LJ parameters of one type pair: 4 eps, sigma^2 and the two cutoff-shift
-// constants, one 128-bit (float) or two (double) LDS loads.
-template <typename R> struct alignas(16) LjPar {
-    R e4, s2, c0, c1;
-};
-
 template <typename R, bool THETA, int TJ, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch bl)
 {
@@ -71,8 +65,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, red);
         return;
     }
+    // the item and its block are independent loads (the block is copied per
+    // item), so everything after them is one dependent step away
     const PairItem it = a.items[blockIdx.x];
-    const PairBlock bk = a.blocks[it.block];
+    const PairBlock bk = a.iblocks[blockIdx.x];
     const SysDev &S = a.sys[bk.sys];
     const double *th = a.theta ? a.theta + 6 * bk.sys : S.theta0;
     const int lane = threadIdx.x & 63;
@@ -92,21 +88,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
     __shared__ LjPar<R> tlj[kLjTab];
 
-    const int nt1 = S.nt1;
+    const int nt1 = bk.nt1;
     const double rc_lj = S.rc_lj, rc_c = S.rc_c;
     if (bk.kind == PK_ATOM) {
+        // the system's table, built at create time; the pair (0, 0) takes
+        // its eps and sigma from theta
+        const LjPar<R> *tab = (std::is_same<R, float>::value
+                                   ? reinterpret_cast<const LjPar<R> *>(a.ljpar_f)
+                                   : reinterpret_cast<const LjPar<R> *>(a.ljpar_d)) + bk.lj_off;
         for (int tp = lane; tp < nt1 * nt1; tp += 64) {
-            double eps = tp == 0 ? th[2] : a.lj_eps[S.lj_off + tp];
-            double sig = tp == 0 ? th[3] : a.lj_sig[S.lj_off + tp];
-            double s2 = sig * sig;
-            double c6 = s2 / (rc_lj * rc_lj);
-            c6 = c6 * c6 * c6;
-            double c12 = c6 * c6;
             LjPar<R> lp;
-            lp.e4 = (R)(4.0 * eps);
-            lp.s2 = (R)s2;
-            lp.c0 = (R)(4.0 * eps * (c12 - c6));
-            lp.c1 = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+            if (tp == 0) {
+                const double eps = th[2], sig = th[3];
+                const double s2 = sig * sig;
+                double c6 = s2 / (rc_lj * rc_lj);
+                c6 = c6 * c6 * c6;
+                const double c12 = c6 * c6;
+                lp.e4 = (R)(4.0 * eps);
+                lp.s2 = (R)s2;
+                lp.c0 = (R)(4.0 * eps * (c12 - c6));
+                lp.c1 = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+            } else {
+                lp = tab[tp];
+            }
             tlj[tp] = lp;
         }
     }
