@@ -7,12 +7,54 @@
 
 namespace mixpi {
 
-__device__ __forceinline__ double wsum(double v)
+// Wave sums by DPP lane moves (VALU operations, no trip through the LDS
+// unit as a shuffle takes).  dpp_d: lane i receives v from the lane that
+// the DPP control CTRL selects within its row of 16; lanes of rows outside
+// ROW_MASK receive 0.  The order of the additions is fixed, so the sums are
+// reproducible bit for bit.  Callers run them with every lane of the rows
+// involved active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ double row16_sum(double v)
+{
+    v += dpp_d<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124, 0xF>(v);   // row_ror:4
+    v += dpp_d<0x128, 0xF>(v);   // row_ror:8
     return v;
 }
+
+// Sum over aligned groups of G lanes (16, 32 or 64), in every lane of the
+// group.
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+    v = row16_sum(v);
+    if constexpr (G == 16) return v;
+    v += dpp_d<0x142, 0xA>(v);   // row_bcast:15: rows 1 and 3 hold rows 0+1 and 2+3
+    if constexpr (G == 32) {
+        const double s0 = readlane_d(v, 31), s1 = readlane_d(v, 63);
+        return (threadIdx.x & 32) ? s1 : s0;
+    }
+    v += dpp_d<0x143, 0xC>(v);   // row_bcast:31: row 3 holds the wave's sum
+    return readlane_d(v, 63);
+}
+
+// Sum over the wave, in every lane.
+__device__ __forceinline__ double wsum(double v) { return group_sum<64>(v); }
 
 // Sum of v over the workgroup (blockDim.x a multiple of 64), valid in
 // thread 0.  red: LDS scratch of blockDim.x / 64 doubles.

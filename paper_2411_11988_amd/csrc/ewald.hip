@@ -36,12 +36,7 @@ namespace {
 constexpr int kEwThreads = 256;
 constexpr int kFftLines = 16;   // lines per FFT workgroup
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wsum(v); }
 
 // Scaled fractional coordinate u = K frac(c / L), its grid base floor(u)
 // and offset w = u - base in [0, 1).

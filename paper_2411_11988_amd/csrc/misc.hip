@@ -14,7 +14,8 @@ struct Vec3 {
 };
 // LPR lanes per row (lanes sl = 0 .. LPR-1 of an aligned group of the
 // wave; LPR = 64 is one wave per row): slots sl, sl + LPR, ...; the group's
-// lanes then reduce by shuffles that stay inside the group, in a fixed order.
+// lanes then reduce by DPP moves that stay inside the group, in a fixed
+// order, and every lane of the group receives the sum.
 template <int LPR>
 __device__ __forceinline__ Vec3 gather_row_group(const GatherArgs &g, long long row, int sl)
 {
@@ -26,13 +27,7 @@ __device__ __forceinline__ Vec3 gather_row_group(const GatherArgs &g, long long 
         y += p[1];
         z += p[2];
     }
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-        x += __shfl_xor(x, o, 64);
-        y += __shfl_xor(y, o, 64);
-        z += __shfl_xor(z, o, 64);
-    }
-    return Vec3{x, y, z};
+    return Vec3{group_sum<LPR>(x), group_sum<LPR>(y), group_sum<LPR>(z)};
 }
 
 // RPW rows per wave, grouped exactly as in the step epilogue, so that a

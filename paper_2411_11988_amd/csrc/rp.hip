@@ -33,8 +33,7 @@ namespace mixpi {
 
 __device__ __forceinline__ double bsum256(double v, double *red)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wsum(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();

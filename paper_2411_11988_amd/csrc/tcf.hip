@@ -18,12 +18,7 @@ namespace {
 
 constexpr int kTcfThreads = 256;
 
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return wsum(v); }
 
 // one wave per particle: lanes stride over its beads
 __global__ __launch_bounds__(kTcfThreads) void k_centroid_v(const PartDev *parts, int n_part,
