@@ -71,7 +71,6 @@ void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t s
 template <int RPW>
 __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
 {
-    __shared__ double red[4];
     if ((int)blockIdx.x >= a.n_blocks) {
         // the extra workgroups: energy reduction (stage B) of the previous step
         __shared__ double racc[kReduceThreads + A_N];
@@ -117,15 +116,27 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
             vir = (q0 - c0) * fx;
         }
     }
-    ke = bsum(ke, red);
-    vir = bsum(vir, red);
-    if (a.vv) esp = bsum(esp, red);
+    // the workgroup's three sums: wave sums, then one exchange through LDS
+    // (waves added in order)
+    __shared__ double red3[3][4];
+    ke = wsum(ke);
+    vir = wsum(vir);
+    if (a.vv) esp = wsum(esp);
+    if (lane == 0) {
+        red3[0][w] = ke;
+        red3[1][w] = vir;
+        red3[2][w] = esp;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int v = 0; v < 3; ++v)
+            for (int k = 0; k < 4; ++k) t[v] += red3[v][k];
         double *e = a.eslot + (long long)blockIdx.x * A_N;
         for (int k = 0; k < A_N; ++k) e[k] = 0.0;
-        e[A_KIN] = ke;
-        e[A_VIR] = vir;
-        e[A_SPRING] = esp;
+        e[A_KIN] = t[0];
+        e[A_VIR] = t[1];
+        e[A_SPRING] = t[2];
     }
 }
 
