@@ -208,10 +208,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 dz -= Lz * rint(dz * iLz);
                 const double r2d = dx * dx + dy * dy + dz * dz;
                 bool ok = live;
-                if constexpr (!SP) ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2max;
+                // masks combine without short-circuit branches (straight-line code)
+                if constexpr (!SP) ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2max);
                 const R r2 = ok ? (R)r2d : (R)1;
                 const R K = kqi * qj;
-                const bool in_c = ok && r2d < rc2_c && K != (R)0;
+                const bool in_c = ok & (r2d < rc2_c) & (K != (R)0);
                 const R ir = rsqrt_r<R>(r2);
                 const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
                 const R gc = K * (ir * ir * ir - irc3);
@@ -224,15 +225,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                     const R s2 = lp.s2 * ir2;
                     const R s6 = s2 * s2 * s2;
                     const R s12 = s6 * s6;
-                    const bool in_lj = ok && r2d < rc2_lj && e4 != (R)0;
+                    const bool in_lj = ok & (r2d < rc2_lj) & (e4 != (R)0);
                     const R vlj = e4 * (s12 - s6) - lp.c0 - (R)0.5 * (r2 - rl2) * c1l;
                     const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
                     g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
                     e0r += in_lj ? vlj : (R)0;
-                    hit = in_lj || in_c;
+                    hit = in_lj | in_c;
                     if (THETA) {
                         // d/d eps and d/d sigma of the (0,0) LJ term
-                        const bool on = in_lj && tp == 0;
+                        const bool on = in_lj & (tp == 0);
                         const R c6 = tlj[0].s2 / rl2;
                         const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
                         const R fs = (R)4 * th_eps / th_sig;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             dy -= Ly * rint(dy * iLy);
             dz -= Lz * rint(dz * iLz);
             const double r2d = dx * dx + dy * dy + dz * dz;
-            const bool ok = jj > jlo && jj < jhi && mi != mj && r2d < rc2;
+            const bool ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2);
             const R r2 = (R)r2d;
             const R kq = e_is_i ? kc * qj : kqi;
             const R ir = rsqrt_r<R>(r2 + ra2);
