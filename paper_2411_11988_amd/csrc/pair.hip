@@ -165,8 +165,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     // per-lane sums of at most TJ terms in R, then FP64 across lanes/tiles
     R e0r = 0, e1r = 0;               // atom: LJ, Coulomb; electron: pp
     R g0r = 0, g1r = 0;               // theta partials (pp: q_e, a; atom: eps, sigma)
-    // in-cutoff slice-pairs of the wave, counted from lane masks on the
-    // scalar unit (wave-uniform)
+    // in-cutoff slice-pairs: a per-lane count (one add per candidate),
+    // summed over the wave after the loop
     int cnt = 0;
     // slots that may interact: real j, and for a group with itself j > i
     const int jlo = bk.same ? (int)max(-1LL, min((long long)TJ, idx - it.j0)) : -1;
@@ -210,7 +210,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 bool ok = live;
                 // masks combine without short-circuit branches (straight-line code)
                 if constexpr (!SP) ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2max);
-                const R r2 = ok ? (R)r2d : (R)1;
+                // no select needed: a masked candidate's r^2 is finite (padding
+                // slots sit at the origin) and every term it feeds is selected away
+                const R r2 = (R)r2d;
                 const R K = kqi * qj;
                 const bool in_c = ok & (r2d < rc2_c) & (K != (R)0);
                 const R ir = rsqrt_r<R>(r2);
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                     g = in_c ? gc : (R)0;
                 }
                 e1r += in_c ? vc : (R)0;
-                cnt += __popcll(__ballot(hit));
+                cnt += hit;
                 const double gd = (double)g;
                 const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
                 fxi += fx;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
             const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
             e0r += ok ? rpq * vq : (R)0;
-            cnt += __popcll(__ballot(ok));
+            cnt += ok;
             if (THETA) {
                 g0r += ok ? vq : (R)0;
                 g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
@@ -345,6 +347,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         }
     }
     double e0 = wsum((double)e0r), e1 = wsum((double)e1r), g0 = 0.0, g1 = 0.0;
+    cnt = (int)wsum((double)cnt);       // exact: at most 64 * TJ
 
     if (THETA) {
         g0 = wsum((double)g0r);
