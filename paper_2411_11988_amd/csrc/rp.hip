@@ -432,16 +432,26 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
         part[(jg * kCircOut + 4 * og + r) * 2 + 1] = dp[r];
     }
     __syncthreads();
-    // thread (o, v, h): half h of the j-groups of output o, value v (q or p)
+    // from here on the first wave alone: it reduces the partials, stores the
+    // outputs and sums the spring energy, ordering its LDS exchanges with
+    // wave-level fences instead of workgroup barriers
+    if (tid >= 64) return;
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // lane (o, v, h): half h of the j-groups of output o, value v (q or p)
+    static_assert(4 * kCircOut == 64, "one lane per (output, value, half)");
     double acc = 0.0;
-    if (tid < 4 * kCircOut) {
+    {
         const int o = tid % kCircOut, v = (tid / kCircOut) & 1, h = tid / (2 * kCircOut);
         for (int g = h * (kCircJg / 2); g < (h + 1) * (kCircJg / 2); ++g)
             acc += part[(g * kCircOut + o) * 2 + v];
     }
-    __syncthreads();
-    if (tid < 4 * kCircOut) part[tid] = acc;
-    __syncthreads();
+    wave_sync();
+    part[tid] = acc;
+    wave_sync();
     if (tid < kCircOut) {
         const double vq2 = part[tid] + part[2 * kCircOut + tid];
         const double vp2 = part[kCircOut + tid] + part[3 * kCircOut + tid];
@@ -456,13 +466,13 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
         const double nraw = s_sum[2][0] + s_sum[2][1] + s_sum[2][2] + s_sum[2][3];
         s_out[kCircOut] = nraw - qc;
     }
-    __syncthreads();
+    wave_sync();
     double esp = 0.0;
     if (tid < kCircOut) {
         const double dlt = s_out[tid] - s_out[tid + 1];
         esp = it.wsp * dlt * dlt;
     }
-    esp = bsum256(esp, red);
+    esp = wsum(esp);
     if (tid == 0) {
         double *e = a.eslot + (long long)blockIdx.x * A_N;
         for (int k = 0; k < A_N; ++k) e[k] = 0.0;
