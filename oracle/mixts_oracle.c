@@ -267,8 +267,10 @@ void orc_forces_o2(const orc_sys *S, const double *q, double *F, double *eout)
     double *Fth = (double *)calloc((size_t)nth * 3 * B, sizeof(double));
     double *eth = (double *)calloc((size_t)nth * E_N, sizeof(double));
 
-    /* nonbonded pairs */
-#pragma omp parallel for schedule(dynamic, 1)
+    /* nonbonded pairs; particles are dealt to the threads round-robin, so for
+       a given thread count every sum has a fixed order (a dynamic schedule
+       would make the rounding, and chaotic trajectories, vary run to run) */
+#pragma omp parallel for schedule(static, 1)
     for (int i = 0; i < S->n; ++i) {
         int tid = 0;
 #ifdef _OPENMP
