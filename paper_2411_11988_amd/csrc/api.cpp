@@ -774,10 +774,10 @@ int choose_tj(const std::vector<PairBlock> &blocks, const std::vector<char> &blo
 // of candidates inside the cutoff, the cutoff sphere's volume over the box
 // volume (at most 1).  A wave visits W = tj / waves j-slots per lane.  Cost
 // model, in VALU instructions of the FP32 build per candidate: the masked
-// sweep spends 72 with LJ, 51 without; the compacted sweep spends 28 on the
-// distance pass plus, per marked slot of the fullest lane (taken as the
+// sweep spends 70 with LJ, 49.5 without; the compacted sweep spends 28 on
+// the distance pass plus, per marked slot of the fullest lane (taken as the
 // mean W p plus 2.4 standard deviations, the largest of 64 binomial
-// counts), 75 on the pair math with LJ, 54 without.
+// counts), 74 on the pair math with LJ, 53 without.
 // Compaction is chosen when it saves at least a tenth, and only for
 // W >= 32: with 16 slots per lane the saving is small and the marked-slot
 // loop (not unrolled, one slot per iteration at scattered LDS addresses)
@@ -790,8 +790,8 @@ bool sparse_pays(const SysDev &S, bool lj, int W)
     const double vol = S.box[0] * S.box[1] * S.box[2];
     const double p = std::min(1.0, 4.0 / 3.0 * kPi * rc * rc * rc / vol);
     const double hits = std::min((double)W, W * p + 2.4 * std::sqrt(W * p * (1.0 - p)));
-    const double dense = (lj ? 72.0 : 51.0) * W;
-    const double compact = 28.0 * W + (lj ? 75.0 : 54.0) * hits;
+    const double dense = (lj ? 70.0 : 49.5) * W;
+    const double compact = 28.0 * W + (lj ? 74.0 : 53.0) * hits;
     return compact < 0.9 * dense;
 }
 
