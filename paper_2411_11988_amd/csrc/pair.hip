@@ -144,7 +144,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             x = a.q[3 * rowj];
             y = a.q[3 * rowj + 1];
             z = a.q[3 * rowj + 2];
-            jq.q = (R)a.charge[pj];
+            // electron-atom blocks with the electron as i take k_e q_j as
+            // their pseudopotential constant: scaled here, once per tile
+            jq.q = (R)(bk.kind == PK_E_ATOM ? kCoulombKcal * a.charge[pj] : a.charge[pj]);
             jq.tm = a.ljt[pj] | (a.mol[pj] << 4);
         }
         sjx[js] = x;
@@ -322,44 +324,48 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         const R psic = (R)(-1.0 / (u_c * sqrt(u_c)));
         const R chic = (R)(1.0 / (u_c * u_c * sqrt(u_c)));
         const R ra2 = (R)a2, rrc2 = (R)rc2, rpa = (R)pa, rpq = (R)pq;
-        const bool e_is_i = bk.kind == PK_E_ATOM;
         const R kqi = (R)(kCoulombKcal * qi);
-        const R kc = (R)kCoulombKcal;
+        // E_IS_I: the electron is the i side and the constant is the j
+        // atom's (pre-scaled) k_e q_j; otherwise the i atom's k_e q_i
+        auto sweep_e = [&](auto e_tag) {
+            constexpr bool E_IS_I = decltype(e_tag)::value;
 #pragma unroll 4
-        for (int t = 0; t < TJ / WAVES; ++t) {
-            const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
-            const JTile<R> jr = jload(jj);
-            double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
-            const R qj = jr.q;
-            const int mj = jr.tm >> 4;
-            dx -= Lx * rint(dx * iLx);
-            dy -= Ly * rint(dy * iLy);
-            dz -= Lz * rint(dz * iLz);
-            const double r2d = dx * dx + dy * dy + dz * dz;
-            const bool ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2);
-            const R r2 = (R)r2d;
-            const R kq = e_is_i ? kc * qj : kqi;
-            const R ir = rsqrt_r<R>(r2 + ra2);
-            const R ir3 = ir * ir * ir;
-            const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
-            const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
-            e0r += ok ? rpq * vq : (R)0;
-            cnt += ok;
-            if (THETA) {
-                g0r += ok ? vq : (R)0;
-                g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
-                                        (R)1.5 * rpa * (r2 - rrc2) * chic)
-                          : (R)0;
+            for (int t = 0; t < TJ / WAVES; ++t) {
+                const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
+                const JTile<R> jr = jload(jj);
+                double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
+                const int mj = jr.tm >> 4;
+                dx -= Lx * rint(dx * iLx);
+                dy -= Ly * rint(dy * iLy);
+                dz -= Lz * rint(dz * iLz);
+                const double r2d = dx * dx + dy * dy + dz * dz;
+                const bool ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2);
+                const R r2 = (R)r2d;
+                const R kq = E_IS_I ? jr.q : kqi;
+                const R ir = rsqrt_r<R>(r2 + ra2);
+                const R ir3 = ir * ir * ir;
+                const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
+                const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
+                e0r += ok ? rpq * vq : (R)0;
+                cnt += ok;
+                if (THETA) {
+                    g0r += ok ? vq : (R)0;
+                    g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
+                                            (R)1.5 * rpa * (r2 - rrc2) * chic)
+                              : (R)0;
+                }
+                const double gd = (double)gq;
+                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+                fxi += fx;
+                fyi += fy;
+                fzi += fz;
+                atomicAdd(&fjx[jj], -fx);
+                atomicAdd(&fjy[jj], -fy);
+                atomicAdd(&fjz[jj], -fz);
             }
-            const double gd = (double)gq;
-            const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
-            fxi += fx;
-            fyi += fy;
-            fzi += fz;
-            atomicAdd(&fjx[jj], -fx);
-            atomicAdd(&fjy[jj], -fy);
-            atomicAdd(&fjz[jj], -fz);
-        }
+        };
+        if (bk.kind == PK_E_ATOM) sweep_e(std::true_type{});
+        else sweep_e(std::false_type{});
     }
     double e0 = wsum((double)e0r), e1 = wsum((double)e1r), g0 = 0.0, g1 = 0.0;
     cnt = (int)wsum((double)cnt);       // exact: at most 64 * TJ
