@@ -149,7 +149,7 @@ struct mixpi_system {
     std::vector<double> h_prop, h_row_fm;
     std::vector<int> h_row_sys;
     std::vector<SysDev> h_sys;
-    unsigned rp_lds = 0;
+    unsigned rp_lds = 0, rp_lds_step = 0, rp_lds_nm = 0;   // dynamic LDS: largest, step items, transform items
     double *d_basis = nullptr;
     double2 *d_tw = nullptr;
     double *d_prop = nullptr;
@@ -350,7 +350,6 @@ struct Build {
     long long rows = 0;
     long long candidates = 0;
     int n_part = 0, n_groups = 0;
-    unsigned rp_lds = 0;
 };
 
 // Orthonormal real normal-mode basis of an N-bead ring, C[j*N + k].
@@ -626,7 +625,6 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 it.basis_off = B.basis_off[N];
                 B.rp_dense.push_back(it);
             }
-            B.rp_lds = std::max(B.rp_lds, (unsigned)((2 * N * N + 4 * 256) * sizeof(double)));
         } else {
             if (!B.tw_off.count(N)) {
                 B.tw_off[N] = (int)B.tw.size();
@@ -663,12 +661,23 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 it.tw_off = B.tw_off[N];
                 B.rp_fft.push_back(it);
             }
-            B.rp_lds = std::max(B.rp_lds, (unsigned)((2 * N - 1) * sizeof(double2)));
         }
     }
     B.sys_rows.push_back({row_base, row});
     B.rows = row;
     B.n_part += n;
+}
+
+// LDS bytes a ring-polymer item needs: the dense basis and its transpose,
+// the complex signal and its twiddles, or the circulant rows (q, p, a, b, c,
+// each N plus its pad) and the partial outputs.  A launch takes the largest
+// over its items, so items of small rings run more workgroups per CU.
+unsigned rp_item_lds(const RpItem &it)
+{
+    const long long N = it.N;
+    if (it.kind == RP_DENSE) return (unsigned)((2 * N * N + 4 * 256) * sizeof(double));
+    if (it.kind == RP_FFT) return (unsigned)((2 * N - 1) * sizeof(double2));
+    return (unsigned)((5 * (N + 64) + 2 * kCircJg * kCircOut) * sizeof(double));
 }
 
 // Rings propagated in bead space (circulant items): the cheapest first,
@@ -737,7 +746,6 @@ void add_circulant(Build &B, const RpItem &rg, int stage0, std::vector<RpItem> &
                 items.push_back(it);
             }
     }
-    B.rp_lds = std::max(B.rp_lds, (unsigned)((5 * (kCircMaxN + 64) + 2 * (256 / (kCircOut / 4)) * kCircOut) * sizeof(double)));
 }
 
 // Cuts the pair blocks with block_slow == slow into 64 x tj tiles: for each
@@ -986,8 +994,9 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     std::vector<RpItem> rp_nm = B.rp_dense;
     rp_nm.insert(rp_nm.end(), B.rp_fft.begin(), B.rp_fft.end());
     S->n_rp_nm = (int)rp_nm.size();
-    std::vector<RpItem> rp = B.rp_dense;
-    S->n_rp_fast = (int)rp.size();
+    // step items, longest first so that they start at once: FFT columns,
+    // then circulant items, then the dense items
+    std::vector<RpItem> rp;
     {
         std::vector<char> circ_ring = choose_circulant(B.rings);
         std::vector<RpItem> circ_items;
@@ -1007,10 +1016,14 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             add_circulant(B, rg, stage0, circ_items);
         }
         rp.insert(rp.end(), circ_items.begin(), circ_items.end());
+        rp.insert(rp.end(), B.rp_dense.begin(), B.rp_dense.end());
         S->n_stage = (int)stage_rows.size();
     }
-    S->n_rp = (int)rp.size();
-    S->rp_lds = std::max<unsigned>(B.rp_lds, kReduceThreads * sizeof(double));
+    S->n_rp = S->n_rp_fast = (int)rp.size();
+    S->rp_lds_step = S->rp_lds_nm = (unsigned)(kReduceThreads * sizeof(double));
+    for (const RpItem &it : rp) S->rp_lds_step = std::max(S->rp_lds_step, rp_item_lds(it));
+    for (const RpItem &it : rp_nm) S->rp_lds_nm = std::max(S->rp_lds_nm, rp_item_lds(it));
+    S->rp_lds = std::max(S->rp_lds_step, S->rp_lds_nm);
 
     // partial-force slots
     S->part_bonded = (long long)S->n_items * (64 + S->pair_tj);
@@ -1399,7 +1412,7 @@ RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double 
     r.f = f;
     r.cent = s->d_cent;
     r.eslot = eslot_buf(s, buf) + (long long)(s->e_rp + lo) * A_N;
-    r.lds_bytes = s->rp_lds;
+    r.lds_bytes = op == OP_STEP ? s->rp_lds_step : s->rp_lds_nm;
     return r;
 }
 

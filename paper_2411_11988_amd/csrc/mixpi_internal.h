@@ -94,6 +94,7 @@ struct BlockRange {
 // free ring-polymer / normal-mode work item
 enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
 constexpr int kCircOut = 16;       // bead outputs per circulant item
+constexpr int kCircJg = 256 / (kCircOut / 4);   // j-groups of a circulant item (4 outputs per thread)
 constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
 enum { OP_STEP = 0, OP_FWD = 1, OP_BWD = 2, OP_LANG = 3, OP_VV = 4 };
 struct RpItem {

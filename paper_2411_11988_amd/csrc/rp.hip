@@ -313,14 +313,13 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 // The spring energy of the item's bead steps (j, j+1) needs the output
 // after the item; it is the dot product of raw (q, p) with the coefficients
 // minus the centroid parts, accumulated with the loads.
-constexpr int kCircJg = 256 / (kCircOut / 4);     // j-groups per item
 __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, double *red)
 {
     const int N = it.N, n = it.n, L = it.logN;
     const int col = it.c0, i = col / 3, d = col - 3 * i;
     const int tid = threadIdx.x;
     const int lpad = L - 6;                      // one pad double per N/64 (a j-group)
-    constexpr int CS = kCircMaxN + 64;           // row stride: q, p, a, b, c rows
+    const int CS = N + 64;                       // row stride: q, p, a, b, c rows (N + pad)
     auto pad = [&](int x) { return x + (x >> lpad); };
     double *sq = smem, *sp = sq + CS, *ca = sp + CS, *cb = ca + CS, *cc = cb + CS;
     double *part = cc + CS;                      // [kCircJg][kCircOut][2]
