@@ -165,7 +165,7 @@ __device__ void fft_lines(double2 *buf, int lines, int lstride, int pstride, boo
     const int half = K / 2, nb = lines * half;
     for (int st = 1; st <= logK; ++st) {
         const int m = 1 << st, h = m >> 1;
-        for (int t = threadIdx.x; t < nb; t += kEwThreads) {
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
             const int l = line_fast ? t % lines : t / half;
             const int bb = line_fast ? t / lines : t % half;
             const int grp = bb / h, pos = bb % h;
@@ -181,7 +181,7 @@ __device__ void fft_lines(double2 *buf, int lines, int lstride, int pstride, boo
 __device__ void bitrev_lines(double2 *buf, int lines, int lstride, int pstride, bool line_fast,
                              int K, int logK)
 {
-    for (int t = threadIdx.x; t < lines * K; t += kEwThreads) {
+    for (int t = threadIdx.x; t < lines * K; t += blockDim.x) {
         const int l = line_fast ? t % lines : t / K;
         const int p = line_fast ? t / lines : t % K;
         const int r = bitrev(p, logK);
@@ -201,8 +201,8 @@ __device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot);
 // Plane x of system s as P[y][z] (row stride K).  Forward: from the
 // fixed-point grid (cleared for the next call), FFT along z then y.
 // Inverse: y then z.
-template <int P>
-__global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign)
+template <int P, int NT>
+__global__ __launch_bounds__(NT) void k_ew_plane(EwaldLaunch a, int sign)
 {
     extern __shared__ double2 plane[];
     const int K = a.K, logK = a.logK;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
     const double2 *tw = a.tw;
     if (a.tw_in_lds) {
         double2 *t = plane + K * K;
-        for (int j = threadIdx.x; j < K / 2; j += kEwThreads) t[j] = a.tw[j];
+        for (int j = threadIdx.x; j < K / 2; j += NT) t[j] = a.tw[j];
         tw = t;
     }
     if (sign < 0) {
@@ -226,13 +226,13 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
         // (particle, y-point) items are shared out, P adds each.
         unsigned long long *acc = (unsigned long long *)plane;   // real words 2e, free 2e + 1
         __shared__ int n_match;
-        for (int e = threadIdx.x; e < K * K; e += kEwThreads) plane[e] = make_double2(0.0, 0.0);
+        for (int e = threadIdx.x; e < K * K; e += NT) plane[e] = make_double2(0.0, 0.0);
         const int batch = K * K < 1024 ? K * K : 1024;
         for (int i0 = a.sys_part[s]; i0 < a.sys_part[s + 1]; i0 += batch) {
             if (threadIdx.x == 0) n_match = 0;
             __syncthreads();
             const int i1 = min(i0 + batch, a.sys_part[s + 1]);
-            for (int i = i0 + threadIdx.x; i < i1; i += kEwThreads) {
+            for (int i = i0 + threadIdx.x; i < i1; i += NT) {
                 if (a.z[i] == 0.0) continue;
                 const int ja = wrap(a.spl_base[4LL * i] - x, K);
                 if (ja >= P) continue;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
             }
             __syncthreads();
             const int items = n_match * P;
-            for (int it = threadIdx.x; it < items; it += kEwThreads) {
+            for (int it = threadIdx.x; it < items; it += NT) {
                 const unsigned long long e = acc[2 * (it / P) + 1];
                 const int i = (int)(e & 0xffffffffu), ja = (int)(e >> 32), jb = it % P;
                 const double *w = a.spl_w + (long long)i * 3 * kMaxOrder;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
             }
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+        for (int e = threadIdx.x; e < K * K; e += NT) {
             const long long fx = (long long)acc[2 * e];
             plane[e] = make_double2((double)fx * a.inv_scale, 0.0);
         }
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
         bitrev_lines(plane, K, 1, ld, true, K, logK);
         fft_lines(plane, K, 1, ld, true, K, logK, tw, sign);      // along y
     } else {
-        for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+        for (int e = threadIdx.x; e < K * K; e += NT) {
             const int y = e / K, z = e % K;
             plane[bitrev(y, logK) * ld + z] = data[e];
         }
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kEwThreads) void k_ew_plane(EwaldLaunch a, int sign
         bitrev_lines(plane, K, ld, 1, false, K, logK);
         fft_lines(plane, K, ld, 1, false, K, logK, tw, sign);     // along z
     }
-    for (int e = threadIdx.x; e < K * K; e += kEwThreads) {
+    for (int e = threadIdx.x; e < K * K; e += NT) {
         const int y = e / K, z = e % K;
         data[e] = plane[y * ld + z];
     }
@@ -550,11 +550,20 @@ void launch_order(const EwaldLaunch &a, hipStream_t st)
     size_t plane_lds = sizeof(double2) * K * K;
     b.tw_in_lds = plane_lds + sizeof(double2) * (K / 2) <= 65536 ? 1 : 0;
     if (b.tw_in_lds) plane_lds += sizeof(double2) * (K / 2);
-    hipLaunchKernelGGL(k_ew_plane<P>, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, -1);
+    // few planes (one system): 1024 threads each, so that spreading and the
+    // plane FFTs use more of the chip; many planes: 256
+    const bool wide = a.n_sys * K < 1024;
+    if (wide)
+        hipLaunchKernelGGL((k_ew_plane<P, 1024>), dim3(a.n_sys * K), dim3(1024), plane_lds, st, b, -1);
+    else
+        hipLaunchKernelGGL((k_ew_plane<P, kEwThreads>), dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, -1);
     const int xgroups = a.n_sys * (K * K / kFftLines);
     hipLaunchKernelGGL(k_ew_xline, dim3(xgroups + a.n_real), dim3(kEwThreads),
                        sizeof(double2) * (kFftLines * K + K / 2), st, a);
-    hipLaunchKernelGGL(k_ew_plane<P>, dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, 1);
+    if (wide)
+        hipLaunchKernelGGL((k_ew_plane<P, 1024>), dim3(a.n_sys * K), dim3(1024), plane_lds, st, b, 1);
+    else
+        hipLaunchKernelGGL((k_ew_plane<P, kEwThreads>), dim3(a.n_sys * K), dim3(kEwThreads), plane_lds, st, b, 1);
     hipLaunchKernelGGL(k_ew_gather<P>, dim3(pblocks + a.n_sys), dim3(kEwThreads), 0, st, a);
 }
 
