@@ -367,16 +367,38 @@ __device__ void real_space(const EwaldLaunch &a, const RealItem &it, int slot)
     const double two_a_rpi = 2.0 * alpha / sqrt(kPi);
     double fx = 0, fy = 0, fz = 0, e = 0;
     if (vi && qi != 0.0) {
-        for (int t = wv; t < it.nj; t += kEwThreads / 64) {
-            const double qq = qi * sq[t];
-            if (qq == 0.0 || it.j0 + t == i) continue;
-            double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
+        // wave wv takes j = wv, wv + 4, ...  A distance pass marks, in bit k
+        // of a per-lane mask, the k-th of them that interacts (inside r_cut,
+        // or of the same molecule: the erf correction); then each lane
+        // evaluates only its marked pairs, in the same order, so the lanes
+        // no longer all run erfc for every j while a fifth of them need it.
+        constexpr int NW = kEwThreads / 64;
+        static_assert(kEwChunk / NW <= 32, "one 32-bit mask per lane");
+        const int nk = (it.nj - wv + NW - 1) / NW;
+        auto sep = [&](int t, double &dx, double &dy, double &dz) {
+            dx = xi - sx[t];
+            dy = yi - sy[t];
+            dz = zi - sz[t];
             dx -= S.box[0] * rint(dx * S.ibox[0]);
             dy -= S.box[1] * rint(dy * S.ibox[1]);
             dz -= S.box[2] * rint(dz * S.ibox[2]);
-            const double r2 = dx * dx + dy * dy + dz * dz;
+            return dx * dx + dy * dy + dz * dz;
+        };
+        unsigned m = 0;
+        for (int k = 0; k < nk; ++k) {
+            const int t = wv + NW * k;
+            double dx, dy, dz;
+            const double r2 = sep(t, dx, dy, dz);
+            const bool on = (qi * sq[t] != 0.0) & (it.j0 + t != i) & ((sm[t] == mi) | (r2 < rc2));
+            m |= on ? (1u << k) : 0u;
+        }
+        while (m != 0) {
+            const int t = wv + NW * __builtin_ctz(m);
+            m &= m - 1;
+            const double qq = qi * sq[t];
+            double dx, dy, dz;
+            const double r2 = sep(t, dx, dy, dz);
             const bool excl = sm[t] == mi;
-            if (!excl && !(r2 < rc2)) continue;
             const double r = sqrt(r2);
             const double ir = 1.0 / r;
             const double gauss = two_a_rpi * exp(-alpha * alpha * r2);
