@@ -60,7 +60,9 @@ __global__ __launch_bounds__(64 * kRdfWaves) void k_rdf(RdfLaunch a)
     const int lane = threadIdx.x & 63;
     const int wv = (int)threadIdx.x >> 6;
     const double L[3] = {S.box[0], S.box[1], S.box[2]};
+    const double iL[3] = {S.ibox[0], S.ibox[1], S.ibox[2]};
     const double rmax = a.rmax;
+    const double screen2 = rmax * rmax * (1.0 + 1e-9);
     const double dr = a.rmax / nbins;
     for (int k = wv; k < rg.count; k += kRdfWaves) {
         const PairItem it = a.items[rg.begin + k];
@@ -103,6 +105,17 @@ __global__ __launch_bounds__(64 * kRdfWaves) void k_rdf(RdfLaunch a)
         for (int js = jlo + 1; js < jhi; ++js) {
             const RdfJ r = sj[wv][js];
             if (r.mol == mi) continue;
+            // cheap screen with multiplications by 1/L: a pair clearly
+            // beyond r_max (margin 1e-9 relative, far above the few ulps the
+            // screen can differ from the exact distance by) is skipped; the
+            // rest take the exact, oracle-identical evaluation below
+            {
+                double ex = xi - r.x, ey = yi - r.y, ez = zi - r.z;
+                ex -= L[0] * rint(ex * iL[0]);
+                ey -= L[1] * rint(ey * iL[1]);
+                ez -= L[2] * rint(ez * iL[2]);
+                if (ex * ex + ey * ey + ez * ez > screen2) continue;
+            }
             double dx = nearest(xi - r.x, L[0]);
             double dy = nearest(yi - r.y, L[1]);
             double dz = nearest(zi - r.z, L[2]);
