@@ -43,6 +43,25 @@ __device__ __forceinline__ double bsum256(double v, double *red)
     return s;
 }
 
+// Global -> LDS copy of n elements; thread t takes t, t + 256, ...  The
+// loads of U consecutive rounds are issued before their LDS stores, so a
+// thread waits on memory once per U rounds instead of once per element
+// (a plain copy loop waits for each load before its store).
+template <int U, typename Get, typename Put>
+__device__ __forceinline__ void lds_fill(int n, Get get, Put put)
+{
+    using T = decltype(get(0));
+    for (int b = threadIdx.x; b < n; b += U * 256) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b + u * 256 < n) v[u] = get(b + u * 256);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b + u * 256 < n) put(b + u * 256, v[u]);
+    }
+}
+
 __device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, double *red)
 {
     const int N = it.N, n = it.n;
@@ -55,10 +74,8 @@ __device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, doub
     double *s2 = s1 + 256;
     double *s3 = s2 + 256;
     const double *Cg = a.basis + it.basis_off;
-    for (int i = tid; i < 2 * N * N; i += 256) sC[i] = Cg[i];
-
     const double hk = a.sys[it.sys].hkick;
-    {   // stage: column fastest
+    {   // stage: column fastest; the state loads go out before the basis
         const int r = tid / CB, cl = tid % CB;
         double v0 = 0.0, v1 = 0.0;
         if (cl < it.ncols) {
@@ -66,6 +83,7 @@ __device__ void rp_dense(const RpLaunch &a, const RpItem &it, double *smem, doub
             v0 = a.in_q[g];
             if (a.op == OP_STEP) v1 = a.p[g] + hk * a.f[g];
         }
+        lds_fill<8>(2 * N * N, [&](int x) { return Cg[x]; }, [&](int x, double v) { sC[x] = v; });
         if (a.op == OP_BWD) s2[r * CB + cl] = v0;
         else { s0[r * CB + cl] = v0; s1[r * CB + cl] = v1; }
     }
@@ -181,24 +199,30 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
     const int col = it.c0, i = col / 3, d = col - 3 * i;
     // stage-major twiddles (N - 1 entries) staged in LDS behind the signal
     double2 *tw = z + N;
-    for (int m = threadIdx.x; m < N - 1; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
+    const double2 *twg = a.twiddle + it.tw_off;
     const int tid = threadIdx.x;
     const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
     const double hk = a.sys[it.sys].hkick;
     auto gaddr = [&](int j) { return (it.row + (long long)j * n) * 3 + col; };
 
     if (a.op == OP_BWD) {
+        lds_fill<4>(N - 1, [&](int m) { return twg[m]; }, [&](int m, double2 v) { tw[m] = v; });
         // modes -> Hermitian spectrum Z; load conj(Z) in bit-reversed order
-        for (int m = tid; m <= N / 2; m += blockDim.x) {
-            if (m == 0 || 2 * m == N) {
-                z[brev(m, L)] = make_double2(rN * a.in_q[gaddr(m)], 0.0);
-            } else {
-                const double x1 = a.in_q[gaddr(m)], x2 = a.in_q[gaddr(N - m)];
-                // Z_m = sqrt(N/2) (xi_m + i xi_{N-m}), Z_{N-m} = conj(Z_m)
-                z[brev(m, L)] = make_double2(rN2 * x1, -rN2 * x2);       // conj(Z_m)
-                z[brev(N - m, L)] = make_double2(rN2 * x1, rN2 * x2);    // conj(Z_{N-m})
-            }
-        }
+        auto lone = [&](int m) { return m == 0 || 2 * m == N; };
+        lds_fill<4>(
+            N / 2 + 1,
+            [&](int m) {
+                return make_double2(a.in_q[gaddr(m)], lone(m) ? 0.0 : a.in_q[gaddr(N - m)]);
+            },
+            [&](int m, double2 x) {
+                if (lone(m)) {
+                    z[brev(m, L)] = make_double2(rN * x.x, 0.0);
+                } else {
+                    // Z_m = sqrt(N/2) (xi_m + i xi_{N-m}), Z_{N-m} = conj(Z_m)
+                    z[brev(m, L)] = make_double2(rN2 * x.x, -rN2 * x.y);       // conj(Z_m)
+                    z[brev(N - m, L)] = make_double2(rN2 * x.x, rN2 * x.y);    // conj(Z_{N-m})
+                }
+            });
         fft_stages(z, tw, N, L);
         for (int j = tid; j < N; j += blockDim.x) a.out_q[gaddr(j)] = z[j].x / N;
         return;
@@ -214,12 +238,23 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
             const int m = tid + r * (int)blockDim.x;
             for (int c = 0; c < 5; ++c) pre[r][c] = m <= N / 2 ? prow(m)[c] : 0.0;
         }
-    for (int j = tid; j < N; j += blockDim.x) {
-        const long long g = gaddr(j);
-        const double re = a.in_q[g];
-        const double im = a.op == OP_STEP ? a.p[g] + hk * a.f[g] : 0.0;
-        z[brev(j, L)] = make_double2(re, im);
-    }
+    // the signal and the twiddles in one fill: one wait on memory per 4 rounds
+    struct In {
+        double2 z, t;
+    };
+    lds_fill<4>(
+        N,
+        [&](int j) {
+            const long long g = gaddr(j);
+            In v;
+            v.z = make_double2(a.in_q[g], a.op == OP_STEP ? a.p[g] + hk * a.f[g] : 0.0);
+            v.t = j < N - 1 ? twg[j] : make_double2(0.0, 0.0);
+            return v;
+        },
+        [&](int j, const In &v) {
+            z[brev(j, L)] = v.z;
+            if (j < N - 1) tw[j] = v.t;
+        });
     fft_stages(z, tw, N, L);
 
     if (a.op == OP_FWD) {
@@ -488,22 +523,49 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
 // noise is an input, indexed by mode like the mode coordinates.  Rows of
 // circulant rings also get their stage rows (q, p + dt/2 F) for the next
 // step, since p changed after the epilogue wrote them.
-__device__ __forceinline__ double lang_o(const RpLaunch &a, long long rowm, int d, double x)
+// The thermostat terms of mode row r (coefficients and noise), and the
+// stage inputs of output row `row`, are loaded before an item's transforms,
+// together with its momenta, so that their memory latency is paid once.
+struct OTerms {
+    double c1, c2, n1, n2;
+};
+__device__ __forceinline__ OTerms o_load(const RpLaunch &a, long long r, int d)
 {
-    const double c1 = a.lang[2 * rowm], c2 = a.lang[2 * rowm + 1];
-    if (a.noise1) x = c1 * x + c2 * a.noise1[3 * rowm + d];
-    if (a.noise2) x = c1 * x + c2 * a.noise2[3 * rowm + d];
+    OTerms t;
+    t.c1 = a.lang[2 * r];
+    t.c2 = a.lang[2 * r + 1];
+    t.n1 = a.noise1 ? a.noise1[3 * r + d] : 0.0;
+    t.n2 = a.noise2 ? a.noise2[3 * r + d] : 0.0;
+    return t;
+}
+__device__ __forceinline__ double o_apply(const RpLaunch &a, const OTerms &t, double x)
+{
+    if (a.noise1) x = t.c1 * x + t.c2 * t.n1;
+    if (a.noise2) x = t.c1 * x + t.c2 * t.n2;
     return x;
 }
 
-__device__ __forceinline__ void lang_store(const RpLaunch &a, long long row, long long g, int d,
-                                           double pn)
+struct StageTerms {
+    int st;
+    double q, hk, f;
+};
+__device__ __forceinline__ StageTerms stage_load(const RpLaunch &a, long long row, long long g)
+{
+    StageTerms s{a.row_stage[row], 0.0, 0.0, 0.0};
+    if (s.st >= 0) {
+        s.q = a.in_q[g];
+        s.hk = a.row_hk[row];
+        s.f = a.f[g];
+    }
+    return s;
+}
+__device__ __forceinline__ void stage_store(const RpLaunch &a, const StageTerms &s, long long g,
+                                            int d, double pn)
 {
     a.p[g] = pn;
-    const int st = a.row_stage[row];
-    if (st >= 0) {
-        a.stage[6LL * st + d] = a.in_q[g];
-        a.stage[6LL * st + 3 + d] = pn + a.row_hk[row] * a.f[g];
+    if (s.st >= 0) {
+        a.stage[6LL * s.st + d] = s.q;
+        a.stage[6LL * s.st + 3 + d] = pn + s.hk * s.f;
     }
 }
 
@@ -517,40 +579,92 @@ __device__ void rp_lang_dense(const RpLaunch &a, const RpItem &it, double *smem)
     double *s0 = sCT + N * N;       // [N][CB] momenta
     double *s2 = s0 + 256;          // [N][CB] modes
     const double *Cg = a.basis + it.basis_off;
-    for (int x = tid; x < 2 * N * N; x += 256) sC[x] = Cg[x];
     const int cl = tid % CB, k = tid / CB;
     const bool valid = cl < it.ncols;
     const int c = it.c0 + cl, i = c / 3, d = c - 3 * i;
-    {
-        const long long g = (it.row + (long long)k * n) * 3 + c;
-        s0[k * CB + cl] = valid ? a.p[g] : 0.0;
+    // thread (k, cl) owns mode row k and bead row k of column cl
+    const long long rowk = it.row + (long long)k * n + i;
+    OTerms t{};
+    StageTerms sg{-1, 0.0, 0.0, 0.0};
+    double p0 = 0.0;
+    if (valid) {
+        p0 = a.p[rowk * 3 + d];
+        t = o_load(a, rowk, d);
+        sg = stage_load(a, rowk, rowk * 3 + d);
     }
+    lds_fill<8>(2 * N * N, [&](int x) { return Cg[x]; }, [&](int x, double v) { sC[x] = v; });
+    s0[k * CB + cl] = p0;
     __syncthreads();
     double pi = 0.0;
     for (int j = 0; j < N; ++j) pi += sC[j * N + k] * s0[j * CB + cl];
-    if (valid) pi = lang_o(a, it.row + (long long)k * n + i, d, pi);
+    if (valid) pi = o_apply(a, t, pi);
     s2[k * CB + cl] = pi;
     __syncthreads();
-    const int j = k;
     double pn = 0.0;
-    for (int m = 0; m < N; ++m) pn += sCT[m * N + j] * s2[m * CB + cl];
-    if (valid) {
-        const long long row = it.row + (long long)j * n + i;
-        lang_store(a, row, row * 3 + d, d, pn);
-    }
+    for (int m = 0; m < N; ++m) pn += sCT[m * N + k] * s2[m * CB + cl];
+    if (valid) stage_store(a, sg, rowk * 3 + d, d, pn);
 }
 
 constexpr int kLangKeep = (kMaxBeads / 2 + 1 + 255) / 256;
+constexpr int kLangPre = 3;     // mode slots with terms prefetched (all for N <= 1024)
+constexpr int kLangOutPre = 4;  // output slots with stage inputs prefetched
 __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
 {
     const int N = it.N, L = it.logN, n = it.n;
     const int col = it.c0, i = col / 3, d = col - 3 * i;
     double2 *tw = z + N;
-    for (int m = threadIdx.x; m < N - 1; m += blockDim.x) tw[m] = a.twiddle[it.tw_off + m];
     const int tid = threadIdx.x;
     const double rN = sqrt((double)N), r2N = sqrt(2.0 / N), rN2 = sqrt(0.5 * N);
     auto rowm = [&](int k) { return it.row + (long long)k * n + i; };
-    for (int j = tid; j < N; j += blockDim.x) z[brev(j, L)] = make_double2(a.p[rowm(j) * 3 + d], 0.0);
+    // modes m and N - m of slot r share a thread; m = 0 and m = N/2 are alone
+    auto lone = [&](int m) { return m == 0 || 2 * m == N; };
+    OTerms ot[kLangPre][2] = {};
+#pragma unroll
+    for (int r = 0; r < kLangPre; ++r) {
+        const int m = tid + r * 256;
+        if (m <= N / 2) {
+            ot[r][0] = o_load(a, rowm(m), d);
+            if (!lone(m)) ot[r][1] = o_load(a, rowm(N - m), d);
+        }
+    }
+    // stage rows of the first outputs: their indices now, their inputs after
+    // the fill (then used after the transforms)
+    int sst[kLangOutPre];
+#pragma unroll
+    for (int r = 0; r < kLangOutPre; ++r) {
+        const int j = tid + r * 256;
+        sst[r] = j < N ? a.row_stage[rowm(j)] : -1;
+    }
+    // momenta and twiddles in one fill: one wait on memory per 4 rounds
+    const double2 *twg = a.twiddle + it.tw_off;
+    struct In {
+        double p;
+        double2 t;
+    };
+    lds_fill<4>(
+        N,
+        [&](int j) {
+            In v;
+            v.p = a.p[rowm(j) * 3 + d];
+            v.t = j < N - 1 ? twg[j] : make_double2(0.0, 0.0);
+            return v;
+        },
+        [&](int j, const In &v) {
+            z[brev(j, L)] = make_double2(v.p, 0.0);
+            if (j < N - 1) tw[j] = v.t;
+        });
+    StageTerms sg[kLangOutPre] = {};
+#pragma unroll
+    for (int r = 0; r < kLangOutPre; ++r) {
+        const int j = tid + r * 256;
+        sg[r].st = sst[r];
+        if (sst[r] >= 0) {
+            const long long row = rowm(j);
+            sg[r].q = a.in_q[row * 3 + d];
+            sg[r].hk = a.row_hk[row];
+            sg[r].f = a.f[row * 3 + d];
+        }
+    }
     fft_stages(z, tw, N, L);
     // modes of p (as the forward transform), thermostatted, then the
     // conjugated Hermitian spectrum of the new modes (as the backward one)
@@ -559,13 +673,21 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
     for (int r = 0; r < kLangKeep; ++r) {
         const int m = tid + r * 256;
         if (m > N / 2) break;
+        OTerms t0, t1;
+        if (r < kLangPre) {
+            t0 = ot[r][0];
+            t1 = ot[r][1];
+        } else {
+            t0 = o_load(a, rowm(m), d);
+            t1 = lone(m) ? t0 : o_load(a, rowm(N - m), d);
+        }
         const double2 Z = z[m];
-        if (m == 0 || 2 * m == N) {
-            const double x = lang_o(a, rowm(m), d, Z.x / rN);
+        if (lone(m)) {
+            const double x = o_apply(a, t0, Z.x / rN);
             keep[r] = make_double2(rN * x, 0.0);
         } else {
-            const double x1 = lang_o(a, rowm(m), d, r2N * Z.x);
-            const double x2 = lang_o(a, rowm(N - m), d, r2N * Z.y);
+            const double x1 = o_apply(a, t0, r2N * Z.x);
+            const double x2 = o_apply(a, t1, r2N * Z.y);
             keep[r] = make_double2(rN2 * x1, rN2 * x2);
         }
     }
@@ -574,7 +696,7 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
     for (int r = 0; r < kLangKeep; ++r) {
         const int m = tid + r * 256;
         if (m > N / 2) break;
-        if (m == 0 || 2 * m == N) {
+        if (lone(m)) {
             z[brev(m, L)] = keep[r];
         } else {
             z[brev(m, L)] = make_double2(keep[r].x, -keep[r].y);
@@ -582,9 +704,13 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
         }
     }
     fft_stages(z, tw, N, L);
-    for (int j = tid; j < N; j += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < kMaxBeads / 256; ++r) {
+        const int j = tid + r * 256;
+        if (j >= N) break;
         const long long row = rowm(j);
-        lang_store(a, row, row * 3 + d, d, z[j].x / N);
+        const StageTerms st = r < kLangOutPre ? sg[r] : stage_load(a, row, row * 3 + d);
+        stage_store(a, st, row * 3 + d, d, z[j].x / N);
     }
 }
 
@@ -603,7 +729,8 @@ __device__ void rp_vv(const RpLaunch &a, const RpItem &it, double *smem, double 
     double *sn = smem + N * nc;         // [N][nc] new q
     const double hk = a.sys[it.sys].hkick;
     auto gaddr = [&](int j, int cl) { return (it.row + (long long)j * n) * 3 + it.c0 + cl; };
-    for (int e = tid; e < N * nc; e += 256) sq[e] = a.in_q[gaddr(e / nc, e % nc)];
+    lds_fill<8>(N * nc, [&](int e) { return a.in_q[gaddr(e / nc, e % nc)]; },
+                [&](int e, double v) { sq[e] = v; });
     __syncthreads();
     const double s1 = sin(kPi / N), lam1 = 4.0 * s1 * s1;
     for (int e = tid; e < N * nc; e += 256) {
