@@ -52,7 +52,7 @@ KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/cs
 # masked-off math of out-of-cutoff candidates; same source-hash condition.
 VALU = {"insts_valu": 3482804, "flop_executed": 158336726}
 TRAFFIC = {"workload": "c3", "tile": "32x2",
-           "sha256": "9e9588c23f3d0c6391550b68c3e12e97ce8b3286b9bcf0cc56920fc99e2cb8d9",
+           "sha256": "feabb4eacfbb95670c9dca8e65deb5232d42817a92f693aea05eb20083a51098",
            "bytes": (990.85 * 2.0 + 6543.73 * 1.0) * 1024}
 
 

@@ -110,6 +110,7 @@ struct mixpi_system {
     int n_rdf_ranges = 0, top_beads = 1, max_nt1 = 1;
     // centroid quantities: particles in handle order, first particle per system
     PartDev *d_parts = nullptr;
+    unsigned char *d_pspec = nullptr;          // species of every particle (correlation sums)
     int *d_sys_part = nullptr;
     std::vector<PartDev> h_parts;
     std::vector<int> h_sys_part;
@@ -230,8 +231,8 @@ void release(mixpi_system *s)
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
                     s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch,
-                    s->d_rdf_ranges, s->d_parts, s->d_sys_part, s->d_red_fE, s->d_red_aE,
-                    s->d_red_vE};
+                    s->d_rdf_ranges, s->d_parts, s->d_pspec, s->d_sys_part, s->d_red_fE,
+                    s->d_red_aE, s->d_red_vE};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -1139,6 +1140,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         std::vector<int> sp = B.sys_part;
         sp.push_back(B.n_part);
         T(upload(&S->d_parts, B.parts));
+        {
+            std::vector<unsigned char> ps(B.parts.size());
+            for (size_t k = 0; k < ps.size(); ++k) ps[k] = (unsigned char)B.parts[k].spec;
+            T(upload(&S->d_pspec, ps));
+        }
         T(upload(&S->d_sys_part, sp));
         S->h_parts = B.parts;
         S->h_sys_part = sp;
@@ -1890,6 +1896,7 @@ int mixpi_vacf_sample(mixpi_system *sys, const double *p, int64_t t, int32_t L, 
     HIP_TRY(hipSetDevice(sys->device));
     TcfLaunch a{};
     a.parts = sys->d_parts;
+    a.spec = sys->d_pspec;
     a.sys_part = sys->d_sys_part;
     a.sys = sys->d_sys;
     a.ring = ring;

@@ -282,6 +282,7 @@ struct PartDev {
 // One sample of the centroid velocity correlator.
 struct TcfLaunch {
     const PartDev *parts;
+    const unsigned char *spec;   // [n_part] species, as parts[i].spec (one byte per particle)
     const int *sys_part;     // [n_sys + 1] first particle of each system
     const SysDev *sys;
     double *ring;            // [L][n_part][3]

@@ -29,11 +29,26 @@ __global__ __launch_bounds__(kTcfThreads) void k_centroid_v(const PartDev *parts
     const int lane = threadIdx.x & 63;
     const PartDev pd = parts[i];
     double sx = 0, sy = 0, sz = 0;
-    for (int j = lane; j < pd.nb; j += 64) {
-        const long long r = pd.row0 + (long long)j * pd.stride;
-        sx += p[3 * r];
-        sy += p[3 * r + 1];
-        sz += p[3 * r + 2];
+    // beads lane, lane + 64, ... added in that order; the loads of U beads
+    // are in flight together
+    constexpr int U = 8;
+    for (int j0 = lane; j0 < pd.nb; j0 += 64 * U) {
+        double v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            const long long r = pd.row0 + (long long)(j < pd.nb ? j : 0) * pd.stride;
+            v[u][0] = p[3 * r];
+            v[u][1] = p[3 * r + 1];
+            v[u][2] = p[3 * r + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + 64 * u < pd.nb) {
+                sx += v[u][0];
+                sy += v[u][1];
+                sz += v[u][2];
+            }
     }
     sx = wave_sum_d(sx);
     sy = wave_sum_d(sy);
@@ -56,12 +71,29 @@ __global__ __launch_bounds__(kTcfThreads) void k_vacf(TcfLaunch a)
     double part[kMaxLjTypes + 1];
 #pragma unroll
     for (int k = 0; k <= kMaxLjTypes; ++k) part[k] = 0.0;
-    for (int i = a.sys_part[s] + threadIdx.x; i < a.sys_part[s + 1]; i += kTcfThreads) {
-        const double d = prv[3LL * i] * cur[3LL * i] + prv[3LL * i + 1] * cur[3LL * i + 1] +
-                         prv[3LL * i + 2] * cur[3LL * i + 2];
-        const int sp = a.parts[i].spec;
+    // particles i, i + 256, ... of the system in that order; the loads of U
+    // particles are in flight together
+    constexpr int U = 8;
+    const int i1 = a.sys_part[s + 1];
+    for (int i0 = a.sys_part[s] + threadIdx.x; i0 < i1; i0 += kTcfThreads * U) {
+        double pv[U][3], cv[U][3];
+        int spv[U];
 #pragma unroll
-        for (int k = 0; k <= kMaxLjTypes; ++k) part[k] += sp == k ? d : 0.0;
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + kTcfThreads * u < i1 ? i0 + kTcfThreads * u : i0;
+            for (int c = 0; c < 3; ++c) {
+                pv[u][c] = prv[3LL * i + c];
+                cv[u][c] = cur[3LL * i + c];
+            }
+            spv[u] = a.spec[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + kTcfThreads * u >= i1) break;
+            const double d = pv[u][0] * cv[u][0] + pv[u][1] * cv[u][1] + pv[u][2] * cv[u][2];
+#pragma unroll
+            for (int k = 0; k <= kMaxLjTypes; ++k) part[k] += spv[u] == k ? d : 0.0;
+        }
     }
     __shared__ double red[kTcfThreads / 64][kMaxLjTypes + 1];
     const int lane = threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
