@@ -1035,7 +1035,9 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     // long runs keep a whole wave each.
     {
         const double avg = B.rows > 0 ? (double)G.row_ptr.back() / B.rows : 0.0;
-        S->fin_rpw = B.rows < 4096 ? 1 : (avg <= 24.0 ? 4 : (avg <= 48.0 ? 2 : 1));
+        // rows per wave by the mean partial run: 4 up to 48 slots (16 lanes a
+        // row, at most three rounds), 2 up to 96
+        S->fin_rpw = B.rows < 4096 ? 1 : (avg <= 48.0 ? 4 : (avg <= 96.0 ? 2 : 1));
         if (const char *env = getenv("MIXPI_FIN_RPW")) {
             const int v = atoi(env);
             if (v == 1 || v == 2 || v == 4) S->fin_rpw = v;
