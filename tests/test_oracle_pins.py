@@ -473,6 +473,69 @@ def test_observables_classical_limits():
     assert e[oracle.E_NAMES.index("kin")] == pytest.approx(ke, rel=1e-13)
 
 
+def _ke_quantum_finite_p(N, w, bh, kT):
+    """Exact kinetic energy (kcal/mol, three Cartesian components) of an
+    N-bead ring in an isotropic harmonic well of frequency w, under the
+    discretised path-integral distribution: (3 kT / 2) [1 + sum_{k>=1}
+    w^2 / (w^2 + w_k^2)], w_k = 2 (N / beta hbar) sin(pi k / N).  It tends
+    to (3 hbar w / 4) coth(beta hbar w / 2) as N grows."""
+    wk = 2.0 * (N / bh) * np.sin(np.pi * np.arange(1, N) / N)
+    return 1.5 * kT * (1.0 + np.sum(w * w / (w * w + wk * wk)))
+
+
+def test_kinetic_estimators_exact_expectation_harmonic_rings():
+    """Kinetic-energy estimators of Sec. Output and Analysis at N > 1:
+    rings of 16, 4 and 1 beads, each in its own harmonic well, one 1-body
+    term per particle in Eq. (mts-hamiltonian) (slice weight 1/N_i, bead
+    force -m w^2 (q - c) / N_i).  The ring distribution is Gaussian with
+    the covariance of the springs of Eq. (mts-hamiltonian-b) plus the well
+    (linear algebra); both estimators are quadratic in q, so their mean
+    over the distribution is exactly the sigma-point average (+/- sqrt(D)
+    times the columns of a Cholesky factor).  Both means must equal the
+    exact finite-N kinetic energy; a flipped virial sign, q instead of
+    q - q_bar, or 3 instead of 3 N_i in the primitive estimator fails."""
+    T = 300.0
+    Ns = [16, 4, 1]
+    masses = [1.00794, 15.9994, 58.9332]
+    bh = _beta_hbar(T)
+    ws = [3.0 / bh, 7.0 / bh, 1.5 / bh]              # beta hbar omega = 3, 7, 1.5
+    centres = np.array([[1.0, -2.0, 0.5], [4.0, 3.0, -1.0], [-3.0, 0.0, 2.0]])
+    B = sum(Ns)
+    s = custom(Ns, np.zeros((B, 3)), mass=masses, temperature=T)
+    o = oracle.OracleSystem(s)
+    kcal = oracle.constants()["kcal"]
+    kT = oracle.constants()["kb_kcal"] * T
+    beta = 1.0 / (sc.k * T / (sc.atomic_mass * 1e-20 / 1e-30))   # 1 / (amu A^2 fs^-2)
+    # covariance of one Cartesian component of every bead (block per particle)
+    cov = np.zeros((B, B))
+    off = np.concatenate([[0], np.cumsum(Ns)])
+    for i, (N, m, w) in enumerate(zip(Ns, masses, ws)):
+        A = (m * w * w / N) * np.eye(N) + (N * m / bh ** 2) * _cyclic_laplacian(N)
+        cov[off[i]:off[i + 1], off[i]:off[i + 1]] = np.linalg.inv(beta * A)
+    Lc = np.linalg.cholesky(cov)
+    centre_rows = np.repeat(centres, Ns, axis=0)
+    well = np.repeat([m * w * w / N / kcal for N, m, w in zip(Ns, masses, ws)], Ns)[:, None]
+    D = 3 * B
+    acc = {"kcv": 0.0, "kprim": 0.0}
+    p0 = np.zeros((B, 3))
+    for c in range(3):                      # sigma points along each Cartesian block
+        for col in range(B):
+            for sign in (1.0, -1.0):
+                q = centre_rows.copy()
+                q[:, c] += sign * math.sqrt(D) * Lc[:, col]
+                F = -well * (q - centre_rows)
+                e = o.observables(q, p0, F, np.zeros(oracle.N_POT))
+                for k in acc:
+                    acc[k] += e[oracle.E_NAMES.index(k)] / (2 * D)
+    want = sum(_ke_quantum_finite_p(N, w, bh, kT) for N, w in zip(Ns, ws))
+    assert acc["kcv"] == pytest.approx(want, rel=1e-11)
+    assert acc["kprim"] == pytest.approx(want, rel=1e-11)
+    # the closed form itself: N = 1 is classical, large N reaches the quantum value
+    assert _ke_quantum_finite_p(1, ws[0], bh, kT) == pytest.approx(1.5 * kT, rel=1e-15)
+    qv = 0.75 * kT * 3.0 / math.tanh(1.5)          # 3 hbar w / 4 coth(beta hbar w / 2)
+    assert _ke_quantum_finite_p(4096, ws[0], bh, kT) == pytest.approx(qv, rel=1e-5)
+
+
 # ---------------------------------------------------------------- thermostat
 # The path-integral Langevin thermostat (PILE) of the paper's NVT runs:
 # an Ornstein-Uhlenbeck step of the momenta in each ring's normal modes.
@@ -542,7 +605,11 @@ def test_pile_samples_the_quantum_harmonic_dimer():
     the bead-averaged <|r1 - r2|^2> sampled by the thermostatted steps
     matches the exact finite-P value 3/(beta mu) sum_k 1/(omega^2 +
     omega_k^2) of the relative coordinate (reduced mass mu) within 4
-    standard errors (block averages)."""
+    standard errors (block averages).  The logged kinetic-energy estimators
+    (centroid virial and primitive) sample the exact finite-P kinetic energy
+    of the pair, 3 kT/2 [2 + sum_{k>=1} omega^2 / (omega^2 + omega_k^2)]
+    (a free centre-of-mass ring plus the relative oscillator), within 4
+    standard errors."""
     P, T, m = 4, 300.0, 1.00794
     mu = m / 2
     bh = _beta_hbar(T)
@@ -563,13 +630,22 @@ def test_pile_samples_the_quantum_harmonic_dimer():
     try:
         qq, pp = s.q, np.zeros_like(s.q)
         F, _ = o.forces(qq)
-        vb = []
+        vb, kcv, kpr = [], [], []
         for chunk in range(40):
             noise = rng.normal(size=(5000, 2, 2 * P, 3))
             qq, pp, F, el = o.step_nvt(qq, pp, noise, 50.0, F=F)
             vb.append(el[:, oracle.E_NAMES.index("bond")])
+            kcv.append(el[:, oracle.E_NAMES.index("kcv")])
+            kpr.append(el[:, oracle.E_NAMES.index("kprim")])
     finally:
         oracle.set_threads(nthreads)
+    kT = oracle.constants()["kb_kcal"] * T
+    want_ke = 1.5 * kT * (2.0 + sum(w * w / (w * w + x * x) for x in wk[1:]))
+    for series in (kcv, kpr):
+        kb_blocks = np.concatenate(series[4:]).reshape(72, -1).mean(axis=1)
+        km, ke = kb_blocks.mean(), kb_blocks.std(ddof=1) / math.sqrt(len(kb_blocks))
+        assert ke < 0.02 * want_ke
+        assert abs(km - want_ke) < 4.0 * ke, (km, want_ke, ke)
     # bead-averaged |r1 - r2|^2 = 2 V_bond / k (V_bond carries the 1/P weights)
     x = 2.0 * np.concatenate(vb[4:]) / kb
     blocks = x.reshape(72, -1).mean(axis=1)
