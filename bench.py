@@ -2,8 +2,9 @@
 
 Workload (default): one 1024-bead electron, a +3 cation and 512 flexible
 waters (1537 classical atoms) in a 24.8 A periodic box; electron-atom
-softened Coulomb cut at 12 A, atom-atom LJ + Coulomb cut at 9 A; FP32 pair
-potentials with FP64 separations, sums and integrator state; dt 0.1 fs.
+softened Coulomb cut at 12 A, atom-atom LJ + Coulomb cut at 9 A; the FP32
+form (FP32 pseudopotential and 1/r seeds, FP64 atom-atom terms, separations,
+sums and integrator state); dt 0.1 fs.
 A step is one full PIMD step: half-kick, exact free ring-polymer
 propagation in normal modes, bead forces of V_mix, half-kick, energies.
 
@@ -26,11 +27,15 @@ if ROOT not in sys.path:
 # Algorithmic FLOPs of the force launch (op counts of the kernel's arithmetic;
 # FMA = 2, add/mul/compare/rint/rsqrt/rcp/sqrt/acos = 1):
 #   every candidate slice-pair: separation, nearest image, r^2, cutoff test
-#   an in-cutoff atom-atom slice-pair adds LJ + Coulomb + force/energy sums
+#   an in-cutoff atom-atom slice-pair adds the Coulomb energy and force,
+#     the force scale and the i/j force and energy sums
+#   one with a Lennard-Jones type pair (eps != 0) inside its cutoff adds the
+#     reciprocal and the LJ energy and force
 #   an in-cutoff electron-atom slice-pair adds the pseudopotential + sums
 #   a bond / angle slice (bonded workgroups of the same launch)
 FLOP_CANDIDATE = 21
-FLOP_ATOM_IN = 42
+FLOP_ATOM_IN = 23
+FLOP_LJ_IN = 19
 FLOP_PP_IN = 25
 FLOP_BOND = 35
 FLOP_ANGLE = 100
@@ -90,7 +95,7 @@ def _workload(name):
                 "water256 N_H=32 N_O=4, gradient workload seed 0 (19.7 A)")
     if name == "c5":
         print("[bench] generating the 64-system batch", file=sys.stderr, flush=True)
-        return (synth.config_c5(),
+        return (synth.config_c5(workers=synth.build_workers()),
                 "batch64 e-/ion/water (P in 256..2048, 128..1024 H2O per system)")
     raise SystemExit(f"unknown workload {name}")
 
@@ -364,6 +369,54 @@ def _run_adjoint(sysm, q, s, mixpi, torch, reps=50):
             "theta": ["pp_q", "pp_a", "eps_00", "sigma_00", "k_bond0", "k_angle0"]}
 
 
+def _split_state(x_rows, idx, s):
+    """Bead tables (particle-major) of every system from a state array in
+    the library layout."""
+    beads = x_rows[idx]
+    out, o = [], 0
+    for x in _as_list(s):
+        n = int(sum(x.n_beads))
+        out.append(beads[o:o + n])
+        o += n
+    return out
+
+
+def _lj_slice_pairs(s, q):
+    """Slice-pairs of V_mix with a Lennard-Jones term inside its cutoff
+    (eps != 0, r^2 < rc_lj^2, different molecules, no electron), from the
+    bead positions q (particle-major bead table) by the slice map: the
+    LJ share of the in-cutoff count, which the FLOP table charges LJ to."""
+    import numpy as np
+    total = 0
+    for x, qx in zip(_as_list(s), q):
+        nb = np.asarray(x.n_beads)
+        off = np.concatenate([[0], np.cumsum(nb)])
+        t = np.asarray(x.lj_type)
+        nt = x.lj_eps.shape[0]
+        lj = (t >= 0) & (np.asarray(x.is_electron) == 0)
+        lj &= np.array([np.any(x.lj_eps[ti] != 0) if ti >= 0 else False for ti in t])
+        idx = np.flatnonzero(lj)
+        if len(idx) < 2:
+            continue
+        L = np.asarray(x.box, dtype=np.float64)
+        rc2 = x.rc_lj ** 2
+        tt = np.clip(t[idx], 0, nt - 1)
+        eps = x.lj_eps[tt[:, None], tt[None, :]]
+        mol = np.asarray(x.mol_id)[idx]
+        upper = np.triu(np.ones((len(idx), len(idx)), dtype=bool), 1)
+        keep = upper & (eps != 0) & (mol[:, None] != mol[None, :])
+        ni = nb[idx]
+        nmax = np.maximum(ni[:, None], ni[None, :])
+        for N in np.unique(nmax[keep]):
+            sel = keep & (nmax == N)
+            for sl in range(int(N)):
+                pos = qx[off[idx] + (sl * ni) // N]
+                d = pos[:, None, :] - pos[None, :, :]
+                d -= L * np.rint(d / L)
+                total += int(np.count_nonzero(sel & ((d * d).sum(-1) < rc2)))
+    return total
+
+
 def _bonded_slices(s):
     """Bond and angle slices: each term is evaluated on N_max slices."""
     n_bond = n_angle = 0
@@ -374,49 +427,102 @@ def _bonded_slices(s):
     return n_bond, n_angle
 
 
-def _cpu_baseline_batch(systems, target_s=15.0):
-    """The FP64 CPU oracle stepping the batch's systems one after another
-    (one step each, in order) until about target_s seconds have passed."""
+def _cpu_info():
+    """CPU model (from /proc/cpuinfo) and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def _oracle_rate(o, q, p, F, target_s, max_steps=200):
+    """Oracle steps from (q, p, F) for about target_s seconds: returns
+    (steps, seconds, pair evaluations per step, state after)."""
+    t = time.perf_counter()
+    q1, p1, F1, _ = o.step(q, p, 1, F=F)
+    one = time.perf_counter() - t
+    n = max(1, min(max_steps, int(target_s / max(one, 1e-6))))
+    evals = sum(o.pair_evals(q1))
+    t = time.perf_counter()
+    q2, p2, F2, _ = o.step(q1, p1, n, F=F1)
+    return n, time.perf_counter() - t, evals, (q2, p2, F2)
+
+
+def _cpu_baseline_batch(systems, target_s):
+    """The FP64 CPU oracle on a batch: every system stepped alone, 10 steps
+    each (after one untimed step), on all cores; the batch's oracle time per
+    step is the sum of the per-system times per step.  A 1-thread pass runs
+    the first systems until target_s / 4 has passed."""
     import oracle
-    evals = 0
-    spent = 0.0
-    done = 0
+    model, cores = _cpu_info()
+    oracle.set_threads(cores)
+    evals = spent = 0.0
     for s in systems:
         o = oracle.OracleSystem(s)
         F, _ = o.forces(s.q)
-        ev = sum(o.pair_evals(s.q))
+        q1, p1, F1, _ = o.step(s.q, s.p, 1, F=F)
+        ev = sum(o.pair_evals(q1))
         t = time.perf_counter()
-        o.step(s.q, s.p, 1, F=F)
-        spent += time.perf_counter() - t
+        o.step(q1, p1, 10, F=F1)
+        dt = (time.perf_counter() - t) / 10
+        spent += dt
         evals += ev
-        done += 1
-        if spent > target_s:
-            break
+    single = dict(evals=0.0, spent=0.0, done=0)
+    oracle.set_threads(1)
+    try:
+        for s in systems:
+            o = oracle.OracleSystem(s)
+            F, _ = o.forces(s.q)
+            t = time.perf_counter()
+            o.step(s.q, s.p, 1, F=F)
+            single["spent"] += time.perf_counter() - t
+            single["evals"] += sum(o.pair_evals(s.q))
+            single["done"] += 1
+            if single["spent"] > target_s / 4:
+                break
+    finally:
+        oracle.set_threads(cores)
     return dict(value=evals / spent, unit="pair-evals/s", cores=oracle.num_threads(),
-                kind="oracle", steps_per_s=done / spent,
-                sample=f"one FP64 oracle step of each of the first {done} of "
-                       f"{len(systems)} systems (forces of the start state untimed)")
+                kind="oracle", cpu_model=model, steps_per_s=1.0 / spent,
+                value_1thread=single["evals"] / single["spent"],
+                sample=(f"each of the {len(systems)} systems alone: 10 FP64 oracle steps after 1 "
+                        f"untimed step; batch step time = sum of the per-system step times "
+                        f"({spent:.3f} s); 1-thread rate from one step of each of the first "
+                        f"{single['done']} systems"))
 
 
 def _cpu_baseline(s, target_s=15.0):
-    """The FP64 CPU oracle stepping the same system on the host cores."""
+    """The FP64 CPU oracle stepping the same system on the host cores: all
+    cores the process may use, then one thread."""
     import oracle
     if isinstance(s, (list, tuple)):
         return _cpu_baseline_batch(s, target_s)
+    model, cores = _cpu_info()
+    oracle.set_threads(cores)
     o = oracle.OracleSystem(s)
     F, _ = o.forces(s.q)
-    t = time.perf_counter()
-    q, p, F, _ = o.step(s.q, s.p, 1, F=F)
-    one = time.perf_counter() - t
-    n = max(1, min(200, int(target_s / max(one, 1e-6))))
-    evals = sum(o.pair_evals(q))
-    t = time.perf_counter()
-    o.step(q, p, n, F=F)
-    dt = time.perf_counter() - t
+    n, dt, evals, state = _oracle_rate(o, s.q, s.p, F, target_s)
+    oracle.set_threads(1)
+    try:
+        n1, dt1, evals1, _ = _oracle_rate(o, *state, target_s / 3, max_steps=50)
+    finally:
+        oracle.set_threads(cores)
     return dict(value=evals * n / dt, unit="pair-evals/s", cores=oracle.num_threads(),
-                kind="oracle", steps_per_s=n / dt,
-                sample=f"{n} FP64 oracle steps of the same system (term-by-term V_mix, "
-                       f"OpenMP over particles), after 1 untimed step")
+                kind="oracle", cpu_model=model, steps_per_s=n / dt,
+                value_1thread=evals1 * n1 / dt1, steps_per_s_1thread=n1 / dt1,
+                sample=f"{n} FP64 oracle steps of the same system on {cores} threads "
+                       f"(term-by-term V_mix, OpenMP over particles) after 1 untimed step; "
+                       f"then {n1} steps on 1 thread")
 
 
 def main():
@@ -463,9 +569,8 @@ def main():
     if args.tile == "auto":
         from paper_2411_11988_amd import tune
         print("[bench] autotuning the pair tile shape", file=sys.stderr, flush=True)
-        cache = os.path.join(ROOT, "gpurun_out", "tiles.json")
-        flags32 = tune.tile_flags(s, mixpi.MIXPI_FP32_ACC64, cache=cache)
-        flags64 = tune.tile_flags(s, mixpi.MIXPI_FP64, cache=cache)
+        flags32 = tune.tile_flags(s, mixpi.MIXPI_FP32_ACC64)
+        flags64 = tune.tile_flags(s, mixpi.MIXPI_FP64)
         inv = {v: k for k, v in mixpi.TILE_FLAGS.items()}
         tile = {"fp32": "%dx%d" % inv[flags32], "fp64": "%dx%d" % inv[flags64]}
     print(f"[bench] {wname}: FP32 pair form, {args.warmup} warmup + {args.steps} timed steps",
@@ -484,8 +589,10 @@ def main():
     cand = sysm.pair_candidates()
     ev_atom, ev_pp = (x / args.steps for x in r32["ev"])
     n_bond, n_angle = _bonded_slices(s)
-    flops = (cand * FLOP_CANDIDATE + ev_atom * FLOP_ATOM_IN + ev_pp * FLOP_PP_IN
-             + n_bond * FLOP_BOND + n_angle * FLOP_ANGLE)
+    q_end = [x for x in _split_state(r32["q"].cpu().numpy(), sysm.bead_index, s)]
+    ev_lj = _lj_slice_pairs(s, q_end)
+    flops = (cand * FLOP_CANDIDATE + ev_atom * FLOP_ATOM_IN + ev_lj * FLOP_LJ_IN
+             + ev_pp * FLOP_PP_IN + n_bond * FLOP_BOND + n_angle * FLOP_ANGLE)
     achieved = flops / (k_us["force"] * 1e-6) / 1e12
 
     out = {
@@ -504,11 +611,13 @@ def main():
         "config": {"workload": wname, "beads": int(sysm.rows), "particles": int(sysm.n_particles),
                    "candidate_slice_pairs": int(cand), "in_cutoff_slice_pairs": ev_step,
                    "systems": len(_as_list(s)), "dt_fs": _as_list(s)[0].dt,
-                   "precision": "fp32 pair potentials, fp64 state and sums",
+                   "precision": ("fp32 electron-atom pseudopotential and 1/r seeds; fp64 atom-atom "
+                                 "terms, separations, state and sums"),
                    "pair_tile_jxwaves": tile},
         "steps_per_s": steps_per_s,
         "kernel_us": k_us,
         "energy_drift_kcal": r32["drift"],
+        "energy_std_kcal": r32["hstd"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": (TRAFFIC["bytes"] if args.workload == TRAFFIC["workload"]
@@ -517,6 +626,7 @@ def main():
                                  else None),
                      "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"],
+                     "lj_slice_pairs": ev_lj,
                      "executed": (_executed(k_us["force"]) if args.workload == TRAFFIC["workload"]
                                   and TRAFFIC["sha256"] == _kernel_sha()
                                   and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
@@ -550,6 +660,7 @@ def main():
         out["fp64"] = {"value": (r64["ev"][0] + r64["ev"][1]) / (r64["ms"] * 1e-3),
                        "steps_per_s": args.steps / (r64["ms"] * 1e-3),
                        "ms_per_step": r64["ms"] / args.steps,
+                       "energy_drift_kcal": r64["drift"], "energy_std_kcal": r64["hstd"],
                        "kernel_us": r64["sysm"].kernel_time(reps, r64["q"], r64["p"], r64["f"])}
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -88,7 +88,10 @@ enum {
 
 typedef enum {
     MIXPI_FP64 = 0,        /* all pair arithmetic in FP64 */
-    MIXPI_FP32_ACC64 = 1   /* FP64 separations and sums, FP32 pair potentials */
+    MIXPI_FP32_ACC64 = 1   /* FP32 electron-atom pseudopotential and FP32 1/r
+                              seeds; atom-atom terms in FP64 from the seed
+                              refined by one FP64 Newton step; FP64
+                              separations and sums */
 } mixpi_precision;
 
 /* flags */
@@ -177,8 +180,9 @@ int mixpi_bead_index(const mixpi_system *sys, int64_t *rows_out);
  *         or NULL for the values given at create
  *   f     device double [rows][3], overwritten (must not alias q)
  *   e_out device double [n_systems][MIXPI_NV] or NULL
- * FP64 precision: arithmetic in FP64.  FP32_ACC64: separations, forces and
- * sums in FP64, pair potentials in FP32. */
+ * FP64 precision: arithmetic in FP64.  FP32_ACC64: the electron-atom
+ * pseudopotential in FP32, everything else in FP64 (see mixpi_precision);
+ * every force and energy term is summed in FP64. */
 int mixpi_forces(mixpi_system *sys, const double *q, const double *theta,
                  double *f, double *e_out, void *stream);
 

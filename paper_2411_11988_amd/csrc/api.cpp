@@ -95,8 +95,7 @@ struct mixpi_system {
     int pair_waves = 1;
 
     SysDev *d_sys = nullptr;
-    LjPar<float> *d_ljpar_f = nullptr;          // LJ tables in the pair sweep's form
-    LjPar<double> *d_ljpar_d = nullptr;
+    LjPar *d_ljpar = nullptr;                   // LJ tables in the pair sweep's form
     double *d_charge = nullptr;
     int *d_ljt = nullptr, *d_mol = nullptr, *d_row_sys = nullptr;
     double *d_row_fm = nullptr, *d_row_hk = nullptr;
@@ -222,7 +221,7 @@ void release(mixpi_system *s)
         (void)hipGraphExecDestroy(g.exec);
         (void)hipGraphDestroy(g.graph);
     }
-    void *ptrs[] = {s->d_sys, s->d_ljpar_f, s->d_ljpar_d, s->d_charge, s->d_ljt, s->d_mol,
+    void *ptrs[] = {s->d_sys, s->d_ljpar, s->d_charge, s->d_ljt, s->d_mol,
                     s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items, s->d_iblocks,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
                     s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
@@ -1104,8 +1103,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_sys, B.sys));
     {
         // LJ tables in the sweep's form: 4 eps, sigma^2, V(rc), V'(rc)/rc
-        std::vector<LjPar<float>> tf(B.lj_eps.size());
-        std::vector<LjPar<double>> td(B.lj_eps.size());
+        std::vector<LjPar> td(B.lj_eps.size());
         for (const SysDev &sd : B.sys) {
             const double rc2 = sd.rc_lj * sd.rc_lj;
             for (int tp = 0; tp < sd.nt1 * sd.nt1; ++tp) {
@@ -1115,14 +1113,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
                 double c6 = s2 / rc2;
                 c6 = c6 * c6 * c6;
                 const double c12 = c6 * c6;
-                const LjPar<double> v{4.0 * eps, s2, 4.0 * eps * (c12 - c6),
-                                      4.0 * eps * (-12.0 * c12 + 6.0 * c6) / rc2};
-                td[k] = v;
-                tf[k] = LjPar<float>{(float)v.e4, (float)v.s2, (float)v.c0, (float)v.c1};
+                td[k] = LjPar{4.0 * eps, s2, 4.0 * eps * (c12 - c6),
+                              4.0 * eps * (-12.0 * c12 + 6.0 * c6) / rc2};
             }
         }
-        T(upload(&S->d_ljpar_f, tf));
-        T(upload(&S->d_ljpar_d, td));
+        T(upload(&S->d_ljpar, td));
     }
     T(upload(&S->d_charge, B.charge));
     T(upload(&S->d_ljt, B.ljt));
@@ -1234,8 +1229,7 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.waves = s->pair_waves;
     a.iblocks = s->d_iblocks + lo;
     a.sys = s->d_sys;
-    a.ljpar_f = s->d_ljpar_f;
-    a.ljpar_d = s->d_ljpar_d;
+    a.ljpar = s->d_ljpar;
     a.charge = s->d_charge;
     a.ljt = s->d_ljt;
     a.mol = s->d_mol;

@@ -68,10 +68,9 @@ struct PairBlock {
 };
 
 // LJ parameters of one type pair in the form the pair sweep uses: 4 eps,
-// sigma^2, c0 = V(rc) and c1 = V'(rc) / rc of the unshifted potential (one
-// 128-bit LDS load in the float form, two in the double form).
-template <typename R> struct alignas(16) LjPar {
-    R e4, s2, c0, c1;
+// sigma^2, c0 = V(rc) and c1 = V'(rc) / rc of the unshifted potential.
+struct alignas(16) LjPar {
+    double e4, s2, c0, c1;
 };
 struct PairItem {
     int block, b, i0, j0;
@@ -119,8 +118,7 @@ struct PairLaunch {
     int waves;               // waves per tile (1 or 2)
     const PairBlock *iblocks; // the block of every item, copied per item
     const SysDev *sys;
-    const LjPar<float> *ljpar_f;   // per system at lj_off: (nt+1)^2 type pairs
-    const LjPar<double> *ljpar_d;
+    const LjPar *ljpar;      // per system at lj_off: (nt+1)^2 type pairs
     const double *charge;
     const int *ljt, *mol;
     const double *q;

@@ -20,9 +20,11 @@
 // its own; a per-row gather in a fixed order sums them (no global atomics).
 //
 // Precision: separations and the nearest-image shift are FP64 (positions
-// sit up to a box length from the origin); the pair potential is evaluated
-// in R (double, or float for the FP32 form); forces and energies are summed
-// in FP64.
+// sit up to a box length from the origin).  The electron-atom
+// pseudopotential is evaluated in R (double, or float for the FP32 form);
+// atom-atom Lennard-Jones and Coulomb terms in FP64 from an R seed of 1/r.
+// Every force, energy and theta term is summed in FP64 (per lane, then
+// across lanes, waves and tiles).
 #include <type_traits>
 
 #include "device_common.h"
@@ -30,13 +32,13 @@
 
 namespace mixpi {
 
-// Reciprocal and reciprocal square root.  FP32 form: the hardware
-// approximations.  FP64 form: the hardware approximation refined by one
-// Newton step (relative error of order 1e-16, against 1e-12 for the form's
-// bar), instead of the correctly rounded division and square root, which
-// cost about four times the instructions.  Both are used only where the
-// argument is a positive, finite r^2 (or r^2 + a^2); masked candidates
-// may produce non-finite values, which the masks select away.
+// Reciprocal square root.  Hardware approximations: v_rsq_f32 in the FP32
+// form, v_rsq_f64 in the FP64 form.  Atom-atom pairs refine either seed by
+// one FP64 Newton step (y <- y (3 - r^2 y^2) / 2, which squares the seed's
+// relative error), and take 1/r^2 as y^2; the electron-atom pseudopotential
+// of the FP32 form uses the FP32 value as it is.  Used only where the
+// argument is a positive, finite r^2 (or r^2 + a^2); masked candidates may
+// produce non-finite values, which the masks select away.
 template <typename R> __device__ __forceinline__ R rsqrt_r(R x);
 template <> __device__ __forceinline__ double rsqrt_r<double>(double x)
 {
@@ -44,29 +46,30 @@ template <> __device__ __forceinline__ double rsqrt_r<double>(double x)
     return y * fma(-0.5 * x * y, y, 1.5);
 }
 template <> __device__ __forceinline__ float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <typename R> __device__ __forceinline__ R rcp_r(R x);
-template <> __device__ __forceinline__ double rcp_r<double>(double x)
-{
-    const double y = __builtin_amdgcn_rcp(x);
-    return y * fma(-x, y, 2.0);
-}
-template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// The j-beads of a tile in LDS as separate arrays (x, y, z, and charge with
-// LJ type | mol id << 4), so that a wave's reads of consecutive j-slots are
-// consecutive 8-byte words: free of bank conflicts, where 32-byte records
-// put four of a wave's slots on the same banks.
-template <typename R> struct JQ;
-template <> struct alignas(8) JQ<float> {
-    float q;
+// 1/sqrt(x) in FP64 from the form's hardware seed and one FP64 Newton step.
+template <typename R> __device__ __forceinline__ double rsqrt_fp64(double x)
+{
+    double y;
+    if constexpr (std::is_same<R, float>::value) y = (double)__builtin_amdgcn_rsqf((float)x);
+    else y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+
+// The j-beads of a tile in LDS as separate arrays (x, y, z, and the charge
+// record), so that a wave's reads of consecutive j-slots are consecutive
+// words: free of bank conflicts, where 32-byte records put four of a wave's
+// slots on the same banks.  The charge record holds the FP64 charge (k_e q_j
+// for an electron-atom block with the electron as i), its R rounding for
+// the pseudopotential sweep, and LJ type | mol id << 4.
+template <typename R> struct alignas(16) JQ {
+    double qd;
+    R q;
     int tm;
-};
-template <> struct alignas(16) JQ<double> {
-    double q;
-    int tm, pad;
 };
 template <typename R> struct JTile {
     double x, y, z;
+    double qd;
     R q;
     int tm;
 };
@@ -98,31 +101,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     // j-slot jj as read by the loops
     auto jload = [&](int jj) {
         const JQ<R> m = sjq[jj];
-        return JTile<R>{sjx[jj], sjy[jj], sjz[jj], m.q, m.tm};
+        return JTile<R>{sjx[jj], sjy[jj], sjz[jj], m.qd, m.q, m.tm};
     };
     __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
-    __shared__ LjPar<R> tlj[kLjTab];
+    __shared__ LjPar tlj[kLjTab];
 
     const int nt1 = bk.nt1;
     const double rc_lj = S.rc_lj, rc_c = S.rc_c;
     if (bk.kind == PK_ATOM) {
         // the system's table, built at create time; the pair (0, 0) takes
         // its eps and sigma from theta
-        const LjPar<R> *tab = (std::is_same<R, float>::value
-                                   ? reinterpret_cast<const LjPar<R> *>(a.ljpar_f)
-                                   : reinterpret_cast<const LjPar<R> *>(a.ljpar_d)) + bk.lj_off;
+        const LjPar *tab = a.ljpar + bk.lj_off;
         for (int tp = lane; tp < nt1 * nt1; tp += 64) {
-            LjPar<R> lp;
+            LjPar lp;
             if (tp == 0) {
                 const double eps = th[2], sig = th[3];
                 const double s2 = sig * sig;
                 double c6 = s2 / (rc_lj * rc_lj);
                 c6 = c6 * c6 * c6;
                 const double c12 = c6 * c6;
-                lp.e4 = (R)(4.0 * eps);
-                lp.s2 = (R)s2;
-                lp.c0 = (R)(4.0 * eps * (c12 - c6));
-                lp.c1 = (R)(4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj));
+                lp.e4 = 4.0 * eps;
+                lp.s2 = s2;
+                lp.c0 = 4.0 * eps * (c12 - c6);
+                lp.c1 = 4.0 * eps * (-12.0 * c12 + 6.0 * c6) / (rc_lj * rc_lj);
             } else {
                 lp = tab[tp];
             }
@@ -146,7 +147,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             z = a.q[3 * rowj + 2];
             // electron-atom blocks with the electron as i take k_e q_j as
             // their pseudopotential constant: scaled here, once per tile
-            jq.q = (R)(bk.kind == PK_E_ATOM ? kCoulombKcal * a.charge[pj] : a.charge[pj]);
+            const double qc = a.charge[pj];
+            jq.qd = bk.kind == PK_E_ATOM ? kCoulombKcal * qc : qc;
+            jq.q = (R)jq.qd;
             jq.tm = a.ljt[pj] | (a.mol[pj] << 4);
         }
         sjx[js] = x;
@@ -179,9 +182,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     const double Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
     const double iLx = S.ibox[0], iLy = S.ibox[1], iLz = S.ibox[2];
     double fxi = 0, fyi = 0, fzi = 0;
-    // per-lane sums of at most TJ terms in R, then FP64 across lanes/tiles
-    R e0r = 0, e1r = 0;               // atom: LJ, Coulomb; electron: pp
-    R g0r = 0, g1r = 0;               // theta partials (pp: q_e, a; atom: eps, sigma)
+    // per-lane energy and theta sums in FP64 (each term converted once),
+    // then FP64 across lanes, waves and tiles
+    double e0r = 0, e1r = 0;          // atom: LJ, Coulomb; electron: pp
+    double g0r = 0, g1r = 0;          // theta partials (pp: q_e, a; atom: eps, sigma)
     // in-cutoff slice-pairs: a per-lane count (one add per candidate),
     // summed over the wave after the loop
     int cnt = 0;
@@ -190,14 +194,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     const int jhi = vi ? jn : 0;
 
     if (bk.kind == PK_ATOM) {
+        // Atom-atom Lennard-Jones and Coulomb in FP64 in both forms, from
+        // the form's 1/r seed refined by one FP64 Newton step: the forces on
+        // a cation are small differences of large first-shell repulsions
+        // and attractions, which FP32 arithmetic would leave about 1e-5 of
+        // the RMS force off; without packed FP32 an FP64 multiply-add issues
+        // at the FP32 rate on this chip, so only the seed is cheaper in FP32.
         const double rc2_lj = rc_lj * rc_lj, rc2_c = rc_c * rc_c;
         const double rc2max = fmax(rc2_lj, rc2_c);
-        const R rl2 = (R)rc2_lj, rcc2 = (R)rc2_c;
-        const R irc = (R)(1.0 / rc_c);
-        const R irc3 = (R)(1.0 / (rc_c * rc_c * rc_c));
-        const R kqi = (R)(kCoulombKcal * qi);
+        const double irc = 1.0 / rc_c;
+        const double irc3 = 1.0 / (rc_c * rc_c * rc_c);
+        const double hc = 0.5 * irc3;
+        const double kqi = kCoulombKcal * qi;
         const int trow = ti * nt1;
-        const R th_eps = (R)th[2], th_sig = (R)th[3];
+        const double th_eps = th[2], th_sig = th[3];
         // LJ: blocks whose type pairs all have eps = 0 (and cannot reach the
         // theta-overridden pair (0, 0)) run a loop without the LJ terms; the
         // masked LJ contribution there is an exact zero, so both loops give
@@ -217,58 +227,56 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             auto body = [&](int jj, bool live) {
                 const JTile<R> jr = jload(jj);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
-                const R qj = jr.q;
                 const int tp = trow + (jr.tm & 15);
                 const int mj = jr.tm >> 4;
                 dx -= Lx * rint(dx * iLx);
                 dy -= Ly * rint(dy * iLy);
                 dz -= Lz * rint(dz * iLz);
-                const double r2d = dx * dx + dy * dy + dz * dz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
                 bool ok = live;
                 // masks combine without short-circuit branches (straight-line code)
-                if constexpr (!SP) ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2max);
+                if constexpr (!SP) ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2 < rc2max);
                 // no select needed: a masked candidate's r^2 is finite (padding
                 // slots sit at the origin) and every term it feeds is selected away
-                const R r2 = (R)r2d;
-                const R K = kqi * qj;
-                const bool in_c = ok & (r2d < rc2_c) & (K != (R)0);
-                const R ir = rsqrt_r<R>(r2);
-                const R vc = K * (ir - irc + (R)0.5 * (r2 - rcc2) * irc3);
-                const R gc = K * (ir * ir * ir - irc3);
-                R g;
+                const double K = kqi * jr.qd;
+                const bool in_c = ok & (r2 < rc2_c) & (K != 0.0);
+                const double ir = rsqrt_fp64<R>(r2);
+                const double ir2 = ir * ir;
+                const double vc = K * ((ir - irc) + (r2 - rc2_c) * hc);
+                const double gc = K * (ir2 * ir - irc3);
+                double g;
                 bool hit = in_c;
                 if constexpr (LJ) {
-                    const LjPar<R> lp = tlj[tp];
-                    const R e4 = lp.e4, c1l = lp.c1;
-                    const R ir2 = rcp_r<R>(r2);
-                    const R s2 = lp.s2 * ir2;
-                    const R s6 = s2 * s2 * s2;
-                    const R s12 = s6 * s6;
-                    const bool in_lj = ok & (r2d < rc2_lj) & (e4 != (R)0);
-                    const R vlj = e4 * (s12 - s6) - lp.c0 - (R)0.5 * (r2 - rl2) * c1l;
-                    const R glj = e4 * ((R)12 * s12 - (R)6 * s6) * ir2 + c1l;
-                    g = (in_lj ? glj : (R)0) + (in_c ? gc : (R)0);
-                    e0r += in_lj ? vlj : (R)0;
+                    const LjPar lp = tlj[tp];
+                    const double e4 = lp.e4, c1l = lp.c1;
+                    const double s2 = lp.s2 * ir2;
+                    const double s6 = s2 * s2 * s2;
+                    const double s12 = s6 * s6;
+                    const bool in_lj = ok & (r2 < rc2_lj) & (e4 != 0.0);
+                    const double vlj = e4 * (s12 - s6) - lp.c0 - 0.5 * (r2 - rc2_lj) * c1l;
+                    const double glj = e4 * (12.0 * s12 - 6.0 * s6) * ir2 + c1l;
+                    g = (in_lj ? glj : 0.0) + (in_c ? gc : 0.0);
+                    e0r += in_lj ? vlj : 0.0;
                     hit = in_lj | in_c;
                     if (THETA) {
                         // d/d eps and d/d sigma of the (0,0) LJ term
                         const bool on = in_lj & (tp == 0);
-                        const R c6 = tlj[0].s2 / rl2;
-                        const R c6c = c6 * c6 * c6, c12c = c6c * c6c;
-                        const R fs = (R)4 * th_eps / th_sig;
-                        const R dsg = fs * ((R)12 * s12 - (R)6 * s6) -
-                                      fs * ((R)12 * c12c - (R)6 * c6c) -
-                                      (R)0.5 * (r2 - rl2) * fs * ((R)-144 * c12c + (R)36 * c6c) / rl2;
-                        g0r += on ? vlj / th_eps : (R)0;
-                        g1r += on ? dsg : (R)0;
+                        const double c6 = tlj[0].s2 / rc2_lj;
+                        const double c6c = c6 * c6 * c6, c12c = c6c * c6c;
+                        const double fs = 4.0 * th_eps / th_sig;
+                        const double dsg = fs * (12.0 * s12 - 6.0 * s6) -
+                                           fs * (12.0 * c12c - 6.0 * c6c) -
+                                           0.5 * (r2 - rc2_lj) * fs * (-144.0 * c12c + 36.0 * c6c) /
+                                               rc2_lj;
+                        g0r += on ? vlj / th_eps : 0.0;
+                        g1r += on ? dsg : 0.0;
                     }
                 } else {
-                    g = in_c ? gc : (R)0;
+                    g = in_c ? gc : 0.0;
                 }
-                e1r += in_c ? vc : (R)0;
+                e1r += in_c ? vc : 0.0;
                 cnt += hit;
-                const double gd = (double)g;
-                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
+                const double fx = g * dx, fy = g * dy, fz = g * dz;
                 fxi += fx;
                 fyi += fy;
                 fzi += fz;
@@ -316,15 +324,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             else sweep(std::false_type{}, std::false_type{});
         }
     } else {
-        // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom
+        // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom,
+        // in R; the theta partials (adjoint launches only) in FP64
         const double rc = S.rc_pp, rc2 = rc * rc;
         const double pa = th[1], a2 = pa * pa, pq = th[0];
         const double u_c = rc2 + a2;
-        const R phic = (R)(1.0 / sqrt(u_c));
-        const R psic = (R)(-1.0 / (u_c * sqrt(u_c)));
-        const R chic = (R)(1.0 / (u_c * u_c * sqrt(u_c)));
-        const R ra2 = (R)a2, rrc2 = (R)rc2, rpa = (R)pa, rpq = (R)pq;
+        const double phicd = 1.0 / sqrt(u_c);
+        const double psicd = -1.0 / (u_c * sqrt(u_c));
+        const double chicd = 1.0 / (u_c * u_c * sqrt(u_c));
+        const R phic = (R)phicd, psic = (R)psicd;
+        const R ra2 = (R)a2, rrc2 = (R)rc2, rpq = (R)pq;
         const R kqi = (R)(kCoulombKcal * qi);
+        const double kqid = kCoulombKcal * qi;
         // E_IS_I: the electron is the i side and the constant is the j
         // atom's (pre-scaled) k_e q_j; otherwise the i atom's k_e q_i
         auto sweep_e = [&](auto e_tag) {
@@ -346,13 +357,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 const R ir3 = ir * ir * ir;
                 const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
                 const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
-                e0r += ok ? rpq * vq : (R)0;
+                e0r += (double)(ok ? rpq * vq : (R)0);
                 cnt += ok;
                 if (THETA) {
-                    g0r += ok ? vq : (R)0;
-                    g1r += ok ? rpq * kq * (-rpa * ir3 - rpa * psic -
-                                            (R)1.5 * rpa * (r2 - rrc2) * chic)
-                              : (R)0;
+                    const double kqd = E_IS_I ? jr.qd : kqid;
+                    const double u = r2d + a2;
+                    const double y = rsqrt_fp64<R>(u);
+                    const double y3 = y * y * y;
+                    const double vqd = kqd * (y - phicd - 0.5 * (r2d - rc2) * psicd);
+                    g0r += ok ? vqd : 0.0;
+                    g1r += ok ? pq * kqd * (-pa * y3 - pa * psicd - 1.5 * pa * (r2d - rc2) * chicd)
+                              : 0.0;
                 }
                 const double gd = (double)gq;
                 const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
@@ -367,12 +382,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         if (bk.kind == PK_E_ATOM) sweep_e(std::true_type{});
         else sweep_e(std::false_type{});
     }
-    double e0 = wsum((double)e0r), e1 = wsum((double)e1r), g0 = 0.0, g1 = 0.0;
+    double e0 = wsum(e0r), e1 = wsum(e1r), g0 = 0.0, g1 = 0.0;
     cnt = (int)wsum((double)cnt);       // exact: at most 64 * TJ
 
     if (THETA) {
-        g0 = wsum((double)g0r);
-        g1 = wsum((double)g1r);
+        g0 = wsum(g0r);
+        g1 = wsum(g1r);
     }
     if (WAVES > 1) {
         // the other waves hand their i-forces and sums to wave 0

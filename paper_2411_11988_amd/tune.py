@@ -7,10 +7,11 @@ actual workload (``mixpi_kernel_time``) and returns the fastest;
 ``tile_flags`` returns the descriptor flags for a workload, measuring once
 per shape bucket and keeping the choice in a JSON cache.
 
-A bucket is (device architecture, precision, number of systems, largest
-ring bead count, total atom count rounded to a power of two): workloads in
-one bucket share the shape of their work lists closely enough to share a
-tile choice.
+A bucket is (device architecture, the built library's content hash,
+precision, number of systems, largest ring bead count, total atom count
+rounded to a power of two): workloads in one bucket share the shape of their
+work lists closely enough to share a tile choice, and a rebuilt library
+(changed kernels) never reuses a stale choice.
 """
 from __future__ import annotations
 
@@ -28,13 +29,30 @@ def _pow2_ceil(x: int) -> int:
     return 1 << max(0, int(x - 1).bit_length())
 
 
+_LIB_HASH = None
+
+
+def library_hash() -> str:
+    """First 16 hex digits of the sha256 of the loaded libmixpi.so."""
+    global _LIB_HASH
+    if _LIB_HASH is None:
+        import hashlib
+        h = hashlib.sha256()
+        with open(mixpi.LIB_PATH, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 20), b""):
+                h.update(chunk)
+        _LIB_HASH = h.hexdigest()[:16]
+    return _LIB_HASH
+
+
 def bucket(systems, precision: int) -> str:
     import torch
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     pmax = max(int(np.max(s.n_beads)) for s in systems)
     atoms = sum(int(np.sum(np.asarray(s.is_electron) == 0)) for s in systems)
-    return f"{arch}|p{precision}|s{len(systems)}|N{pmax}|A{_pow2_ceil(atoms)}"
+    return (f"{arch}|lib{library_hash()}|p{precision}|s{len(systems)}|N{pmax}"
+            f"|A{_pow2_ceil(atoms)}")
 
 
 def _state(sysm, systems):

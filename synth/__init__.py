@@ -15,5 +15,6 @@ from .systems import (  # noqa: F401
     config_c3,
     config_c4_states,
     config_c5,
+    build_workers,
     water_bead_total,
 )

@@ -545,21 +545,42 @@ def config_c4_states(n: int = 10, small: bool = False):
     return [config_c2(seed=s) for s in range(n)]
 
 
+def _c5_system(args):
+    i, p, w = args
+    box = (float(w) * 29.915) ** (1.0 / 3.0)
+    return solvated_electron(int(w), int(p), box, seed=1000 + i, rc_pp=12.0, rc_aa=9.0,
+                             dt=0.1, name=f"c5-{i}-e{p}-w{w}")
+
+
 def config_c5(seed: int = 0, n_systems: int = 64,
               p_choices=(256, 512, 1024, 2048),
-              w_choices=(128, 256, 512, 1024)):
+              w_choices=(128, 256, 512, 1024), workers: int | None = None):
     """Batch of independent electron/ion/water systems with uneven sizes.
 
     The (P, N_w) draws use ``default_rng(seed)``; system i is built with seed
-    1000 + i.  Boxes at 29.915 A^3 per water (about 1.0 g/cm^3).
+    1000 + i.  Boxes at 29.915 A^3 per water (about 1.0 g/cm^3).  With
+    ``workers`` > 1 the systems are built in that many child processes
+    (each system has its own seed, so the result is the same).
     """
     rng = np.random.default_rng(seed)
     ps = rng.choice(p_choices, size=n_systems)
     ws = rng.choice(w_choices, size=n_systems)
-    out = []
-    for i in range(n_systems):
-        box = (float(ws[i]) * 29.915) ** (1.0 / 3.0)
-        out.append(solvated_electron(int(ws[i]), int(ps[i]), box, seed=1000 + i,
-                                     rc_pp=12.0, rc_aa=9.0, dt=0.1,
-                                     name=f"c5-{i}-e{ps[i]}-w{ws[i]}"))
-    return out
+    jobs = [(i, int(ps[i]), int(ws[i])) for i in range(n_systems)]
+    if workers and workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=workers,
+                                    mp_context=mp.get_context("spawn")) as ex:
+            return list(ex.map(_c5_system, jobs))
+    return [_c5_system(j) for j in jobs]
+
+
+def build_workers() -> int:
+    """Worker processes for building many systems: the host's cores, at
+    most 16."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))

@@ -43,18 +43,6 @@ def theta_err(d, want):
     return float((np.abs(d - want) / den).max())
 
 
-def theta_err_fp32(d, want, theta, e):
-    """The FP32 form's bar for gradients: the error of theta_k dV/dtheta_k,
-    an energy, relative to the potential-energy scale sum_k |V_k| -- the
-    FP32 energy rule of the parity tests carried over to each parameter
-    direction."""
-    d, want, theta = np.asarray(d), np.asarray(want), np.asarray(theta)
-    e = np.asarray(e)
-    err = np.abs(theta * (d - want))
-    den = np.abs(e[1:6]).sum()
-    return float((err / den).max())
-
-
 def _systems():
     return [
         ("tiny1", synth.tiny_random(1)),
@@ -81,10 +69,7 @@ def test_adjoint_matches_oracle(mp, name, s, prec):
     assert force_err(-from_rows(s, host(dq), rows), Fo) <= TOL_F[prec]
     want = o.dvdtheta(s.q)
     d = host(dth)[0]
-    if prec == FP64:
-        assert theta_err(d, want) <= TOL_TH[prec], (d, want)
-    else:
-        assert theta_err_fp32(d, want, default_theta(s), eo) <= TOL_TH[prec], (d, want)
+    assert theta_err(d, want) <= TOL_TH[prec], (d, want, theta_err(d, want))
 
 
 @pytest.mark.parametrize("name,s", SYSTEMS[1:3], ids=[n for n, _ in SYSTEMS[1:3]])
@@ -202,10 +187,7 @@ def test_adjoint_c4_full_size(mp, prec):
     d = host(dth)[0]
     want = o.dvdtheta(s.q)
     assert d[0] == 0.0 and d[1] == 0.0
-    if prec == FP64:
-        assert theta_err(d, want) <= TOL_TH[prec], (d, want)
-    else:
-        assert theta_err_fp32(d, want, default_theta(s), eo) <= TOL_TH[prec], (d, want)
+    assert theta_err(d, want) <= TOL_TH[prec], (d, want, theta_err(d, want))
 
 
 @pytest.mark.timeout(600)
