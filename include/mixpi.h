@@ -186,6 +186,28 @@ int mixpi_bead_index(const mixpi_system *sys, int64_t *rows_out);
 int mixpi_forces(mixpi_system *sys, const double *q, const double *theta,
                  double *f, double *e_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forces and energies of mixpi_forces, computed by the same kernels in the
+ * same order (equal results bit for bit), with the partial-force slots,
+ * energy slots and reducer partials of the evaluation in a static device
+ * array of the library instead of the handle's buffers.  The call performs
+ * no allocation.  Arguments as mixpi_forces.  The array holds 16 MiB
+ * (MIXPI_STATIC_SCRATCH_BYTES) on every device the library runs on, until
+ * the process ends; its address on a device is looked up by mixpi_create /
+ * mixpi_batch_create with that device current.  Needed: 24 bytes per
+ * partial-force position of the handle plus 128 bytes per energy slot of
+ * its force evaluation (about 3.6 MB for one 1024-bead electron with 512
+ * waters, 7 MB for 256 waters at 32/4 beads); a larger handle gets
+ * MIXPI_E_UNSUPPORTED.  Every call on a device shares that device's array
+ * and overwrites it entirely before reading it: calls that overlap in time
+ * on one device (different streams, host threads or handles without
+ * ordering) race and give wrong results.  With mixpi_use_ewald on it
+ * returns MIXPI_E_UNSUPPORTED.  Asynchronous on stream. */
+#define MIXPI_STATIC_SCRATCH_BYTES (16u << 20)
+int mixpi_forces_static(mixpi_system *sys, const double *q, const double *theta, double *f,
+                        double *e_out, void *stream);
+
 /* V_mix only: e_out device double [n_systems][MIXPI_NV]. */
 int mixpi_energy(mixpi_system *sys, const double *q, const double *theta,
                  double *e_out, void *stream);

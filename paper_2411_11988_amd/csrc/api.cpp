@@ -17,6 +17,9 @@
 
 using namespace mixpi;
 
+static_assert(kStaticScratchBytes == MIXPI_STATIC_SCRATCH_BYTES,
+              "the static scratch size and its public constant must agree");
+
 namespace {
 
 thread_local std::string g_err;
@@ -158,6 +161,7 @@ struct mixpi_system {
     int *d_dest = nullptr;
     double *d_part = nullptr;
     long long n_slots = 0, part_bonded = 0;
+    long long n_positions = 0;     // partial-force positions (CSR entries of all rows)
     // epilogue blocks (4 rows of one system)
     BlockRange *d_fblocks = nullptr;
     int n_fblocks = 0;
@@ -924,6 +928,15 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         delete S;
         return fail(MIXPI_E_HIP, "hipGetDevice failed (no GPU?)");
     }
+    {
+        // the static scratch of mixpi_forces_static: its address on this device
+        const hipError_t e = static_scratch_init(S->device);
+        if (e != hipSuccess) {
+            delete S;
+            return fail(MIXPI_E_HIP, "locating the static scratch on device %d: %s", S->device,
+                        hipGetErrorString(e));
+        }
+    }
     S->n_sys = n_sys;
     S->precision = descs[0]->precision;
     S->flags = descs[0]->flags;
@@ -1054,6 +1067,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         return fail(MIXPI_E_UNSUPPORTED, "too many partial-force slots (%lld)", G.n_slots);
     }
     S->n_slots = G.n_slots;
+    S->n_positions = G.row_ptr.back();
 
     // energy slots and their systems
     S->e_bonded = S->n_items;
@@ -1620,6 +1634,53 @@ int mixpi_forces(mixpi_system *sys, const double *q, const double *theta, double
     ReduceB rb = reduce_b_args(sys, LIST_FORCE);
     rb.e_out = e_out;
     launch_reduce(reduce_a_args(sys, 0, LIST_FORCE), rb, st);
+    return last_launch_error();
+}
+
+int mixpi_forces_static(mixpi_system *sys, const double *q, const double *theta, double *f,
+                        double *e_out, void *stream)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!q || !f) return fail(MIXPI_E_INVALID, "q and f must be non-null");
+    if ((const void *)q == (const void *)f) return fail(MIXPI_E_INVALID, "f must not alias q");
+    if (sys->ew_use)
+        return fail(MIXPI_E_UNSUPPORTED, "mixpi_forces_static does not cover centroid Ewald "
+                                         "terms (mixpi_use_ewald(sys, 0) first)");
+    // scratch layout: partial-force positions [3 per position], the energy
+    // slots of the force range [0, e_rp), the reducer's chunk partials;
+    // each region 256-byte aligned
+    auto up = [](size_t n) { return (n + 31) & ~size_t(31); };   // doubles, 256-byte steps
+    const size_t n_part = up((size_t)3 * std::max<long long>(sys->n_positions, 1));
+    const size_t n_eslot = up((size_t)A_N * std::max(sys->e_rp, 1));
+    const size_t n_partial = up((size_t)A_N * std::max(sys->nch_f, 1));
+    const size_t need = (n_part + n_eslot + n_partial) * sizeof(double);
+    if (need > kStaticScratchBytes)
+        return fail(MIXPI_E_UNSUPPORTED,
+                    "mixpi_forces_static needs %zu bytes of scratch for this handle; the static "
+                    "scratch holds %zu (use mixpi_forces)",
+                    need, (size_t)kStaticScratchBytes);
+    double *base = static_scratch_ptr(sys->device);
+    if (!base) return fail(MIXPI_E_HIP, "static scratch not located on device %d", sys->device);
+    double *part = base, *eslot = base + n_part, *partial = eslot + n_eslot;
+    HIP_TRY(hipSetDevice(sys->device));
+    hipStream_t st = (hipStream_t)stream;
+    PairLaunch pa = pair_args(sys, q, theta);
+    pa.part = part;
+    pa.eslot = eslot;
+    BondedLaunch ba = bonded_args(sys, q, theta);
+    ba.part = part;
+    ba.eslot = eslot + (long long)sys->e_bonded * A_N;
+    launch_pair(pa, ba, sys->precision, false, st);
+    GatherArgs ga = gather_args(sys);
+    ga.part = part;
+    launch_gather(ga, sys->rows, f, st, sys->fin_rpw);
+    ReduceA ra = reduce_a_args(sys, 0, LIST_FORCE);
+    ra.eslot = eslot;
+    ra.partial = partial;
+    ReduceB rb = reduce_b_args(sys, LIST_FORCE);
+    rb.partial = partial;
+    rb.e_out = e_out;
+    launch_reduce(ra, rb, st);
     return last_launch_error();
 }
 

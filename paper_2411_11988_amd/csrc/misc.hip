@@ -1,10 +1,45 @@
 // Force gather, half-kick/estimator epilogue, energy reducer and small
 // bookkeeping kernels.
+#include <mutex>
+
 #include "mixpi.h"
 #include "mixpi_internal.h"
 #include "device_common.h"
 
 namespace mixpi {
+
+// ---------------------------------------------------------------------------
+// Device scratch of mixpi_forces_static: the partial-force slots, energy
+// slots and reducer partials of one force evaluation, in a fixed array that
+// every GPU the library runs on holds until the process ends.  In host code
+// the array's name is not a device address: the address is looked up once
+// per device (with that device current) and kept; only that address is ever
+// passed to kernels.
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    double *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+double *static_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 // ---------------------------------------------------------------------------
 // F[row] = sum over the row's partial-force slots, a contiguous run in the

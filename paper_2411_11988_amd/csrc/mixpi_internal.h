@@ -328,6 +328,14 @@ struct EwaldLaunch {
 };
 void launch_ewald(const EwaldLaunch &a, hipStream_t st);
 
+// Static device scratch of mixpi_forces_static (defined in misc.hip): its
+// size, the per-device lookup of its address (at handle creation, with the
+// device current) and the address found for a device (null before).
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch_init(int device);
+double *static_scratch_ptr(int device);
+
 void launch_fill(double *x, long long n, double v, hipStream_t st);
 void launch_delay(long long ticks_100mhz, hipStream_t st);
 void launch_gather(const GatherArgs &g, long long rows, double *f, hipStream_t st, int rpw);

@@ -31,6 +31,7 @@ MIXPI_NTHETA = 6
 MIXPI_FP64 = 0
 MIXPI_FP32_ACC64 = 1
 MIXPI_FLAG_CHECK_FINITE = 1
+MIXPI_STATIC_SCRATCH_BYTES = 16 << 20
 MIXPI_FLAG_TILE_J32 = 1 << 4
 MIXPI_FLAG_TILE_J64 = 1 << 5
 MIXPI_FLAG_TILE_WAVES1 = 1 << 6
@@ -88,6 +89,7 @@ def load():
         "mixpi_sizes": ([P, P, P, P, P], C.c_int),
         "mixpi_bead_index": ([P, P], C.c_int),
         "mixpi_forces": ([P, P, P, P, P, P], C.c_int),
+        "mixpi_forces_static": ([P, P, P, P, P, P], C.c_int),
         "mixpi_energy": ([P, P, P, P, P], C.c_int),
         "mixpi_energy_adjoint": ([P, P, P, P, P, P, P], C.c_int),
         "mixpi_nm_transform": ([P, I32, P, P, P], C.c_int),
@@ -193,6 +195,11 @@ def _stream(stream):
 
 def mixpi_forces(h, q, theta, f, e_out, stream=None) -> None:
     _check(load().mixpi_forces(h, _ptr(q), _ptr(theta), _ptr(f), _ptr(e_out), _stream(stream)))
+
+
+def mixpi_forces_static(h, q, theta, f, e_out, stream=None) -> None:
+    _check(load().mixpi_forces_static(h, _ptr(q), _ptr(theta), _ptr(f), _ptr(e_out),
+                                      _stream(stream)))
 
 
 def mixpi_energy(h, q, theta, e_out, stream=None) -> None:
@@ -328,6 +335,11 @@ class System:
         if e_out is None:
             e_out = torch.empty((self.n_systems, MIXPI_NV), dtype=torch.float64, device=q.device)
         mixpi_forces(self.h, q, theta, f, e_out, stream)
+        return f, e_out
+
+    def forces_static(self, q, f, e_out, theta=None, stream=None):
+        """mixpi_forces_static: into caller buffers, allocating nothing."""
+        mixpi_forces_static(self.h, q, theta, f, e_out, stream)
         return f, e_out
 
     def energy(self, q, theta=None, e_out=None, stream=None):

@@ -99,6 +99,7 @@ def test_rejects_bad_topology(mp):
 def test_null_handle_and_out(mp):
     lib = mp.load()
     assert lib.mixpi_forces(None, None, None, None, None, None) == mp.MIXPI_E_INVALID
+    assert lib.mixpi_forces_static(None, None, None, None, None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_step(None, 1, None, None, None, None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_create(None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_rdf(None, None, 5.0, 10, 9, None, None) == mp.MIXPI_E_INVALID
