@@ -139,7 +139,14 @@ struct mixpi_system {
     // normal modes: dense items first, then FFT items
     RpItem *d_rp = nullptr;       // items of the step
     RpItem *d_rp_nm = nullptr;    // items of the normal-mode transforms
-    int n_rp = 0, n_rp_fast = 0, n_rp_nm = 0;
+    RpItem *d_rp_lang = nullptr;  // items of the Langevin and velocity-Verlet launches
+    int n_rp = 0, n_rp_fast = 0, n_rp_nm = 0, n_rp_lang = 0;
+    // matrix-core items: columns, generator tables, step items; spring
+    // weights of the rows they propagate (epilogue)
+    MfmaCol *d_mf_cols = nullptr;
+    double *d_mf_tab = nullptr;
+    double *d_row_spw = nullptr;
+    int n_mf_step = 0;
     double *d_circ = nullptr;
     // circulant rings' stage rows: q and p + dt/2 F of each of their bead rows
     double *d_stage = nullptr;
@@ -152,7 +159,8 @@ struct mixpi_system {
     std::vector<double> h_prop, h_row_fm;
     std::vector<int> h_row_sys;
     std::vector<SysDev> h_sys;
-    unsigned rp_lds = 0, rp_lds_step = 0, rp_lds_nm = 0;   // dynamic LDS: largest, step items, transform items
+    // dynamic LDS: largest, step items, transform items, Langevin / VV items
+    unsigned rp_lds = 0, rp_lds_step = 0, rp_lds_nm = 0, rp_lds_lang = 0;
     double *d_basis = nullptr;
     double2 *d_tw = nullptr;
     double *d_prop = nullptr;
@@ -228,7 +236,8 @@ void release(mixpi_system *s)
     void *ptrs[] = {s->d_sys, s->d_ljpar, s->d_charge, s->d_ljt, s->d_mol,
                     s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items, s->d_iblocks,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
-                    s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_circ, s->d_stage,
+                    s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_rp_lang, s->d_mf_cols,
+                    s->d_mf_tab, s->d_row_spw, s->d_circ, s->d_stage,
                     s->d_row_stage, s->d_stage_rows, s->d_lang, s->d_basis, s->d_tw,
                     s->d_prop, s->d_row_ptr,
                     s->d_dest, s->d_part, s->d_fblocks, s->d_eslot, s->d_red_f, s->d_red_a,
@@ -351,6 +360,14 @@ struct Build {
     std::vector<double> ew_z;                  // Ewald charge per particle (0 for electrons)
     std::vector<int> sys_part;                 // first particle of each system
     std::vector<std::pair<long long, long long>> sys_rows;   // [begin, end) per system
+    struct GroupRec {
+        int sys;
+        long long row;
+        int N, n;
+    };
+    std::vector<GroupRec> groups;              // every group of every system, in row order
+    std::vector<MfmaCol> mf_cols;              // columns of the matrix-core items
+    std::vector<double> mf_tab;                // their generator tables
     long long rows = 0;
     long long candidates = 0;
     int n_part = 0, n_groups = 0;
@@ -445,6 +462,7 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         i = j;
     }
     B.n_groups += (int)groups.size();
+    for (const Group &g : groups) B.groups.push_back(Build::GroupRec{s, g.row, g.N, g.n});
     B.sys_part.push_back(p_base);
     for (const Group &g : groups)
         for (int i = 0; i < g.n; ++i) {
@@ -676,9 +694,10 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
 // the complex signal and its twiddles, or the circulant rows (q, p, a, b, c,
 // each N plus its pad) and the partial outputs.  A launch takes the largest
 // over its items, so items of small rings run more workgroups per CU.
-unsigned rp_item_lds(const RpItem &it)
+unsigned rp_item_lds(const RpItem &it, int op = OP_STEP, int precision = 0)
 {
     const long long N = it.N;
+    if (it.kind == RP_MFMA) return mfma_lds_bytes(it.N, op, precision);
     if (it.kind == RP_DENSE) return (unsigned)((2 * N * N + 4 * 256) * sizeof(double));
     if (it.kind == RP_FFT) return (unsigned)((2 * N - 1) * sizeof(double2));
     return (unsigned)((5 * (N + 64) + 2 * kCircJg * kCircOut) * sizeof(double));
@@ -749,6 +768,131 @@ void add_circulant(Build &B, const RpItem &rg, int stage0, std::vector<RpItem> &
                 it.wsp = wsp;
                 items.push_back(it);
             }
+    }
+}
+
+// Matrix-core transform items of every group with N >= kMfMinN: the
+// columns of all groups of one bead count share the basis (a cos table of N
+// entries), 16 columns and 16 output rows per item.
+void add_mfma_transforms(Build &B, std::vector<RpItem> &items)
+{
+    std::map<int, std::vector<int>> by_n;      // N -> groups
+    for (size_t g = 0; g < B.groups.size(); ++g)
+        if (B.groups[g].N >= kMfMinN) by_n[B.groups[g].N].push_back((int)g);
+    for (auto &kv : by_n) {
+        const int N = kv.first;
+        const int tab = (int)B.mf_tab.size();
+        for (int m = 0; m < N; ++m) B.mf_tab.push_back(std::cos(2.0 * kPi * m / N));
+        std::vector<MfmaCol> cols;
+        std::vector<int> col_sys;
+        for (int g : kv.second) {
+            const auto &G = B.groups[g];
+            for (int i = 0; i < G.n; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    cols.push_back(MfmaCol{G.row + i, -1, G.n, d});
+                    col_sys.push_back(G.sys);
+                }
+        }
+        for (size_t c0 = 0; c0 < cols.size(); c0 += kMfCols) {
+            const int nc = (int)std::min<size_t>(kMfCols, cols.size() - c0);
+            const int base = (int)B.mf_cols.size();
+            B.mf_cols.insert(B.mf_cols.end(), cols.begin() + c0, cols.begin() + c0 + nc);
+            for (int o0 = 0; o0 < N; o0 += kMfRows) {
+                RpItem it{};
+                it.kind = RP_MFMA;
+                it.sys = col_sys[c0];
+                it.N = N;
+                it.logN = ilog2(N);
+                it.c0 = base;
+                it.ncols = nc;
+                it.o0 = o0;
+                it.circ_off = tab;
+                items.push_back(it);
+            }
+        }
+    }
+}
+
+// Matrix-core propagation items for the groups marked in `use`: rings are
+// put into propagator classes (equal bead count and equal propagation
+// coefficients of every mode, so equal circulant rows a_d, b_d, c_d); the
+// columns of a class, across groups and systems, share one table.  Every
+// row of such a group gets a stage row (the items update q and p in place)
+// and the epilogue's spring weight k/2.
+void add_mfma_propagation(Build &B, const std::vector<char> &use, std::vector<int> &row_stage,
+                          std::vector<long long> &stage_rows, std::vector<double> &row_spw,
+                          std::vector<RpItem> &items)
+{
+    std::map<std::vector<double>, int> cls;    // coefficients -> class
+    std::vector<std::vector<MfmaCol>> cls_cols;
+    std::vector<int> cls_tab, cls_n, cls_sys;
+    std::vector<double> cls_dtm;
+    for (size_t g = 0; g < B.groups.size(); ++g) {
+        if (!use[g]) continue;
+        const auto &G = B.groups[g];
+        const int N = G.N;
+        const int stage0 = (int)stage_rows.size();
+        for (long long x = 0; x < (long long)N * G.n; ++x) {
+            row_stage[G.row + x] = stage0 + (int)x;
+            stage_rows.push_back(G.row + x);
+            row_spw[G.row + x] = 0.5 * B.row_ksp[G.row + x];
+        }
+        for (int i = 0; i < G.n; ++i) {
+            std::vector<double> key((size_t)3 * N + 1);
+            key[0] = N;
+            for (int k = 0; k < N; ++k)
+                for (int c = 0; c < 3; ++c)
+                    key[1 + 3 * k + c] = B.prop[5 * (size_t)(G.row + (long long)k * G.n + i) + c];
+            auto f = cls.find(key);
+            int id;
+            if (f == cls.end()) {
+                id = (int)cls_cols.size();
+                cls[key] = id;
+                cls_cols.emplace_back();
+                cls_n.push_back(N);
+                cls_sys.push_back(G.sys);
+                cls_dtm.push_back(key[1 + 1]);               // mode 0: dt / m_f
+                cls_tab.push_back((int)B.mf_tab.size());
+                // rows_d = (1/N) sum_k f_k cos(2 pi k d / N) of a, b, c
+                std::vector<double> cs(N);
+                for (int m = 0; m < N; ++m) cs[m] = std::cos(2.0 * kPi * m / N);
+                const size_t off = B.mf_tab.size();
+                B.mf_tab.resize(off + 3 * (size_t)N, 0.0);
+                for (int d = 0; d < N; ++d)
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = 0.0;
+                        for (int k = 0; k < N; ++k)
+                            acc += key[1 + 3 * k + c] * cs[(int)(((long long)k * d) % N)];
+                        B.mf_tab[off + (size_t)c * N + d] = acc / N;
+                    }
+            } else {
+                id = f->second;
+            }
+            for (int d = 0; d < 3; ++d)
+                cls_cols[id].push_back(MfmaCol{G.row + i, (long long)stage0 + i, G.n, d});
+        }
+    }
+    for (size_t id = 0; id < cls_cols.size(); ++id) {
+        const auto &cols = cls_cols[id];
+        const int N = cls_n[id];
+        for (size_t c0 = 0; c0 < cols.size(); c0 += kMfCols) {
+            const int nc = (int)std::min<size_t>(kMfCols, cols.size() - c0);
+            const int base = (int)B.mf_cols.size();
+            B.mf_cols.insert(B.mf_cols.end(), cols.begin() + c0, cols.begin() + c0 + nc);
+            for (int o0 = 0; o0 < N; o0 += kMfRows) {
+                RpItem it{};
+                it.kind = RP_MFMA;
+                it.sys = cls_sys[id];
+                it.N = N;
+                it.logN = ilog2(N);
+                it.c0 = base;
+                it.ncols = nc;
+                it.o0 = o0;
+                it.circ_off = cls_tab[id];
+                it.dtm = cls_dtm[id];
+                items.push_back(it);
+            }
+        }
     }
 }
 
@@ -1000,22 +1144,43 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     }
     S->n_bblocks = (int)bblocks.size();
 
-    std::vector<int> row_stage;
+    std::vector<int> row_stage((size_t)B.rows, -1);
     std::vector<long long> stage_rows;
-    // normal-mode items.  Transforms: dense, then FFT.  Step: dense, FFT of
-    // the rings not chosen for the bead-space step, circulant items.
-    std::vector<RpItem> rp_nm = B.rp_dense;
-    rp_nm.insert(rp_nm.end(), B.rp_fft.begin(), B.rp_fft.end());
+    std::vector<double> row_spw((size_t)B.rows, 0.0);
+    // Matrix-core (MFMA) items: transforms of every group with N >= 16
+    // unless MIXPI_NM_MFMA=0; the step's propagation of those groups when
+    // MIXPI_RING_MFMA=1.
+    const bool nm_mfma = !(getenv("MIXPI_NM_MFMA") && atoi(getenv("MIXPI_NM_MFMA")) == 0);
+    const bool ring_mfma = getenv("MIXPI_RING_MFMA") && atoi(getenv("MIXPI_RING_MFMA")) == 1;
+    std::vector<char> grp_mfma(B.groups.size(), 0);
+    for (size_t g = 0; g < B.groups.size(); ++g)
+        grp_mfma[g] = ring_mfma && B.groups[g].N >= kMfMinN;
+    auto grp_of_row = [&](long long row) {
+        size_t g = 0;
+        while (g + 1 < B.groups.size() && B.groups[g + 1].row <= row) ++g;
+        return g;
+    };
+    // Langevin and velocity-Verlet launches: dense, then FFT items (whole columns)
+    std::vector<RpItem> rp_lang = B.rp_dense;
+    rp_lang.insert(rp_lang.end(), B.rp_fft.begin(), B.rp_fft.end());
+    S->n_rp_lang = (int)rp_lang.size();
+    // transforms: matrix-core items for N >= 16, dense / FFT items below
+    std::vector<RpItem> rp_nm;
+    for (const RpItem &it : rp_lang)
+        if (!nm_mfma || it.N < kMfMinN) rp_nm.push_back(it);
+    if (nm_mfma) add_mfma_transforms(B, rp_nm);
     S->n_rp_nm = (int)rp_nm.size();
     // step items, longest first so that they start at once: FFT columns,
-    // then circulant items, then the dense items
+    // then circulant items, then matrix-core items, then the dense items
     std::vector<RpItem> rp;
     {
-        std::vector<char> circ_ring = choose_circulant(B.rings);
-        std::vector<RpItem> circ_items;
-        row_stage.assign((size_t)B.rows, -1);
-        for (size_t r = 0; r < B.rings.size(); ++r) {
-            const RpItem &rg = B.rings[r];
+        std::vector<RpItem> rings;
+        for (const RpItem &rg : B.rings)
+            if (!grp_mfma[grp_of_row(rg.row)]) rings.push_back(rg);
+        std::vector<char> circ_ring = choose_circulant(rings);
+        std::vector<RpItem> circ_items, mf_items;
+        for (size_t r = 0; r < rings.size(); ++r) {
+            const RpItem &rg = rings[r];
             if (!circ_ring[r]) {
                 for (const RpItem &it : B.rp_fft)
                     if (it.row == rg.row) rp.push_back(it);
@@ -1028,15 +1193,23 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             }
             add_circulant(B, rg, stage0, circ_items);
         }
+        add_mfma_propagation(B, grp_mfma, row_stage, stage_rows, row_spw, mf_items);
         rp.insert(rp.end(), circ_items.begin(), circ_items.end());
-        rp.insert(rp.end(), B.rp_dense.begin(), B.rp_dense.end());
+        rp.insert(rp.end(), mf_items.begin(), mf_items.end());
+        for (const RpItem &it : B.rp_dense)
+            if (!grp_mfma[grp_of_row(it.row)]) rp.push_back(it);
         S->n_stage = (int)stage_rows.size();
+        S->n_mf_step = (int)mf_items.size();
     }
     S->n_rp = S->n_rp_fast = (int)rp.size();
-    S->rp_lds_step = S->rp_lds_nm = (unsigned)(kReduceThreads * sizeof(double));
-    for (const RpItem &it : rp) S->rp_lds_step = std::max(S->rp_lds_step, rp_item_lds(it));
-    for (const RpItem &it : rp_nm) S->rp_lds_nm = std::max(S->rp_lds_nm, rp_item_lds(it));
-    S->rp_lds = std::max(S->rp_lds_step, S->rp_lds_nm);
+    const unsigned lds0 = (unsigned)(kReduceThreads * sizeof(double));
+    S->rp_lds_step = S->rp_lds_nm = S->rp_lds_lang = lds0;
+    for (const RpItem &it : rp)
+        S->rp_lds_step = std::max(S->rp_lds_step, rp_item_lds(it, OP_STEP, S->precision));
+    for (const RpItem &it : rp_nm)
+        S->rp_lds_nm = std::max(S->rp_lds_nm, rp_item_lds(it, OP_FWD, S->precision));
+    for (const RpItem &it : rp_lang) S->rp_lds_lang = std::max(S->rp_lds_lang, rp_item_lds(it));
+    S->rp_lds = std::max({S->rp_lds_step, S->rp_lds_nm, S->rp_lds_lang});
 
     // partial-force slots
     S->part_bonded = (long long)S->n_items * (64 + S->pair_tj);
@@ -1169,6 +1342,10 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     T(upload(&S->d_angle_t0, B.angle_t0));
     T(upload(&S->d_rp, rp));
     T(upload(&S->d_rp_nm, rp_nm));
+    T(upload(&S->d_rp_lang, rp_lang));
+    T(upload(&S->d_mf_cols, B.mf_cols.empty() ? std::vector<MfmaCol>(1, MfmaCol{}) : B.mf_cols));
+    T(upload(&S->d_mf_tab, B.mf_tab.empty() ? std::vector<double>(1, 0.0) : B.mf_tab));
+    if (S->n_mf_step > 0) T(upload(&S->d_row_spw, row_spw));
     T(upload(&S->d_circ, B.circ.empty() ? std::vector<double>(1, 0.0) : B.circ));
     T(upload(&S->d_row_stage, row_stage));
     T(upload(&S->d_stage_rows, stage_rows.empty() ? std::vector<long long>(1, 0) : stage_rows));
@@ -1408,10 +1585,16 @@ RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double 
     if (op == OP_STEP) {
         r.items = s->d_rp + lo;
         r.n_items = hi - lo;
-    } else {
+    } else if (op == OP_FWD || op == OP_BWD) {
         r.items = s->d_rp_nm;
         r.n_items = s->n_rp_nm;
+    } else {
+        r.items = s->d_rp_lang;
+        r.n_items = s->n_rp_lang;
     }
+    r.mf_cols = s->d_mf_cols;
+    r.mf_tab = s->d_mf_tab;
+    r.precision = s->precision;
     r.circ = s->d_circ;
     r.stage = s->d_stage;
     r.lang = s->d_lang;
@@ -1428,7 +1611,8 @@ RpLaunch rp_args(mixpi_system *s, int op, const double *in, double *out, double 
     r.f = f;
     r.cent = s->d_cent;
     r.eslot = eslot_buf(s, buf) + (long long)(s->e_rp + lo) * A_N;
-    r.lds_bytes = op == OP_STEP ? s->rp_lds_step : s->rp_lds_nm;
+    r.lds_bytes = op == OP_STEP ? s->rp_lds_step
+                                : (op == OP_FWD || op == OP_BWD ? s->rp_lds_nm : s->rp_lds_lang);
     return r;
 }
 
@@ -1451,6 +1635,7 @@ FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f,
     fl.row_prev = s->d_row_prev;
     fl.row_next = s->d_row_next;
     fl.row_ksp = s->d_row_ksp;
+    fl.row_spw = s->d_row_spw;
     return fl;
 }
 

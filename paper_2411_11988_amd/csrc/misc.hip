@@ -134,6 +134,13 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
             const double qn = a.q[3 * a.row_next[row] + (x - 3 * row)];
             fsp = -k * (2.0 * q0 - qp - qn);
             if (sl < 3) esp = 0.5 * k * (q0 - qn) * (q0 - qn);
+        } else if (a.row_spw) {
+            // rings propagated by matrix-core items: their spring energy here
+            const double spw = a.row_spw[row];
+            if (spw != 0.0 && sl < 3) {
+                const double qn = a.q[3 * a.row_next[row] + sl];
+                esp = spw * (q0 - qn) * (q0 - qn);
+            }
         }
         const double few = a.ew_rowf && sl < 3 ? a.ew_rowf[x] : 0.0;
         const Vec3 fv = gather_row_group<LPR>(a.gather, row, sl);
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
     __shared__ double red3[3][4];
     ke = wsum(ke);
     vir = wsum(vir);
-    if (a.vv) esp = wsum(esp);
+    if (a.vv || a.row_spw) esp = wsum(esp);
     if (lane == 0) {
         red3[0][w] = ke;
         red3[1][w] = vir;

@@ -91,7 +91,17 @@ struct BlockRange {
 };
 
 // free ring-polymer / normal-mode work item
-enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2 };
+enum { RP_DENSE = 0, RP_FFT = 1, RP_CIRC = 2, RP_MFMA = 3 };
+// A column of an MFMA item: component d of one ring.  Bead j of the column is
+// element (row0 + j * stride) * 3 + d of a state array, and stage row
+// srow0 + j * stride (propagation items; -1 otherwise).
+struct MfmaCol {
+    long long row0, srow0;
+    int stride, d;
+};
+constexpr int kMfCols = 16;        // columns of an MFMA item (the instructions' 16-wide N)
+constexpr int kMfRows = 16;        // output rows of an MFMA item
+constexpr int kMfMinN = 16;        // smallest ring an MFMA item takes
 constexpr int kCircOut = 16;       // bead outputs per circulant item
 constexpr int kCircJg = 256 / (kCircOut / 4);   // j-groups of a circulant item (4 outputs per thread)
 constexpr int kCircMaxN = 2048;    // largest ring propagated in bead space
@@ -108,6 +118,7 @@ struct RpItem {
     int circ_off;         // circulant: offset (doubles) of the particle's a, b, c rows
     int stage0;           // circulant: stage row of the group's first bead row
     double wsp;           // circulant: spring energy per squared bead step, kcal/mol/A^2
+    double dtm;           // MFMA propagation: dt / m_f of its columns (sum of the b row)
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -188,6 +199,11 @@ struct RpLaunch {
     const double2 *twiddle;  // per N, stage-major exp(-2 pi i pos / 2^s), N - 1 entries
     const double *prop;      // [rows][5] a, b, c, d, spring coefficient
     const double *circ;      // circulant propagator rows a_d, b_d, c_d per particle
+    // MFMA items: their columns, and the generator tables (propagation: rows
+    // a_d, b_d, c_d of a propagator class; transforms: cos(2 pi m / N))
+    const MfmaCol *mf_cols;
+    const double *mf_tab;
+    int precision;           // 0: FP64 matrix instructions, 1: FP32 with FP64 sums
     double *stage;           // circulant rings' step inputs [stage rows][6]: q, p + dt/2 F
                              // (read by OP_STEP, written by OP_LANG)
     // OP_LANG: Langevin half steps of p in normal modes, pi <- c1 pi + c2 eta
@@ -208,6 +224,20 @@ struct RpLaunch {
     ReduceA reduce;
 };
 void launch_rp(const RpLaunch &a, hipStream_t st);
+
+// LDS of an MFMA item: the generator table as FP64 or FP32 (propagation: the
+// a, b, c rows; transforms: the cos table), then the four waves' results
+// ([wave][2][4][64] doubles) and column sums ([wave][2][64]).
+__host__ __device__ inline unsigned mfma_tab_doubles(int N, int op, int precision)
+{
+    const unsigned n = (unsigned)((op == OP_STEP ? 3 : 1) * N);
+    const unsigned bytes = n * (precision ? 4u : 8u);
+    return ((bytes + 7) / 8 + 31) / 32 * 32;
+}
+__host__ __device__ inline unsigned mfma_lds_bytes(int N, int op, int precision)
+{
+    return (mfma_tab_doubles(N, op, precision) + 4 * 2 * 4 * 64 + 4 * 2 * 64) * 8;
+}
 const void *rp_kernel_symbol();
 
 // Gathers F[row] = sum of its partial-force slots.  The slots of a row are
@@ -238,6 +268,10 @@ struct FinishLaunch {
     int vv;
     const long long *row_prev, *row_next;  // [rows] neighbour bead rows of the ring
     const double *row_ksp;                 // [rows] spring constant, kcal/mol/A^2
+    // split-propagator steps: the spring energy k/2 |q - q_next|^2 of the
+    // rows whose ring the matrix-core items propagate (row_spw = k/2 there,
+    // 0 elsewhere; null: none)
+    const double *row_spw;
     const double *ew_rowf;                 // [rows][3] centroid-Ewald force, added (may be null)
 };
 void launch_finish(const FinishLaunch &a, hipStream_t st);

@@ -26,6 +26,8 @@
 // xi_k^2 and the centroid of the new positions (mode 0 / sqrt N, stored for
 // every bead row), backward transform, store of q and p, and zeroing of F for
 // the force accumulation that follows.
+#include <type_traits>
+
 #include "device_common.h"
 #include "mixpi_internal.h"
 
@@ -515,6 +517,187 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core (MFMA) items.  A ring's exact free propagator and its normal-
+// mode transform are dense N x N matrices applied to the ring's columns:
+//   transform (mixpi_nm_transform): xi = C^T x and x = C xi with the
+//     orthonormal basis C, generated from a table of cos(2 pi m / N) at
+//     m = (j k) mod N (a sine mode at m - N/4);
+//   step: q' = a * q + b * p, p' = c * q + a * p with the circulant rows
+//     a_d, b_d, c_d of the propagator C diag(f) C^T (see rp_circ), generated
+//     at d = (j - j') mod N; the transform, the per-mode propagation and the
+//     back transform in one product, with nothing in between to keep.
+// One item: 16 output rows of up to 16 columns that share the matrix (the
+// columns of every ring of one propagator class, across the systems of a
+// batch), so one 16x16x4 matrix instruction covers every column.  The four
+// waves each take a quarter of the K range (beads) and add their 16x16
+// results in LDS in a fixed order.  FP64 form: FP64 matrix instructions.
+// FP32 form: FP32 matrix instructions on reference-shifted columns (bead 0 of
+// each column subtracted, restored in FP64 with the exact row sums of the
+// matrix: sum a = 1, sum b = dt/m_f, sum c = 0; a transform's mode 0 in FP64),
+// FP32 sums over 64 beads added into FP64 accumulators.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    using V = mf_d4;
+    static __device__ __forceinline__ V mma(double x, double y, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+    // A: lane l holds A[l % 16][l / 16]; B: lane l holds B[l / 16][l % 16];
+    // result register r of lane l holds row (l / 16) + 4 r, column l % 16
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using V = mf_f4;
+    static __device__ __forceinline__ V mma(float x, float y, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+    }
+    // as above, but result register r of lane l holds row 4 (l / 16) + r
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+template <typename T>
+__device__ void rp_mfma(const RpLaunch &a, const RpItem &it, double *smem)
+{
+    using M = Mfma<T>;
+    using V = typename M::V;
+    const int N = it.N, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const bool prop = a.op == OP_STEP, bwd = a.op == OP_BWD;
+    T *tab = reinterpret_cast<T *>(smem);
+    double *red = smem + mfma_tab_doubles(N, a.op, a.precision);
+    double *csum = red + 4 * 2 * 4 * 64;
+    const int ntab = (prop ? 3 : 1) * N;
+    const double *tg = a.mf_tab + it.circ_off;
+    lds_fill<8>(ntab, [&](int x) { return tg[x]; }, [&](int x, double v) { tab[x] = (T)v; });
+
+    // this lane's column (l % 16) and its reference values (bead 0)
+    const int c = lane & 15;
+    const bool cv = c < it.ncols;
+    const MfmaCol col = a.mf_cols[it.c0 + (cv ? c : 0)];
+    const double rsN = 1.0 / sqrt((double)N), r2N = sqrt(2.0 / N);
+    double ref0 = 0.0, ref1 = 0.0;
+    if (cv) {
+        if (prop) {
+            const double *sr = a.stage + 6 * col.srow0;
+            ref0 = sr[col.d];
+            ref1 = sr[3 + col.d];
+        } else {
+            ref0 = a.in_q[3 * col.row0 + col.d];   // bead 0 (forward) or mode 0 (backward)
+        }
+    }
+    __syncthreads();
+
+    // the output row of this lane's A operand, and its fixed sine shift and
+    // scale in the forward transform
+    const int m = it.o0 + c;
+    const int ph_m = 2 * m > N ? N / 4 : 0;
+    const int mask = N - 1;
+    V d0 = {}, d1 = {};          // q' (or the transform) and p'
+    double h0[4] = {0, 0, 0, 0}, h1[4] = {0, 0, 0, 0};   // FP64 sums (FP32 form)
+    double sx = 0.0, sy = 0.0;   // column sums of the shifted inputs (propagation)
+    const int kq = N >> 2;       // beads of each wave
+    const int kb = w * kq;
+    int chunk = 0;
+    for (int s = kb; s < kb + kq; s += 4) {
+        const int kk = s + (lane >> 4);            // this lane's bead (or mode) of the B operand
+        double x = 0.0, y = 0.0;
+        if (cv) {
+            if (prop) {
+                const double *sr = a.stage + 6 * (col.srow0 + (long long)kk * col.stride);
+                x = sr[col.d] - ref0;
+                y = sr[3 + col.d] - ref1;
+            } else {
+                const double v = a.in_q[3 * (col.row0 + (long long)kk * col.stride) + col.d];
+                if (bwd) x = kk == 0 ? 0.0 : (2 * kk == N ? rsN : r2N) * v;
+                else x = v - ref0;
+            }
+        }
+        if (prop) {
+            sx += x;
+            sy += y;
+            const int idx = (m - kk) & mask;
+            const T ga = tab[idx], gb = tab[N + idx], gc = tab[2 * N + idx];
+            const T bx = (T)x, by = (T)y;
+            d0 = M::mma(ga, bx, d0);
+            d0 = M::mma(gb, by, d0);
+            d1 = M::mma(gc, bx, d1);
+            d1 = M::mma(ga, by, d1);
+        } else {
+            // forward: row m is the mode, kk the bead; backward: the reverse
+            const int idx = bwd ? ((m * kk - (2 * kk > N ? N / 4 : 0)) & mask)
+                                : ((kk * m - ph_m) & mask);
+            d0 = M::mma(tab[idx], (T)x, d0);
+        }
+        if constexpr (std::is_same<T, float>::value) {
+            if (++chunk == 16) {     // 64 beads summed in FP32: move them to FP64
+                chunk = 0;
+                for (int r = 0; r < 4; ++r) {
+                    h0[r] += (double)d0[r];
+                    h1[r] += (double)d1[r];
+                }
+                d0 = V{};
+                d1 = V{};
+            }
+        }
+    }
+    double o0[4], o1[4];
+    for (int r = 0; r < 4; ++r) {
+        o0[r] = h0[r] + (double)d0[r];
+        o1[r] = h1[r] + (double)d1[r];
+    }
+    // the four waves' partial results and column sums, added by wave 0 in order
+    for (int r = 0; r < 4; ++r) {
+        red[((w * 2 + 0) * 4 + r) * 64 + lane] = o0[r];
+        red[((w * 2 + 1) * 4 + r) * 64 + lane] = o1[r];
+    }
+    csum[(w * 2 + 0) * 64 + lane] = sx;
+    csum[(w * 2 + 1) * 64 + lane] = sy;
+    __syncthreads();
+    if (w != 0) return;
+    for (int r = 0; r < 4; ++r) {
+        for (int v = 1; v < 4; ++v) {
+            o0[r] += red[((v * 2 + 0) * 4 + r) * 64 + lane];
+            o1[r] += red[((v * 2 + 1) * 4 + r) * 64 + lane];
+        }
+    }
+    if (prop) {
+        double tx = 0.0, ty = 0.0;
+        for (int v = 0; v < 4; ++v)
+            for (int g = 0; g < 4; ++g) {
+                tx += csum[(v * 2 + 0) * 64 + 16 * g + c];
+                ty += csum[(v * 2 + 1) * 64 + 16 * g + c];
+            }
+        const double pbar = ref1 + ty / N;
+        const double qc = ref0 + tx / N + it.dtm * pbar;     // the propagated centroid
+        const double q0 = ref0 + it.dtm * ref1;
+        if (cv)
+            for (int r = 0; r < 4; ++r) {
+                const int mr = it.o0 + M::row(lane, r);
+                const long long g = 3 * (col.row0 + (long long)mr * col.stride) + col.d;
+                a.out_q[g] = q0 + o0[r];
+                a.p[g] = ref1 + o1[r];
+                a.cent[g] = qc;
+            }
+        if (lane == 0) {
+            // the spring energy of these rows is summed by the epilogue
+            double *e = a.eslot + (long long)blockIdx.x * A_N;
+            for (int k = 0; k < A_N; ++k) e[k] = 0.0;
+        }
+    } else if (cv) {
+        for (int r = 0; r < 4; ++r) {
+            const int mr = it.o0 + M::row(lane, r);
+            const long long g = 3 * (col.row0 + (long long)mr * col.stride) + col.d;
+            double v = o0[r];
+            if (bwd) v += ref0 * rsN;                           // mode 0
+            else v = (mr == 0 || 2 * mr == N ? rsN : r2N) * v + (mr == 0 ? ref0 * sqrt((double)N) : 0.0);
+            a.out_q[g] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Path-integral Langevin thermostat (the PILE thermostat of the paper's NVT
 // runs): each ring's momenta are projected onto the normal modes, every mode
 // takes one or two Ornstein-Uhlenbeck half steps pi <- c1 pi + c2 eta
@@ -791,6 +974,11 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
     }
     if (a.op == OP_VV) {
         rp_vv(a, it, smem, red);
+        return;
+    }
+    if (it.kind == RP_MFMA) {
+        if (a.precision) rp_mfma<float>(a, it, smem);
+        else rp_mfma<double>(a, it, smem);
         return;
     }
     if (it.kind == RP_DENSE) rp_dense(a, it, smem, red);
