@@ -771,14 +771,15 @@ void add_circulant(Build &B, const RpItem &rg, int stage0, std::vector<RpItem> &
     }
 }
 
-// Matrix-core transform items of every group with N >= kMfMinN: the
+// Matrix-core transform items of the groups whose N `use` accepts: the
 // columns of all groups of one bead count share the basis (a cos table of N
 // entries), 16 columns and 16 output rows per item.
-void add_mfma_transforms(Build &B, std::vector<RpItem> &items)
+template <typename Use>
+void add_mfma_transforms(Build &B, std::vector<RpItem> &items, Use use)
 {
     std::map<int, std::vector<int>> by_n;      // N -> groups
     for (size_t g = 0; g < B.groups.size(); ++g)
-        if (B.groups[g].N >= kMfMinN) by_n[B.groups[g].N].push_back((int)g);
+        if (use(B.groups[g].N)) by_n[B.groups[g].N].push_back((int)g);
     for (auto &kv : by_n) {
         const int N = kv.first;
         const int tab = (int)B.mf_tab.size();
@@ -1147,14 +1148,25 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     std::vector<int> row_stage((size_t)B.rows, -1);
     std::vector<long long> stage_rows;
     std::vector<double> row_spw((size_t)B.rows, 0.0);
-    // Matrix-core (MFMA) items: transforms of every group with N >= 16
-    // unless MIXPI_NM_MFMA=0; the step's propagation of those groups when
-    // MIXPI_RING_MFMA=1.
-    const bool nm_mfma = !(getenv("MIXPI_NM_MFMA") && atoi(getenv("MIXPI_NM_MFMA")) == 0);
-    const bool ring_mfma = getenv("MIXPI_RING_MFMA") && atoi(getenv("MIXPI_RING_MFMA")) == 1;
+    // Matrix-core (MFMA) items for rings of 16 to 64 beads, in the
+    // transforms and in the step (replacing the dense items there); larger
+    // rings keep the FFT and circulant items, which do the same exact work in
+    // O(N log N) or spread over many workgroups, where a 16-row matrix item
+    // re-reads its whole 2N x 16 input (measured: C5's ring launch 34 us
+    // with FFT items, 83-108 us with matrix items; C2's 32-bead hydrogens
+    // 8.6 -> 6.8 us with them).  MIXPI_NM_MFMA / MIXPI_RING_MFMA = 0 or 1
+    // turn them off or on for every ring with N >= 16.
+    auto mfma_rule = [](const char *name) {
+        const char *env = getenv(name);
+        return env ? atoi(env) : -1;
+    };
+    const int nm_rule = mfma_rule("MIXPI_NM_MFMA"), ring_rule = mfma_rule("MIXPI_RING_MFMA");
+    auto mfma_for = [](int rule, int N) {
+        if (N < kMfMinN || rule == 0) return false;
+        return rule == 1 || N <= kDenseMaxN;
+    };
     std::vector<char> grp_mfma(B.groups.size(), 0);
-    for (size_t g = 0; g < B.groups.size(); ++g)
-        grp_mfma[g] = ring_mfma && B.groups[g].N >= kMfMinN;
+    for (size_t g = 0; g < B.groups.size(); ++g) grp_mfma[g] = mfma_for(ring_rule, B.groups[g].N);
     auto grp_of_row = [&](long long row) {
         size_t g = 0;
         while (g + 1 < B.groups.size() && B.groups[g + 1].row <= row) ++g;
@@ -1167,8 +1179,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     // transforms: matrix-core items for N >= 16, dense / FFT items below
     std::vector<RpItem> rp_nm;
     for (const RpItem &it : rp_lang)
-        if (!nm_mfma || it.N < kMfMinN) rp_nm.push_back(it);
-    if (nm_mfma) add_mfma_transforms(B, rp_nm);
+        if (!mfma_for(nm_rule, it.N)) rp_nm.push_back(it);
+    add_mfma_transforms(B, rp_nm, [&](int N) { return mfma_for(nm_rule, N); });
     S->n_rp_nm = (int)rp_nm.size();
     // step items, longest first so that they start at once: FFT columns,
     // then circulant items, then matrix-core items, then the dense items
@@ -1205,7 +1217,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     const unsigned lds0 = (unsigned)(kReduceThreads * sizeof(double));
     S->rp_lds_step = S->rp_lds_nm = S->rp_lds_lang = lds0;
     for (const RpItem &it : rp)
-        S->rp_lds_step = std::max(S->rp_lds_step, rp_item_lds(it, OP_STEP, S->precision));
+        S->rp_lds_step = std::max(S->rp_lds_step, rp_item_lds(it, OP_STEP, 0));
     for (const RpItem &it : rp_nm)
         S->rp_lds_nm = std::max(S->rp_lds_nm, rp_item_lds(it, OP_FWD, S->precision));
     for (const RpItem &it : rp_lang) S->rp_lds_lang = std::max(S->rp_lds_lang, rp_item_lds(it));

@@ -203,7 +203,7 @@ struct RpLaunch {
     // a_d, b_d, c_d of a propagator class; transforms: cos(2 pi m / N))
     const MfmaCol *mf_cols;
     const double *mf_tab;
-    int precision;           // 0: FP64 matrix instructions, 1: FP32 with FP64 sums
+    int precision;           // transforms: 0 FP64 matrix instructions, 1 FP32 with FP64 sums
     double *stage;           // circulant rings' step inputs [stage rows][6]: q, p + dt/2 F
                              // (read by OP_STEP, written by OP_LANG)
     // OP_LANG: Langevin half steps of p in normal modes, pi <- c1 pi + c2 eta

@@ -530,11 +530,13 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
 // columns of every ring of one propagator class, across the systems of a
 // batch), so one 16x16x4 matrix instruction covers every column.  The four
 // waves each take a quarter of the K range (beads) and add their 16x16
-// results in LDS in a fixed order.  FP64 form: FP64 matrix instructions.
-// FP32 form: FP32 matrix instructions on reference-shifted columns (bead 0 of
-// each column subtracted, restored in FP64 with the exact row sums of the
-// matrix: sum a = 1, sum b = dt/m_f, sum c = 0; a transform's mode 0 in FP64),
-// FP32 sums over 64 beads added into FP64 accumulators.
+// results in LDS in a fixed order.  The step uses FP64 matrix instructions
+// in both forms: FP32 ones drift the conserved energy.  Transforms: FP64 in
+// the FP64 form; in the FP32 form FP32 matrix instructions on columns
+// shifted by their bead 0 (restored in FP64; a transform's mode 0 in FP64),
+// FP32 sums over 64 beads added into FP64 accumulators.  The shift is exact
+// algebra for the step too (the matrices' row sums are exact: sum a = 1,
+// sum b = dt/m_f, sum c = 0), so both forms share the code.
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
@@ -565,8 +567,9 @@ __device__ void rp_mfma(const RpLaunch &a, const RpItem &it, double *smem)
     using V = typename M::V;
     const int N = it.N, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool prop = a.op == OP_STEP, bwd = a.op == OP_BWD;
+    constexpr int tprec = std::is_same<T, float>::value ? 1 : 0;   // table layout of T
     T *tab = reinterpret_cast<T *>(smem);
-    double *red = smem + mfma_tab_doubles(N, a.op, a.precision);
+    double *red = smem + mfma_tab_doubles(N, a.op, tprec);
     double *csum = red + 4 * 2 * 4 * 64;
     const int ntab = (prop ? 3 : 1) * N;
     const double *tg = a.mf_tab + it.circ_off;
@@ -599,46 +602,62 @@ __device__ void rp_mfma(const RpLaunch &a, const RpItem &it, double *smem)
     double sx = 0.0, sy = 0.0;   // column sums of the shifted inputs (propagation)
     const int kq = N >> 2;       // beads of each wave
     const int kb = w * kq;
+    // the loads of KU bead steps go out together, then their matrix
+    // instructions (a loop that waited for each step's loads would be bound
+    // by memory latency)
+    constexpr int KU = 8;
     int chunk = 0;
-    for (int s = kb; s < kb + kq; s += 4) {
-        const int kk = s + (lane >> 4);            // this lane's bead (or mode) of the B operand
-        double x = 0.0, y = 0.0;
-        if (cv) {
-            if (prop) {
-                const double *sr = a.stage + 6 * (col.srow0 + (long long)kk * col.stride);
-                x = sr[col.d] - ref0;
-                y = sr[3 + col.d] - ref1;
-            } else {
-                const double v = a.in_q[3 * (col.row0 + (long long)kk * col.stride) + col.d];
-                if (bwd) x = kk == 0 ? 0.0 : (2 * kk == N ? rsN : r2N) * v;
-                else x = v - ref0;
-            }
-        }
-        if (prop) {
-            sx += x;
-            sy += y;
-            const int idx = (m - kk) & mask;
-            const T ga = tab[idx], gb = tab[N + idx], gc = tab[2 * N + idx];
-            const T bx = (T)x, by = (T)y;
-            d0 = M::mma(ga, bx, d0);
-            d0 = M::mma(gb, by, d0);
-            d1 = M::mma(gc, bx, d1);
-            d1 = M::mma(ga, by, d1);
-        } else {
-            // forward: row m is the mode, kk the bead; backward: the reverse
-            const int idx = bwd ? ((m * kk - (2 * kk > N ? N / 4 : 0)) & mask)
-                                : ((kk * m - ph_m) & mask);
-            d0 = M::mma(tab[idx], (T)x, d0);
-        }
-        if constexpr (std::is_same<T, float>::value) {
-            if (++chunk == 16) {     // 64 beads summed in FP32: move them to FP64
-                chunk = 0;
-                for (int r = 0; r < 4; ++r) {
-                    h0[r] += (double)d0[r];
-                    h1[r] += (double)d1[r];
+    for (int s0 = kb; s0 < kb + kq; s0 += 4 * KU) {
+        double xs[KU], ys[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int kk = s0 + 4 * u + (lane >> 4);   // this lane's bead (or mode) of the B operand
+            double x = 0.0, y = 0.0;
+            if (cv && kk < kb + kq) {
+                if (prop) {
+                    const double *sr = a.stage + 6 * (col.srow0 + (long long)kk * col.stride);
+                    x = sr[col.d] - ref0;
+                    y = sr[3 + col.d] - ref1;
+                } else {
+                    const double v = a.in_q[3 * (col.row0 + (long long)kk * col.stride) + col.d];
+                    if (bwd) x = kk == 0 ? 0.0 : (2 * kk == N ? rsN : r2N) * v;
+                    else x = v - ref0;
                 }
-                d0 = V{};
-                d1 = V{};
+            }
+            xs[u] = x;
+            ys[u] = y;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int kk = s0 + 4 * u + (lane >> 4);
+            if (s0 + 4 * u >= kb + kq) break;            // wave-uniform
+            const double x = xs[u], y = ys[u];
+            if (prop) {
+                sx += x;
+                sy += y;
+                const int idx = (m - kk) & mask;
+                const T ga = tab[idx], gb = tab[N + idx], gc = tab[2 * N + idx];
+                const T bx = (T)x, by = (T)y;
+                d0 = M::mma(ga, bx, d0);
+                d0 = M::mma(gb, by, d0);
+                d1 = M::mma(gc, bx, d1);
+                d1 = M::mma(ga, by, d1);
+            } else {
+                // forward: row m is the mode, kk the bead; backward: the reverse
+                const int idx = bwd ? ((m * kk - (2 * kk > N ? N / 4 : 0)) & mask)
+                                    : ((kk * m - ph_m) & mask);
+                d0 = M::mma(tab[idx], (T)x, d0);
+            }
+            if constexpr (std::is_same<T, float>::value) {
+                if (++chunk == 16) {     // 64 beads summed in FP32: move them to FP64
+                    chunk = 0;
+                    for (int r = 0; r < 4; ++r) {
+                        h0[r] += (double)d0[r];
+                        h1[r] += (double)d1[r];
+                    }
+                    d0 = V{};
+                    d1 = V{};
+                }
             }
         }
     }
@@ -977,7 +996,8 @@ __global__ __launch_bounds__(256) void k_rp(RpLaunch a)
         return;
     }
     if (it.kind == RP_MFMA) {
-        if (a.precision) rp_mfma<float>(a, it, smem);
+        // the step's propagation uses FP64 matrix instructions in both forms
+        if (a.precision && a.op != OP_STEP) rp_mfma<float>(a, it, smem);
         else rp_mfma<double>(a, it, smem);
         return;
     }
