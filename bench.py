@@ -571,8 +571,7 @@ def main():
         print("[bench] autotuning the pair tile shape", file=sys.stderr, flush=True)
         flags32 = tune.tile_flags(s, mixpi.MIXPI_FP32_ACC64)
         flags64 = tune.tile_flags(s, mixpi.MIXPI_FP64)
-        inv = {v: k for k, v in mixpi.TILE_FLAGS.items()}
-        tile = {"fp32": "%dx%d" % inv[flags32], "fp64": "%dx%d" % inv[flags64]}
+        tile = {"fp32": tune.describe(flags32), "fp64": tune.describe(flags64)}
     print(f"[bench] {wname}: FP32 pair form, {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
     r32 = _run(s, mixpi.MIXPI_FP32_ACC64, args.steps, args.warmup, mixpi, torch, flags32)
@@ -613,7 +612,7 @@ def main():
                    "systems": len(_as_list(s)), "dt_fs": _as_list(s)[0].dt,
                    "precision": ("fp32 electron-atom pseudopotential and 1/r seeds; fp64 atom-atom "
                                  "terms, separations, state and sums"),
-                   "pair_tile_jxwaves": tile},
+                   "pair_tile_tj_x_waves": tile},
         "steps_per_s": steps_per_s,
         "kernel_us": k_us,
         "energy_drift_kcal": r32["drift"],
@@ -624,7 +623,7 @@ def main():
                                  and TRAFFIC["sha256"] == _kernel_sha()
                                  and (tile == "heuristic" or tile["fp32"] == TRAFFIC["tile"])
                                  else None),
-                     "kernel": "k_pair<float,false,TJ,WAVES> (pair_tile_jxwaves)",
+                     "kernel": "k_pair<float,false,WAVES> (pair_tile_tj_x_waves)",
                      "flop_per_launch": flops, "launch_us": k_us["force"],
                      "lj_slice_pairs": ev_lj,
                      "executed": (_executed(k_us["force"]) if args.workload == TRAFFIC["workload"]

@@ -96,14 +96,21 @@ typedef enum {
 
 /* flags */
 #define MIXPI_FLAG_CHECK_FINITE 1   /* mixpi_step syncs and reports non-finite H */
-/* Tile shape of the pair sweep (at most one of each pair; none = the
- * library's choice from the work size): the j-tile width and the waves that
- * share a 64-bead i-tile.  Results agree to rounding for every shape; an
+/* Tile shape of the pair sweep (at most one flag of each kind; none = the
+ * library's choice from the work size).  TILE_J*: the j-tile width TJ of the
+ * system's tiles (the systems of a batch may differ).  Waves per tile (equal
+ * across a batch): TILE_WAVES1 one wave on a 64 x TJ tile; TILE_WAVES2 two
+ * waves splitting its j-beads; TILE_I128 / TILE_I256 a 128 x TJ or 256 x TJ
+ * tile, two or four waves of 64 i-beads sharing the j-beads (fewer
+ * partial-force slots).  Results agree to rounding for every shape; an
  * autotuner times them and picks one per workload. */
+#define MIXPI_FLAG_TILE_J16 (1 << 8)
 #define MIXPI_FLAG_TILE_J32 (1 << 4)
 #define MIXPI_FLAG_TILE_J64 (1 << 5)
 #define MIXPI_FLAG_TILE_WAVES1 (1 << 6)
 #define MIXPI_FLAG_TILE_WAVES2 (1 << 7)
+#define MIXPI_FLAG_TILE_I128 (1 << 9)
+#define MIXPI_FLAG_TILE_I256 (1 << 10)
 
 typedef struct mixpi_system mixpi_system;   /* opaque, owned by the library */
 

@@ -94,20 +94,24 @@ struct mixpi_system {
     int n_part = 0, n_groups = 0;
     long long candidates = 0;
     std::vector<long long> bead_index;
-    int pair_tj = 64;
-    int pair_waves = 1;
+    std::vector<int> pair_tj;                   // j-tile width of each system's items
+    int pair_tj_all = 0;                        // their common width, 0 if they differ
+    int pair_waves = 1;                         // j-split waves per pair tile
+    int pair_iw = 1;                            // i-split waves per pair tile
 
     SysDev *d_sys = nullptr;
     LjPar *d_ljpar = nullptr;                   // LJ tables in the pair sweep's form
     double *d_charge = nullptr;
     int *d_ljt = nullptr, *d_mol = nullptr, *d_row_sys = nullptr;
     double *d_row_fm = nullptr, *d_row_hk = nullptr;
-    // pair sweep: items on fast groups first, then items touching FFT groups
+    // pair sweep: items in system and block order
     PairBlock *d_blocks = nullptr;
     PairItem *d_items = nullptr;
     PairBlock *d_iblocks = nullptr;             // the block of every item
-    int n_items = 0, n_items_fast = 0;
-    // radial distribution: system-pure runs of pair items, largest bead count
+    int n_items = 0;
+    // radial distribution: the pair blocks' 64 x 64 tiles in system-pure runs,
+    // largest bead count
+    PairItem *d_rdf_items = nullptr;
     BlockRange *d_rdf_ranges = nullptr;
     int n_rdf_ranges = 0, top_beads = 1, max_nt1 = 1;
     // centroid quantities: particles in handle order, first particle per system
@@ -234,7 +238,7 @@ void release(mixpi_system *s)
         (void)hipGraphDestroy(g.graph);
     }
     void *ptrs[] = {s->d_sys, s->d_ljpar, s->d_charge, s->d_ljt, s->d_mol,
-                    s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items, s->d_iblocks,
+                    s->d_row_sys, s->d_row_fm, s->d_row_hk, s->d_blocks, s->d_items, s->d_iblocks, s->d_rdf_items,
                     s->d_bterms, s->d_bblocks, s->d_bond_k, s->d_bond_r0, s->d_angle_k,
                     s->d_angle_t0, s->d_rp, s->d_rp_nm, s->d_rp_lang, s->d_mf_cols,
                     s->d_mf_tab, s->d_row_spw, s->d_circ, s->d_stage,
@@ -267,11 +271,12 @@ int validate(const mixpi_system_desc *d, int idx)
     if (d->n_lj_types > 0 && (!d->lj_eps || !d->lj_sigma))
         return fail(MIXPI_E_INVALID, "system %d: LJ tables are null", idx);
     {
-        const int known = MIXPI_FLAG_CHECK_FINITE | MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_J64 |
-                          MIXPI_FLAG_TILE_WAVES1 | MIXPI_FLAG_TILE_WAVES2;
+        const int tjf = MIXPI_FLAG_TILE_J16 | MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_J64;
+        const int jobf = MIXPI_FLAG_TILE_WAVES1 | MIXPI_FLAG_TILE_WAVES2 | MIXPI_FLAG_TILE_I128 |
+                         MIXPI_FLAG_TILE_I256;
+        const int known = MIXPI_FLAG_CHECK_FINITE | tjf | jobf;
         const int f = d->flags;
-        if ((f & ~known) || ((f & MIXPI_FLAG_TILE_J32) && (f & MIXPI_FLAG_TILE_J64)) ||
-            ((f & MIXPI_FLAG_TILE_WAVES1) && (f & MIXPI_FLAG_TILE_WAVES2)))
+        if ((f & ~known) || __builtin_popcount(f & tjf) > 1 || __builtin_popcount(f & jobf) > 1)
             return fail(MIXPI_E_INVALID, "system %d: bad flags 0x%x", idx, f);
     }
     for (int i = 0; i < n; ++i) {
@@ -348,7 +353,6 @@ struct Build {
     std::vector<double> row_fm, row_hk, row_ksp;
     std::vector<long long> row_prev, row_next;
     std::vector<PairBlock> blocks;
-    std::vector<char> block_slow;              // block touches an FFT group
     std::vector<BondedTerm> bterms, bterms_slow;
     std::vector<RpItem> rp_fft, rp_dense;
     std::vector<RpItem> rings;                 // one per big ring column group (circulant candidates)
@@ -541,7 +545,6 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                         if (ta[a] && tb[b] && (d->lj_eps[a * nt + b] != 0.0 || (a == 0 && b == 0)))
                             pb.lj = 1;
             }
-            B.block_slow.push_back(A.N > kDenseMaxN || Bg.N > kDenseMaxN);
             B.blocks.push_back(pb);
             const long long pairs = pb.same ? (long long)A.n * (A.n - 1) / 2 : (long long)A.n * Bg.n;
             B.candidates += pairs * A.N;
@@ -897,59 +900,80 @@ void add_mfma_propagation(Build &B, const std::vector<char> &use, std::vector<in
     }
 }
 
-// Cuts the pair blocks with block_slow == slow into 64 x tj tiles: for each
-// j-bead b, i-tiles of 64 beads of the contiguous i-run times j-tiles of tj
-// particles (upper triangle only for a group with itself).
-std::vector<PairItem> pair_items(const std::vector<PairBlock> &blocks,
-                                 const std::vector<char> &block_slow, bool slow, int tj)
+// Cuts pair block bi into 64 iw x tj items: for each j-bead b, the i-tiles
+// of 64 iw beads of its contiguous i-run times the j-tiles of tj particles
+// (for a group with itself only tiles that hold some j > i).  The items of
+// one (b, i0) follow each other, j0 ascending.
+void block_items(const PairBlock &pb, int bi, int tj, int iw, std::vector<PairItem> &out)
 {
-    std::vector<PairItem> items;
-    for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        if ((bool)block_slow[bi] != slow) continue;
-        const PairBlock &pb = blocks[bi];
-        const long long li = (long long)pb.na << pb.shift;
-        for (int b = 0; b < pb.nbeads_b; ++b)
-            for (long long i0 = 0; i0 < li; i0 += 64)
-                for (int j0 = 0; j0 < pb.nb; j0 += tj) {
-                    if (pb.same && j0 < i0) continue;
-                    items.push_back(PairItem{(int)bi, b, (int)i0, j0});
-                }
-    }
-    return items;
+    const long long li = (long long)pb.na << pb.shift;
+    for (int b = 0; b < pb.nbeads_b; ++b)
+        for (long long i0 = 0; i0 < li; i0 += 64 * iw)
+            for (int j0 = 0; j0 < pb.nb; j0 += tj) {
+                if (pb.same && j0 + tj <= i0) continue;
+                PairItem it{};
+                it.block = bi;
+                it.b = b;
+                it.i0 = (int)i0;
+                it.j0 = j0;
+                it.tj = tj;
+                out.push_back(it);
+            }
 }
 
-// Tile width of the pair sweep: 64-wide j-tiles unless that leaves the
-// chip with fewer than about two waves per SIMD (1024 SIMDs), then 32.
-int choose_tj(const std::vector<PairBlock> &blocks, const std::vector<char> &block_slow)
+// Cost of sweeping one lane over W j-slots of an atom block, in VALU
+// instructions of the FP32 build.  p: the expected share of candidates
+// inside the cutoff, the cutoff sphere's volume over the box volume (at
+// most 1).  The masked sweep spends 70 per slot with LJ, 49.5 without; the
+// compacted sweep spends 28 per slot on the distance pass plus, per marked
+// slot of the fullest lane (taken as the mean W p plus 2.4 standard
+// deviations, the largest of 64 binomial counts), 74 on the pair math with
+// LJ, 53 without.
+double atom_sweep_cost(const SysDev &S, bool lj, int W, bool compact)
 {
-    const size_t n64 = pair_items(blocks, block_slow, false, 64).size() +
-                       pair_items(blocks, block_slow, true, 64).size();
-    return n64 < 2048 ? 32 : 64;
-}
-
-// Whether an atom block is swept in compacted form.  p: the expected share
-// of candidates inside the cutoff, the cutoff sphere's volume over the box
-// volume (at most 1).  A wave visits W = tj / waves j-slots per lane.  Cost
-// model, in VALU instructions of the FP32 build per candidate: the masked
-// sweep spends 70 with LJ, 49.5 without; the compacted sweep spends 28 on
-// the distance pass plus, per marked slot of the fullest lane (taken as the
-// mean W p plus 2.4 standard deviations, the largest of 64 binomial
-// counts), 74 on the pair math with LJ, 53 without.
-// Compaction is chosen when it saves at least a tenth, and only for
-// W >= 32: with 16 slots per lane the saving is small and the marked-slot
-// loop (not unrolled, one slot per iteration at scattered LDS addresses)
-// runs slower per instruction than the masked loop, so it loses (measured
-// on both forms).
-bool sparse_pays(const SysDev &S, bool lj, int W)
-{
-    if (W < 32) return false;
+    if (!compact) return (lj ? 70.0 : 49.5) * W;
     const double rc = std::max(S.rc_lj, S.rc_c);
     const double vol = S.box[0] * S.box[1] * S.box[2];
     const double p = std::min(1.0, 4.0 / 3.0 * kPi * rc * rc * rc / vol);
     const double hits = std::min((double)W, W * p + 2.4 * std::sqrt(W * p * (1.0 - p)));
-    const double dense = (lj ? 70.0 : 49.5) * W;
-    const double compact = 28.0 * W + (lj ? 74.0 : 53.0) * hits;
-    return compact < 0.9 * dense;
+    return 28.0 * W + (lj ? 74.0 : 53.0) * hits;
+}
+
+// Whether an atom block with W = tj slots per lane is swept in compacted
+// form: when that saves at least a tenth, and only for W >= 32.  With 16
+// slots per lane the saving is small and the marked-slot loop (not
+// unrolled, one slot per iteration at scattered LDS addresses) runs slower
+// per instruction than the masked loop, so it loses (measured on both forms).
+bool sparse_pays(const SysDev &S, bool lj, int W)
+{
+    if (W < 32) return false;
+    return atom_sweep_cost(S, lj, W, true) < 0.9 * atom_sweep_cost(S, lj, W, false);
+}
+
+// Default j-tile width (every system of a handle): 64-wide j-tiles unless
+// that leaves the chip with fewer than about two waves per SIMD (1024 SIMDs),
+// then 32.
+int default_tj(const std::vector<PairBlock> &blocks)
+{
+    std::vector<PairItem> items;
+    for (size_t bi = 0; bi < blocks.size(); ++bi) block_items(blocks[bi], (int)bi, 64, 1, items);
+    return items.size() < 2048 ? 32 : 64;
+}
+
+// Natural partial-force slots of the items, in order: 64 iw i-slots, then
+// tj j-slots each (for a launch of one width, item k's start at
+// k (64 iw + tj), as the kernel assumes).  Returns the number of slots (-1
+// past 2^31 - 1).
+long long assign_item_slots(std::vector<PairItem> &items, int iw)
+{
+    long long next = 0;
+    for (PairItem &it : items) {
+        it.islot = (int)next;
+        it.jslot = (int)(next + 64 * iw);
+        next += 64 * iw + it.tj;
+        if (next > (1LL << 31) - 1) return -1;
+    }
+    return next;
 }
 
 // Workgroup ranges over a list sorted by system: chunks of at most `per`
@@ -1002,11 +1026,12 @@ int reducer_plan(const std::vector<int> &eslot_sys, const std::vector<std::pair<
     return (int)cb.size();
 }
 
-// Partial-force slots and the per-row gather lists.  Slot numbering: pair
-// item k owns slots k*(64+tj) + [0, 64) for its i-beads and + 64 + [0, tj)
-// for its j-beads; bonded term t owns part_bonded + 3t + (0, 1, 2) for its
-// beads r[0], r[1] (and r[2] of an angle).  Rows list their slots in this
-// order, so every gather sums in a fixed order.
+// Partial-force slots and the per-row gather lists.  Natural slots: the
+// pair items' (64 i-slots, then tj j-slots each, as assign_item_slots
+// numbers them), then bonded term t owns
+// part_bonded + 3t + (0, 1, 2) for its beads r[0], r[1] (and r[2] of an
+// angle).  Rows list their slots in this order, so every gather sums in a
+// fixed order.
 struct Gather {
     std::vector<long long> row_ptr;   // [rows + 1] CSR positions of each row's slots
     std::vector<int> dest;            // [n_slots] position of each natural slot, -1 unused
@@ -1014,8 +1039,8 @@ struct Gather {
 };
 
 Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
-                    const std::vector<PairItem> &items, int tj,
-                    const std::vector<BondedTerm> &terms, long long part_bonded)
+                    const std::vector<PairItem> &items, int iw, const std::vector<BondedTerm> &terms,
+                    long long part_bonded)
 {
     Gather G;
     std::vector<long long> cnt(rows + 1, 0);
@@ -1024,14 +1049,14 @@ Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
             const PairItem &it = items[k];
             const PairBlock &pb = blocks[it.block];
             const long long li = (long long)pb.na << pb.shift;
-            const long long base = (long long)k * (64 + tj);
-            for (int l = 0; l < 64; ++l) {
+            for (int l = 0; l < 64 * iw; ++l) {
                 const long long idx = (long long)it.i0 + l;
-                if (idx < li) emit(pb.rowa + ((long long)it.b << pb.shift) * pb.na + idx, base + l);
+                if (idx < li)
+                    emit(pb.rowa + ((long long)it.b << pb.shift) * pb.na + idx, (long long)it.islot + l);
             }
-            const int jn = std::min(tj, pb.nb - it.j0);
+            const int jn = std::min(it.tj, pb.nb - it.j0);
             for (int l = 0; l < jn; ++l)
-                emit(pb.rowb + (long long)it.b * pb.nb + it.j0 + l, base + 64 + l);
+                emit(pb.rowb + (long long)it.b * pb.nb + it.j0 + l, (long long)it.jslot + l);
         }
         for (size_t t = 0; t < terms.size(); ++t) {
             const long long b = part_bonded + 3 * (long long)t;
@@ -1060,8 +1085,12 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int s = 0; s < n_sys; ++s) {
         int rc = validate(descs[s], s);
         if (rc) return rc;
-        if (descs[s]->precision != descs[0]->precision || descs[s]->flags != descs[0]->flags)
-            return fail(MIXPI_E_INVALID, "all systems of a batch must share precision and flags");
+        // the j-tile width may differ per system; every other flag is shared
+        const int tjf = MIXPI_FLAG_TILE_J16 | MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_J64;
+        if (descs[s]->precision != descs[0]->precision ||
+            (descs[s]->flags & ~tjf) != (descs[0]->flags & ~tjf))
+            return fail(MIXPI_E_INVALID,
+                        "all systems of a batch must share precision and flags (tile widths aside)");
     }
     Build B;
     for (int s = 0; s < n_sys; ++s) add_system(B, descs[s], s);
@@ -1091,30 +1120,56 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->candidates = B.candidates;
     S->bead_index = B.bead_index;
 
-    // pair items: fast groups first, then items touching an FFT group
-    S->pair_tj = choose_tj(B.blocks, B.block_slow);
-    if (S->flags & MIXPI_FLAG_TILE_J32) S->pair_tj = 32;
-    if (S->flags & MIXPI_FLAG_TILE_J64) S->pair_tj = 64;
-    if (const char *env = getenv("MIXPI_PAIR_TJ")) {
-        const int v = atoi(env);
-        if (v == 32 || v == 64) S->pair_tj = v;
-    }
-    std::vector<PairItem> items = pair_items(B.blocks, B.block_slow, false, S->pair_tj);
-    S->n_items_fast = (int)items.size();
+    // Pair items: per system with its j-tile width (a MIXPI_FLAG_TILE_J*
+    // flag of its description, else MIXPI_PAIR_TJ = 16, 32 or 64, else
+    // default_tj), in system and block order.
     {
-        auto slow = pair_items(B.blocks, B.block_slow, true, S->pair_tj);
-        items.insert(items.end(), slow.begin(), slow.end());
+        int tj0 = default_tj(B.blocks);
+        if (const char *env = getenv("MIXPI_PAIR_TJ")) {
+            const int v = atoi(env);
+            if (v == 16 || v == 32 || v == 64) tj0 = v;
+        }
+        S->pair_tj.assign(n_sys, tj0);
+        for (int y = 0; y < n_sys; ++y) {
+            const int f = descs[y]->flags;
+            if (f & MIXPI_FLAG_TILE_J16) S->pair_tj[y] = 16;
+            if (f & MIXPI_FLAG_TILE_J32) S->pair_tj[y] = 32;
+            if (f & MIXPI_FLAG_TILE_J64) S->pair_tj[y] = 64;
+        }
     }
+    S->pair_tj_all = S->pair_tj[0];
+    for (int y = 1; y < n_sys; ++y)
+        if (S->pair_tj[y] != S->pair_tj_all) S->pair_tj_all = 0;
+    // Waves per tile: two j-split waves while the launch has fewer than ~4
+    // 64-bead tiles per SIMD (1024 SIMDs): more, shorter waves even out the
+    // SIMDs and hide latency; else one.  MIXPI_PAIR_WAVES = 1 or 2 and
+    // MIXPI_PAIR_IW = 1, 2 or 4 (i-split waves, with one j-wave), or the
+    // TILE_WAVES / TILE_I flags, choose instead.
+    {
+        std::vector<PairItem> one;
+        for (size_t bi = 0; bi < B.blocks.size(); ++bi)
+            block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], 1, one);
+        S->pair_waves = one.size() < 4096 ? 2 : 1;
+        S->pair_iw = 1;
+        if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
+            const int v = atoi(env);
+            if (v == 1 || v == 2) S->pair_waves = v;
+        }
+        if (const char *env = getenv("MIXPI_PAIR_IW")) {
+            const int v = atoi(env);
+            if (v == 1 || v == 2 || v == 4) S->pair_iw = v;
+        }
+        if (S->flags & (MIXPI_FLAG_TILE_WAVES1 | MIXPI_FLAG_TILE_WAVES2 | MIXPI_FLAG_TILE_I128 |
+                        MIXPI_FLAG_TILE_I256)) {
+            S->pair_waves = (S->flags & MIXPI_FLAG_TILE_WAVES2) ? 2 : 1;
+            S->pair_iw = (S->flags & MIXPI_FLAG_TILE_I128) ? 2 : (S->flags & MIXPI_FLAG_TILE_I256) ? 4 : 1;
+        }
+        if (S->pair_iw > 1) S->pair_waves = 1;
+    }
+    std::vector<PairItem> items;
+    for (size_t bi = 0; bi < B.blocks.size(); ++bi)
+        block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], S->pair_iw, items);
     S->n_items = (int)items.size();
-    // two waves per tile while the launch has fewer than ~4 tiles per SIMD
-    // (1024 SIMDs): more, shorter waves even out the SIMDs and hide latency
-    S->pair_waves = S->n_items < 4096 ? 2 : 1;
-    if (S->flags & MIXPI_FLAG_TILE_WAVES1) S->pair_waves = 1;
-    if (S->flags & MIXPI_FLAG_TILE_WAVES2) S->pair_waves = 2;
-    if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
-        const int v = atoi(env);
-        if (v == 1 || v == 2) S->pair_waves = v;
-    }
     {
         // compacted sweep for atom blocks with few in-cutoff candidates;
         // MIXPI_PAIR_SPARSE=0 or 1 forces it off or on for every atom block
@@ -1127,8 +1182,28 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             if (pb.kind != PK_ATOM) continue;
             pb.sparse = force >= 0 ? force
                                    : sparse_pays(B.sys[pb.sys], pb.lj != 0,
-                                                 S->pair_tj / S->pair_waves);
+                                                 S->pair_tj[pb.sys] / S->pair_waves);
         }
+    }
+    {
+        // launch order: the most expensive tiles first, so that the cheap
+        // ones fill in at the end (stable within equal cost)
+        std::vector<double> cost(B.blocks.size());
+        for (size_t bi = 0; bi < B.blocks.size(); ++bi) {
+            const PairBlock &pb = B.blocks[bi];
+            const int W = S->pair_tj[pb.sys] / S->pair_waves;
+            cost[bi] = S->pair_iw * (pb.kind == PK_ATOM
+                                         ? atom_sweep_cost(B.sys[pb.sys], pb.lj != 0, W, pb.sparse != 0)
+                                         : 48.5 * W);
+        }
+        std::stable_sort(items.begin(), items.end(), [&](const PairItem &x, const PairItem &y) {
+            return cost[x.block] > cost[y.block];
+        });
+    }
+    const long long item_slots = assign_item_slots(items, S->pair_iw);
+    if (item_slots < 0) {
+        delete S;
+        return fail(MIXPI_E_UNSUPPORTED, "too many partial-force slots");
     }
 
     // bonded terms and their system-pure blocks
@@ -1224,8 +1299,8 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->rp_lds = std::max({S->rp_lds_step, S->rp_lds_nm, S->rp_lds_lang});
 
     // partial-force slots
-    S->part_bonded = (long long)S->n_items * (64 + S->pair_tj);
-    Gather G = build_gather(B.rows, B.blocks, items, S->pair_tj, terms, S->part_bonded);
+    S->part_bonded = item_slots;
+    Gather G = build_gather(B.rows, B.blocks, items, S->pair_iw, terms, S->part_bonded);
 
     // epilogue blocks: 4 waves of rpw rows of one system.  Many rows with
     // short partial runs share a wave (64 / rpw lanes per row); few rows or
@@ -1266,19 +1341,26 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     for (int b = 0; b < S->n_bblocks; ++b) eslot_sys[S->e_bonded + b] = bblocks[b].sys;
     for (int r = 0; r < S->n_rp; ++r) eslot_sys[S->e_rp + r] = rp[r].sys;
     for (int f = 0; f < S->n_fblocks; ++f) eslot_sys[S->e_fin + f] = fblocks[f].sys;
-    // radial distribution: runs of at most K items of one system, K chosen
-    // for about 2048 workgroups and so that no LDS count can pass 2^32
+    // radial distribution: the blocks' 64 x 64 tiles in runs of at most K
+    // tiles of one system, K chosen for about 2048 workgroups and so that no
+    // LDS count can pass 2^32
     std::vector<BlockRange> rdf_ranges;
+    std::vector<PairItem> rdf_items;
     {
         for (const SysDev &sd : B.sys) S->max_nt1 = std::max(S->max_nt1, sd.nt1);
         for (const PairBlock &pb : B.blocks)
             S->top_beads = std::max(S->top_beads, pb.nbeads_b << pb.shift);
-        const long long per_item = 64LL * S->pair_tj * S->top_beads;
+        std::vector<int> rdf_sys;
+        for (size_t bi = 0; bi < B.blocks.size(); ++bi) {
+            block_items(B.blocks[bi], (int)bi, kRdfTj, 1, rdf_items);
+            rdf_sys.resize(rdf_items.size(), B.blocks[bi].sys);
+        }
+        const int n_rdf = (int)rdf_items.size();
+        const long long per_item = 64LL * kRdfTj * S->top_beads;
         const long long cap = std::max(1LL, std::min(64LL, 0xffffffffLL / per_item));
-        const long long want = (S->n_items + 2047) / 2048;
+        const long long want = (n_rdf + 2047) / 2048;
         const int K = (int)std::max(1LL, std::min(cap, want));
-        rdf_ranges = system_blocks(std::vector<int>(eslot_sys.begin(), eslot_sys.begin() + S->n_items),
-                                   0, S->n_items, K);
+        rdf_ranges = system_blocks(rdf_sys, 0, n_rdf, K);
         S->n_rdf_ranges = (int)rdf_ranges.size();
     }
     // per-system slot lists (stable order) for the reducer
@@ -1331,6 +1413,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         for (size_t k = 0; k < items.size(); ++k) ib[k] = B.blocks[items[k].block];
         T(upload(&S->d_iblocks, ib));
     }
+    T(upload(&S->d_rdf_items, rdf_items));
     T(upload(&S->d_rdf_ranges, rdf_ranges));
     {
         std::vector<int> sp = B.sys_part;
@@ -1420,17 +1503,15 @@ enum Part { ALL = 0, FAST = 1, SLOW = 2 };
 
 double *eslot_buf(mixpi_system *s, int buf) { return s->d_eslot + (long long)buf * s->n_eslots * A_N; }
 
-PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int buf = 0,
-                     Part part = ALL)
+PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int buf = 0)
 {
     PairLaunch a{};
-    const int lo = part == SLOW ? s->n_items_fast : 0;
-    const int hi = part == FAST ? s->n_items_fast : s->n_items;
-    a.items = s->d_items + lo;
-    a.n_items = hi - lo;
-    a.tj = s->pair_tj;
+    a.items = s->d_items;
+    a.n_items = s->n_items;
+    a.tj = s->pair_tj_all;
     a.waves = s->pair_waves;
-    a.iblocks = s->d_iblocks + lo;
+    a.iw = s->pair_iw;
+    a.iblocks = s->d_iblocks;
     a.sys = s->d_sys;
     a.ljpar = s->d_ljpar;
     a.charge = s->d_charge;
@@ -1439,7 +1520,6 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.q = q;
     a.part = s->d_part;
     a.dest = s->d_dest;
-    a.item0 = lo;
     a.theta = theta;
     a.eslot = eslot_buf(s, buf);
     return a;
@@ -2117,7 +2197,7 @@ int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, i
                     nbins, sys->max_nt1 * (sys->max_nt1 + 1) / 2, kRdfLdsBytes);
     HIP_TRY(hipSetDevice(sys->device));
     RdfLaunch a{};
-    a.items = sys->d_items;
+    a.items = sys->d_rdf_items;
     a.ranges = sys->d_rdf_ranges;
     a.blocks = sys->d_blocks;
     a.sys = sys->d_sys;
@@ -2129,7 +2209,7 @@ int mixpi_rdf(mixpi_system *sys, const double *q, double r_max, int32_t nbins, i
     a.unit = 1.0 / sys->top_beads;
     a.nbins = nbins;
     a.nspec = nspec;
-    a.tj = sys->pair_tj;
+    a.tj = kRdfTj;
     a.top = sys->top_beads;
     launch_rdf(a, sys->n_rdf_ranges, (int)lds, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());

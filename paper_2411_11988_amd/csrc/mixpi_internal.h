@@ -72,9 +72,15 @@ struct PairBlock {
 struct alignas(16) LjPar {
     double e4, s2, c0, c1;
 };
+// A 64 iw x tj tile of a pair block (iw: the launch's i-split waves): j-bead
+// b, i-beads [i0, i0 + 64 iw) of the block's i-run, j-particles
+// [j0, j0 + tj).  Its i-forces go to natural partial-force slots
+// islot + [0, 64 iw), its j-reactions to jslot + [0, tj).
 struct PairItem {
     int block, b, i0, j0;
+    int tj, islot, jslot, pad;
 };
+constexpr int kMaxTj = 64;
 
 // One slice of a bonded term: kind 0 = bond (r[0], r[1]), kind 1 = angle
 // (end r[0], vertex r[1], end r[2]); w = 1 / N_max.  Owns partial-force
@@ -125,8 +131,9 @@ struct RpItem {
 struct PairLaunch {
     const PairItem *items;
     int n_items;
-    int tj;                  // j-tile width (32 or 64)
-    int waves;               // waves per tile (1 or 2)
+    int tj;                  // j-tile width of every item (16, 32, 64), or 0: per item
+    int waves;               // j-split waves per tile (1 or 2)
+    int iw;                  // i-split waves per tile (1, 2 or 4; with waves = 1)
     const PairBlock *iblocks; // the block of every item, copied per item
     const SysDev *sys;
     const LjPar *ljpar;      // per system at lj_off: (nt+1)^2 type pairs
@@ -135,10 +142,8 @@ struct PairLaunch {
     const double *q;
     double *part;            // partial forces [positions][3], row-contiguous
     const int *dest;         // position of every natural slot (-1: unused)
-    int item0;               // global index of items[0] (natural slot base = index * (64 + tj))
     const double *theta;
-    double *eslot;           // energy slot of global item k: eslot + k * A_N
-    int n_bblocks;           // bonded workgroups run after the pair tiles
+    double *eslot;           // energy slot of item k: eslot + k * A_N
 };
 
 struct BondedLaunch {
@@ -301,6 +306,7 @@ struct RdfLaunch {
     int nbins, nspec, tj, top;
 };
 constexpr int kRdfLdsBytes = 56 * 1024;
+constexpr int kRdfTj = 64;         // j-tile width of the histogram's tiles
 void launch_rdf(const RdfLaunch &a, int n_ranges, int lds_bytes, hipStream_t st);
 
 // A particle for centroid quantities: bead j sits at row row0 + j * stride.

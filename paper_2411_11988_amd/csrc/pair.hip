@@ -7,11 +7,15 @@
 // the state of group g is a [N_g][n_g][3] block.  For a group pair (a, b)
 // with N_b = N_a >> shift, the slice-pairs that meet bead b of group b are
 // exactly the rows [b << shift, (b + 1) << shift) of group a -- a contiguous
-// run of n_a << shift beads.  One work item is a 64 x TJ tile of that
-// rectangle (or of the upper triangle for a group with itself): one lane per
-// i-bead, the TJ j-beads staged in LDS; with WAVES = 2 two waves share the
-// tile, each taking half of the j-beads (more, shorter waves when a launch
-// has few tiles per SIMD), and hand their i-forces to wave 0 at the end.  Lane l visits j-slot
+// run of n_a << shift beads.  One work item is a 64 IW x TJ tile of that
+// rectangle (or of the upper triangle for a group with itself), TJ = 16, 32
+// or 64 per system: one lane per i-bead, the TJ j-beads staged in LDS.
+// With WAVES = 2 (IW = 1) two waves share a 64-bead i-tile, each taking half
+// of the j-beads (more, shorter waves when a launch has few tiles per
+// SIMD), and hand their i-forces to wave 0 at the end.  With IW = 2 or 4
+// each of IW waves takes its own 64 i-beads against all TJ j-beads, and the
+// j-reactions of all of them meet in one LDS accumulator (one j-partial per
+// IW i-tiles: fewer partial-force slots for large launches).  Lane l visits j-slot
 // (l + t) mod TJ at step t, so the lanes spread over distinct j-beads and
 // the Newton-3 reaction goes to a per-j LDS accumulator with a return-less
 // LDS atomic add; i-forces stay in registers.  The loop body has no
@@ -56,55 +60,74 @@ template <typename R> __device__ __forceinline__ double rsqrt_fp64(double x)
     return y * fma(-0.5 * x * y, y, 1.5);
 }
 
-// The j-beads of a tile in LDS as separate arrays (x, y, z, and the charge
-// record), so that a wave's reads of consecutive j-slots are consecutive
-// words: free of bank conflicts, where 32-byte records put four of a wave's
-// slots on the same banks.  The charge record holds the FP64 charge (k_e q_j
-// for an electron-atom block with the electron as i), its R rounding for
-// the pseudopotential sweep, and LJ type | mol id << 4.
-template <typename R> struct alignas(16) JQ {
-    double qd;
-    R q;
-    int tm;
+// The j-beads of a tile in LDS as separate arrays of 8-byte elements, so
+// that one byte offset (slot * 8) addresses every field of a slot and a
+// wave's reads of consecutive slots are consecutive words (free of bank
+// conflicts).  Fields: position; the FP64 charge (k_e q_j for an
+// electron-atom block with the electron as i); the slot's molecule and
+// index in its group (-1: padding); its LJ type as a byte offset into the
+// type-pair table, and the R-rounded pseudopotential constant pp_q k_e q_j
+// (FP32 form).
+struct alignas(8) JMol {
+    int mol, jg;
 };
-template <typename R> struct JTile {
-    double x, y, z;
-    double qd;
-    R q;
-    int tm;
+struct alignas(8) JTyp {
+    int jt;        // LJ type * sizeof(LjPar)
+    float kq;      // pp_q k_e q_j, FP32
 };
-template <typename R, bool THETA, int TJ, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch bl)
+template <typename R> struct JSlot {
+    double x, y, z, qd;
+    int mol, jg, jt;
+    float kq;
+};
+// LDS of a pair workgroup with tiles up to TJM wide, WAVES j-split waves and
+// IW i-split waves (the workgroups per CU are LDS-bound near 10 KB, so
+// nothing unused is kept).
+template <typename R, int TJM, int WAVES, int IW> struct PairLds {
+    double sjx[TJM], sjy[TJM], sjz[TJM], sjq[TJM];
+    JMol sjm[TJM];
+    JTyp sjt[TJM];
+    double fjx[TJM], fjy[TJM], fjz[TJM];
+    LjPar tlj[kLjTab];
+    double xs[WAVES > 1 ? WAVES : 1][3][WAVES > 1 ? 64 : 1];   // i-forces handed to wave 0
+    double es[WAVES > IW ? WAVES : IW][5];                      // the waves' sums
+};
+
+// Element at byte offset off of an LDS array.
+template <typename T> __device__ __forceinline__ T &at(T *base, int off)
 {
-    __shared__ double red[WAVES];
-    if ((int)blockIdx.x >= a.n_items) {
-        // bonded workgroups of the same launch (64 terms each)
-        const int bb = blockIdx.x - a.n_items;
-        bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, red);
-        return;
-    }
-    // the item and its block are independent loads (the block is copied per
-    // item), so everything after them is one dependent step away
-    const PairItem it = a.items[blockIdx.x];
-    const PairBlock bk = a.iblocks[blockIdx.x];
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+
+// One item of j-tile width TJ.
+// FIXED: every item of the launch has width TJ, so item k's natural slots
+// start at k (64 IW + TJ), known before the item is loaded.
+template <typename R, bool THETA, int TJ, int WAVES, int IW, bool FIXED, int TJM>
+__device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &it, const PairBlock &bk,
+                                          PairLds<R, TJM, WAVES, IW> &L)
+{
     const SysDev &S = a.sys[bk.sys];
     const double *th = a.theta ? a.theta + 6 * bk.sys : S.theta0;
     const int lane = threadIdx.x & 63;
-    const int wv = (int)threadIdx.x >> 6;        // wave: j-slots wv*TJ/WAVES ...
+    const int wv = WAVES > 1 ? (int)threadIdx.x >> 6 : 0;   // j-split wave: j-slots wv*TJ/WAVES ...
+    const int iw = IW > 1 ? (int)threadIdx.x >> 6 : 0;      // i-split wave: i-beads i0 + 64 iw ...
     // output positions of this lane's slots, fetched early
-    const long long sb = (long long)(a.item0 + blockIdx.x) * (64 + TJ);
-    const int di = a.dest[sb + lane];
-    const int dj = (int)threadIdx.x < TJ ? a.dest[sb + 64 + threadIdx.x] : -1;
+    const long long si = FIXED ? (long long)blockIdx.x * (64 * IW + TJ) : it.islot;
+    const long long sj = FIXED ? si + 64 * IW : it.jslot;
+    const int di = a.dest[si + 64 * iw + lane];
+    const int dj = (int)threadIdx.x < TJ ? a.dest[sj + threadIdx.x] : -1;
 
-    __shared__ double sjx[TJ], sjy[TJ], sjz[TJ];
-    __shared__ JQ<R> sjq[TJ];
-    // j-slot jj as read by the loops
-    auto jload = [&](int jj) {
-        const JQ<R> m = sjq[jj];
-        return JTile<R>{sjx[jj], sjy[jj], sjz[jj], m.qd, m.q, m.tm};
+    double *const sjx = L.sjx, *const sjy = L.sjy, *const sjz = L.sjz, *const sjq = L.sjq;
+    JMol *const sjm = L.sjm;
+    JTyp *const sjt = L.sjt;
+    double *const fjx = L.fjx, *const fjy = L.fjy, *const fjz = L.fjz;
+    LjPar *const tlj = L.tlj;
+    // the j-slot at byte offset o (slot * 8) as read by the loops
+    auto jload = [&](int o) {
+        const JMol m = at(sjm, o);
+        const JTyp t = at(sjt, o);
+        return JSlot<R>{at(sjx, o), at(sjy, o), at(sjz, o), at(sjq, o), m.mol, m.jg, t.jt, t.kq};
     };
-    __shared__ double fjx[TJ], fjy[TJ], fjz[TJ];
-    __shared__ LjPar tlj[kLjTab];
 
     const int nt1 = bk.nt1;
     const double rc_lj = S.rc_lj, rc_c = S.rc_c;
@@ -136,8 +159,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     const int jn = min(TJ, bk.nb - it.j0);
     if ((int)threadIdx.x < TJ) {
         const int js = threadIdx.x;
-        double x = 0, y = 0, z = 0;
-        JQ<R> jq{};
+        double x = 0, y = 0, z = 0, qd = 0;
+        JMol jm{-1, -1};
+        JTyp jt{0, 0.0f};
         if (js < jn) {
             const int j = it.j0 + js;
             const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
@@ -148,14 +172,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             // electron-atom blocks with the electron as i take k_e q_j as
             // their pseudopotential constant: scaled here, once per tile
             const double qc = a.charge[pj];
-            jq.qd = bk.kind == PK_E_ATOM ? kCoulombKcal * qc : qc;
-            jq.q = (R)jq.qd;
-            jq.tm = a.ljt[pj] | (a.mol[pj] << 4);
+            qd = bk.kind == PK_E_ATOM ? kCoulombKcal * qc : qc;
+            jm.mol = a.mol[pj];
+            jm.jg = j;
+            jt.jt = a.ljt[pj] * (int)sizeof(LjPar);
+            jt.kq = (float)(th[0] * qd);
         }
         sjx[js] = x;
         sjy[js] = y;
         sjz[js] = z;
-        sjq[js] = jq;
+        sjq[js] = qd;
+        sjm[js] = jm;
+        sjt[js] = jt;
         fjx[js] = 0.0;
         fjy[js] = 0.0;
         fjz[js] = 0.0;
@@ -163,7 +191,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
 
     // i bead
     const long long li = (long long)bk.na << bk.shift;
-    const long long idx = (long long)it.i0 + lane;
+    const long long idx = (long long)it.i0 + 64 * iw + lane;
     const bool vi = idx < li;
     const long long rowi = bk.rowa + ((long long)it.b << bk.shift) * bk.na + idx;
     double xi = 0, yi = 0, zi = 0, qi = 0;
@@ -189,9 +217,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     // in-cutoff slice-pairs: a per-lane count (one add per candidate),
     // summed over the wave after the loop
     int cnt = 0;
-    // slots that may interact: real j, and for a group with itself j > i
-    const int jlo = bk.same ? (int)max(-1LL, min((long long)TJ, idx - it.j0)) : -1;
-    const int jhi = vi ? jn : 0;
+    // slots that may interact: jg > key, i.e. real j (padding has jg = -1),
+    // for a group with itself j > i, and none for a lane past the i-run
+    const int key = !vi ? 0x7fffffff : (bk.same ? (int)idx : -1);
+    // this lane's first slot offset, and the wave's slots (j-split waves)
+    const int lane8 = lane * 8, wv8 = wv * (TJ / WAVES) * 8;
+    constexpr int M8 = (TJ / WAVES) * 8 - 1;
 
     if (bk.kind == PK_ATOM) {
         // Atom-atom Lennard-Jones and Coulomb in FP64 in both forms, from
@@ -202,11 +233,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         // at the FP32 rate on this chip, so only the seed is cheaper in FP32.
         const double rc2_lj = rc_lj * rc_lj, rc2_c = rc_c * rc_c;
         const double rc2max = fmax(rc2_lj, rc2_c);
-        const double irc = 1.0 / rc_c;
-        const double irc3 = 1.0 / (rc_c * rc_c * rc_c);
+        // rc_c = 0 (no bead-resolved Coulomb): finite stand-ins, every
+        // Coulomb term is masked by r^2 < 0
+        const double irc = rc_c > 0.0 ? 1.0 / rc_c : 0.0;
+        const double irc3 = rc_c > 0.0 ? 1.0 / (rc_c * rc_c * rc_c) : 0.0;
         const double hc = 0.5 * irc3;
         const double kqi = kCoulombKcal * qi;
-        const int trow = ti * nt1;
+        const int trow = ti * nt1 * (int)sizeof(LjPar);   // byte offset of the i type's row
         const double th_eps = th[2], th_sig = th[3];
         // LJ: blocks whose type pairs all have eps = 0 (and cannot reach the
         // theta-overridden pair (0, 0)) run a loop without the LJ terms; the
@@ -222,45 +255,50 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             constexpr bool LJ = decltype(lj_tag)::value;
             constexpr bool SP = decltype(sp_tag)::value;
             constexpr int W = TJ / WAVES;
-            // candidate (this lane's i-bead, j-slot jj); with SP the distance
-            // pass has already established that it interacts iff `live`
-            auto body = [&](int jj, bool live) {
-                const JTile<R> jr = jload(jj);
+            // candidate (this lane's i-bead, the j-slot at byte offset o);
+            // with SP the distance pass has already established that it
+            // interacts iff `live`
+            auto body = [&](int o, bool live) {
+                const JSlot<R> jr = jload(o);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
-                const int tp = trow + (jr.tm & 15);
-                const int mj = jr.tm >> 4;
+                const int tp = trow + jr.jt;
                 dx -= Lx * rint(dx * iLx);
                 dy -= Ly * rint(dy * iLy);
                 dz -= Lz * rint(dz * iLz);
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 bool ok = live;
-                // masks combine without short-circuit branches (straight-line code)
-                if constexpr (!SP) ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2 < rc2max);
-                // no select needed: a masked candidate's r^2 is finite (padding
-                // slots sit at the origin) and every term it feeds is selected away
+                // masks combine without short-circuit branches (straight-line
+                // code); each term below also tests its own cutoff
+                if constexpr (!SP) ok = (jr.jg > key) & (mi != jr.mol);
+                // Masked terms are multiplied by 0 instead of selected away:
+                // r^2 is clamped to 1e-20 A^2 (only coincident beads, all
+                // masked, are below it), so every term is finite; a term kept
+                // is multiplied by 1, exactly.
                 const double K = kqi * jr.qd;
                 const bool in_c = ok & (r2 < rc2_c) & (K != 0.0);
-                const double ir = rsqrt_fp64<R>(r2);
+                const double mc = in_c ? 1.0 : 0.0;
+                const double ir = rsqrt_fp64<R>(fmax(r2, 1e-20));
                 const double ir2 = ir * ir;
                 const double vc = K * ((ir - irc) + (r2 - rc2_c) * hc);
                 const double gc = K * (ir2 * ir - irc3);
                 double g;
                 bool hit = in_c;
                 if constexpr (LJ) {
-                    const LjPar lp = tlj[tp];
+                    const LjPar lp = at(tlj, tp);
                     const double e4 = lp.e4, c1l = lp.c1;
                     const double s2 = lp.s2 * ir2;
                     const double s6 = s2 * s2 * s2;
                     const double s12 = s6 * s6;
                     const bool in_lj = ok & (r2 < rc2_lj) & (e4 != 0.0);
+                    const double mlj = in_lj ? 1.0 : 0.0;
                     const double vlj = e4 * (s12 - s6) - lp.c0 - 0.5 * (r2 - rc2_lj) * c1l;
                     const double glj = e4 * (12.0 * s12 - 6.0 * s6) * ir2 + c1l;
-                    g = (in_lj ? glj : 0.0) + (in_c ? gc : 0.0);
-                    e0r += in_lj ? vlj : 0.0;
+                    g = fma(glj, mlj, gc * mc);
+                    e0r = fma(vlj, mlj, e0r);
                     hit = in_lj | in_c;
                     if (THETA) {
                         // d/d eps and d/d sigma of the (0,0) LJ term
-                        const bool on = in_lj & (tp == 0);
+                        const bool on = in_lj & (tp == 0);   // type pair (0, 0)
                         const double c6 = tlj[0].s2 / rc2_lj;
                         const double c6c = c6 * c6 * c6, c12c = c6c * c6c;
                         const double fs = 4.0 * th_eps / th_sig;
@@ -272,29 +310,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                         g1r += on ? dsg : 0.0;
                     }
                 } else {
-                    g = in_c ? gc : 0.0;
+                    g = gc * mc;
                 }
-                e1r += in_c ? vc : 0.0;
+                e1r = fma(vc, mc, e1r);
                 cnt += hit;
                 const double fx = g * dx, fy = g * dy, fz = g * dz;
                 fxi += fx;
                 fyi += fy;
                 fzi += fz;
                 if (SP && !live) return;   // nothing to add: spare the LDS
-                atomicAdd(&fjx[jj], -fx);
-                atomicAdd(&fjy[jj], -fy);
-                atomicAdd(&fjz[jj], -fz);
+                atomicAdd(&at(fjx, o), -fx);
+                atomicAdd(&at(fjy, o), -fy);
+                atomicAdd(&at(fjz, o), -fz);
             };
             if constexpr (!SP) {
 #pragma unroll 4
-                for (int t = 0; t < W; ++t) body(wv * W + ((lane + t) & (W - 1)), true);
+                for (int t = 0; t < W; ++t) body(((lane8 + 8 * t) & M8) | wv8, true);
             } else {
                 using Mask = std::conditional_t<(W > 32), unsigned long long, unsigned>;
                 Mask m = 0;
 #pragma unroll 4
                 for (int t = 0; t < W; ++t) {
-                    const int jj = wv * W + ((lane + t) & (W - 1));
-                    const JTile<R> jr = jload(jj);
+                    const int o = ((lane8 + 8 * t) & M8) | wv8;
+                    const JSlot<R> jr = jload(o);
                     double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
                     dx -= Lx * rint(dx * iLx);
                     dy -= Ly * rint(dy * iLy);
@@ -302,7 +340,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                     const double r2d = dx * dx + dy * dy + dz * dz;
                     // non-short-circuit: no branch, so the unrolled steps' LDS
                     // reads are issued together
-                    const bool ok = (jj > jlo) & (jj < jhi) & (mi != (jr.tm >> 4)) & (r2d < rc2max);
+                    const bool ok = (jr.jg > key) & (mi != jr.mol) & (r2d < rc2max);
                     m |= ok ? (Mask(1) << t) : Mask(0);
                 }
                 // wave-uniform trip count: the most marked slots of any lane
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                     if constexpr (W > 32) t = live ? __builtin_ctzll(m) : 0;
                     else t = live ? __builtin_ctz(m) : 0;
                     m &= m - 1;
-                    body(wv * W + ((lane + t) & (W - 1)), live);
+                    body(((lane8 + 8 * t) & M8) | wv8, live);
                 }
             }
         };
@@ -332,32 +370,37 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         const double phicd = 1.0 / sqrt(u_c);
         const double psicd = -1.0 / (u_c * sqrt(u_c));
         const double chicd = 1.0 / (u_c * u_c * sqrt(u_c));
-        const R phic = (R)phicd, psic = (R)psicd;
-        const R ra2 = (R)a2, rrc2 = (R)rc2, rpq = (R)pq;
-        const R kqi = (R)(kCoulombKcal * qi);
+        const R phic = (R)phicd, psic = (R)psicd, hpsic = (R)(0.5 * psicd);
+        const R ra2 = (R)a2, rrc2 = (R)rc2;
         const double kqid = kCoulombKcal * qi;
+        // the constant pp_q k_e q_atom of an atom-i block (R)
+        const R kqi = (R)(pq * kqid);
         // E_IS_I: the electron is the i side and the constant is the j
-        // atom's (pre-scaled) k_e q_j; otherwise the i atom's k_e q_i
+        // atom's pp_q k_e q_j (its slot's kq in the FP32 form); otherwise the
+        // i atom's
         auto sweep_e = [&](auto e_tag) {
             constexpr bool E_IS_I = decltype(e_tag)::value;
 #pragma unroll 4
             for (int t = 0; t < TJ / WAVES; ++t) {
-                const int jj = wv * (TJ / WAVES) + ((lane + t) & (TJ / WAVES - 1));
-                const JTile<R> jr = jload(jj);
+                const int o = ((lane8 + 8 * t) & M8) | wv8;
+                const JSlot<R> jr = jload(o);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
-                const int mj = jr.tm >> 4;
                 dx -= Lx * rint(dx * iLx);
                 dy -= Ly * rint(dy * iLy);
                 dz -= Lz * rint(dz * iLz);
                 const double r2d = dx * dx + dy * dy + dz * dz;
-                const bool ok = (jj > jlo) & (jj < jhi) & (mi != mj) & (r2d < rc2);
+                const bool ok = (jr.jg > key) & (mi != jr.mol) & (r2d < rc2);
                 const R r2 = (R)r2d;
-                const R kq = E_IS_I ? jr.q : kqi;
+                R kq = kqi;
+                if constexpr (E_IS_I) {
+                    if constexpr (std::is_same<R, float>::value) kq = jr.kq;
+                    else kq = pq * jr.qd;
+                }
                 const R ir = rsqrt_r<R>(r2 + ra2);
                 const R ir3 = ir * ir * ir;
-                const R vq = kq * (ir - phic - (R)0.5 * (r2 - rrc2) * psic);
-                const R gq = ok ? rpq * kq * (ir3 + psic) : (R)0;
-                e0r += (double)(ok ? rpq * vq : (R)0);
+                const R vq = kq * (ir - phic - (r2 - rrc2) * hpsic);
+                const R gq = ok ? kq * (ir3 + psic) : (R)0;
+                e0r += (double)(ok ? vq : (R)0);
                 cnt += ok;
                 if (THETA) {
                     const double kqd = E_IS_I ? jr.qd : kqid;
@@ -374,9 +417,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
                 fxi += fx;
                 fyi += fy;
                 fzi += fz;
-                atomicAdd(&fjx[jj], -fx);
-                atomicAdd(&fjy[jj], -fy);
-                atomicAdd(&fjz[jj], -fz);
+                atomicAdd(&at(fjx, o), -fx);
+                atomicAdd(&at(fjy, o), -fy);
+                atomicAdd(&at(fjz, o), -fz);
             }
         };
         if (bk.kind == PK_E_ATOM) sweep_e(std::true_type{});
@@ -391,8 +434,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     }
     if (WAVES > 1) {
         // the other waves hand their i-forces and sums to wave 0
-        __shared__ double xs[WAVES][3][64];
-        __shared__ double es[WAVES][5];
+        auto &xs = L.xs;
+        auto &es = L.es;
         if (wv > 0) {
             xs[wv][0][lane] = fxi;
             xs[wv][1][lane] = fyi;
@@ -417,12 +460,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
             g1 += es[v][3];
             cnt += (int)es[v][4];
         }
+    } else if (IW > 1) {
+        // the i-split waves' sums meet in wave 0, in wave order
+        auto &es = L.es;
+        if (lane == 0) {
+            es[iw][0] = e0;
+            es[iw][1] = e1;
+            es[iw][2] = g0;
+            es[iw][3] = g1;
+            es[iw][4] = (double)cnt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int v = 1; v < IW; ++v) {
+                e0 += es[v][0];
+                e1 += es[v][1];
+                g0 += es[v][2];
+                g1 += es[v][3];
+                cnt += (int)es[v][4];
+            }
+        }
     } else {
         __syncthreads();
     }
 
-    // partial forces of this tile go to its own slots (64 i-slots, then TJ
-    // j-slots), each stored at its row-contiguous position; the per-row
+    // partial forces of this tile go to its own slots (64 IW i-slots, then
+    // TJ j-slots), each stored at its row-contiguous position; the per-row
     // gather sums them, so no two workgroups write the same address
     const double w = bk.w;
     if (vi) {
@@ -431,14 +494,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
         o[1] = w * fyi;
         o[2] = w * fzi;
     }
-    if (lane < jn) {
+    if ((int)threadIdx.x < jn) {
         double *o = a.part + 3LL * dj;
-        o[0] = w * fjx[lane];
-        o[1] = w * fjy[lane];
-        o[2] = w * fjz[lane];
+        o[0] = w * fjx[threadIdx.x];
+        o[1] = w * fjy[threadIdx.x];
+        o[2] = w * fjz[threadIdx.x];
     }
-    if (lane == 0) {
-        double *e = a.eslot + (long long)(a.item0 + blockIdx.x) * A_N;
+    if (threadIdx.x == 0) {
+        double *e = a.eslot + (long long)blockIdx.x * A_N;
         for (int k = 0; k < A_N; ++k) e[k] = 0.0;
         if (bk.kind == PK_ATOM) {
             e[A_LJ] = w * e0;
@@ -455,17 +518,60 @@ __global__ __launch_bounds__(64 * WAVES) void k_pair(PairLaunch a, BondedLaunch 
     }
 }
 
-template <int TJ, int WAVES>
+// TJ > 0: every item of the launch has that width; TJ = 0: each item's own
+// width (a batch whose systems differ; the widest body sets the registers).
+// The fixed-width FP32-form force kernels are held to 96 VGPRs, five waves
+// per SIMD (the compiler fits them without spills; left alone it takes a few
+// more and drops to four; the FP64 form would spill).
+template <typename R, bool THETA, int TJ, int WAVES, int IW>
+__global__ __launch_bounds__(64 * WAVES * IW) __attribute__((amdgpu_waves_per_eu(TJ > 0 && !THETA && sizeof(R) == 4 ? 5 : 1)))
+void k_pair(PairLaunch a, BondedLaunch bl)
+{
+    __shared__ double red[WAVES * IW];
+    if ((int)blockIdx.x >= a.n_items) {
+        // bonded workgroups of the same launch (64 terms each)
+        const int bb = blockIdx.x - a.n_items;
+        bonded_block<THETA>(bl, bl.blocks[bb], bl.eslot + (long long)bb * A_N, red);
+        return;
+    }
+    // the item and its block are independent loads (the block is copied per
+    // item), so everything after them is one dependent step away
+    const PairItem it = a.items[blockIdx.x];
+    const PairBlock bk = a.iblocks[blockIdx.x];
+    constexpr int TJM = TJ > 0 ? TJ : kMaxTj;
+    __shared__ PairLds<R, TJM, WAVES, IW> L;
+    if constexpr (TJ > 0) {
+        pair_tile<R, THETA, TJ, WAVES, IW, true>(a, it, bk, L);
+    } else {
+        if (it.tj == 16) pair_tile<R, THETA, 16, WAVES, IW, false>(a, it, bk, L);
+        else if (it.tj == 32) pair_tile<R, THETA, 32, WAVES, IW, false>(a, it, bk, L);
+        else pair_tile<R, THETA, 64, WAVES, IW, false>(a, it, bk, L);
+    }
+}
+
+template <int TJ, int WAVES, int IW>
 void launch_pair_tj(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
                     hipStream_t st)
 {
-    dim3 grid(a.n_items + b.n_blocks), block(64 * WAVES);
+    dim3 grid(a.n_items + b.n_blocks), block(64 * WAVES * IW);
     if (precision == 0) {
-        if (with_theta) hipLaunchKernelGGL((k_pair<double, true, TJ, WAVES>), grid, block, 0, st, a, b);
-        else hipLaunchKernelGGL((k_pair<double, false, TJ, WAVES>), grid, block, 0, st, a, b);
+        if (with_theta) hipLaunchKernelGGL((k_pair<double, true, TJ, WAVES, IW>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<double, false, TJ, WAVES, IW>), grid, block, 0, st, a, b);
     } else {
-        if (with_theta) hipLaunchKernelGGL((k_pair<float, true, TJ, WAVES>), grid, block, 0, st, a, b);
-        else hipLaunchKernelGGL((k_pair<float, false, TJ, WAVES>), grid, block, 0, st, a, b);
+        if (with_theta) hipLaunchKernelGGL((k_pair<float, true, TJ, WAVES, IW>), grid, block, 0, st, a, b);
+        else hipLaunchKernelGGL((k_pair<float, false, TJ, WAVES, IW>), grid, block, 0, st, a, b);
+    }
+}
+
+template <int WAVES, int IW>
+void launch_pair_w(const PairLaunch &a, const BondedLaunch &b, int precision, bool with_theta,
+                   hipStream_t st)
+{
+    switch (a.tj) {
+    case 16: launch_pair_tj<16, WAVES, IW>(a, b, precision, with_theta, st); break;
+    case 32: launch_pair_tj<32, WAVES, IW>(a, b, precision, with_theta, st); break;
+    case 64: launch_pair_tj<64, WAVES, IW>(a, b, precision, with_theta, st); break;
+    default: launch_pair_tj<0, WAVES, IW>(a, b, precision, with_theta, st); break;
     }
 }
 
@@ -491,14 +597,10 @@ void launch_pair(const PairLaunch &a, const BondedLaunch &b, int precision, bool
         launch_bonded(b, with_theta, st);
         return;
     }
-    if (a.n_items + b.n_blocks <= 0) return;
-    if (a.tj == 32) {
-        if (a.waves == 2) launch_pair_tj<32, 2>(a, b, precision, with_theta, st);
-        else launch_pair_tj<32, 1>(a, b, precision, with_theta, st);
-    } else {
-        if (a.waves == 2) launch_pair_tj<64, 2>(a, b, precision, with_theta, st);
-        else launch_pair_tj<64, 1>(a, b, precision, with_theta, st);
-    }
+    if (a.waves == 2) launch_pair_w<2, 1>(a, b, precision, with_theta, st);
+    else if (a.iw == 2) launch_pair_w<1, 2>(a, b, precision, with_theta, st);
+    else if (a.iw == 4) launch_pair_w<1, 4>(a, b, precision, with_theta, st);
+    else launch_pair_w<1, 1>(a, b, precision, with_theta, st);
 }
 
 }  // namespace mixpi

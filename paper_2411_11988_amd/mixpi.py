@@ -32,14 +32,20 @@ MIXPI_FP64 = 0
 MIXPI_FP32_ACC64 = 1
 MIXPI_FLAG_CHECK_FINITE = 1
 MIXPI_STATIC_SCRATCH_BYTES = 16 << 20
+MIXPI_FLAG_TILE_J16 = 1 << 8
 MIXPI_FLAG_TILE_J32 = 1 << 4
 MIXPI_FLAG_TILE_J64 = 1 << 5
 MIXPI_FLAG_TILE_WAVES1 = 1 << 6
 MIXPI_FLAG_TILE_WAVES2 = 1 << 7
-TILE_FLAGS = {(32, 1): MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_WAVES1,
-              (32, 2): MIXPI_FLAG_TILE_J32 | MIXPI_FLAG_TILE_WAVES2,
-              (64, 1): MIXPI_FLAG_TILE_J64 | MIXPI_FLAG_TILE_WAVES1,
-              (64, 2): MIXPI_FLAG_TILE_J64 | MIXPI_FLAG_TILE_WAVES2}
+MIXPI_FLAG_TILE_I128 = 1 << 9
+MIXPI_FLAG_TILE_I256 = 1 << 10
+TJ_FLAGS = {16: MIXPI_FLAG_TILE_J16, 32: MIXPI_FLAG_TILE_J32, 64: MIXPI_FLAG_TILE_J64}
+# waves per tile: "w1" one wave, "w2" two waves splitting the j-beads,
+# "i2" / "i4" two / four waves of 64 i-beads sharing them
+WAVES_FLAGS = {"w1": MIXPI_FLAG_TILE_WAVES1, "w2": MIXPI_FLAG_TILE_WAVES2,
+               "i2": MIXPI_FLAG_TILE_I128, "i4": MIXPI_FLAG_TILE_I256}
+# (j-tile width, waves per tile) -> descriptor flags
+TILE_FLAGS = {(tj, w): TJ_FLAGS[tj] | WAVES_FLAGS[w] for tj in TJ_FLAGS for w in WAVES_FLAGS}
 
 
 class MixPIError(RuntimeError):
@@ -290,10 +296,15 @@ def mixpi_ewald(h, q, f, e_out, stream=None):
 class System:
     """Owns a library handle for one system or a batch of systems."""
 
-    def __init__(self, systems, precision: int = MIXPI_FP64, flags: int = 0):
+    def __init__(self, systems, precision: int = MIXPI_FP64, flags=0):
+        """flags: one value for every system, or a list with one per system
+        (the systems of a batch may differ in their j-tile width flag only)."""
         single = not isinstance(systems, (list, tuple))
         syss = [systems] if single else list(systems)
-        pairs = [make_desc(s, precision, flags) for s in syss]
+        fl = list(flags) if isinstance(flags, (list, tuple)) else [flags] * len(syss)
+        if len(fl) != len(syss):
+            raise ValueError(f"{len(fl)} flag values for {len(syss)} systems")
+        pairs = [make_desc(s, precision, f) for s, f in zip(syss, fl)]
         self._keep = pairs
         if single:
             self.h = mixpi_create(pairs[0][0])

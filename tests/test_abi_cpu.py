@@ -125,7 +125,26 @@ def test_rejects_out_of_range_mol_id(mp):
 def test_rejects_conflicting_tile_flags(mp):
     s = synth.tiny_random(0)
     for bad in (mp.MIXPI_FLAG_TILE_J32 | mp.MIXPI_FLAG_TILE_J64,
-                mp.MIXPI_FLAG_TILE_WAVES1 | mp.MIXPI_FLAG_TILE_WAVES2, 1 << 12):
+                mp.MIXPI_FLAG_TILE_J16 | mp.MIXPI_FLAG_TILE_J32,
+                mp.MIXPI_FLAG_TILE_J16 | mp.MIXPI_FLAG_TILE_J64,
+                mp.MIXPI_FLAG_TILE_WAVES1 | mp.MIXPI_FLAG_TILE_WAVES2,
+                mp.MIXPI_FLAG_TILE_WAVES2 | mp.MIXPI_FLAG_TILE_I128,
+                mp.MIXPI_FLAG_TILE_I128 | mp.MIXPI_FLAG_TILE_I256, 1 << 12):
         with pytest.raises(mp.MixPIError) as e:
             mp.System(s, flags=bad)
         assert e.value.code == mp.MIXPI_E_INVALID and "flags" in str(e.value)
+
+
+def test_batch_flags_may_differ_in_tile_width_only(mp):
+    """The systems of a batch may carry different j-tile width flags; any
+    other flag difference is rejected before the device is touched."""
+    s0, s1 = synth.tiny_random(0), synth.tiny_random(1)
+    with pytest.raises(mp.MixPIError) as e:
+        mp.System([s0, s1], flags=[mp.MIXPI_FLAG_TILE_WAVES1, mp.MIXPI_FLAG_TILE_WAVES2])
+    assert e.value.code == mp.MIXPI_E_INVALID and "flags" in str(e.value)
+    try:
+        mp.System([s0, s1], flags=[mp.MIXPI_FLAG_TILE_J16, mp.MIXPI_FLAG_TILE_J64]).close()
+    except mp.MixPIError as err:   # no device here: only the device step may fail
+        assert err.code == mp.MIXPI_E_HIP, err
+    with pytest.raises(ValueError):
+        mp.System([s0, s1], flags=[0])

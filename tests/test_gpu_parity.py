@@ -291,12 +291,22 @@ def test_steps_are_bit_reproducible(mp, name, s):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("tj,waves", [(32, 1), (32, 2), (64, 1), (64, 2)])
-def test_pair_tile_variants(mp, tj, waves, monkeypatch):
-    """Every tile shape of the force launch (j-tile width, waves per tile)
-    gives the oracle's forces and energies in both forms."""
+SHAPES = [(16, "w1"), (16, "w2"), (16, "i4"), (32, "w1"), (32, "w2"), (32, "i2"),
+          (64, "w1"), (64, "w2"), (64, "i2"), (64, "i4")]
+
+
+def _set_shape(monkeypatch, tj, waves):
     monkeypatch.setenv("MIXPI_PAIR_TJ", str(tj))
-    monkeypatch.setenv("MIXPI_PAIR_WAVES", str(waves))
+    monkeypatch.setenv("MIXPI_PAIR_WAVES", "2" if waves == "w2" else "1")
+    monkeypatch.setenv("MIXPI_PAIR_IW", waves[1] if waves[0] == "i" else "1")
+
+
+@pytest.mark.parametrize("tj,waves", SHAPES)
+def test_pair_tile_variants(mp, tj, waves, monkeypatch):
+    """Every tile shape of the force launch (j-tile width; one wave, two
+    waves splitting the j-beads, or two / four waves of 64 i-beads each)
+    gives the oracle's forces and energies in both forms."""
+    _set_shape(monkeypatch, tj, waves)
     for name, s in (SYSTEMS[4], SYSTEMS[7]):
         Fo, eo = oracle.OracleSystem(s).forces(s.q)
         for prec in (FP64, FP32):
@@ -308,7 +318,25 @@ def test_pair_tile_variants(mp, tj, waves, monkeypatch):
             assert energy_err(host(e)[0], eo) <= TOL_E[prec]
 
 
-@pytest.mark.parametrize("tj,waves", [(32, 1), (32, 2), (64, 1), (64, 2)])
+@pytest.mark.parametrize("tj,waves", [(16, "i2"), (32, "i4"), (64, "i2"), (64, "i4")])
+def test_pair_i_split_tiles_span_several_i_tiles(mp, tj, waves, monkeypatch):
+    """Tiles of 128 or 256 i-beads on blocks whose i-runs span several of
+    them: 1200 one-bead atoms (upper-triangle tiles of a group with itself)
+    and 4-bead H with 2-bead O (a group pair with shift 1)."""
+    _set_shape(monkeypatch, tj, waves)
+    for name, s in (("water-400", synth.water_box(400, 23.0, 1, 1, seed=3, rc=9.0)),
+                    ("water-h4-o2", synth.water_box(150, 17.0, 4, 2, seed=6, rc=7.0))):
+        Fo, eo = oracle.OracleSystem(s).forces(s.q)
+        for prec in (FP64, FP32):
+            print(f"[i-split] tj={tj} waves={waves} {name} prec={prec}", flush=True)
+            sysm = mp.System(s, precision=prec)
+            f, e = sysm.forces(dev(to_rows(s, s.q)))
+            F = from_rows(s, host(f))
+            assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
+            assert energy_err(host(e)[0], eo) <= TOL_E[prec]
+
+
+@pytest.mark.parametrize("tj,waves", [(32, "w1"), (32, "w2"), (64, "w1"), (64, "w2"), (64, "i4")])
 def test_pair_compacted_sweep(mp, tj, waves, monkeypatch):
     """The compacted atom-atom sweep (a distance pass marks each lane's
     in-cutoff j-slots; the pair math runs for those only) against the masked
@@ -319,8 +347,7 @@ def test_pair_compacted_sweep(mp, tj, waves, monkeypatch):
     ulp), so they agree to rounding: forces and gradients to 1e-12 (FP64)
     or 1e-6 (FP32) of the RMS force; energies and theta-weighted d/dtheta to
     1e-12 (FP64) or 1e-7 (FP32) of the energy scale sum_k |V_k|."""
-    monkeypatch.setenv("MIXPI_PAIR_TJ", str(tj))
-    monkeypatch.setenv("MIXPI_PAIR_WAVES", str(waves))
+    _set_shape(monkeypatch, tj, waves)
     for name, s in (SYSTEMS[4], SYSTEMS[6], SYSTEMS[7]):
         osys = oracle.OracleSystem(s)
         Fo, eo = osys.forces(s.q)

@@ -24,17 +24,45 @@ def test_autotune_picks_a_shape_and_caches_it(mp, tmp_path):
     from paper_2411_11988_amd import tune
     s = synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4, rc_aa=6.0, n_h=2, n_o=1)
     best, times = tune.autotune(s, reps=8)
-    assert set(times) == {(32, 1), (32, 2), (64, 1), (64, 2)}
+    assert set(times) == {f"{tj}x{w}" for tj in tune.TJS for w in tune.WAVES}
     assert all(np.isfinite(t) and t > 0 for t in times.values())
-    assert times[best] == min(times.values())
+    assert times[f"{best['tj'][tune.size_class(s)]}x{best['waves']}"] == min(times.values())
     cache = tmp_path / "tiles.json"
     flags = tune.tile_flags(s, cache=str(cache))
     table = json.loads(cache.read_text())
     key = tune.bucket(s, mp.MIXPI_FP32_ACC64)
-    assert key in table and (table[key]["tj"], table[key]["waves"]) in mp.TILE_FLAGS
-    assert flags == mp.TILE_FLAGS[(table[key]["tj"], table[key]["waves"])]
+    e = table[key]
+    assert flags == mp.TILE_FLAGS[(e["tj"][tune.size_class(s)], e["waves"])]
     assert tune.tile_flags(s, cache=str(cache)) == flags       # read back, no retune
     sysm = mp.System(s, precision=mp.MIXPI_FP32_ACC64, flags=flags)
     f, _ = sysm.forces(dev(to_rows(s, s.q)))
     Fo, _ = oracle.OracleSystem(s).forces(s.q)
     assert force_err(from_rows(s, host(f)), Fo) <= 1e-5
+
+
+def test_autotune_batch_per_class_widths(mp, tmp_path):
+    """A batch of two size classes: the tuner returns one flag value per
+    system, equal within a class, and the batch built with them matches each
+    system's oracle forces."""
+    from paper_2411_11988_amd import tune
+    systems = [synth.solvated_electron(40, 64, 11.5, seed=k, rc_pp=5.5, rc_aa=5.4, n_h=2, n_o=1)
+               for k in range(2)]
+    systems += [synth.solvated_electron(90, 128, 14.0, seed=10 + k, rc_pp=6.4, rc_aa=6.0,
+                                        n_h=2, n_o=1) for k in range(2)]
+    assert len(set(tune.size_class(s) for s in systems)) == 2
+    flags = tune.tile_flags(systems, cache=str(tmp_path / "tiles.json"))
+    assert isinstance(flags, list) and len(flags) == 4
+    assert flags[0] == flags[1] and flags[2] == flags[3]
+    b = mp.System(systems, precision=mp.MIXPI_FP32_ACC64, flags=flags)
+    off = 0
+    idx = b.bead_index
+    qa = np.concatenate([s.q for s in systems])
+    qr = np.empty_like(qa)
+    qr[idx] = qa
+    f, _ = b.forces(dev(qr))
+    F = host(f)[idx]
+    for s in systems:
+        n = len(s.q)
+        Fo, _ = oracle.OracleSystem(s).forces(s.q)
+        assert force_err(F[off:off + n], Fo) <= 1e-5
+        off += n
