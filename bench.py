@@ -612,7 +612,10 @@ def main():
                    "systems": len(_as_list(s)), "dt_fs": _as_list(s)[0].dt,
                    "precision": ("fp32 electron-atom pseudopotential and 1/r seeds; fp64 atom-atom "
                                  "terms, separations, state and sums"),
-                   "pair_tile_tj_x_waves": tile},
+                   "pair_tile_tj_x_waves": tile,
+                   "pair_shape_fp32": dict(zip(("tj", "waves", "i_waves"),
+                                               (sorted(set(sysm.pair_shape()[0])),
+                                                *sysm.pair_shape()[1:])))},
         "steps_per_s": steps_per_s,
         "kernel_us": k_us,
         "energy_drift_kcal": r32["drift"],

@@ -924,19 +924,19 @@ void block_items(const PairBlock &pb, int bi, int tj, int iw, std::vector<PairIt
 // Cost of sweeping one lane over W j-slots of an atom block, in VALU
 // instructions of the FP32 build.  p: the expected share of candidates
 // inside the cutoff, the cutoff sphere's volume over the box volume (at
-// most 1).  The masked sweep spends 70 per slot with LJ, 49.5 without; the
-// compacted sweep spends 28 per slot on the distance pass plus, per marked
-// slot of the fullest lane (taken as the mean W p plus 2.4 standard
-// deviations, the largest of 64 binomial counts), 74 on the pair math with
-// LJ, 53 without.
+// most 1).  The masked sweep spends 64.5 per slot with LJ, 45.5 without;
+// the compacted sweep spends 22.5 per slot on the distance pass plus, per
+// marked slot of the fullest lane (taken as the mean W p plus 2.4 standard
+// deviations, the largest of 64 binomial counts), 69 on the pair math with
+// LJ, 50 without (counted in the gfx950 assembly of the loops).
 double atom_sweep_cost(const SysDev &S, bool lj, int W, bool compact)
 {
-    if (!compact) return (lj ? 70.0 : 49.5) * W;
+    if (!compact) return (lj ? 64.5 : 45.5) * W;
     const double rc = std::max(S.rc_lj, S.rc_c);
     const double vol = S.box[0] * S.box[1] * S.box[2];
     const double p = std::min(1.0, 4.0 / 3.0 * kPi * rc * rc * rc / vol);
     const double hits = std::min((double)W, W * p + 2.4 * std::sqrt(W * p * (1.0 - p)));
-    return 28.0 * W + (lj ? 74.0 : 53.0) * hits;
+    return 22.5 * W + (lj ? 69.0 : 50.0) * hits;
 }
 
 // Whether an atom block with W = tj slots per lane is swept in compacted
@@ -950,14 +950,13 @@ bool sparse_pays(const SysDev &S, bool lj, int W)
     return atom_sweep_cost(S, lj, W, true) < 0.9 * atom_sweep_cost(S, lj, W, false);
 }
 
-// Default j-tile width (every system of a handle): 64-wide j-tiles unless
-// that leaves the chip with fewer than about two waves per SIMD (1024 SIMDs),
-// then 32.
-int default_tj(const std::vector<PairBlock> &blocks)
+// 64 x 64 tiles of the handle's pair blocks: the work size that picks the
+// default tile shape.
+size_t tiles64(const std::vector<PairBlock> &blocks)
 {
     std::vector<PairItem> items;
     for (size_t bi = 0; bi < blocks.size(); ++bi) block_items(blocks[bi], (int)bi, 64, 1, items);
-    return items.size() < 2048 ? 32 : 64;
+    return items.size();
 }
 
 // Natural partial-force slots of the items, in order: 64 iw i-slots, then
@@ -1123,8 +1122,14 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     // Pair items: per system with its j-tile width (a MIXPI_FLAG_TILE_J*
     // flag of its description, else MIXPI_PAIR_TJ = 16, 32 or 64, else
     // default_tj), in system and block order.
+    // Default shape by the work size n64 (64 x 64 tiles), against 1024 SIMDs
+    // (measured on the workloads of 1e3 to 1e5 such tiles): below 1024
+    // tiles 16-wide j-tiles (more, shorter waves), below 8192 32-wide, else
+    // 64-wide; from 16384 tiles on, 256 x 64 tiles (four i-split waves:
+    // fewer partial-force slots, the epilogue reads less).
+    const size_t n64 = tiles64(B.blocks);
     {
-        int tj0 = default_tj(B.blocks);
+        int tj0 = n64 < 1024 ? 16 : (n64 < 8192 ? 32 : 64);
         if (const char *env = getenv("MIXPI_PAIR_TJ")) {
             const int v = atoi(env);
             if (v == 16 || v == 32 || v == 64) tj0 = v;
@@ -1140,17 +1145,18 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->pair_tj_all = S->pair_tj[0];
     for (int y = 1; y < n_sys; ++y)
         if (S->pair_tj[y] != S->pair_tj_all) S->pair_tj_all = 0;
-    // Waves per tile: two j-split waves while the launch has fewer than ~4
-    // 64-bead tiles per SIMD (1024 SIMDs): more, shorter waves even out the
-    // SIMDs and hide latency; else one.  MIXPI_PAIR_WAVES = 1 or 2 and
-    // MIXPI_PAIR_IW = 1, 2 or 4 (i-split waves, with one j-wave), or the
-    // TILE_WAVES / TILE_I flags, choose instead.
+    // Waves per tile: two j-split waves while the launch has fewer than one
+    // 64-bead tile per SIMD: more, shorter waves even out the SIMDs and hide
+    // latency; else one, or four i-split waves from 16384 64 x 64 tiles on.
+    // MIXPI_PAIR_WAVES = 1 or 2 and MIXPI_PAIR_IW = 1, 2 or 4 (i-split
+    // waves, with one j-wave), or the TILE_WAVES / TILE_I flags, choose
+    // instead.
     {
         std::vector<PairItem> one;
         for (size_t bi = 0; bi < B.blocks.size(); ++bi)
             block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], 1, one);
-        S->pair_waves = one.size() < 4096 ? 2 : 1;
-        S->pair_iw = 1;
+        S->pair_waves = one.size() < 1024 ? 2 : 1;
+        S->pair_iw = n64 >= 16384 ? 4 : 1;
         if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
             const int v = atoi(env);
             if (v == 1 || v == 2) S->pair_waves = v;
@@ -1194,7 +1200,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             const int W = S->pair_tj[pb.sys] / S->pair_waves;
             cost[bi] = S->pair_iw * (pb.kind == PK_ATOM
                                          ? atom_sweep_cost(B.sys[pb.sys], pb.lj != 0, W, pb.sparse != 0)
-                                         : 48.5 * W);
+                                         : 41.0 * W);
         }
         std::stable_sort(items.begin(), items.end(), [&](const PairItem &x, const PairItem &y) {
             return cost[x.block] > cost[y.block];
@@ -2407,6 +2413,16 @@ int mixpi_use_ewald(mixpi_system *sys, int32_t on)
         clear_graphs(sys);
     }
     sys->ew_use = on != 0;
+    return MIXPI_OK;
+}
+
+int mixpi_pair_shape(const mixpi_system *sys, int32_t *tj, int32_t *waves, int32_t *i_waves)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (tj)
+        for (int y = 0; y < sys->n_sys; ++y) tj[y] = sys->pair_tj[y];
+    if (waves) *waves = sys->pair_waves;
+    if (i_waves) *i_waves = sys->pair_iw;
     return MIXPI_OK;
 }
 

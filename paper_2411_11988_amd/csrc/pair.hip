@@ -238,6 +238,7 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         const double irc = rc_c > 0.0 ? 1.0 / rc_c : 0.0;
         const double irc3 = rc_c > 0.0 ? 1.0 / (rc_c * rc_c * rc_c) : 0.0;
         const double hc = 0.5 * irc3;
+        const double vc0 = irc + rc2_c * hc;   // Coulomb term: K (1/r + r^2 hc - vc0)
         const double kqi = kCoulombKcal * qi;
         const int trow = ti * nt1 * (int)sizeof(LjPar);   // byte offset of the i type's row
         const double th_eps = th[2], th_sig = th[3];
@@ -276,11 +277,11 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 // is multiplied by 1, exactly.
                 const double K = kqi * jr.qd;
                 const bool in_c = ok & (r2 < rc2_c) & (K != 0.0);
-                const double mc = in_c ? 1.0 : 0.0;
+                const double Km = in_c ? K : 0.0;     // the Coulomb constant, 0 if masked
                 const double ir = rsqrt_fp64<R>(fmax(r2, 1e-20));
                 const double ir2 = ir * ir;
-                const double vc = K * ((ir - irc) + (r2 - rc2_c) * hc);
-                const double gc = K * (ir2 * ir - irc3);
+                const double vc = Km * (fma(r2, hc, ir) - vc0);
+                const double gc = Km * fma(ir2, ir, -irc3);
                 double g;
                 bool hit = in_c;
                 if constexpr (LJ) {
@@ -293,7 +294,7 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     const double mlj = in_lj ? 1.0 : 0.0;
                     const double vlj = e4 * (s12 - s6) - lp.c0 - 0.5 * (r2 - rc2_lj) * c1l;
                     const double glj = e4 * (12.0 * s12 - 6.0 * s6) * ir2 + c1l;
-                    g = fma(glj, mlj, gc * mc);
+                    g = fma(glj, mlj, gc);
                     e0r = fma(vlj, mlj, e0r);
                     hit = in_lj | in_c;
                     if (THETA) {
@@ -310,18 +311,18 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                         g1r += on ? dsg : 0.0;
                     }
                 } else {
-                    g = gc * mc;
+                    g = gc;
                 }
-                e1r = fma(vc, mc, e1r);
+                e1r += vc;
                 cnt += hit;
-                const double fx = g * dx, fy = g * dy, fz = g * dz;
-                fxi += fx;
-                fyi += fy;
-                fzi += fz;
+                fxi = fma(g, dx, fxi);
+                fyi = fma(g, dy, fyi);
+                fzi = fma(g, dz, fzi);
                 if (SP && !live) return;   // nothing to add: spare the LDS
-                atomicAdd(&at(fjx, o), -fx);
-                atomicAdd(&at(fjy, o), -fy);
-                atomicAdd(&at(fjz, o), -fz);
+                const double ng = -g;
+                atomicAdd(&at(fjx, o), ng * dx);
+                atomicAdd(&at(fjy, o), ng * dy);
+                atomicAdd(&at(fjz, o), ng * dz);
             };
             if constexpr (!SP) {
 #pragma unroll 4
@@ -396,11 +397,14 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     if constexpr (std::is_same<R, float>::value) kq = jr.kq;
                     else kq = pq * jr.qd;
                 }
+                // a masked candidate gets the constant 0 (r^2 + a^2 > 0, so
+                // its terms are finite zeros): no branch, no selects after
+                const R kqm = ok ? kq : (R)0;
                 const R ir = rsqrt_r<R>(r2 + ra2);
                 const R ir3 = ir * ir * ir;
-                const R vq = kq * (ir - phic - (r2 - rrc2) * hpsic);
-                const R gq = ok ? kq * (ir3 + psic) : (R)0;
-                e0r += (double)(ok ? vq : (R)0);
+                const R vq = kqm * (ir - phic - (r2 - rrc2) * hpsic);
+                const R gq = kqm * (ir3 + psic);
+                e0r += (double)vq;
                 cnt += ok;
                 if (THETA) {
                     const double kqd = E_IS_I ? jr.qd : kqid;
@@ -412,14 +416,13 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     g1r += ok ? pq * kqd * (-pa * y3 - pa * psicd - 1.5 * pa * (r2d - rc2) * chicd)
                               : 0.0;
                 }
-                const double gd = (double)gq;
-                const double fx = gd * dx, fy = gd * dy, fz = gd * dz;
-                fxi += fx;
-                fyi += fy;
-                fzi += fz;
-                atomicAdd(&at(fjx, o), -fx);
-                atomicAdd(&at(fjy, o), -fy);
-                atomicAdd(&at(fjz, o), -fz);
+                const double gd = (double)gq, ngd = -gd;
+                fxi = fma(gd, dx, fxi);
+                fyi = fma(gd, dy, fyi);
+                fzi = fma(gd, dz, fzi);
+                atomicAdd(&at(fjx, o), ngd * dx);
+                atomicAdd(&at(fjy, o), ngd * dy);
+                atomicAdd(&at(fjz, o), ngd * dz);
             }
         };
         if (bk.kind == PK_E_ATOM) sweep_e(std::true_type{});
