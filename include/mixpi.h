@@ -154,17 +154,23 @@ typedef struct {
 /* Message of the last failure on this thread ("" if none). */
 const char *mixpi_last_error(void);
 
-/* Validates desc and builds a one-system handle on the current HIP device:
- * constant tables (normal-mode bases, propagator coefficients), pair and
- * bonded work lists.  Errors: MIXPI_E_INVALID, _NOT_POW2, _ORDER,
- * _UNSUPPORTED (more than 8 LJ types, N > 4096), _HIP.  *out is NULL on
- * failure. */
+/* Validates desc and builds a one-system handle on the current HIP device
+ * for the mixed time-slicing ring-polymer Hamiltonian (arXiv 2411.11988,
+ * Sec. Theory, MixTS Ring Polymer Hamiltonian, Eq. mts-hamiltonian): one
+ * state holding every bead of every particle, with the bead pairing of each
+ * interaction taken from the bead-index bookkeeping (Sec. Implementation,
+ * Overview) and bead counts restricted to powers of two (Sec.
+ * Implementation, Setup).  Builds the constant tables (normal-mode bases,
+ * propagator coefficients) and the pair and bonded work lists.  Errors:
+ * MIXPI_E_INVALID, _NOT_POW2, _ORDER, _UNSUPPORTED (more than 8 LJ types,
+ * N > 4096), _HIP.  *out is NULL on failure. */
 int mixpi_create(const mixpi_system_desc *desc, mixpi_system **out);
 
 /* A batch of n independent systems sharing one handle: every entry point
  * then processes all systems in the same launches.  Arrays in the library
  * layout hold the systems back to back; per-system outputs are indexed by
- * system.  All systems must share precision and flags. */
+ * system.  All systems must share precision and flags, except the j-tile
+ * width flags (MIXPI_FLAG_TILE_J*), which may differ per system. */
 int mixpi_batch_create(const mixpi_system_desc *const *descs, int32_t n,
                        mixpi_system **out);
 
@@ -215,7 +221,10 @@ int mixpi_forces(mixpi_system *sys, const double *q, const double *theta,
 int mixpi_forces_static(mixpi_system *sys, const double *q, const double *theta, double *f,
                         double *e_out, void *stream);
 
-/* V_mix only: e_out device double [n_systems][MIXPI_NV]. */
+/* V_mix only (the external potential of Eq. mts-hamiltonian, the part the
+ * split propagator of Sec. Implementation, Evaluation kicks with): the
+ * energies of mixpi_forces without the forces.  e_out device double
+ * [n_systems][MIXPI_NV]; other arguments as mixpi_forces. */
 int mixpi_energy(mixpi_system *sys, const double *q, const double *theta,
                  double *e_out, void *stream);
 
@@ -228,7 +237,9 @@ int mixpi_energy_adjoint(mixpi_system *sys, const double *q, const double *theta
                          const double *grad_e, double *dq, double *dtheta,
                          void *stream);
 
-/* Ring-polymer normal-mode transform of each particle's beads, per Cartesian
+/* Ring-polymer normal-mode transform (the modes in which the free
+ * ring-polymer part, Eq. free-rp-hamiltonian, is integrated exactly; Sec.
+ * Implementation, Evaluation) of each particle's beads, per Cartesian
  * component, in the orthonormal real basis C (bead j, mode k) of the cyclic
  * ring: k = 0: 1/sqrt(N); 0 < k < N/2: sqrt(2/N) cos(2 pi j k / N);
  * k = N/2: (-1)^j/sqrt(N); N/2 < k < N: sqrt(2/N) sin(2 pi j k / N).
