@@ -703,7 +703,7 @@ unsigned rp_item_lds(const RpItem &it, int op = OP_STEP, int precision = 0)
     if (it.kind == RP_MFMA) return mfma_lds_bytes(it.N, op, precision);
     if (it.kind == RP_DENSE) return (unsigned)((2 * N * N + 4 * 256) * sizeof(double));
     if (it.kind == RP_FFT) return (unsigned)((2 * N - 1) * sizeof(double2));
-    return (unsigned)((5 * (N + 64) + 2 * kCircJg * kCircOut) * sizeof(double));
+    return (unsigned)((5 * (N + 64)) * sizeof(double));
 }
 
 // Rings propagated in bead space (circulant items): the cheapest first,

@@ -198,7 +198,7 @@ __device__ __forceinline__ int brev(int j, int L) { return (int)(__brev((unsigne
 __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *red)
 {
     const int N = it.N, L = it.logN, n = it.n;
-    const int col = it.c0, i = col / 3, d = col - 3 * i;
+    const int col = it.c0, i = col / 3;
     // stage-major twiddles (N - 1 entries) staged in LDS behind the signal
     double2 *tw = z + N;
     const double2 *twg = a.twiddle + it.tw_off;
@@ -344,9 +344,11 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
 // the items of a column write q and p in place.  All global loads of a
 // thread are issued before its first LDS store.  Thread (og, jg) sums 4
 // consecutive outputs over a contiguous 1/64 of the ring, sliding its
-// coefficient window by one bead per step; LDS rows are padded by one
-// double per 1/64 of the ring, so the 16 j-groups of a wave read 16
-// distinct banks and the coefficient reads spread evenly over the banks.
+// coefficient window by one bead per step; wave og holds the 64 j-groups of
+// one output group.  LDS rows are padded by one double per 1/64 of the ring,
+// so a wave's 64 bead reads and its 64 coefficient reads are 17 doubles
+// apart (distinct banks); the 64 j-group sums of each output are then a
+// wave sum, with no LDS round trip.
 // The spring energy of the item's bead steps (j, j+1) needs the output
 // after the item; it is the dot product of raw (q, p) with the coefficients
 // minus the centroid parts, accumulated with the loads.
@@ -359,7 +361,6 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
     const int CS = N + 64;                       // row stride: q, p, a, b, c rows (N + pad)
     auto pad = [&](int x) { return x + (x >> lpad); };
     double *sq = smem, *sp = sq + CS, *ca = sp + CS, *cb = ca + CS, *cc = cb + CS;
-    double *part = cc + CS;                      // [kCircJg][kCircOut][2]
     __shared__ double s_sum[3][4];
     __shared__ double s_out[kCircOut + 1];
     const double *coef = a.circ + it.circ_off;
@@ -421,8 +422,8 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
     __syncthreads();
 
     // thread (og, jg): outputs o0 + 4 og + r, beads jg*seg .. jg*seg + seg - 1
-    constexpr int OG = kCircOut / 4;
-    const int og = tid % OG, jg = tid / OG;
+    static_assert(kCircOut / 4 * kCircJg == 256, "one wave per output group");
+    const int og = tid / kCircJg, jg = tid % kCircJg;
     const int seg = N / kCircJg;
     const int i0 = it.o0 + 4 * og;
     const int jb = jg * seg;
@@ -462,37 +463,25 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
         wb[0] = nb0;
         wc[0] = nc0;
     }
+    // the j-groups of output group og are the lanes of wave og: eight wave
+    // sums (fixed order) give its four outputs
+    double oq[4], op[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        part[(jg * kCircOut + 4 * og + r) * 2] = dq[r];
-        part[(jg * kCircOut + 4 * og + r) * 2 + 1] = dp[r];
+        oq[r] = wsum(dq[r]);
+        op[r] = wsum(dp[r]);
     }
-    __syncthreads();
-    // from here on the first wave alone: it reduces the partials, stores the
-    // outputs and sums the spring energy, ordering its LDS exchanges with
-    // wave-level fences instead of workgroup barriers
-    if (tid >= 64) return;
-    auto wave_sync = [] {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-    // lane (o, v, h): half h of the j-groups of output o, value v (q or p)
-    static_assert(4 * kCircOut == 64, "one lane per (output, value, half)");
-    double acc = 0.0;
-    {
-        const int o = tid % kCircOut, v = (tid / kCircOut) & 1, h = tid / (2 * kCircOut);
-        for (int g = h * (kCircJg / 2); g < (h + 1) * (kCircJg / 2); ++g)
-            acc += part[(g * kCircOut + o) * 2 + v];
-    }
-    wave_sync();
-    part[tid] = acc;
-    wave_sync();
-    if (tid < kCircOut) {
-        const double vq2 = part[tid] + part[2 * kCircOut + tid];
-        const double vp2 = part[kCircOut + tid] + part[3 * kCircOut + tid];
-        s_out[tid] = vq2;
-        const long long gq = (it.row + (long long)(it.o0 + tid) * n) * 3 + col;
+    const int lane = tid & 63;
+    if (lane < 4) {
+        double vq2 = oq[0], vp2 = op[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            vq2 = lane == r ? oq[r] : vq2;
+            vp2 = lane == r ? op[r] : vp2;
+        }
+        const int o = 4 * og + lane;
+        s_out[o] = vq2;
+        const long long gq = (it.row + (long long)(it.o0 + o) * n) * 3 + col;
         a.out_q[gq] = qc + vq2;
         a.p[gq] = pbar + vp2;
         a.cent[gq] = qc;
@@ -502,7 +491,9 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
         const double nraw = s_sum[2][0] + s_sum[2][1] + s_sum[2][2] + s_sum[2][3];
         s_out[kCircOut] = nraw - qc;
     }
-    wave_sync();
+    __syncthreads();
+    // the spring energy of the item's bead steps, by the first wave
+    if (tid >= 64) return;
     double esp = 0.0;
     if (tid < kCircOut) {
         const double dlt = s_out[tid] - s_out[tid + 1];
