@@ -82,7 +82,7 @@ def _executed(launch_us):
             "valu_issue_frac": VALU["insts_valu"] * 4 / 1024 / (t * 2.4e9)}
 
 
-def _workload(name):
+def _workload(name, gen_workers=None):
     import synth
     if name == "c3":
         return synth.config_c3(), "e1024-ion-512w (1024-bead e-, +3 ion, 512 H2O, 24.8 A)"
@@ -95,7 +95,8 @@ def _workload(name):
                 "water256 N_H=32 N_O=4, gradient workload seed 0 (19.7 A)")
     if name == "c5":
         print("[bench] generating the 64-system batch", file=sys.stderr, flush=True)
-        return (synth.config_c5(workers=synth.build_workers()),
+        workers = synth.build_workers() if gen_workers is None else (gen_workers or None)
+        return (synth.config_c5(workers=workers),
                 "batch64 e-/ion/water (P in 256..2048, 128..1024 H2O per system)")
     raise SystemExit(f"unknown workload {name}")
 
@@ -539,11 +540,15 @@ def main():
     ap.add_argument("--observables", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the radial distribution, velocity correlation and centroid "
                          "Ewald calls on the workload's configuration")
-    ap.add_argument("--tile", default="auto", choices=["auto", "heuristic"],
-                    help="pair-sweep tile shape: autotuned per workload bucket (default) or "
-                         "the library's size heuristic")
+    ap.add_argument("--tile", default="heuristic", choices=["auto", "heuristic"],
+                    help="pair-sweep tile shape: the library's choice from the work size "
+                         "(default; measured best on these workloads) or autotuned per "
+                         "workload bucket")
     ap.add_argument("--kernel-sha", action="store_true",
                     help="print the sha256 of the force-kernel sources and exit")
+    ap.add_argument("--gen-workers", type=int, default=None,
+                    help="processes that build the batch's systems (0: this process alone; "
+                         "default: the host's cores, at most 16)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (a known-size "
                          "kernel that calibrates hardware byte counters)")
@@ -562,7 +567,7 @@ def main():
     from paper_2411_11988_amd import mixpi
     mixpi.load()
     torch.cuda.set_device(0)
-    s, wname = _workload(args.workload)
+    s, wname = _workload(args.workload, args.gen_workers)
 
     flags32 = flags64 = 0
     tile = "heuristic"
@@ -613,7 +618,7 @@ def main():
                    "precision": ("fp32 electron-atom pseudopotential and 1/r seeds; fp64 atom-atom "
                                  "terms, separations, state and sums"),
                    "pair_tile_tj_x_waves": tile,
-                   "pair_shape_fp32": dict(zip(("tj", "waves", "i_waves"),
+                   "pair_shape_fp32": dict(zip(("tj", "waves", "i_waves", "j_run"),
                                                (sorted(set(sysm.pair_shape()[0])),
                                                 *sysm.pair_shape()[1:])))},
         "steps_per_s": steps_per_s,

@@ -390,9 +390,11 @@ int mixpi_pair_candidates(const mixpi_system *sys, int64_t *candidates);
 /* Tile shape the handle's pair sweep runs with (the MIXPI_FLAG_TILE_* flags
  * or the library's choice): tj (host int32 [n_systems], or NULL) the j-tile
  * width of each system; waves the j-split waves per tile (1 or 2); i_waves
- * the i-split waves (1, 2 or 4: tiles of 64 i_waves i-beads).  Any pointer
- * may be NULL.  No device work. */
-int mixpi_pair_shape(const mixpi_system *sys, int32_t *tj, int32_t *waves, int32_t *i_waves);
+ * the i-split waves (1, 2 or 4: tiles of 64 i_waves i-beads); j_run the
+ * most j-tiles one tile sweeps in turn (its i-forces stored once).  Any
+ * pointer may be NULL.  No device work. */
+int mixpi_pair_shape(const mixpi_system *sys, int32_t *tj, int32_t *waves, int32_t *i_waves,
+                     int32_t *j_run);
 
 /* Slice-pair evaluations with at least one term inside its cutoff, counted
  * on the device by every force evaluation since the last reset (forces,

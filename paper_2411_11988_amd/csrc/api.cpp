@@ -98,6 +98,7 @@ struct mixpi_system {
     int pair_tj_all = 0;                        // their common width, 0 if they differ
     int pair_waves = 1;                         // j-split waves per pair tile
     int pair_iw = 1;                            // i-split waves per pair tile
+    int pair_jrun = 1;                          // most j-tiles per pair item
 
     SysDev *d_sys = nullptr;
     LjPar *d_ljpar = nullptr;                   // LJ tables in the pair sweep's form
@@ -900,25 +901,28 @@ void add_mfma_propagation(Build &B, const std::vector<char> &use, std::vector<in
     }
 }
 
-// Cuts pair block bi into 64 iw x tj items: for each j-bead b, the i-tiles
-// of 64 iw beads of its contiguous i-run times the j-tiles of tj particles
-// (for a group with itself only tiles that hold some j > i).  The items of
-// one (b, i0) follow each other, j0 ascending.
-void block_items(const PairBlock &pb, int bi, int tj, int iw, std::vector<PairItem> &out)
+// Cuts pair block bi into items: for each j-bead b, the i-tiles of 64 iw
+// beads of its contiguous i-run times runs of up to jrun consecutive j-tiles
+// of tj particles (for a group with itself only tiles that hold some
+// j > i).  The items of one (b, i0) follow each other, j0 ascending.
+void block_items(const PairBlock &pb, int bi, int tj, int iw, int jrun, std::vector<PairItem> &out)
 {
     const long long li = (long long)pb.na << pb.shift;
     for (int b = 0; b < pb.nbeads_b; ++b)
-        for (long long i0 = 0; i0 < li; i0 += 64 * iw)
-            for (int j0 = 0; j0 < pb.nb; j0 += tj) {
-                if (pb.same && j0 + tj <= i0) continue;
+        for (long long i0 = 0; i0 < li; i0 += 64 * iw) {
+            int j0 = 0;
+            while (pb.same && j0 + tj <= i0) j0 += tj;
+            for (; j0 < pb.nb; j0 += jrun * tj) {
                 PairItem it{};
                 it.block = bi;
                 it.b = b;
                 it.i0 = (int)i0;
                 it.j0 = j0;
                 it.tj = tj;
+                it.nj = std::min(jrun, (pb.nb - j0 + tj - 1) / tj);
                 out.push_back(it);
             }
+        }
 }
 
 // Cost of sweeping one lane over W j-slots of an atom block, in VALU
@@ -955,21 +959,21 @@ bool sparse_pays(const SysDev &S, bool lj, int W)
 size_t tiles64(const std::vector<PairBlock> &blocks)
 {
     std::vector<PairItem> items;
-    for (size_t bi = 0; bi < blocks.size(); ++bi) block_items(blocks[bi], (int)bi, 64, 1, items);
+    for (size_t bi = 0; bi < blocks.size(); ++bi) block_items(blocks[bi], (int)bi, 64, 1, 1, items);
     return items.size();
 }
 
 // Natural partial-force slots of the items, in order: 64 iw i-slots, then
-// tj j-slots each (for a launch of one width, item k's start at
-// k (64 iw + tj), as the kernel assumes).  Returns the number of slots (-1
-// past 2^31 - 1).
-long long assign_item_slots(std::vector<PairItem> &items, int iw)
+// jrun tj j-slots each (a shorter run leaves some unused; for a launch of
+// one width, item k's start at k (64 iw + jrun tj), as the kernel assumes).
+// Returns the number of slots (-1 past 2^31 - 1).
+long long assign_item_slots(std::vector<PairItem> &items, int iw, int jrun)
 {
     long long next = 0;
     for (PairItem &it : items) {
         it.islot = (int)next;
         it.jslot = (int)(next + 64 * iw);
-        next += 64 * iw + it.tj;
+        next += 64 * iw + (long long)jrun * it.tj;
         if (next > (1LL << 31) - 1) return -1;
     }
     return next;
@@ -1053,9 +1057,11 @@ Gather build_gather(long long rows, const std::vector<PairBlock> &blocks,
                 if (idx < li)
                     emit(pb.rowa + ((long long)it.b << pb.shift) * pb.na + idx, (long long)it.islot + l);
             }
-            const int jn = std::min(it.tj, pb.nb - it.j0);
-            for (int l = 0; l < jn; ++l)
-                emit(pb.rowb + (long long)it.b * pb.nb + it.j0 + l, (long long)it.jslot + l);
+            for (int k = 0; k < it.nj; ++k) {
+                const int j0 = it.j0 + k * it.tj, jn = std::min(it.tj, pb.nb - j0);
+                for (int l = 0; l < jn; ++l)
+                    emit(pb.rowb + (long long)it.b * pb.nb + j0 + l, (long long)it.jslot + k * it.tj + l);
+            }
         }
         for (size_t t = 0; t < terms.size(); ++t) {
             const long long b = part_bonded + 3 * (long long)t;
@@ -1125,8 +1131,9 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     // Default shape by the work size n64 (64 x 64 tiles), against 1024 SIMDs
     // (measured on the workloads of 1e3 to 1e5 such tiles): below 1024
     // tiles 16-wide j-tiles (more, shorter waves), below 8192 32-wide, else
-    // 64-wide; from 16384 tiles on, 256 x 64 tiles (four i-split waves:
-    // fewer partial-force slots, the epilogue reads less).
+    // 64-wide; from 16384 tiles on, 128 x 64 tiles (two i-split waves) that
+    // sweep runs of four j-tiles: fewer partial-force slots to write and
+    // gather.
     const size_t n64 = tiles64(B.blocks);
     {
         int tj0 = n64 < 1024 ? 16 : (n64 < 8192 ? 32 : 64);
@@ -1147,16 +1154,16 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
         if (S->pair_tj[y] != S->pair_tj_all) S->pair_tj_all = 0;
     // Waves per tile: two j-split waves while the launch has fewer than one
     // 64-bead tile per SIMD: more, shorter waves even out the SIMDs and hide
-    // latency; else one, or four i-split waves from 16384 64 x 64 tiles on.
+    // latency; else one, or two i-split waves from 16384 64 x 64 tiles on.
     // MIXPI_PAIR_WAVES = 1 or 2 and MIXPI_PAIR_IW = 1, 2 or 4 (i-split
     // waves, with one j-wave), or the TILE_WAVES / TILE_I flags, choose
     // instead.
     {
         std::vector<PairItem> one;
         for (size_t bi = 0; bi < B.blocks.size(); ++bi)
-            block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], 1, one);
+            block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], 1, 1, one);
         S->pair_waves = one.size() < 1024 ? 2 : 1;
-        S->pair_iw = n64 >= 16384 ? 4 : 1;
+        S->pair_iw = n64 >= 16384 ? 2 : 1;
         if (const char *env = getenv("MIXPI_PAIR_WAVES")) {
             const int v = atoi(env);
             if (v == 1 || v == 2) S->pair_waves = v;
@@ -1171,10 +1178,19 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             S->pair_iw = (S->flags & MIXPI_FLAG_TILE_I128) ? 2 : (S->flags & MIXPI_FLAG_TILE_I256) ? 4 : 1;
         }
         if (S->pair_iw > 1) S->pair_waves = 1;
+        // j-runs: from 16384 64 x 64 tiles on, each item sweeps 4 j-tiles and
+        // stores its i-forces once (fewer partial-force slots to write and
+        // gather); MIXPI_PAIR_JRUN = 1, 2, 4 or 8 chooses instead
+        S->pair_jrun = n64 >= 16384 ? 4 : 1;
+        if (const char *env = getenv("MIXPI_PAIR_JRUN")) {
+            const int v = atoi(env);
+            if (v == 1 || v == 2 || v == 4 || v == 8) S->pair_jrun = v;
+        }
     }
     std::vector<PairItem> items;
     for (size_t bi = 0; bi < B.blocks.size(); ++bi)
-        block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], S->pair_iw, items);
+        block_items(B.blocks[bi], (int)bi, S->pair_tj[B.blocks[bi].sys], S->pair_iw, S->pair_jrun,
+                    items);
     S->n_items = (int)items.size();
     {
         // compacted sweep for atom blocks with few in-cutoff candidates;
@@ -1203,10 +1219,10 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
                                          : 41.0 * W);
         }
         std::stable_sort(items.begin(), items.end(), [&](const PairItem &x, const PairItem &y) {
-            return cost[x.block] > cost[y.block];
+            return cost[x.block] * x.nj > cost[y.block] * y.nj;
         });
     }
-    const long long item_slots = assign_item_slots(items, S->pair_iw);
+    const long long item_slots = assign_item_slots(items, S->pair_iw, S->pair_jrun);
     if (item_slots < 0) {
         delete S;
         return fail(MIXPI_E_UNSUPPORTED, "too many partial-force slots");
@@ -1358,7 +1374,7 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
             S->top_beads = std::max(S->top_beads, pb.nbeads_b << pb.shift);
         std::vector<int> rdf_sys;
         for (size_t bi = 0; bi < B.blocks.size(); ++bi) {
-            block_items(B.blocks[bi], (int)bi, kRdfTj, 1, rdf_items);
+            block_items(B.blocks[bi], (int)bi, kRdfTj, 1, 1, rdf_items);
             rdf_sys.resize(rdf_items.size(), B.blocks[bi].sys);
         }
         const int n_rdf = (int)rdf_items.size();
@@ -1517,6 +1533,7 @@ PairLaunch pair_args(mixpi_system *s, const double *q, const double *theta, int 
     a.tj = s->pair_tj_all;
     a.waves = s->pair_waves;
     a.iw = s->pair_iw;
+    a.jrun = s->pair_jrun;
     a.iblocks = s->d_iblocks;
     a.sys = s->d_sys;
     a.ljpar = s->d_ljpar;
@@ -2416,13 +2433,15 @@ int mixpi_use_ewald(mixpi_system *sys, int32_t on)
     return MIXPI_OK;
 }
 
-int mixpi_pair_shape(const mixpi_system *sys, int32_t *tj, int32_t *waves, int32_t *i_waves)
+int mixpi_pair_shape(const mixpi_system *sys, int32_t *tj, int32_t *waves, int32_t *i_waves,
+                     int32_t *j_run)
 {
     if (int rc = check_sys(sys)) return rc;
     if (tj)
         for (int y = 0; y < sys->n_sys; ++y) tj[y] = sys->pair_tj[y];
     if (waves) *waves = sys->pair_waves;
     if (i_waves) *i_waves = sys->pair_iw;
+    if (j_run) *j_run = sys->pair_jrun;
     return MIXPI_OK;
 }
 

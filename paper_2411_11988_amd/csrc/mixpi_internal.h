@@ -72,13 +72,14 @@ struct PairBlock {
 struct alignas(16) LjPar {
     double e4, s2, c0, c1;
 };
-// A 64 iw x tj tile of a pair block (iw: the launch's i-split waves): j-bead
-// b, i-beads [i0, i0 + 64 iw) of the block's i-run, j-particles
-// [j0, j0 + tj).  Its i-forces go to natural partial-force slots
-// islot + [0, 64 iw), its j-reactions to jslot + [0, tj).
+// A pair-sweep item of a pair block (iw: the launch's i-split waves): j-bead
+// b, i-beads [i0, i0 + 64 iw) of the block's i-run against nj consecutive
+// j-tiles of tj particles from j0 (a j-run).  Its i-forces go to natural
+// partial-force slots islot + [0, 64 iw), the reactions of j-tile k to
+// jslot + k tj + [0, tj).
 struct PairItem {
     int block, b, i0, j0;
-    int tj, islot, jslot, pad;
+    int tj, islot, jslot, nj;
 };
 constexpr int kMaxTj = 64;
 
@@ -134,6 +135,7 @@ struct PairLaunch {
     int tj;                  // j-tile width of every item (16, 32, 64), or 0: per item
     int waves;               // j-split waves per tile (1 or 2)
     int iw;                  // i-split waves per tile (1, 2 or 4; with waves = 1)
+    int jrun;                // most j-tiles of an item (natural slot stride 64 iw + jrun tj)
     const PairBlock *iblocks; // the block of every item, copied per item
     const SysDev *sys;
     const LjPar *ljpar;      // per system at lj_off: (nt+1)^2 type pairs

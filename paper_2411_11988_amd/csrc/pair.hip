@@ -87,7 +87,9 @@ template <typename R, int TJM, int WAVES, int IW> struct PairLds {
     double sjx[TJM], sjy[TJM], sjz[TJM], sjq[TJM];
     JMol sjm[TJM];
     JTyp sjt[TJM];
-    double fjx[TJM], fjy[TJM], fjz[TJM];
+    // j-reactions: one accumulator per i-split wave, summed in wave order at
+    // the store (atomics of different waves would land in timing order)
+    double fjx[IW][TJM], fjy[IW][TJM], fjz[IW][TJM];
     LjPar tlj[kLjTab];
     double xs[WAVES > 1 ? WAVES : 1][3][WAVES > 1 ? 64 : 1];   // i-forces handed to wave 0
     double es[WAVES > IW ? WAVES : IW][5];                      // the waves' sums
@@ -99,9 +101,11 @@ template <typename T> __device__ __forceinline__ T &at(T *base, int off)
     return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
 }
 
-// One item of j-tile width TJ.
+// One item of j-tile width TJ: its i-beads against it.nj consecutive
+// j-tiles (a j-run), one after the other through the same LDS, the i-forces
+// summed over the run and stored once.
 // FIXED: every item of the launch has width TJ, so item k's natural slots
-// start at k (64 IW + TJ), known before the item is loaded.
+// start at k (64 IW + jrun TJ), known before the item is loaded.
 template <typename R, bool THETA, int TJ, int WAVES, int IW, bool FIXED, int TJM>
 __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &it, const PairBlock &bk,
                                           PairLds<R, TJM, WAVES, IW> &L)
@@ -112,15 +116,15 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     const int wv = WAVES > 1 ? (int)threadIdx.x >> 6 : 0;   // j-split wave: j-slots wv*TJ/WAVES ...
     const int iw = IW > 1 ? (int)threadIdx.x >> 6 : 0;      // i-split wave: i-beads i0 + 64 iw ...
     // output positions of this lane's slots, fetched early
-    const long long si = FIXED ? (long long)blockIdx.x * (64 * IW + TJ) : it.islot;
+    const long long si = FIXED ? (long long)blockIdx.x * (64 * IW + a.jrun * TJ) : it.islot;
     const long long sj = FIXED ? si + 64 * IW : it.jslot;
     const int di = a.dest[si + 64 * iw + lane];
-    const int dj = (int)threadIdx.x < TJ ? a.dest[sj + threadIdx.x] : -1;
+    int dj = -1;
 
     double *const sjx = L.sjx, *const sjy = L.sjy, *const sjz = L.sjz, *const sjq = L.sjq;
     JMol *const sjm = L.sjm;
     JTyp *const sjt = L.sjt;
-    double *const fjx = L.fjx, *const fjy = L.fjy, *const fjz = L.fjz;
+    double *const fjx = L.fjx[iw], *const fjy = L.fjy[iw], *const fjz = L.fjz[iw];
     LjPar *const tlj = L.tlj;
     // the j-slot at byte offset o (slot * 8) as read by the loops
     auto jload = [&](int o) {
@@ -154,16 +158,18 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         }
     }
 
-    // j tile: bead b of group b, particles j0 .. j0 + jn; padding slots get
-    // harmless values and are masked out
-    const int jn = min(TJ, bk.nb - it.j0);
-    if ((int)threadIdx.x < TJ) {
+    // j-tile kj of the run: bead b of group b, particles j0 .. j0 + jn;
+    // padding slots get harmless values and are masked out
+    auto stage = [&](int kj) {
+        const int j0 = it.j0 + kj * TJ, jn = min(TJ, bk.nb - j0);
+        if ((int)threadIdx.x >= TJ) return;
         const int js = threadIdx.x;
+        dj = a.dest[sj + kj * TJ + js];
         double x = 0, y = 0, z = 0, qd = 0;
         JMol jm{-1, -1};
         JTyp jt{0, 0.0f};
         if (js < jn) {
-            const int j = it.j0 + js;
+            const int j = j0 + js;
             const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
             const int pj = bk.pb0 + j;
             x = a.q[3 * rowj];
@@ -184,10 +190,13 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         sjq[js] = qd;
         sjm[js] = jm;
         sjt[js] = jt;
-        fjx[js] = 0.0;
-        fjy[js] = 0.0;
-        fjz[js] = 0.0;
-    }
+        for (int v = 0; v < IW; ++v) {
+            L.fjx[v][js] = 0.0;
+            L.fjy[v][js] = 0.0;
+            L.fjz[v][js] = 0.0;
+        }
+    };
+    stage(0);
 
     // i bead
     const long long li = (long long)bk.na << bk.shift;
@@ -223,6 +232,35 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     // this lane's first slot offset, and the wave's slots (j-split waves)
     const int lane8 = lane * 8, wv8 = wv * (TJ / WAVES) * 8;
     constexpr int M8 = (TJ / WAVES) * 8 - 1;
+    const double w = bk.w;
+    // the j-tiles of the run: tile 0 is staged above; after each sweep its
+    // j-reactions go to their slots, and the next tile replaces it
+    const int nj = it.nj;
+    auto run = [&](auto &&sweep_tile) {
+        for (int kj = 0; kj < nj; ++kj) {
+            if (kj > 0) {
+                __syncthreads();      // the previous tile's reactions are stored
+                stage(kj);
+                __syncthreads();
+            }
+            sweep_tile();
+            __syncthreads();          // every wave's reactions are in
+            const int jn = min(TJ, bk.nb - (it.j0 + kj * TJ));
+            if ((int)threadIdx.x < jn) {
+                double *o = a.part + 3LL * dj;
+                const int t = threadIdx.x;
+                double sx = L.fjx[0][t], sy = L.fjy[0][t], sz = L.fjz[0][t];
+                for (int v = 1; v < IW; ++v) {
+                    sx += L.fjx[v][t];
+                    sy += L.fjy[v][t];
+                    sz += L.fjz[v][t];
+                }
+                o[0] = w * sx;
+                o[1] = w * sy;
+                o[2] = w * sz;
+            }
+        }
+    };
 
     if (bk.kind == PK_ATOM) {
         // Atom-atom Lennard-Jones and Coulomb in FP64 in both forms, from
@@ -356,11 +394,11 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
             }
         };
         if (bk.lj) {
-            if (bk.sparse) sweep(std::true_type{}, std::true_type{});
-            else sweep(std::true_type{}, std::false_type{});
+            if (bk.sparse) run([&] { sweep(std::true_type{}, std::true_type{}); });
+            else run([&] { sweep(std::true_type{}, std::false_type{}); });
         } else {
-            if (bk.sparse) sweep(std::false_type{}, std::true_type{});
-            else sweep(std::false_type{}, std::false_type{});
+            if (bk.sparse) run([&] { sweep(std::false_type{}, std::true_type{}); });
+            else run([&] { sweep(std::false_type{}, std::false_type{}); });
         }
     } else {
         // electron-atom pseudopotential K / sqrt(r^2 + a^2), K = k_e pp_q q_atom,
@@ -425,8 +463,8 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 atomicAdd(&at(fjz, o), ngd * dz);
             }
         };
-        if (bk.kind == PK_E_ATOM) sweep_e(std::true_type{});
-        else sweep_e(std::false_type{});
+        if (bk.kind == PK_E_ATOM) run([&] { sweep_e(std::true_type{}); });
+        else run([&] { sweep_e(std::false_type{}); });
     }
     double e0 = wsum(e0r), e1 = wsum(e1r), g0 = 0.0, g1 = 0.0;
     cnt = (int)wsum((double)cnt);       // exact: at most 64 * TJ
@@ -483,25 +521,17 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 cnt += (int)es[v][4];
             }
         }
-    } else {
-        __syncthreads();
     }
 
-    // partial forces of this tile go to its own slots (64 IW i-slots, then
-    // TJ j-slots), each stored at its row-contiguous position; the per-row
-    // gather sums them, so no two workgroups write the same address
-    const double w = bk.w;
+    // partial forces of this item go to its own slots (64 IW i-slots, then
+    // TJ j-slots per j-tile, stored above), each at its row-contiguous
+    // position; the per-row gather sums them, so no two workgroups write the
+    // same address
     if (vi) {
         double *o = a.part + 3LL * di;
         o[0] = w * fxi;
         o[1] = w * fyi;
         o[2] = w * fzi;
-    }
-    if ((int)threadIdx.x < jn) {
-        double *o = a.part + 3LL * dj;
-        o[0] = w * fjx[threadIdx.x];
-        o[1] = w * fjy[threadIdx.x];
-        o[2] = w * fjz[threadIdx.x];
     }
     if (threadIdx.x == 0) {
         double *e = a.eslot + (long long)blockIdx.x * A_N;
@@ -523,11 +553,12 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
 
 // TJ > 0: every item of the launch has that width; TJ = 0: each item's own
 // width (a batch whose systems differ; the widest body sets the registers).
-// The fixed-width FP32-form force kernels are held to 96 VGPRs, five waves
-// per SIMD (the compiler fits them without spills; left alone it takes a few
-// more and drops to four; the FP64 form would spill).
+// The fixed-width one-wave FP32-form force kernels are held to 96 VGPRs,
+// five waves per SIMD (the compiler fits them without spills; left alone it
+// takes a few more and drops to four; the FP64 form and the multi-wave
+// tiles would spill).
 template <typename R, bool THETA, int TJ, int WAVES, int IW>
-__global__ __launch_bounds__(64 * WAVES * IW) __attribute__((amdgpu_waves_per_eu(TJ > 0 && !THETA && sizeof(R) == 4 ? 5 : 1)))
+__global__ __launch_bounds__(64 * WAVES * IW) __attribute__((amdgpu_waves_per_eu(TJ > 0 && !THETA && sizeof(R) == 4 && WAVES * IW == 1 ? 5 : 1)))
 void k_pair(PairLaunch a, BondedLaunch bl)
 {
     __shared__ double red[WAVES * IW];

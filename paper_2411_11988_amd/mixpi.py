@@ -101,7 +101,7 @@ def load():
         "mixpi_nm_transform": ([P, I32, P, P, P], C.c_int),
         "mixpi_step": ([P, I32, P, P, P, P, P], C.c_int),
         "mixpi_pair_candidates": ([P, P], C.c_int),
-        "mixpi_pair_shape": ([P, P, P, P], C.c_int),
+        "mixpi_pair_shape": ([P, P, P, P, P], C.c_int),
         "mixpi_pair_evals": ([P, P, I32, P], C.c_int),
         "mixpi_step_prepare": ([P, I32, P, P, P, P], C.c_int),
         "mixpi_kernel_time": ([P, I32, P, P, P, P, P], C.c_int),
@@ -228,11 +228,11 @@ def mixpi_step(h, nsteps: int, q, p, f, elog, stream=None) -> None:
 
 
 def mixpi_pair_shape(h, n_systems: int) -> tuple:
-    """(j-tile width per system, j-split waves, i-split waves)."""
+    """(j-tile width per system, j-split waves, i-split waves, j-run)."""
     tj = (C.c_int32 * n_systems)()
-    w, iw = C.c_int32(), C.c_int32()
-    _check(load().mixpi_pair_shape(h, tj, C.byref(w), C.byref(iw)))
-    return list(tj), w.value, iw.value
+    w, iw, jr = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().mixpi_pair_shape(h, tj, C.byref(w), C.byref(iw), C.byref(jr)))
+    return list(tj), w.value, iw.value, jr.value
 
 
 def mixpi_pair_candidates(h) -> int:
@@ -394,7 +394,7 @@ class System:
         return mixpi_pair_candidates(self.h)
 
     def pair_shape(self):
-        """(j-tile width per system, j-split waves, i-split waves)."""
+        """(j-tile width per system, j-split waves, i-split waves, j-run)."""
         return mixpi_pair_shape(self.h, self.n_systems)
 
     def pair_evals(self, reset: bool = False, stream=None):

@@ -116,12 +116,18 @@ def c5():
 def test_batch_full_size_forces_every_system(mp, c5, prec):
     """The 64-system batch at full size: forces and energies of every
     system of the batched handle against the oracle (FP64 form 1e-12; FP32
-    form forces 1e-5 x RMS, energies 1e-6 per term)."""
+    form forces 1e-5 x RMS, energies 1e-6 per term), and equal bits from a
+    repeated call."""
     systems, q, _, rows = c5
     b = mp.System(systems, precision=prec)
-    f, e = b.forces(dev(q))
+    qd = dev(q)
+    f, e = b.forces(qd)
     f, e = host(f), host(e)
     assert np.isfinite(f).all() and np.isfinite(e).all()
+    # the same bits from a second call (several waves of a tile add to the
+    # same j-partials: their sums keep a fixed order)
+    f2, e2 = b.forces(qd)
+    assert np.array_equal(f, host(f2)) and np.array_equal(e, host(e2))
     tol_f, tol_e = (1e-12, 1e-12) if prec == 0 else (1e-5, 1e-6)
     worst_f = worst_e = 0.0
     for k, s in enumerate(systems):

@@ -336,6 +336,34 @@ def test_pair_i_split_tiles_span_several_i_tiles(mp, tj, waves, monkeypatch):
             assert energy_err(host(e)[0], eo) <= TOL_E[prec]
 
 
+@pytest.mark.parametrize("tj,waves,jrun", [(16, "w1", 4), (16, "w2", 2), (32, "i2", 8),
+                                           (64, "w1", 2), (64, "i4", 4)])
+def test_pair_j_runs(mp, tj, waves, jrun, monkeypatch):
+    """Items that sweep several j-tiles in turn (j-runs, the last run of an
+    i-tile shorter), with every tile shape: forces, energies and pair counts
+    against the oracle; the same bits from repeated calls."""
+    _set_shape(monkeypatch, tj, waves)
+    monkeypatch.setenv("MIXPI_PAIR_JRUN", str(jrun))
+    for name, s in (("water-400", synth.water_box(400, 23.0, 1, 1, seed=3, rc=9.0)),
+                    ("water-h4-o2", synth.water_box(150, 17.0, 4, 2, seed=6, rc=7.0)),
+                    SYSTEMS[7]):
+        o = oracle.OracleSystem(s)
+        Fo, eo = o.forces(s.q)
+        for prec in (FP64, FP32):
+            print(f"[j-run] tj={tj} waves={waves} jrun={jrun} {name} prec={prec}", flush=True)
+            sysm = mp.System(s, precision=prec)
+            assert sysm.pair_shape()[3] == jrun
+            q = dev(to_rows(s, s.q))
+            sysm.pair_evals(reset=True)
+            f, e = sysm.forces(q)
+            F = from_rows(s, host(f))
+            assert force_err(F, Fo) <= TOL_F[prec], force_err(F, Fo)
+            assert energy_err(host(e)[0], eo) <= TOL_E[prec]
+            assert sysm.pair_evals() == o.pair_evals(s.q)
+            f2, _ = sysm.forces(q)
+            assert np.array_equal(host(f), host(f2))
+
+
 @pytest.mark.parametrize("tj,waves", [(32, "w1"), (32, "w2"), (64, "w1"), (64, "w2"), (64, "i4")])
 def test_pair_compacted_sweep(mp, tj, waves, monkeypatch):
     """The compacted atom-atom sweep (a distance pass marks each lane's

@@ -72,20 +72,20 @@ def test_default_shape_by_work_size(mp):
     """Without shape flags the handle picks the tile shape from its work
     size (64 x 64 tiles): 16-wide j-tiles and two j-split waves for the
     64-bead electron with 32 waters, 16-wide tiles with one wave for the
-    1024-bead electron with 512 waters, 64-wide tiles with four i-split
-    waves for the 64-system batch."""
-    for make, want in ((synth.config_c1, ([16], 2, 1)), (synth.config_c3, ([16], 1, 1))):
+    1024-bead electron with 512 waters, 64-wide tiles with two i-split
+    waves and runs of four j-tiles for the 64-system batch."""
+    for make, want in ((synth.config_c1, ([16], 2, 1, 1)), (synth.config_c3, ([16], 1, 1, 1))):
         s = make()
         sysm = mp.System(s)
         assert sysm.pair_shape() == want, (s.name, sysm.pair_shape())
         sysm.close()
     systems = synth.config_c5(workers=synth.build_workers())
     b = mp.System(systems)
-    tj, w, iw = b.pair_shape()
-    assert tj == [64] * len(systems) and (w, iw) == (1, 4), (tj[:3], w, iw)
+    tj, w, iw, jr = b.pair_shape()
+    assert tj == [64] * len(systems) and (w, iw, jr) == (1, 2, 4), (tj[:3], w, iw, jr)
     b.close()
     # flags override, per system in a batch
     fl = [mp.TILE_FLAGS[(32, "w2")], mp.TILE_FLAGS[(16, "w2")]]
     b = mp.System([synth.config_c1(), synth.config_c1()], flags=fl)
-    assert b.pair_shape() == ([32, 16], 2, 1)
+    assert b.pair_shape() == ([32, 16], 2, 1, 1)
     b.close()
