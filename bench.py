@@ -282,7 +282,17 @@ def _run_observables(sysm, q, p, s, mixpi, torch, reps=50):
     e = torch.zeros((sysm.n_systems, 3), dtype=torch.float64, device="cuda")
     ew_us = timed(lambda: sysm.ewald(q, f, e), reps)
     cand = sysm.pair_candidates()
-    return {"rdf": {"us_per_call": rdf_us, "nbins": nb, "r_max": rmax,
+    # normal-mode transforms of the whole state (matrix-core items for rings
+    # of 16 to 64 beads, FFT or dense items otherwise), forward and backward;
+    # algorithmic bytes: the state in and out, 48 B per bead row
+    nm = torch.empty_like(q)
+    fwd_us = timed(lambda: sysm.nm_transform(q, +1, out=nm), reps)
+    bwd_us = timed(lambda: sysm.nm_transform(nm, -1, out=f), reps)
+    nm_bytes = 48 * int(sysm.rows)
+    return {"nm_transform": {"fwd_us": fwd_us, "bwd_us": bwd_us, "bytes": nm_bytes,
+                             "fwd_GBps": nm_bytes / (fwd_us * 1e-6) / 1e9,
+                             "bwd_GBps": nm_bytes / (bwd_us * 1e-6) / 1e9},
+            "rdf": {"us_per_call": rdf_us, "nbins": nb, "r_max": rmax,
                     "slice_pairs_per_s": cand / (rdf_us * 1e-6)},
             "vacf": {"us_per_sample": vacf_us, "lags": L},
             "ewald": {"us_per_call": ew_us, "alpha": alpha, "r_cut": rcut, "grid": grid,
