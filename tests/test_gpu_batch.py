@@ -181,3 +181,30 @@ def test_batch_pair_counts(mp):
     aa, ea = b.pair_evals(reset=True)
     want = np.sum([oracle.OracleSystem(s).pair_evals(s.q) for s in systems], axis=0)
     assert (aa, ea) == (int(want[0]), int(want[1]))
+
+
+@pytest.mark.parametrize("waves,jrun", [("w1", 2), ("i2", 2), ("w2", 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_mixed_widths_with_j_runs(mp, prec, waves, jrun, monkeypatch):
+    """A batch whose systems sweep with different tile widths (16, 32 and
+    64 j-beads in one force launch), with i-split waves and j-runs: every
+    system against the oracle, and equal bits from a repeated call."""
+    monkeypatch.setenv("MIXPI_PAIR_JRUN", str(jrun))
+    systems = mixed_batch()
+    widths = [16, 64, 32, 64, 16]
+    flags = [mp.TILE_FLAGS[(tj, waves)] for tj in widths]
+    b = mp.System(systems, precision=prec, flags=flags)
+    tj, w, iw, jr = b.pair_shape()
+    assert list(tj) == widths and jr == jrun
+    q, rows = pack(systems, [s.q for s in systems])
+    qd = dev(q)
+    f, e = b.forces(qd)
+    f, e = host(f), host(e)
+    f2, e2 = b.forces(qd)
+    assert np.array_equal(f, host(f2)) and np.array_equal(e, host(e2))
+    tol_f, tol_e = (1e-12, 1e-12) if prec == 0 else (1e-5, 1e-6)
+    for k, s in enumerate(systems):
+        print(f"[batch widths] system {k} prec={prec} {waves} jrun={jrun}", flush=True)
+        Fo, eo = oracle.OracleSystem(s).forces(s.q)
+        assert force_err(f[rows[k]], Fo) <= tol_f, k
+        assert energy_err(e[k], eo) <= tol_e, k
