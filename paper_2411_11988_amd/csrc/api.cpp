@@ -546,6 +546,18 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                         if (ta[a] && tb[b] && (d->lj_eps[a * nt + b] != 0.0 || (a == 0 && b == 0)))
                             pb.lj = 1;
             }
+            {
+                // the molecule compare can be left out where no two distinct
+                // particles of the two groups share a molecule id
+                std::map<int, int> ma;
+                for (int x = 0; x < A.n; ++x) ++ma[d->mol_id[A.p0 + x]];
+                pb.mol = 0;
+                if (pb.same) {
+                    for (auto &kv : ma) pb.mol |= kv.second > 1;
+                } else {
+                    for (int x = 0; x < Bg.n; ++x) pb.mol |= ma.count(d->mol_id[Bg.p0 + x]) > 0;
+                }
+            }
             B.blocks.push_back(pb);
             const long long pairs = pb.same ? (long long)A.n * (A.n - 1) / 2 : (long long)A.n * Bg.n;
             B.candidates += pairs * A.N;

@@ -56,6 +56,14 @@ __device__ __forceinline__ double group_sum(double v)
 // Sum over the wave, in every lane.
 __device__ __forceinline__ double wsum(double v) { return group_sum<64>(v); }
 
+// The wave's lane mask of b (bit l: lane l is active and has b set), a
+// wave-uniform value.  A mask of one compare is that compare's own result,
+// and masks combine with scalar instructions.
+__device__ __forceinline__ unsigned long long lanes(bool b)
+{
+    return __builtin_amdgcn_ballot_w64(b);
+}
+
 // Sum of v over the workgroup (blockDim.x a multiple of 64), valid in
 // thread 0.  red: LDS scratch of blockDim.x / 64 doubles.
 __device__ __forceinline__ double bsum(double v, double *red)

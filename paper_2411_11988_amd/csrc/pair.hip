@@ -223,15 +223,25 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     // then FP64 across lanes, waves and tiles
     double e0r = 0, e1r = 0;          // atom: LJ, Coulomb; electron: pp
     double g0r = 0, g1r = 0;          // theta partials (pp: q_e, a; atom: eps, sigma)
-    // in-cutoff slice-pairs: a per-lane count (one add per candidate),
-    // summed over the wave after the loop
+    // in-cutoff slice-pairs of the wave: each candidate step adds the
+    // population count of its lane mask (scalar instructions, wave-uniform)
     int cnt = 0;
     // slots that may interact: jg > key, i.e. real j (padding has jg = -1),
     // for a group with itself j > i, and none for a lane past the i-run
     const int key = !vi ? 0x7fffffff : (bk.same ? (int)idx : -1);
-    // this lane's first slot offset, and the wave's slots (j-split waves)
-    const int lane8 = lane * 8, wv8 = wv * (TJ / WAVES) * 8;
-    constexpr int M8 = (TJ / WAVES) * 8 - 1;
+    // step t of a lane's sweep of its wave's W = TJ / WAVES slots takes slot
+    // (lane mod W) XOR t (byte offset base ^ 8t, the wave's slot range in
+    // the high bits of base): every lane visits each slot once, and at each
+    // step the lanes mod W visit distinct slots, so the LDS reads and the
+    // reaction adds spread over the slots
+    const int base8 = ((lane & (TJ / WAVES - 1)) * 8) | (wv * (TJ / WAVES) * 8);
+    // base8 made opaque to the optimiser where a sweep starts, so that
+    // base8 ^ 8t stays one XOR per step (knowing base8 a multiple of 8, it
+    // would shift (base ^ t) instead)
+    auto opaque = [](int v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    };
     const double w = bk.w;
     // the j-tiles of the run: tile 0 is staged above; after each sweep its
     // j-reactions go to their slots, and the next tile replaces it
@@ -321,7 +331,9 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 const double vc = Km * (fma(r2, hc, ir) - vc0);
                 const double gc = Km * fma(ir2, ir, -irc3);
                 double g;
-                bool hit = in_c;
+                // the in-cutoff count takes the same conditions as lane
+                // masks (scalar instructions)
+                unsigned long long hits = lanes(r2 < rc2_c) & lanes(K != 0.0);
                 if constexpr (LJ) {
                     const LjPar lp = at(tlj, tp);
                     const double e4 = lp.e4, c1l = lp.c1;
@@ -334,7 +346,7 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     const double glj = e4 * (12.0 * s12 - 6.0 * s6) * ir2 + c1l;
                     g = fma(glj, mlj, gc);
                     e0r = fma(vlj, mlj, e0r);
-                    hit = in_lj | in_c;
+                    hits |= lanes(r2 < rc2_lj) & lanes(e4 != 0.0);
                     if (THETA) {
                         // d/d eps and d/d sigma of the (0,0) LJ term
                         const bool on = in_lj & (tp == 0);   // type pair (0, 0)
@@ -352,7 +364,8 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     g = gc;
                 }
                 e1r += vc;
-                cnt += hit;
+                cnt += __builtin_popcountll(
+                    hits & (SP ? lanes(live) : lanes(jr.jg > key) & lanes(mi != jr.mol)));
                 fxi = fma(g, dx, fxi);
                 fyi = fma(g, dy, fyi);
                 fzi = fma(g, dz, fzi);
@@ -362,15 +375,16 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 atomicAdd(&at(fjy, o), ng * dy);
                 atomicAdd(&at(fjz, o), ng * dz);
             };
+            const int b8 = opaque(base8);
             if constexpr (!SP) {
 #pragma unroll 4
-                for (int t = 0; t < W; ++t) body(((lane8 + 8 * t) & M8) | wv8, true);
+                for (int t = 0; t < W; ++t) body(b8 ^ (8 * t), true);
             } else {
                 using Mask = std::conditional_t<(W > 32), unsigned long long, unsigned>;
                 Mask m = 0;
 #pragma unroll 4
                 for (int t = 0; t < W; ++t) {
-                    const int o = ((lane8 + 8 * t) & M8) | wv8;
+                    const int o = b8 ^ (8 * t);
                     const JSlot<R> jr = jload(o);
                     double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
                     dx -= Lx * rint(dx * iLx);
@@ -389,7 +403,7 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                     if constexpr (W > 32) t = live ? __builtin_ctzll(m) : 0;
                     else t = live ? __builtin_ctz(m) : 0;
                     m &= m - 1;
-                    body(((lane8 + 8 * t) & M8) | wv8, live);
+                    body(b8 ^ (8 * t), live);
                 }
             }
         };
@@ -417,18 +431,22 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         // E_IS_I: the electron is the i side and the constant is the j
         // atom's pp_q k_e q_j (its slot's kq in the FP32 form); otherwise the
         // i atom's
-        auto sweep_e = [&](auto e_tag) {
+        // MOL: some pair of the block may share a molecule id (else the
+        // compare is left out; it would always pass)
+        auto sweep_e = [&](auto e_tag, auto mol_tag) {
             constexpr bool E_IS_I = decltype(e_tag)::value;
+            constexpr bool MOL = decltype(mol_tag)::value;
+            const int b8 = opaque(base8);
 #pragma unroll 4
             for (int t = 0; t < TJ / WAVES; ++t) {
-                const int o = ((lane8 + 8 * t) & M8) | wv8;
+                const int o = b8 ^ (8 * t);
                 const JSlot<R> jr = jload(o);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
                 dx -= Lx * rint(dx * iLx);
                 dy -= Ly * rint(dy * iLy);
                 dz -= Lz * rint(dz * iLz);
                 const double r2d = dx * dx + dy * dy + dz * dz;
-                const bool ok = (jr.jg > key) & (mi != jr.mol) & (r2d < rc2);
+                const bool ok = (jr.jg > key) & (!MOL || mi != jr.mol) & (r2d < rc2);
                 const R r2 = (R)r2d;
                 R kq = kqi;
                 if constexpr (E_IS_I) {
@@ -443,7 +461,8 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 const R vq = kqm * (ir - phic - (r2 - rrc2) * hpsic);
                 const R gq = kqm * (ir3 + psic);
                 e0r += (double)vq;
-                cnt += ok;
+                cnt += __builtin_popcountll(lanes(jr.jg > key) & lanes(!MOL || mi != jr.mol) &
+                                            lanes(r2d < rc2));
                 if (THETA) {
                     const double kqd = E_IS_I ? jr.qd : kqid;
                     const double u = r2d + a2;
@@ -463,11 +482,15 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 atomicAdd(&at(fjz, o), ngd * dz);
             }
         };
-        if (bk.kind == PK_E_ATOM) run([&] { sweep_e(std::true_type{}); });
-        else run([&] { sweep_e(std::false_type{}); });
+        if (bk.kind == PK_E_ATOM) {
+            if (bk.mol) run([&] { sweep_e(std::true_type{}, std::true_type{}); });
+            else run([&] { sweep_e(std::true_type{}, std::false_type{}); });
+        } else {
+            if (bk.mol) run([&] { sweep_e(std::false_type{}, std::true_type{}); });
+            else run([&] { sweep_e(std::false_type{}, std::false_type{}); });
+        }
     }
     double e0 = wsum(e0r), e1 = wsum(e1r), g0 = 0.0, g1 = 0.0;
-    cnt = (int)wsum((double)cnt);       // exact: at most 64 * TJ
 
     if (THETA) {
         g0 = wsum(g0r);
