@@ -186,6 +186,20 @@ int mixpi_sizes(const mixpi_system *sys, int64_t *n_bead_rows, int32_t *n_partic
  * layout. */
 int mixpi_bead_index(const mixpi_system *sys, int64_t *rows_out);
 
+/* The library layout by groups (the bead-index bookkeeping of Sec.
+ * Implementation, Overview, kept as index arithmetic): a group is a maximal
+ * run of particles of one system with equal bead count N and electron flag
+ * (particles in descending N order, so every slice map between two groups
+ * is a power-of-two shift).  Bead a of the group's particle i (0 <= i < n)
+ * sits at row first_row + a n + i: bead-major, so the 64-row tiles of the
+ * pair sweep hold consecutive particles of one bead.
+ *   n_groups      out, required: the number of groups
+ *   group_offsets out, int64 [5 * n_groups] or NULL (to ask the count
+ *                 first): per group, in row order, (first row, N, n, first
+ *                 particle over the handle, system)
+ * Host memory; no device work. */
+int mixpi_layout(const mixpi_system *sys, int64_t *group_offsets, int32_t *n_groups);
+
 /* Bead forces F = -dV_mix/dq (Eq. mts-hamiltonian).
  *   q     device double [rows][3], library layout (positions, unwrapped)
  *   theta device double [n_systems][6] overriding (pp_q, pp_a, eps and
@@ -259,6 +273,21 @@ int mixpi_nm_transform(mixpi_system *sys, int32_t dir, const double *in, double 
  * mixpi_step_prepare); later calls with the same pointers replay it. */
 int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *f,
                double *elog, void *stream);
+
+/* mixpi_step of a batch (mixpi_batch_create) whose state lives in separate
+ * arrays per system: q[k], p[k], f[k] are device double [rows_k][3] of
+ * system k in its own layout (the rows a handle of that system alone
+ * would have; mixpi_layout gives each system's groups).  q, p, f are host
+ * arrays of n_systems device pointers; elog as mixpi_step.  Same results
+ * bit for bit as mixpi_step on the systems' rows placed back to back.
+ * Where the arrays already sit back to back in one allocation (q[k] =
+ * q[0] + 3 x first row of system k, likewise p and f), it is mixpi_step on
+ * q[0], p[0], f[0]; otherwise the states are copied (device to device, on
+ * stream) into staging arrays of the handle, stepped, and copied back. The
+ * staging arrays (72 bytes per bead row) are allocated by the first such
+ * call and kept until mixpi_destroy: that call is not graph-capturable. */
+int mixpi_batch_step(mixpi_system *sys, int32_t nsteps, double *const *q, double *const *p,
+                     double *const *f, double *elog, void *stream);
 
 /* Path-integral Langevin thermostat (the PILE thermostat of the paper's NVT
  * runs, Sec. "Examples and Discussion"), for mixpi_step_nvt.  Each ring's

@@ -94,6 +94,9 @@ struct mixpi_system {
     int n_part = 0, n_groups = 0;
     long long candidates = 0;
     std::vector<long long> bead_index;
+    std::vector<long long> layout;              // per group: first row, N, n, first particle, system
+    std::vector<long long> sys_row0;            // first row of each system, then the row count
+    double *d_bstage = nullptr;                 // mixpi_batch_step staging: q, p, f [rows][3] each
     std::vector<int> pair_tj;                   // j-tile width of each system's items
     int pair_tj_all = 0;                        // their common width, 0 if they differ
     int pair_waves = 1;                         // j-split waves per pair tile
@@ -249,7 +252,7 @@ void release(mixpi_system *s)
                     s->d_partial, s->d_red_v, s->d_row_prev, s->d_row_next, s->d_row_ksp,
                     s->d_npairs, s->d_nonfinite, s->d_cent, s->d_scratch,
                     s->d_rdf_ranges, s->d_parts, s->d_pspec, s->d_sys_part, s->d_red_fE,
-                    s->d_red_aE, s->d_red_vE};
+                    s->d_red_aE, s->d_red_vE, s->d_bstage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -369,6 +372,7 @@ struct Build {
         int sys;
         long long row;
         int N, n;
+        int p;                                 // first particle (over the handle)
     };
     std::vector<GroupRec> groups;              // every group of every system, in row order
     std::vector<MfmaCol> mf_cols;              // columns of the matrix-core items
@@ -467,7 +471,8 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
         i = j;
     }
     B.n_groups += (int)groups.size();
-    for (const Group &g : groups) B.groups.push_back(Build::GroupRec{s, g.row, g.N, g.n});
+    for (const Group &g : groups)
+        B.groups.push_back(Build::GroupRec{s, g.row, g.N, g.n, p_base + g.p0});
     B.sys_part.push_back(p_base);
     for (const Group &g : groups)
         for (int i = 0; i < g.n; ++i) {
@@ -1136,6 +1141,11 @@ int create_impl(const mixpi_system_desc *const *descs, int n_sys, mixpi_system *
     S->n_groups = B.n_groups;
     S->candidates = B.candidates;
     S->bead_index = B.bead_index;
+    for (const auto &g : B.groups)
+        S->layout.insert(S->layout.end(), {g.row, (long long)g.N, (long long)g.n, (long long)g.p,
+                                           (long long)g.sys});
+    for (const auto &r : B.sys_rows) S->sys_row0.push_back(r.first);
+    S->sys_row0.push_back(B.rows);
 
     // Pair items: per system with its j-tile width (a MIXPI_FLAG_TILE_J*
     // flag of its description, else MIXPI_PAIR_TJ = 16, 32 or 64, else
@@ -1934,6 +1944,15 @@ int mixpi_bead_index(const mixpi_system *sys, int64_t *rows_out)
     return MIXPI_OK;
 }
 
+int mixpi_layout(const mixpi_system *sys, int64_t *group_offsets, int32_t *n_groups)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!n_groups) return fail(MIXPI_E_INVALID, "n_groups is null");
+    *n_groups = sys->n_groups;
+    if (group_offsets) std::copy(sys->layout.begin(), sys->layout.end(), group_offsets);
+    return MIXPI_OK;
+}
+
 int mixpi_forces(mixpi_system *sys, const double *q, const double *theta, double *f,
                  double *e_out, void *stream)
 {
@@ -2064,6 +2083,47 @@ int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *
     GraphEntry *ge = nullptr;
     if (int rc = step_graph(sys, nsteps, q, p, f, elog, &ge)) return rc;
     return run_graph(sys, ge, stream);
+}
+
+int mixpi_batch_step(mixpi_system *sys, int32_t nsteps, double *const *q, double *const *p,
+                     double *const *f, double *elog, void *stream)
+{
+    if (int rc = check_sys(sys)) return rc;
+    if (!q || !p || !f) return fail(MIXPI_E_INVALID, "q, p and f must be non-null arrays");
+    const int n = sys->n_sys;
+    bool packed = true;     // every system's arrays where the batch layout puts them
+    for (int k = 0; k < n; ++k) {
+        if (!q[k] || !p[k] || !f[k])
+            return fail(MIXPI_E_INVALID, "system %d: null state pointer", k);
+        const long long off = 3 * sys->sys_row0[k];
+        packed = packed && q[k] == q[0] + off && p[k] == p[0] + off && f[k] == f[0] + off;
+    }
+    if (packed) return mixpi_step(sys, nsteps, q[0], p[0], f[0], elog, stream);
+    if (nsteps <= 0) return fail(MIXPI_E_INVALID, "nsteps must be positive");
+    HIP_TRY(hipSetDevice(sys->device));
+    const size_t words = 3 * (size_t)sys->rows;
+    if (!sys->d_bstage) HIP_TRY(hipMalloc(&sys->d_bstage, 3 * words * sizeof(double)));
+    double *sq = sys->d_bstage, *sp = sq + words, *sf = sp + words;
+    hipStream_t st = (hipStream_t)stream;
+    auto move = [&](bool in) -> hipError_t {
+        for (int k = 0; k < n; ++k) {
+            const long long off = 3 * sys->sys_row0[k];
+            const size_t bytes = 3 * (size_t)(sys->sys_row0[k + 1] - sys->sys_row0[k]) * sizeof(double);
+            double *const mine[3] = {sq + off, sp + off, sf + off};
+            double *const theirs[3] = {q[k], p[k], f[k]};
+            for (int a = 0; a < 3; ++a) {
+                const hipError_t e =
+                    in ? hipMemcpyAsync(mine[a], theirs[a], bytes, hipMemcpyDeviceToDevice, st)
+                       : hipMemcpyAsync(theirs[a], mine[a], bytes, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    };
+    HIP_TRY(move(true));
+    if (int rc = mixpi_step(sys, nsteps, sq, sp, sf, elog, stream)) return rc;
+    HIP_TRY(move(false));
+    return MIXPI_OK;
 }
 
 int mixpi_set_thermostat(mixpi_system *sys, double tau0)

@@ -94,12 +94,14 @@ def load():
         "mixpi_destroy": ([P], C.c_int),
         "mixpi_sizes": ([P, P, P, P, P], C.c_int),
         "mixpi_bead_index": ([P, P], C.c_int),
+        "mixpi_layout": ([P, P, P], C.c_int),
         "mixpi_forces": ([P, P, P, P, P, P], C.c_int),
         "mixpi_forces_static": ([P, P, P, P, P, P], C.c_int),
         "mixpi_energy": ([P, P, P, P, P], C.c_int),
         "mixpi_energy_adjoint": ([P, P, P, P, P, P, P], C.c_int),
         "mixpi_nm_transform": ([P, I32, P, P, P], C.c_int),
         "mixpi_step": ([P, I32, P, P, P, P, P], C.c_int),
+        "mixpi_batch_step": ([P, I32, P, P, P, P, P], C.c_int),
         "mixpi_pair_candidates": ([P, P], C.c_int),
         "mixpi_pair_shape": ([P, P, P, P, P], C.c_int),
         "mixpi_pair_evals": ([P, P, I32, P], C.c_int),
@@ -225,6 +227,25 @@ def mixpi_nm_transform(h, direction: int, x_in, x_out, stream=None) -> None:
 def mixpi_step(h, nsteps: int, q, p, f, elog, stream=None) -> None:
     _check(load().mixpi_step(h, int(nsteps), _ptr(q), _ptr(p), _ptr(f), _ptr(elog),
                              _stream(stream)))
+
+
+def mixpi_batch_step(h, nsteps: int, qs, ps, fs, elog, stream=None) -> None:
+    """qs, ps, fs: one device array per system (its own rows)."""
+    n = len(qs)
+    if len(ps) != n or len(fs) != n:
+        raise ValueError("qs, ps and fs need one array per system")
+    arr = [(C.c_void_p * n)(*[x.data_ptr() for x in xs]) for xs in (qs, ps, fs)]
+    _check(load().mixpi_batch_step(h, int(nsteps), arr[0], arr[1], arr[2], _ptr(elog),
+                                   _stream(stream)))
+
+
+def mixpi_layout(h) -> np.ndarray:
+    """int64 [n_groups][5]: (first row, N, n, first particle, system) per group."""
+    ng = C.c_int32()
+    _check(load().mixpi_layout(h, None, C.byref(ng)))
+    out = np.zeros((ng.value, 5), dtype=np.int64)
+    _check(load().mixpi_layout(h, out.ctypes.data, C.byref(ng)))
+    return out
 
 
 def mixpi_pair_shape(h, n_systems: int) -> tuple:
@@ -388,6 +409,13 @@ class System:
 
     def step(self, nsteps: int, q, p, f, elog=None, stream=None):
         mixpi_step(self.h, nsteps, q, p, f, elog, stream)
+
+    def batch_step(self, nsteps: int, qs, ps, fs, elog=None, stream=None):
+        """mixpi_batch_step: one device array per system for q, p and f."""
+        mixpi_batch_step(self.h, nsteps, qs, ps, fs, elog, stream)
+
+    def layout(self) -> np.ndarray:
+        return mixpi_layout(self.h)
         return elog
 
     def pair_candidates(self) -> int:

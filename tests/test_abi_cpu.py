@@ -107,6 +107,8 @@ def test_null_handle_and_out(mp):
     assert lib.mixpi_set_ewald(None, 0.3, 5.0, 32, 6) == mp.MIXPI_E_INVALID
     assert lib.mixpi_ewald(None, None, None, None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_use_ewald(None, 1) == mp.MIXPI_E_INVALID
+    assert lib.mixpi_layout(None, None, None) == mp.MIXPI_E_INVALID
+    assert lib.mixpi_batch_step(None, 1, None, None, None, None, None) == mp.MIXPI_E_INVALID
     assert lib.mixpi_destroy(None) == mp.MIXPI_OK
     assert b"null" in lib.mixpi_last_error()
 

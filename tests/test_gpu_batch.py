@@ -208,3 +208,63 @@ def test_batch_mixed_widths_with_j_runs(mp, prec, waves, jrun, monkeypatch):
         Fo, eo = oracle.OracleSystem(s).forces(s.q)
         assert force_err(f[rows[k]], Fo) <= tol_f, k
         assert energy_err(e[k], eo) <= tol_e, k
+
+
+def test_layout_matches_bead_index(mp):
+    """mixpi_layout's groups reproduce every system's bead rows: bead a of
+    particle p of a group at first_row + a n + (p - first particle)."""
+    systems = mixed_batch()
+    b = mp.System(systems)
+    lay = b.layout()
+    assert lay.shape == (b.n_groups, 5)
+    nb = np.concatenate([np.asarray(s.n_beads) for s in systems])
+    sys_of = np.concatenate([np.full(len(s.n_beads), k) for k, s in enumerate(systems)])
+    first = np.concatenate([[0], np.cumsum(nb)[:-1]])
+    seen = np.zeros(b.rows, dtype=bool)
+    for row0, N, n, p0, k in lay:
+        assert np.all(nb[p0:p0 + n] == N) and np.all(sys_of[p0:p0 + n] == k)
+        for i in range(n):
+            got = b.bead_index[first[p0 + i]:first[p0 + i] + N]
+            assert np.array_equal(got, row0 + np.arange(N) * n + i)
+        seen[row0:row0 + N * n] = True
+    assert seen.all()
+    assert np.all(np.diff(lay[:, 0]) > 0)
+
+
+def test_batch_step_with_separate_arrays(mp):
+    """mixpi_batch_step with one device array per system equals mixpi_step
+    on the systems' rows back to back, bit for bit, both with separate
+    allocations (staged) and with views into one allocation (direct), over
+    two calls in a row."""
+    import torch
+    systems = mixed_batch()
+    b = mp.System(systems)
+    q, rows = pack(systems, [s.q for s in systems])
+    p, _ = pack(systems, [s.p for s in systems])
+    qd, pd = dev(q), dev(p)
+    fd, _ = b.forces(qd)
+    n_steps, ne = 3, mp.MIXPI_NE
+    el_ref = torch.zeros((2, n_steps, len(systems), ne), dtype=torch.float64, device="cuda")
+    q0, p0, f0 = qd.clone(), pd.clone(), fd.clone()
+    for c in range(2):
+        b.step(n_steps, qd, pd, fd, el_ref[c])
+    lens = [len(r) for r in rows]
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    # separate allocations: each system's rows in its own tensor
+    qs = [q0[offs[k]:offs[k + 1]].clone() for k in range(len(systems))]
+    ps = [p0[offs[k]:offs[k + 1]].clone() for k in range(len(systems))]
+    fs = [f0[offs[k]:offs[k + 1]].clone() for k in range(len(systems))]
+    el = torch.zeros_like(el_ref)
+    for c in range(2):
+        b.batch_step(n_steps, qs, ps, fs, el[c])
+    assert torch.equal(torch.cat(qs), qd) and torch.equal(torch.cat(ps), pd)
+    assert torch.equal(torch.cat(fs), fd) and torch.equal(el, el_ref)
+    # views into one allocation: the direct path
+    qv, pv, fv = q0.clone(), p0.clone(), f0.clone()
+    el2 = torch.zeros_like(el_ref)
+    for c in range(2):
+        b.batch_step(n_steps, [qv[offs[k]:offs[k + 1]] for k in range(len(systems))],
+                     [pv[offs[k]:offs[k + 1]] for k in range(len(systems))],
+                     [fv[offs[k]:offs[k + 1]] for k in range(len(systems))], el2[c])
+    assert torch.equal(qv, qd) and torch.equal(pv, pd) and torch.equal(fv, fd)
+    assert torch.equal(el2, el_ref)
