@@ -56,6 +56,22 @@ __device__ __forceinline__ double group_sum(double v)
 // Sum over the wave, in every lane.
 __device__ __forceinline__ double wsum(double v) { return group_sum<64>(v); }
 
+// A value equal in every lane, moved to scalar registers (the first active
+// lane's copy): frees vector registers and lets address arithmetic on it
+// run in scalar instructions.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v)
+{
+    const unsigned long long u = (unsigned long long)v;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v)
+{
+    return __longlong_as_double(uni(__double_as_longlong(v)));
+}
+
 // The wave's lane mask of b (bit l: lane l is active and has b set), a
 // wave-uniform value.  A mask of one compare is that compare's own result,
 // and masks combine with scalar instructions.

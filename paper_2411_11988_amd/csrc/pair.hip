@@ -593,8 +593,15 @@ void k_pair(PairLaunch a, BondedLaunch bl)
     }
     // the item and its block are independent loads (the block is copied per
     // item), so everything after them is one dependent step away
-    const PairItem it = a.items[blockIdx.x];
-    const PairBlock bk = a.iblocks[blockIdx.x];
+    PairItem it = a.items[blockIdx.x];
+    PairBlock bk = a.iblocks[blockIdx.x];
+    // both are the same in every lane: scalar registers
+    it = PairItem{uni(it.block), uni(it.b), uni(it.i0), uni(it.j0),
+                  uni(it.tj), uni(it.islot), uni(it.jslot), uni(it.nj)};
+    bk = PairBlock{uni(bk.sys), uni(bk.kind), uni(bk.same), uni(bk.shift), uni(bk.na),
+                   uni(bk.nb), uni(bk.pa0), uni(bk.pb0), uni(bk.rowa), uni(bk.rowb),
+                   uni(bk.w), uni(bk.nbeads_b), uni(bk.lj), uni(bk.sparse), uni(bk.lj_off),
+                   uni(bk.nt1), uni(bk.mol)};
     constexpr int TJM = TJ > 0 ? TJ : kMaxTj;
     __shared__ PairLds<R, TJM, WAVES, IW> L;
     if constexpr (TJ > 0) {
