@@ -426,6 +426,16 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
     S.theta0[3] = nt > 0 ? d->lj_sigma[0] : 1.0;
     S.theta0[4] = d->n_bond_types > 0 ? d->bond_k[0] : 0.0;
     S.theta0[5] = d->n_angle_types > 0 ? d->angle_k[0] : 0.0;
+    // the pair sweep's cutoff constants, formed once (launches that pass
+    // theta form the theta-dependent ones in the kernel)
+    S.irc = d->rc_coul > 0.0 ? 1.0 / d->rc_coul : 0.0;
+    S.irc3 = d->rc_coul > 0.0 ? 1.0 / (d->rc_coul * d->rc_coul * d->rc_coul) : 0.0;
+    {
+        const double u_c = d->rc_pp * d->rc_pp + d->pp_a * d->pp_a;
+        S.pp_phic = 1.0 / std::sqrt(u_c);
+        S.pp_psic = -1.0 / (u_c * std::sqrt(u_c));
+        S.pp_chic = 1.0 / (u_c * u_c * std::sqrt(u_c));
+    }
     const double V = d->box[0] * d->box[1] * d->box[2];
     S.bg_energy = d->background ? -kPi * kCoulombKcal * d->rc_coul * d->rc_coul * Q * Q / (5.0 * V)
                                 : 0.0;

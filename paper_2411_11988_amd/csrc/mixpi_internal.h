@@ -40,6 +40,9 @@ struct SysDev {
     double box[3], ibox[3];
     double rc_lj, rc_c, rc_pp;
     double theta0[6];     // pp_q, pp_a, eps_00, sigma_00, k_bond0, k_angle0
+    double irc, irc3;     // 1 / rc_c and 1 / rc_c^3 (0 when rc_c = 0)
+    // 1 / sqrt(u), -1 / u^(3/2), 1 / u^(5/2) at u = rc_pp^2 + pp_a^2 (theta0)
+    double pp_phic, pp_psic, pp_chic;
     double bg_energy;     // uniform-background constant (kcal/mol)
     double kT;            // kcal/mol
     double cv_const;      // sum_i 3/(2 beta)

@@ -136,12 +136,12 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     const int nt1 = bk.nt1;
     const double rc_lj = S.rc_lj, rc_c = S.rc_c;
     if (bk.kind == PK_ATOM) {
-        // the system's table, built at create time; the pair (0, 0) takes
-        // its eps and sigma from theta
+        // the system's table, built at create time; with theta passed, the
+        // pair (0, 0) takes its eps and sigma from it
         const LjPar *tab = a.ljpar + bk.lj_off;
         for (int tp = lane; tp < nt1 * nt1; tp += 64) {
             LjPar lp;
-            if (tp == 0) {
+            if (tp == 0 && a.theta) {
                 const double eps = th[2], sig = th[3];
                 const double s2 = sig * sig;
                 double c6 = s2 / (rc_lj * rc_lj);
@@ -206,7 +206,8 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     double xi = 0, yi = 0, zi = 0, qi = 0;
     int ti = 0, mi = -1;
     if (vi) {
-        const int pi = bk.pa0 + (int)(idx % bk.na);
+        // idx < na N_a: a 32-bit remainder
+        const int pi = bk.pa0 + (int)((unsigned)idx % (unsigned)bk.na);
         xi = a.q[3 * rowi];
         yi = a.q[3 * rowi + 1];
         zi = a.q[3 * rowi + 2];
@@ -283,8 +284,7 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         const double rc2max = fmax(rc2_lj, rc2_c);
         // rc_c = 0 (no bead-resolved Coulomb): finite stand-ins, every
         // Coulomb term is masked by r^2 < 0
-        const double irc = rc_c > 0.0 ? 1.0 / rc_c : 0.0;
-        const double irc3 = rc_c > 0.0 ? 1.0 / (rc_c * rc_c * rc_c) : 0.0;
+        const double irc = S.irc, irc3 = S.irc3;
         const double hc = 0.5 * irc3;
         const double vc0 = irc + rc2_c * hc;   // Coulomb term: K (1/r + r^2 hc - vc0)
         const double kqi = kCoulombKcal * qi;
@@ -419,10 +419,13 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         // in R; the theta partials (adjoint launches only) in FP64
         const double rc = S.rc_pp, rc2 = rc * rc;
         const double pa = th[1], a2 = pa * pa, pq = th[0];
-        const double u_c = rc2 + a2;
-        const double phicd = 1.0 / sqrt(u_c);
-        const double psicd = -1.0 / (u_c * sqrt(u_c));
-        const double chicd = 1.0 / (u_c * u_c * sqrt(u_c));
+        double phicd = S.pp_phic, psicd = S.pp_psic, chicd = S.pp_chic;
+        if (a.theta) {
+            const double u_c = rc2 + a2;
+            phicd = 1.0 / sqrt(u_c);
+            psicd = -1.0 / (u_c * sqrt(u_c));
+            chicd = 1.0 / (u_c * u_c * sqrt(u_c));
+        }
         const R phic = (R)phicd, psic = (R)psicd, hpsic = (R)(0.5 * psicd);
         const R ra2 = (R)a2, rrc2 = (R)rc2;
         const double kqid = kCoulombKcal * qi;
