@@ -493,7 +493,11 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
             else run([&] { sweep_e(std::false_type{}, std::false_type{}); });
         }
     }
-    double e0 = wsum(e0r), e1 = wsum(e1r), g0 = 0.0, g1 = 0.0;
+    // e0: LJ (atom blocks with LJ) or pseudopotential; e1: Coulomb (atom
+    // blocks); a sum that the block cannot have is an exact 0
+    double e0 = (bk.kind != PK_ATOM || bk.lj) ? wsum(e0r) : 0.0;
+    double e1 = bk.kind == PK_ATOM ? wsum(e1r) : 0.0;
+    double g0 = 0.0, g1 = 0.0;
 
     if (THETA) {
         g0 = wsum(g0r);
