@@ -1769,6 +1769,8 @@ FinishLaunch finish_args(mixpi_system *s, const double *q, double *p, double *f,
     fl.blocks = s->d_fblocks;
     fl.rpw = s->fin_rpw;
     fl.n_blocks = s->n_fblocks;
+    fl.uniform = s->n_sys == 1 ? 1 : 0;
+    fl.rows = s->rows;
     fl.gather = gather_args(s);
     fl.row_fm = s->d_row_fm;
     fl.row_hk = s->d_row_hk;

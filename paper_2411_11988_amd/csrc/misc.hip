@@ -112,9 +112,15 @@ __global__ __launch_bounds__(256) void k_finish(FinishLaunch a)
         reduce_b_part(a.reduce, blockIdx.x - a.n_blocks, racc);
         return;
     }
-    const BlockRange br = a.blocks[blockIdx.x];
     // RPW rows per wave: row w * RPW + lane / LPR of the block, lane sl of it
     constexpr int LPR = 64 / RPW;
+    BlockRange br;
+    if (a.uniform) {
+        const long long b0 = (long long)blockIdx.x * (4 * RPW);
+        br = BlockRange{0, (int)b0, (int)min((long long)(4 * RPW), a.rows - b0), 0};
+    } else {
+        br = a.blocks[blockIdx.x];
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = lane % LPR, ri = w * RPW + lane / LPR;
     double ke = 0.0, vir = 0.0, esp = 0.0;

@@ -262,6 +262,10 @@ struct GatherArgs {
 struct FinishLaunch {
     const BlockRange *blocks;  // one per workgroup: 4 rpw bead rows of one system
     int n_blocks;
+    // one system: block b is rows [b * 4 rpw, (b + 1) * 4 rpw) of `rows`,
+    // formed from the workgroup index (blocks unread)
+    int uniform;
+    long long rows;
     int rpw;                   // bead rows per wave: 1, 2 or 4
     GatherArgs gather;
     const double *row_fm;      // [rows] fictitious mass of the bead row
