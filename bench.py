@@ -55,10 +55,10 @@ KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/cs
 # --pmc (SQ_INSTS_VALU and the FP32/FP64 add/mul/fma/transcendental
 # instruction counters, 64 lanes each, FMA = 2): executed FLOP including the
 # masked-off math of out-of-cutoff candidates; same source-hash condition.
-VALU = {"insts_valu": 2907205, "flop_executed": 155743254}
+VALU = {"insts_valu": 2716407, "flop_executed": 145581526}
 TRAFFIC = {"workload": "c3", "tile": "16xw1",
-           "sha256": "ed44a24acd6870311db3ad6361c7dbb10cfd6f6f3bb2669e27723f953e067d50",
-           "bytes": (1484.57 * 2.0 + 10886.55 * 1.0) * 1024}
+           "sha256": "fd3649a27d1635369207a5005eda8e8cf5995708fb5af84a519a4d70bce6a760",
+           "bytes": (1473.07 * 2.0 + 10882.04 * 1.0) * 1024}
 
 
 def _kernel_sha():
