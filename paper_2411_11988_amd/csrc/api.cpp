@@ -573,6 +573,21 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                     for (int x = 0; x < Bg.n; ++x) pb.mol |= ma.count(d->mol_id[Bg.p0 + x]) > 0;
                 }
             }
+            {
+                // electron (i) - atom (j) blocks in a box large against the
+                // pseudopotential cutoff cull the j-atoms out of reach of a
+                // tile's beads: a sphere of r_c + 3 A (the cutoff plus a
+                // typical extent of 64 to 128 beads of an electron) under
+                // 0.6 of the box volume; MIXPI_PAIR_CULL = 0 or 1 turns it
+                // off or on for every such block
+                const double rr = d->rc_pp + 3.0;
+                const double vbox = d->box[0] * d->box[1] * d->box[2];
+                pb.cull = pb.kind == PK_E_ATOM && 4.18879 * rr * rr * rr < 0.6 * vbox;
+                if (const char *env = getenv("MIXPI_PAIR_CULL")) {
+                    const int v = atoi(env);
+                    if (v == 0 || v == 1) pb.cull = pb.kind == PK_E_ATOM && v == 1;
+                }
+            }
             B.blocks.push_back(pb);
             const long long pairs = pb.same ? (long long)A.n * (A.n - 1) / 2 : (long long)A.n * Bg.n;
             B.candidates += pairs * A.N;

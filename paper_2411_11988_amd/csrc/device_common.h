@@ -56,6 +56,20 @@ __device__ __forceinline__ double group_sum(double v)
 // Sum over the wave, in every lane.
 __device__ __forceinline__ double wsum(double v) { return group_sum<64>(v); }
 
+// Largest v over the wave, in every lane (the steps of group_sum<64> with
+// max; rows that a broadcast step leaves out receive 0 there, but their
+// values do not reach lane 63, whose result every lane reads).
+__device__ __forceinline__ double wmax(double v)
+{
+    v = fmax(v, dpp_d<0xB1, 0xF>(v));
+    v = fmax(v, dpp_d<0x4E, 0xF>(v));
+    v = fmax(v, dpp_d<0x124, 0xF>(v));
+    v = fmax(v, dpp_d<0x128, 0xF>(v));
+    v = fmax(v, dpp_d<0x142, 0xA>(v));
+    v = fmax(v, dpp_d<0x143, 0xC>(v));
+    return readlane_d(v, 63);
+}
+
 // A value equal in every lane, moved to scalar registers (the first active
 // lane's copy): frees vector registers and lets address arithmetic on it
 // run in scalar instructions.

@@ -69,6 +69,7 @@ struct PairBlock {
     int sparse;           // atom block swept in compacted form (few in-cutoff candidates)
     int lj_off, nt1;      // the system's LJ table offset and LJ types + 1
     int mol;              // some pair of the two groups may share a molecule id
+    int cull;             // electron-atom block whose tiles cull unreachable j-atoms
 };
 
 // LJ parameters of one type pair in the form the pair sweep uses: 4 eps,

@@ -93,6 +93,8 @@ template <typename R, int TJM, int WAVES, int IW> struct PairLds {
     LjPar tlj[kLjTab];
     double xs[WAVES > 1 ? WAVES : 1][3][WAVES > 1 ? 64 : 1];   // i-forces handed to wave 0
     double es[WAVES > IW ? WAVES : IW][5];                      // the waves' sums
+    double cbox[IW][6];   // culled tiles: each i-split wave's bead box
+    int ncomp;            // culled tiles: slots the sweep visits
 };
 
 // Element at byte offset off of an LDS array.
@@ -158,45 +160,111 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         }
     }
 
+    // Culled tiles (electron-atom blocks in boxes large against the
+    // cutoff, one j-wave): the j-atoms that no i-bead of the item can reach
+    // are left out of the sweep.  The item's i-beads lie in a box [lo, hi]
+    // of minimum-image offsets from its first bead; a j-atom whose periodic
+    // gap to that box is at least r_c (plus 1e-6 A against rounding) has
+    // every pair distance at least r_c (triangle inequality of the
+    // minimum-image distance), so all its terms would be masked.  The kept
+    // atoms are staged first (in staging order), padded to a multiple of 4.
+    // Only tiles of several i-split waves cull (their 128 or 256 beads
+    // amortise the box; the one-wave kernels stay within their registers).
+    constexpr bool CULLABLE = WAVES == 1 && IW > 1;
+    const bool cull = CULLABLE && bk.cull != 0;
+    double rx = 0, ry = 0, rz = 0, lox = 0, loy = 0, loz = 0, hix = 0, hiy = 0, hiz = 0;
+    const double rcut = S.rc_pp + 1e-6, rcut2 = rcut * rcut;
+    int jslot = -1;      // staging lane: its slot in the staged tile (-1: culled)
+
     // j-tile kj of the run: bead b of group b, particles j0 .. j0 + jn;
     // padding slots get harmless values and are masked out
-    auto stage = [&](int kj) {
+    struct JLoad {
+        double x, y, z, qd;
+        JMol jm;
+        JTyp jt;
+    };
+    auto stage_load = [&](int kj) {
+        JLoad v{0.0, 0.0, 0.0, 0.0, JMol{-1, -1}, JTyp{0, 0.0f}};
         const int j0 = it.j0 + kj * TJ, jn = min(TJ, bk.nb - j0);
-        if ((int)threadIdx.x >= TJ) return;
         const int js = threadIdx.x;
-        dj = a.dest[sj + kj * TJ + js];
-        double x = 0, y = 0, z = 0, qd = 0;
-        JMol jm{-1, -1};
-        JTyp jt{0, 0.0f};
+        if (js < TJ) dj = a.dest[sj + kj * TJ + js];
         if (js < jn) {
             const int j = j0 + js;
             const long long rowj = bk.rowb + (long long)it.b * bk.nb + j;
             const int pj = bk.pb0 + j;
-            x = a.q[3 * rowj];
-            y = a.q[3 * rowj + 1];
-            z = a.q[3 * rowj + 2];
+            v.x = a.q[3 * rowj];
+            v.y = a.q[3 * rowj + 1];
+            v.z = a.q[3 * rowj + 2];
             // electron-atom blocks with the electron as i take k_e q_j as
             // their pseudopotential constant: scaled here, once per tile
             const double qc = a.charge[pj];
-            qd = bk.kind == PK_E_ATOM ? kCoulombKcal * qc : qc;
-            jm.mol = a.mol[pj];
-            jm.jg = j;
-            jt.jt = a.ljt[pj] * (int)sizeof(LjPar);
-            jt.kq = (float)(th[0] * qd);
+            v.qd = bk.kind == PK_E_ATOM ? kCoulombKcal * qc : qc;
+            v.jm.mol = a.mol[pj];
+            v.jm.jg = j;
+            v.jt.jt = a.ljt[pj] * (int)sizeof(LjPar);
+            v.jt.kq = (float)(th[0] * v.qd);
         }
-        sjx[js] = x;
-        sjy[js] = y;
-        sjz[js] = z;
-        sjq[js] = qd;
-        sjm[js] = jm;
-        sjt[js] = jt;
-        for (int v = 0; v < IW; ++v) {
-            L.fjx[v][js] = 0.0;
-            L.fjy[v][js] = 0.0;
-            L.fjz[v][js] = 0.0;
-        }
+        return v;
     };
-    stage(0);
+    auto put = [&](int slot, const JLoad &v) {
+        sjx[slot] = v.x;
+        sjy[slot] = v.y;
+        sjz[slot] = v.z;
+        sjq[slot] = v.qd;
+        sjm[slot] = v.jm;
+        sjt[slot] = v.jt;
+    };
+    // periodic gap along one axis from offset d to the interval [lo, hi]
+    // (offsets within half a box of the reference)
+    auto gap = [](double d, double lo, double hi, double L) {
+        double g = fmax(0.0, fmax(lo - d, d - hi));
+        g = fmin(g, fmax(0.0, fmax(lo - (d + L), (d + L) - hi)));
+        return fmin(g, fmax(0.0, fmax(lo - (d - L), (d - L) - hi)));
+    };
+    auto stage_write = [&](int kj, const JLoad &v) {
+        const int js = threadIdx.x;
+        if (js >= TJ) return;
+        if (!cull) {
+            jslot = js;
+            put(js, v);
+            for (int u = 0; u < IW; ++u) {
+                L.fjx[u][js] = 0.0;
+                L.fjy[u][js] = 0.0;
+                L.fjz[u][js] = 0.0;
+            }
+            return;
+        }
+        const int jn = min(TJ, bk.nb - (it.j0 + kj * TJ));
+        bool keep = false;
+        if (js < jn) {
+            double dx = v.x - rx, dy = v.y - ry, dz = v.z - rz;
+            dx -= S.box[0] * rint(dx * S.ibox[0]);
+            dy -= S.box[1] * rint(dy * S.ibox[1]);
+            dz -= S.box[2] * rint(dz * S.ibox[2]);
+            const double gx = gap(dx, lox, hix, S.box[0]);
+            const double gy = gap(dy, loy, hiy, S.box[1]);
+            const double gz = gap(dz, loz, hiz, S.box[2]);
+            keep = gx * gx + gy * gy + gz * gz < rcut2;
+        }
+        // the staging lanes are the first TJ lanes of wave 0
+        const unsigned long long km = lanes(keep);
+        const int n = __builtin_popcountll(km);
+        const int n4 = (n + 3) & ~3;
+        jslot = keep ? (int)__builtin_amdgcn_mbcnt_hi((unsigned)(km >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u))
+                     : -1;
+        if (keep) put(jslot, v);
+        if (js >= n && js < n4) put(js, JLoad{0.0, 0.0, 0.0, 0.0, JMol{-1, -1}, JTyp{0, 0.0f}});
+        if (js < n4) {
+            for (int u = 0; u < IW; ++u) {
+                L.fjx[u][js] = 0.0;
+                L.fjy[u][js] = 0.0;
+                L.fjz[u][js] = 0.0;
+            }
+        }
+        if (js == 0) L.ncomp = n4;
+    };
+    JLoad jv0 = stage_load(0);
 
     // i bead
     const long long li = (long long)bk.na << bk.shift;
@@ -215,6 +283,45 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         ti = a.ljt[pi];
         mi = a.mol[pi];
     }
+    if (cull) {
+        // the item's first i-bead is the reference; the box of the offsets
+        // of every wave's beads
+        const long long row0 = bk.rowa + ((long long)it.b << bk.shift) * bk.na + it.i0;
+        rx = a.q[3 * row0];
+        ry = a.q[3 * row0 + 1];
+        rz = a.q[3 * row0 + 2];
+        double dx = xi - rx, dy = yi - ry, dz = zi - rz;
+        dx -= S.box[0] * rint(dx * S.ibox[0]);
+        dy -= S.box[1] * rint(dy * S.ibox[1]);
+        dz -= S.box[2] * rint(dz * S.ibox[2]);
+        constexpr double kBig = 1e300;
+        hix = wmax(vi ? dx : -kBig);
+        hiy = wmax(vi ? dy : -kBig);
+        hiz = wmax(vi ? dz : -kBig);
+        lox = -wmax(vi ? -dx : -kBig);
+        loy = -wmax(vi ? -dy : -kBig);
+        loz = -wmax(vi ? -dz : -kBig);
+        if constexpr (IW > 1) {
+            if (lane == 0) {
+                L.cbox[iw][0] = lox;
+                L.cbox[iw][1] = loy;
+                L.cbox[iw][2] = loz;
+                L.cbox[iw][3] = hix;
+                L.cbox[iw][4] = hiy;
+                L.cbox[iw][5] = hiz;
+            }
+            __syncthreads();
+            for (int u = 0; u < IW; ++u) {
+                lox = fmin(lox, L.cbox[u][0]);
+                loy = fmin(loy, L.cbox[u][1]);
+                loz = fmin(loz, L.cbox[u][2]);
+                hix = fmax(hix, L.cbox[u][3]);
+                hiy = fmax(hiy, L.cbox[u][4]);
+                hiz = fmax(hiz, L.cbox[u][5]);
+            }
+        }
+    }
+    stage_write(0, jv0);
     __syncthreads();
 
     const double Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
@@ -250,21 +357,28 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
     auto run = [&](auto &&sweep_tile) {
         for (int kj = 0; kj < nj; ++kj) {
             if (kj > 0) {
+                const JLoad jv = stage_load(kj);
                 __syncthreads();      // the previous tile's reactions are stored
-                stage(kj);
+                stage_write(kj, jv);
                 __syncthreads();
             }
             sweep_tile();
             __syncthreads();          // every wave's reactions are in
             const int jn = min(TJ, bk.nb - (it.j0 + kj * TJ));
             if ((int)threadIdx.x < jn) {
+                // a culled atom's reaction is an exact 0
                 double *o = a.part + 3LL * dj;
-                const int t = threadIdx.x;
-                double sx = L.fjx[0][t], sy = L.fjy[0][t], sz = L.fjz[0][t];
-                for (int v = 1; v < IW; ++v) {
-                    sx += L.fjx[v][t];
-                    sy += L.fjy[v][t];
-                    sz += L.fjz[v][t];
+                const int t = jslot;
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+                if (t >= 0) {
+                    sx = L.fjx[0][t];
+                    sy = L.fjy[0][t];
+                    sz = L.fjz[0][t];
+                    for (int v = 1; v < IW; ++v) {
+                        sx += L.fjx[v][t];
+                        sy += L.fjy[v][t];
+                        sz += L.fjz[v][t];
+                    }
                 }
                 o[0] = w * sx;
                 o[1] = w * sy;
@@ -436,13 +550,14 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
         // i atom's
         // MOL: some pair of the block may share a molecule id (else the
         // compare is left out; it would always pass)
-        auto sweep_e = [&](auto e_tag, auto mol_tag) {
+        // CULL: the staged tile holds L.ncomp slots (a multiple of 4; the
+        // kept atoms, then padding); lane l sweeps them from slot l mod
+        // ncomp on, wrapping around
+        auto sweep_e = [&](auto e_tag, auto mol_tag, auto cull_tag) {
             constexpr bool E_IS_I = decltype(e_tag)::value;
             constexpr bool MOL = decltype(mol_tag)::value;
-            const int b8 = opaque(base8);
-#pragma unroll 4
-            for (int t = 0; t < TJ / WAVES; ++t) {
-                const int o = b8 ^ (8 * t);
+            constexpr bool CULL = decltype(cull_tag)::value;
+            auto step = [&](int o) {
                 const JSlot<R> jr = jload(o);
                 double dx = xi - jr.x, dy = yi - jr.y, dz = zi - jr.z;
                 dx -= Lx * rint(dx * iLx);
@@ -483,14 +598,39 @@ __device__ __forceinline__ void pair_tile(const PairLaunch &a, const PairItem &i
                 atomicAdd(&at(fjx, o), ngd * dx);
                 atomicAdd(&at(fjy, o), ngd * dy);
                 atomicAdd(&at(fjz, o), ngd * dz);
+            };
+            if constexpr (CULL) {
+                const int nc = uni(L.ncomp);
+                if (nc == 0) return;
+                int s = (int)((unsigned)lane % (unsigned)nc);
+                for (int t = 0; t < nc; t += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        step(s * 8);
+                        s = s + 1 == nc ? 0 : s + 1;
+                    }
+                }
+            } else {
+                const int b8 = opaque(base8);
+#pragma unroll 4
+                for (int t = 0; t < TJ / WAVES; ++t) step(b8 ^ (8 * t));
             }
         };
+        using T1 = std::true_type;
+        using F0 = std::false_type;
         if (bk.kind == PK_E_ATOM) {
-            if (bk.mol) run([&] { sweep_e(std::true_type{}, std::true_type{}); });
-            else run([&] { sweep_e(std::true_type{}, std::false_type{}); });
+            if (cull) {
+                if constexpr (CULLABLE) {
+                    if (bk.mol) run([&] { sweep_e(T1{}, T1{}, T1{}); });
+                    else run([&] { sweep_e(T1{}, F0{}, T1{}); });
+                }
+            } else {
+                if (bk.mol) run([&] { sweep_e(T1{}, T1{}, F0{}); });
+                else run([&] { sweep_e(T1{}, F0{}, F0{}); });
+            }
         } else {
-            if (bk.mol) run([&] { sweep_e(std::false_type{}, std::true_type{}); });
-            else run([&] { sweep_e(std::false_type{}, std::false_type{}); });
+            if (bk.mol) run([&] { sweep_e(F0{}, T1{}, F0{}); });
+            else run([&] { sweep_e(F0{}, F0{}, F0{}); });
         }
     }
     // e0: LJ (atom blocks with LJ) or pseudopotential; e1: Coulomb (atom
@@ -608,7 +748,7 @@ void k_pair(PairLaunch a, BondedLaunch bl)
     bk = PairBlock{uni(bk.sys), uni(bk.kind), uni(bk.same), uni(bk.shift), uni(bk.na),
                    uni(bk.nb), uni(bk.pa0), uni(bk.pb0), uni(bk.rowa), uni(bk.rowb),
                    uni(bk.w), uni(bk.nbeads_b), uni(bk.lj), uni(bk.sparse), uni(bk.lj_off),
-                   uni(bk.nt1), uni(bk.mol)};
+                   uni(bk.nt1), uni(bk.mol), uni(bk.cull)};
     constexpr int TJM = TJ > 0 ? TJ : kMaxTj;
     __shared__ PairLds<R, TJM, WAVES, IW> L;
     if constexpr (TJ > 0) {

@@ -364,6 +364,41 @@ def test_pair_j_runs(mp, tj, waves, jrun, monkeypatch):
             assert np.array_equal(host(f), host(f2))
 
 
+@pytest.mark.parametrize("tj,waves,jrun", [(16, "i2", 1), (64, "i2", 4), (32, "i4", 2)])
+def test_pair_culled_electron_tiles(mp, tj, waves, jrun, monkeypatch):
+    """Electron-atom tiles of i-split waves that leave out the j-atoms out of
+    reach of their beads (forced on; a box large against the cutoff, so
+    most tiles cull some atoms and some cull all): forces, energies and
+    in-cutoff pair counts against the oracle, the same bits from a repeated
+    call, and the forces of the uncull sweep to rounding."""
+    _set_shape(monkeypatch, tj, waves)
+    monkeypatch.setenv("MIXPI_PAIR_JRUN", str(jrun))
+    for name, s in (("e256-w300", synth.solvated_electron(300, 256, 21.0, seed=7, rc_pp=6.0,
+                                                           rc_aa=6.0)),
+                    ("e64-w120-h2", synth.solvated_electron(120, 64, 15.4, seed=8, rc_pp=4.5,
+                                                             rc_aa=5.0, n_h=2, n_o=1))):
+        o = oracle.OracleSystem(s)
+        Fo, eo = o.forces(s.q)
+        for prec in (FP64, FP32):
+            print(f"[cull] tj={tj} waves={waves} jrun={jrun} {name} prec={prec}", flush=True)
+            q = dev(to_rows(s, s.q))
+            out = []
+            for cull in ("1", "0"):
+                monkeypatch.setenv("MIXPI_PAIR_CULL", cull)
+                sysm = mp.System(s, precision=prec)
+                sysm.pair_evals(reset=True)
+                f, e = sysm.forces(q)
+                F = from_rows(s, host(f))
+                assert force_err(F, Fo) <= TOL_F[prec], (cull, force_err(F, Fo))
+                assert energy_err(host(e)[0], eo) <= TOL_E[prec], cull
+                assert sysm.pair_evals() == o.pair_evals(s.q), cull
+                f2, _ = sysm.forces(q)
+                assert np.array_equal(host(f), host(f2)), cull
+                out.append(F)
+                del sysm
+            assert force_err(out[0], out[1]) <= (1e-13 if prec == FP64 else 1e-6)
+
+
 @pytest.mark.parametrize("tj,waves", [(32, "w1"), (32, "w2"), (64, "w1"), (64, "w2"), (64, "i4")])
 def test_pair_compacted_sweep(mp, tj, waves, monkeypatch):
     """The compacted atom-atom sweep (a distance pass marks each lane's
