@@ -55,10 +55,10 @@ KERNEL_SOURCES = ("paper_2411_11988_amd/csrc/pair.hip", "paper_2411_11988_amd/cs
 # --pmc (SQ_INSTS_VALU and the FP32/FP64 add/mul/fma/transcendental
 # instruction counters, 64 lanes each, FMA = 2): executed FLOP including the
 # masked-off math of out-of-cutoff candidates; same source-hash condition.
-VALU = {"insts_valu": 2716407, "flop_executed": 145581526}
+VALU = {"insts_valu": 2735846, "flop_executed": 145581526}
 TRAFFIC = {"workload": "c3", "tile": "16xw1",
-           "sha256": "fd3649a27d1635369207a5005eda8e8cf5995708fb5af84a519a4d70bce6a760",
-           "bytes": (1473.07 * 2.0 + 10882.04 * 1.0) * 1024}
+           "sha256": "5d4d5abf13605b5d4dbccc336afb924da8a35d3db5a473980d866f468fe38e89",
+           "bytes": (1491.95 * 2.0 + 10880.76 * 1.0) * 1024}
 
 
 def _kernel_sha():

@@ -89,6 +89,37 @@ def test_theta_override_matches_oracle(mp, name, s):
     assert theta_err(host(dth)[0], o.dvdtheta(s.q)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_adjoint_with_culled_tiles(mp, prec, monkeypatch):
+    """dV/dq and dV/dtheta, and forces at a theta override, with electron-
+    atom tiles that leave out the atoms out of reach of their beads (forced
+    on; 128 x 64 tiles in a box large against the cutoff), against the
+    oracle."""
+    for k, v in (("MIXPI_PAIR_TJ", "64"), ("MIXPI_PAIR_WAVES", "1"), ("MIXPI_PAIR_IW", "2"),
+                 ("MIXPI_PAIR_CULL", "1")):
+        monkeypatch.setenv(k, v)
+    s = synth.solvated_electron(300, 256, 21.0, seed=7, rc_pp=6.0, rc_aa=6.0)
+    sysm = mp.System(s, precision=prec)
+    assert sysm.pair_shape()[1:3] == (1, 2)
+    rows = layout_rows(s)
+    q = dev(to_rows(s, s.q, rows))
+    dq, dth = sysm.energy_adjoint(q)
+    o = oracle.OracleSystem(s)
+    Fo, _ = o.forces(s.q)
+    assert force_err(-from_rows(s, host(dq), rows), Fo) <= TOL_F[prec]
+    assert theta_err(host(dth)[0], o.dvdtheta(s.q)) <= TOL_TH[prec]
+    if prec == FP64:
+        th = default_theta(s) * np.array([1.1, 0.9, 1.2, 1.05, 0.8, 1.3])
+        thd = dev(th.reshape(1, 6))
+        f, e = sysm.forces(q, theta=thd)
+        ot = oracle.OracleSystem(s, theta=th)
+        Fo, eo = ot.forces(s.q)
+        assert force_err(from_rows(s, host(f), rows), Fo) <= 1e-12
+        assert energy_err(host(e)[0], eo) <= 1e-12
+        _, dth = sysm.energy_adjoint(q, theta=thd)
+        assert theta_err(host(dth)[0], ot.dvdtheta(s.q)) <= 1e-12
+
+
 def test_adjoint_scales_with_upstream_gradient(mp):
     import torch
     s = SYSTEMS[1][1]
