@@ -448,7 +448,7 @@ def _culled_candidates(s, q, shape):
         nb = np.asarray(x.n_beads)
         ele = np.asarray(x.is_electron)
         L = np.asarray(x.box, dtype=np.float64)
-        big = 4.18879 * (x.rc_pp + 3.0) ** 3 < 0.6 * float(np.prod(L))
+        big = 4.0 / 3.0 * np.pi * (x.rc_pp + 3.0) ** 3 < 0.6 * float(np.prod(L))
         if not (big or env == "1") or ele.sum() != 1 or ele[0] != 1 or np.any(nb[1:] != 1):
             continue
         P, tj = int(nb[0]), int(tjs[k])

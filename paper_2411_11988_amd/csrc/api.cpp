@@ -582,7 +582,7 @@ void add_system(Build &B, const mixpi_system_desc *d, int s)
                 // off or on for every such block
                 const double rr = d->rc_pp + 3.0;
                 const double vbox = d->box[0] * d->box[1] * d->box[2];
-                pb.cull = pb.kind == PK_E_ATOM && 4.18879 * rr * rr * rr < 0.6 * vbox;
+                pb.cull = pb.kind == PK_E_ATOM && 4.0 / 3.0 * kPi * rr * rr * rr < 0.6 * vbox;
                 if (const char *env = getenv("MIXPI_PAIR_CULL")) {
                     const int v = atoi(env);
                     if (v == 0 || v == 1) pb.cull = pb.kind == PK_E_ATOM && v == 1;

@@ -13,15 +13,18 @@
 // With WAVES = 2 (IW = 1) two waves share a 64-bead i-tile, each taking half
 // of the j-beads (more, shorter waves when a launch has few tiles per
 // SIMD), and hand their i-forces to wave 0 at the end.  With IW = 2 or 4
-// each of IW waves takes its own 64 i-beads against all TJ j-beads, and the
-// j-reactions of all of them meet in one LDS accumulator (one j-partial per
-// IW i-tiles: fewer partial-force slots for large launches).  Lane l visits j-slot
-// (l + t) mod TJ at step t, so the lanes spread over distinct j-beads and
-// the Newton-3 reaction goes to a per-j LDS accumulator with a return-less
-// LDS atomic add; i-forces stay in registers.  The loop body has no
-// branches: cutoff, exclusion and padding are select masks, so consecutive
-// steps overlap.  Each tile stores its i- and j-partial forces into slots of
-// its own; a per-row gather in a fixed order sums them (no global atomics).
+// each of IW waves takes its own 64 i-beads against all TJ j-beads; each
+// wave adds its j-reactions to its own LDS accumulator and the store sums
+// them in wave order (one j-partial per IW i-tiles: fewer partial-force
+// slots for large launches).  Lane l visits j-slot (l mod W) XOR t at step
+// t, so the lanes spread over distinct j-beads and the Newton-3 reaction
+// goes to a per-j LDS accumulator with a return-less LDS atomic add;
+// i-forces stay in registers.  The loop body has no branches: cutoff,
+// exclusion and padding are multiplicative masks, so consecutive steps
+// overlap.  Electron-atom tiles of i-split waves in large boxes leave out
+// the atoms no bead of the tile can reach (a box bound; see pair_tile).
+// Each tile stores its i- and j-partial forces into slots of its own; a
+// per-row gather in a fixed order sums them (no global atomics).
 //
 // Precision: separations and the nearest-image shift are FP64 (positions
 // sit up to a box length from the origin).  The electron-atom
