@@ -440,7 +440,7 @@ __device__ void rp_circ(const RpLaunch &a, const RpItem &it, double *smem, doubl
     // this thread's beads lie in one pad segment: pad(j) = j + jg
     const double *qrow = sq + jb + jg;
     int dn = (i0 - jb - 1) & (N - 1);            // next coefficient index
-#pragma unroll 4
+#pragma unroll 8
     for (int t = 0; t < seg; ++t) {
         const double qj = qrow[t], pj = qrow[t + CS];
         const int x = dn + (dn >> lpad);
