@@ -752,17 +752,33 @@ unsigned rp_item_lds(const RpItem &it, int op = OP_STEP, int precision = 0)
 // Rings propagated in bead space (circulant items): the cheapest first,
 // while the total multiply-adds stay within a budget of about two waves of
 // items over the chip, where they beat one FFT workgroup per column in
-// latency.  A ring needs N <= kCircMaxN.
+// latency.  A ring needs N <= kCircMaxN.  Only handles with few ring
+// columns (at most kCircMaxCols over all their rings) use them: with many
+// columns the FFT workgroups already fill the chip, and the circulant
+// items only add work beside them (measured on the 64-system batch: ring
+// launch 30.1 us with circulant items for its smaller rings, 23.9 us with
+// FFT items only; one 1024-bead ring: 6.4 against 11.4 us).
+// MIXPI_RING_CIRC = 0 or 1 turns them off, or on whatever the column count.
+constexpr int kCircMaxCols = 24;
 std::vector<char> choose_circulant(const std::vector<RpItem> &rings)
 {
     std::vector<char> use(rings.size(), 0);
-    if (const char *env = getenv("MIXPI_RING_CIRC"))
-        if (atoi(env) == 0) return use;
+    int force = -1;
+    if (const char *env = getenv("MIXPI_RING_CIRC")) force = atoi(env);
+    if (force == 0) return use;
+    long long cols = 0;
+    for (const RpItem &rg : rings) cols += 3LL * rg.n;
+    if (force != 1 && cols > kCircMaxCols) return use;
     std::vector<size_t> order(rings.size());
     for (size_t r = 0; r < rings.size(); ++r) order[r] = r;
     auto cost = [&](size_t r) { return 12.0 * rings[r].n * (double)rings[r].N * rings[r].N; };
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) < cost(y); });
-    const double budget = 32.0 * 1024 * 1024;
+    // MIXPI_RING_CIRC_MMAC: the budget in millions of multiply-adds
+    double budget = 32.0 * 1024 * 1024;
+    if (const char *env = getenv("MIXPI_RING_CIRC_MMAC")) {
+        const double v = atof(env);
+        if (v >= 0.0) budget = v * 1024 * 1024;
+    }
     double used = 0.0;
     for (size_t r : order) {
         if (rings[r].N > kCircMaxN) continue;
