@@ -278,7 +278,9 @@ int mixpi_step(mixpi_system *sys, int32_t nsteps, double *q, double *p, double *
  * arrays per system: q[k], p[k], f[k] are device double [rows_k][3] of
  * system k in its own layout (the rows a handle of that system alone
  * would have; mixpi_layout gives each system's groups).  q, p, f are host
- * arrays of n_systems device pointers; elog as mixpi_step.  Same results
+ * arrays of n_systems device pointers; nsteps and elog as mixpi_step
+ * (nsteps = 0 does nothing; a negative count or a null pointer is
+ * MIXPI_E_INVALID, with the state untouched).  Same results
  * bit for bit as mixpi_step on the systems' rows placed back to back.
  * Where the arrays already sit back to back in one allocation (q[k] =
  * q[0] + 3 x first row of system k, likewise p and f), it is mixpi_step on

@@ -2141,8 +2141,9 @@ int mixpi_batch_step(mixpi_system *sys, int32_t nsteps, double *const *q, double
         const long long off = 3 * sys->sys_row0[k];
         packed = packed && q[k] == q[0] + off && p[k] == p[0] + off && f[k] == f[0] + off;
     }
+    if (nsteps < 0) return fail(MIXPI_E_INVALID, "nsteps must be >= 0");
     if (packed) return mixpi_step(sys, nsteps, q[0], p[0], f[0], elog, stream);
-    if (nsteps <= 0) return fail(MIXPI_E_INVALID, "nsteps must be positive");
+    if (nsteps == 0) return MIXPI_OK;
     HIP_TRY(hipSetDevice(sys->device));
     const size_t words = 3 * (size_t)sys->rows;
     if (!sys->d_bstage) HIP_TRY(hipMalloc(&sys->d_bstage, 3 * words * sizeof(double)));

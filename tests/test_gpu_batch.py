@@ -268,3 +268,27 @@ def test_batch_step_with_separate_arrays(mp):
                      [fv[offs[k]:offs[k + 1]] for k in range(len(systems))], el2[c])
     assert torch.equal(qv, qd) and torch.equal(pv, pd) and torch.equal(fv, fd)
     assert torch.equal(el2, el_ref)
+
+
+def test_batch_step_rejects_bad_arguments(mp):
+    """mixpi_batch_step: null pointer arrays, a null entry and a negative
+    step count are errors; zero steps do nothing; the state is untouched."""
+    import ctypes as C
+    import torch
+    systems = mixed_batch()[:2]
+    b = mp.System(systems)
+    q, rows = pack(systems, [s.q for s in systems])
+    qs = [dev(q[r]) for r in rows]
+    ps = [torch.zeros_like(x) for x in qs]
+    fs = [torch.zeros_like(x) for x in qs]
+    lib = mp.load()
+    arr = [(C.c_void_p * 2)(*[x.data_ptr() for x in xs]) for xs in (qs, ps, fs)]
+    before = [host(x).copy() for x in qs]
+    assert lib.mixpi_batch_step(b.h, 1, None, arr[1], arr[2], None, None) == mp.MIXPI_E_INVALID
+    bad = (C.c_void_p * 2)(qs[0].data_ptr(), None)
+    assert lib.mixpi_batch_step(b.h, 1, bad, arr[1], arr[2], None, None) == mp.MIXPI_E_INVALID
+    assert lib.mixpi_batch_step(b.h, -1, arr[0], arr[1], arr[2], None, None) == mp.MIXPI_E_INVALID
+    assert lib.mixpi_batch_step(b.h, 0, arr[0], arr[1], arr[2], None, None) == mp.MIXPI_OK
+    torch.cuda.synchronize()
+    for x, bx in zip(qs, before):
+        assert np.array_equal(host(x), bx)
