@@ -151,16 +151,81 @@ __device__ __forceinline__ double2 cmul(double2 x, double2 y)
 }
 
 // In-place decimation-in-time FFT (exp(-2 pi i jk/N)) of a bit-reversed
-// input held in LDS.  Radix-2 stages are fused in pairs (one radix-4 pass:
-// each thread loads 4 points, applies stages s and s+1, stores 4 points),
-// which halves the LDS round trips and barriers; an odd log2 N starts with
-// one plain radix-2 stage.  Twiddles are stage-major (stage s at offset
-// 2^(s-1) - 1, entries exp(-2 pi i pos / 2^s)), so the lanes of a pass read
-// consecutive entries.
+// input held in LDS.  Radix-2 stages are fused into passes over LDS: a
+// radix-4 pass (each thread loads 4 points, applies stages s and s+1 in
+// registers, stores 4 points) or, where N/8 still gives every thread of the
+// workgroup a group (N >= 2048 at 256 threads), a radix-8 pass over stages
+// s..s+2.  Leading stages that the pass width does not divide form one
+// radix-2 or radix-4 pass.  Fewer passes mean fewer LDS round trips and
+// barriers; below that size the radix-8 pass leaves threads idle and ran
+// slower.  R8 = false keeps radix-4 passes at every size: the Langevin items
+// use it, since radix-8 code there raised the launch's register count (152
+// to 169 VGPRs) and slowed the thermostatted step.  Twiddles are stage-major
+// (stage s at offset 2^(s-1) - 1, entries exp(-2 pi i pos / 2^s)), so the
+// lanes of a pass read consecutive entries.
+__device__ __forceinline__ void bfly(double2 &a, double2 &b, double2 w)
+{
+    const double2 t = cmul(b, w);
+    b = make_double2(a.x - t.x, a.y - t.y);
+    a = make_double2(a.x + t.x, a.y + t.y);
+}
+
+// stages s and s+1 (half-lengths h and 2h)
+__device__ __forceinline__ void fft_pass4(double2 *z, const double2 *tw, int N, int s)
+{
+    const int h = 1 << (s - 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < N / 4; b += blockDim.x) {
+        const int pos = b & (h - 1);
+        const int i0 = ((b >> (s - 1)) << (s + 1)) + pos;
+        double2 x0 = z[i0], x1 = z[i0 + h], x2 = z[i0 + 2 * h], x3 = z[i0 + 3 * h];
+        const double2 w1 = tw[h - 1 + pos];                  // stage s
+        bfly(x0, x1, w1);
+        bfly(x2, x3, w1);
+        bfly(x0, x2, tw[2 * h - 1 + pos]);                   // stage s+1
+        bfly(x1, x3, tw[2 * h - 1 + pos + h]);
+        z[i0] = x0;
+        z[i0 + h] = x1;
+        z[i0 + 2 * h] = x2;
+        z[i0 + 3 * h] = x3;
+    }
+}
+
+// stages s, s+1 and s+2
+__device__ __forceinline__ void fft_pass8(double2 *z, const double2 *tw, int N, int s)
+{
+    const int h = 1 << (s - 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < N / 8; b += blockDim.x) {
+        const int pos = b & (h - 1);
+        const int i0 = ((b >> (s - 1)) << (s + 2)) + pos;
+        double2 x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = z[i0 + k * h];
+        const double2 w1 = tw[h - 1 + pos];                  // stage s
+        bfly(x[0], x[1], w1);
+        bfly(x[2], x[3], w1);
+        bfly(x[4], x[5], w1);
+        bfly(x[6], x[7], w1);
+        const double2 u0 = tw[2 * h - 1 + pos], u1 = tw[2 * h - 1 + pos + h];
+        bfly(x[0], x[2], u0);                                // stage s+1
+        bfly(x[1], x[3], u1);
+        bfly(x[4], x[6], u0);
+        bfly(x[5], x[7], u1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bfly(x[j], x[j + 4], tw[4 * h - 1 + pos + j * h]);  // stage s+2
+#pragma unroll
+        for (int k = 0; k < 8; ++k) z[i0 + k * h] = x[k];
+    }
+}
+
+template <bool R8>
 __device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
 {
+    const int r = R8 && N >= 8 * (int)blockDim.x ? 3 : 2;
     int s = 1;
-    if (L & 1) {
+    const int lead = L % r;
+    if (lead == 1) {
         __syncthreads();
         for (int b = threadIdx.x; b < N / 2; b += blockDim.x) {
             const double2 u = z[2 * b], v = z[2 * b + 1];
@@ -168,27 +233,13 @@ __device__ void fft_stages(double2 *z, const double2 *tw, int N, int L)
             z[2 * b + 1] = make_double2(u.x - v.x, u.y - v.y);
         }
         s = 2;
+    } else if (lead == 2) {
+        fft_pass4(z, tw, N, 1);
+        s = 3;
     }
-    for (; s < L; s += 2) {
-        const int h = 1 << (s - 1);
-        __syncthreads();
-        for (int b = threadIdx.x; b < N / 4; b += blockDim.x) {
-            const int pos = b & (h - 1);
-            const int i0 = ((b >> (s - 1)) << (s + 1)) + pos;
-            const int i1 = i0 + h, i2 = i0 + 2 * h, i3 = i0 + 3 * h;
-            const double2 w1 = tw[h - 1 + pos];            // stage s: exp(-2 pi i pos / 2h)
-            const double2 w2 = tw[2 * h - 1 + pos];        // stage s+1: exp(-2 pi i pos / 4h)
-            const double2 w3 = tw[2 * h - 1 + pos + h];
-            const double2 a0 = z[i0], a1 = cmul(z[i1], w1), a2 = z[i2], a3 = cmul(z[i3], w1);
-            const double2 b0 = make_double2(a0.x + a1.x, a0.y + a1.y);
-            const double2 b1 = make_double2(a0.x - a1.x, a0.y - a1.y);
-            const double2 c2 = cmul(make_double2(a2.x + a3.x, a2.y + a3.y), w2);
-            const double2 c3 = cmul(make_double2(a2.x - a3.x, a2.y - a3.y), w3);
-            z[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
-            z[i2] = make_double2(b0.x - c2.x, b0.y - c2.y);
-            z[i1] = make_double2(b1.x + c3.x, b1.y + c3.y);
-            z[i3] = make_double2(b1.x - c3.x, b1.y - c3.y);
-        }
+    for (; s < L; s += r) {
+        if (r == 3) fft_pass8(z, tw, N, s);
+        else fft_pass4(z, tw, N, s);
     }
     __syncthreads();
 }
@@ -225,7 +276,7 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
                     z[brev(N - m, L)] = make_double2(rN2 * x.x, rN2 * x.y);    // conj(Z_{N-m})
                 }
             });
-        fft_stages(z, tw, N, L);
+        fft_stages<true>(z, tw, N, L);
         for (int j = tid; j < N; j += blockDim.x) a.out_q[gaddr(j)] = z[j].x / N;
         return;
     }
@@ -257,7 +308,7 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
             z[brev(j, L)] = v.z;
             if (j < N - 1) tw[j] = v.t;
         });
-    fft_stages(z, tw, N, L);
+    fft_stages<true>(z, tw, N, L);
 
     if (a.op == OP_FWD) {
         for (int m = tid; m <= N / 2; m += blockDim.x) {
@@ -312,7 +363,7 @@ __device__ void rp_fft(const RpLaunch &a, const RpItem &it, double2 *z, double *
             z[j].y = -z[j].y;
         }
     }
-    fft_stages(z, tw, N, L);
+    fft_stages<true>(z, tw, N, L);
     const double iN = 1.0 / N;
     const double cq = cent_s;
     for (int j = tid; j < N; j += blockDim.x) {
@@ -858,7 +909,7 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
             sg[r].f = a.f[row * 3 + d];
         }
     }
-    fft_stages(z, tw, N, L);
+    fft_stages<false>(z, tw, N, L);
     // modes of p (as the forward transform), thermostatted, then the
     // conjugated Hermitian spectrum of the new modes (as the backward one)
     double2 keep[kLangKeep];
@@ -896,7 +947,7 @@ __device__ void rp_lang_fft(const RpLaunch &a, const RpItem &it, double2 *z)
             z[brev(N - m, L)] = make_double2(keep[r].x, keep[r].y);
         }
     }
-    fft_stages(z, tw, N, L);
+    fft_stages<false>(z, tw, N, L);
 #pragma unroll
     for (int r = 0; r < kMaxBeads / 256; ++r) {
         const int j = tid + r * 256;
