@@ -67,7 +67,7 @@ def test_energy_matches_forces_call(mp, name, s):
     assert np.allclose(host(e1), host(e2), rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096])
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
 def test_nm_transform_matches_oracle(mp, N):
     print(f"[nm] N={N}", flush=True)
     rng = np.random.default_rng(N)
@@ -190,6 +190,18 @@ def test_e256_ten_steps_fp64(mp):
     err = _per_step(mp, SYSTEMS[7][1], 10)
     print("  max per-step errors (q, p, E):", err.max(axis=0), flush=True)
     assert (err <= 1e-12).all(), err
+
+
+@pytest.mark.parametrize("circ", ["0", "1"], ids=["fft", "circulant"])
+def test_e2048_step_fp64(mp, circ, monkeypatch):
+    """A 2048-bead electron ring (its FFT columns take radix-8 passes) among
+    waters, one FP64 step against the oracle at the FP64 bar, through FFT
+    items and through bead-space circulant items."""
+    monkeypatch.setenv("MIXPI_RING_CIRC", circ)
+    monkeypatch.setenv("MIXPI_RING_CIRC_MMAC", "64")     # 12 N^2 = 48 M multiply-adds
+    print(f"[step64] e2048 circ={circ}", flush=True)
+    s = synth.solvated_electron(40, 2048, 11.0, seed=11, rc_pp=5.4, rc_aa=5.0, n_h=1, n_o=1)
+    _step_compare(mp, s, FP64, 1, 1e-12, 1e-12, 1e-12)
 
 
 @pytest.mark.parametrize("sparse", ["auto", "1"])
