@@ -58,12 +58,14 @@ CASES = [
     ("water-h8-o2", lambda: synth.water_box(40, 11.0, 8, 2, seed=4, rc=5.4)),
     ("e256-water", lambda: synth.solvated_electron(70, 256, 13.0, seed=5, rc_pp=6.4, rc_aa=6.0,
                                                    n_h=2, n_o=1)),
+    ("e2048-water", lambda: synth.solvated_electron(40, 2048, 11.0, seed=11, rc_pp=5.4,
+                                                    rc_aa=5.0, n_h=1, n_o=1)),
 ]
 
 
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_nvt_matches_oracle(mp, name, make):
-    """Dense (N <= 64) and FFT / circulant (N = 256) rings, 5 steps."""
+    """Dense (N <= 64) and FFT / circulant (N = 256, 2048) rings, 5 steps."""
     print(f"[nvt] {name}", flush=True)
     _nvt_compare(mp, make(), 5, 25.0, 7, 1e-12, 1e-12, 1e-12)
 
